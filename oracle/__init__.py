@@ -1,0 +1,276 @@
+"""CPU oracle for block-merged ray marching (City-on-Web, arXiv 2312.16457).
+
+TEST INFRASTRUCTURE ONLY: the plain definition that the GPU renderer is
+checked against.  Only the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the renderer never does, and the
+two share no code.  The C source (oracle.c) holds the arithmetic; this module
+only marshals numpy arrays.
+
+Pinning status of each function (what fixes it other than itself) is listed
+in tests/test_oracle_pins.py; there is no "parity unpinned" function here
+except the scene-level appearance (see the module docstring of those tests).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+
+MERGED, MONOLITHIC, REVERSED, BY_ID, ALPHA_NORM = range(5)
+
+
+def build():
+    """Compile oracle.c with gcc: fp32 decisions must not be contracted."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-o", LIB, os.path.join(HERE, "oracle.c"), "-lm"]
+    subprocess.check_call(cmd)
+
+
+class _Block(C.Structure):
+    _fields_ = [
+        ("block_id", C.c_int), ("lod", C.c_int),
+        ("lo", C.c_float * 3), ("hi", C.c_float * 3),
+        ("R", C.c_int), ("Rp", C.c_int), ("O", C.c_int),
+        ("dtype", C.c_int),
+        ("g8", C.c_void_p), ("p8", C.c_void_p * 3),
+        ("gf", C.c_void_p), ("pf", C.c_void_p * 3),
+        ("scale", (C.c_float * 8) * 4), ("offset", (C.c_float * 8) * 4),
+    ]
+
+
+class _View(C.Structure):
+    _fields_ = [
+        ("W", C.c_int), ("H", C.c_int), ("x0", C.c_int), ("y0", C.c_int), ("w", C.c_int), ("h", C.c_int),
+        ("eye", C.c_float * 3), ("R", C.c_float * 9),
+        ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+    ]
+
+
+class _Params(C.Structure):
+    _fields_ = [("mode", C.c_int), ("n_steps", C.c_int), ("delta", C.c_float), ("max_steps", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
+        L.orc_occupancy.argtypes = [C.POINTER(_Block), vp]
+        L.orc_ztop.argtypes = [C.POINTER(_Block), vp]
+        L.orc_ztop.restype = C.c_double
+        L.orc_render.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), C.POINTER(_View),
+                                 vp, C.c_int, C.POINTER(_Params), vp, vp, C.c_int, C.c_int,
+                                 vp, vp, vp, vp, vp, vp, C.c_int]
+        L.orc_ray_blocks.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(_View), vp, C.c_int,
+                                     C.POINTER(_Params), C.c_int, C.c_int, vp, C.c_int]
+        L.orc_adjoint.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), C.POINTER(_View),
+                                  vp, C.c_int, C.POINTER(_Params), vp, vp, C.c_int, vp, vp,
+                                  C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), vp]
+        L.orc_select.argtypes = [C.POINTER(_View), C.c_int, vp, vp, vp, vp, vp, vp, C.c_int, C.c_int,
+                                 vp, C.c_int]
+        L.orc_mlp.argtypes = [vp, vp, vp]
+        L.orc_field.argtypes = [C.POINTER(_Block), C.c_int, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def make_view(v):
+    s = _View()
+    s.W, s.H = int(v.W), int(v.H)
+    s.x0, s.y0, s.w, s.h = (int(x) for x in v.crop)
+    s.eye[:] = [float(x) for x in np.asarray(v.eye, np.float32)]
+    s.R[:] = [float(x) for x in np.asarray(v.R, np.float32).reshape(-1)]
+    s.fx, s.fy, s.cx, s.cy = v.fx, v.fy, v.cx, v.cy
+    return s
+
+
+def make_params(p):
+    s = _Params()
+    s.mode, s.n_steps, s.delta, s.max_steps = int(p.mode), int(p.n_steps), float(p.delta), int(p.max_steps)
+    return s
+
+
+class OracleScene:
+    """ctypes view of a list of BlockLod entries.
+
+    uint8 blocks are passed as bytes plus their fp32 scale/offset; float blocks
+    are held as fp64 copies (exact), which tests may perturb in place for
+    finite differences.  `need` restricts which blocks get textures (others
+    only contribute their AABB to the scene box)."""
+
+    def __init__(self, blocks, need=None):
+        self.blocks = list(blocks)
+        self.n = len(self.blocks)
+        self.arr = (_Block * self.n)()
+        self.keep = []
+        self.f64 = {}
+        for k, b in enumerate(self.blocks):
+            s = self.arr[k]
+            s.block_id, s.lod = int(b.block_id), int(b.lod)
+            s.lo[:] = [float(x) for x in b.aabb_min]
+            s.hi[:] = [float(x) for x in b.aabb_max]
+            s.R, s.Rp, s.O = int(b.grid_res), int(b.plane_res), int(b.occ_res)
+            for t in range(4):
+                s.scale[t][:] = [float(x) for x in b.scale[t]]
+                s.offset[t][:] = [float(x) for x in b.offset[t]]
+            if need is not None and k not in need:
+                s.dtype = 1 if b.dtype == 1 else 0
+                continue
+            if b.dtype == 0:
+                s.dtype = 0
+                g = np.ascontiguousarray(b.grid)
+                ps = [np.ascontiguousarray(p) for p in b.planes]
+                self.keep += [g] + ps
+                s.g8 = g.ctypes.data
+                for i in range(3):
+                    s.p8[i] = ps[i].ctypes.data
+            else:
+                s.dtype = 1
+                g = np.ascontiguousarray(b.grid, dtype=np.float64)
+                ps = [np.ascontiguousarray(p, dtype=np.float64) for p in b.planes]
+                self.f64[k] = (g, ps)
+                s.gf = g.ctypes.data
+                for i in range(3):
+                    s.pf[i] = ps[i].ctypes.data
+
+    def index(self, block_id, lod):
+        for k, b in enumerate(self.blocks):
+            if b.block_id == block_id and b.lod == lod:
+                return k
+        raise KeyError((block_id, lod))
+
+
+def occupancy(ob, k):
+    b = ob.blocks[k]
+    out = np.zeros((b.occ_res,) * 3, np.uint8)
+    r = lib().orc_occupancy(C.byref(ob.arr[k]), _ptr(out))
+    if r != 0:
+        raise ValueError("bad resolutions")
+    return out
+
+
+def ztop(ob, k, occ):
+    return lib().orc_ztop(C.byref(ob.arr[k]), _ptr(np.ascontiguousarray(occ)))
+
+
+def _occ_ptrs(ob, occs):
+    arr = (C.c_void_p * ob.n)()
+    for k in range(ob.n):
+        o = occs.get(k) if isinstance(occs, dict) else occs[k]
+        arr[k] = None if o is None else o.ctypes.data
+    return arr
+
+
+def pixels_of(view, rows=None, stride=1):
+    """Absolute pixel coordinates of a view's crop, row-major (optionally a
+    subset of rows)."""
+    x0, y0, w, h = view.crop
+    ys = np.arange(y0, y0 + h) if rows is None else np.asarray(rows)
+    ys = ys[::stride] if rows is None else ys
+    xs = np.arange(x0, x0 + w)
+    jj, ii = np.meshgrid(ys, xs, indexing="ij")
+    return np.stack([ii.reshape(-1), jj.reshape(-1)], axis=1).astype(np.int32)
+
+
+def render(ob, occs, view, set_idx, params, mlp, pix=None, composite=MERGED, nthreads=0):
+    L = lib()
+    if pix is None:
+        pix = pixels_of(view)
+    pix = np.ascontiguousarray(pix, np.int32)
+    n = pix.shape[0]
+    setv = np.ascontiguousarray(set_idx, np.int32)
+    w = np.ascontiguousarray(mlp, np.float64)
+    out = dict(rgb=np.zeros((n, 3)), trans=np.zeros(n), aux=np.zeros((n, 8)),
+               n_eval=np.zeros(n, np.int64), n_march=np.zeros(n, np.int64),
+               order_ok=np.zeros(n, np.int32))
+    vs, ps = make_view(view), make_params(params)
+    L.orc_render(ob.arr, ob.n, _occ_ptrs(ob, occs), C.byref(vs), _ptr(setv), len(setv), C.byref(ps),
+                 _ptr(w), _ptr(pix), n, composite, _ptr(out["rgb"]), _ptr(out["trans"]),
+                 _ptr(out["aux"]), _ptr(out["n_eval"]), _ptr(out["n_march"]),
+                 _ptr(out["order_ok"]), int(nthreads))
+    return out
+
+
+def ray_blocks(ob, view, set_idx, params, i, j, cap=128):
+    setv = np.ascontiguousarray(set_idx, np.int32)
+    out = np.zeros(cap, np.int32)
+    vs, ps = make_view(view), make_params(params)
+    m = lib().orc_ray_blocks(ob.arr, ob.n, C.byref(vs), _ptr(setv), len(setv), C.byref(ps), int(i),
+                             int(j), _ptr(out), cap)
+    return out[:m]
+
+
+def adjoint(ob, occs, view, set_idx, params, mlp, pix, grad_rgb, grad_trans=None):
+    """fp64 adjoint; returns ({block index: (grad_grid, [grad_planes])}, grad_mlp)."""
+    L = lib()
+    pix = np.ascontiguousarray(pix, np.int32)
+    setv = np.ascontiguousarray(set_idx, np.int32)
+    grads = {}
+    gg = (C.c_void_p * ob.n)()
+    gp = (C.c_void_p * (3 * ob.n))()
+    for k in set(int(s) for s in setv):
+        b = ob.blocks[k]
+        g = np.zeros(b.grid.shape, np.float64)
+        ps = [np.zeros(p.shape, np.float64) for p in b.planes]
+        grads[k] = (g, ps)
+        gg[k] = g.ctypes.data
+        for i in range(3):
+            gp[3 * k + i] = ps[i].ctypes.data
+    gm = np.zeros(499, np.float64)
+    gr = np.ascontiguousarray(grad_rgb, np.float64)
+    gt = None if grad_trans is None else np.ascontiguousarray(grad_trans, np.float64)
+    vs, ps_ = make_view(view), make_params(params)
+    r = L.orc_adjoint(ob.arr, ob.n, _occ_ptrs(ob, occs), C.byref(vs), _ptr(setv), len(setv),
+                      C.byref(ps_), _ptr(np.ascontiguousarray(mlp, np.float64)), _ptr(pix), pix.shape[0],
+                      _ptr(gr), _ptr(gt), gg, gp, _ptr(gm))
+    if r != 0:
+        raise ValueError("adjoint needs float blocks")
+    return grads, gm
+
+
+def select(view, entries, ztops, thresholds=(2.0, 4.0, 8.0), cull=True, cap=4096):
+    """entries: list of BlockLod (or objects with block_id, lod, aabb_min, aabb_max);
+    ztops: per entry.  Returns chosen entry indices in front-to-back order."""
+    n = len(entries)
+    ids = np.array([e.block_id for e in entries], np.int32)
+    lods = np.array([e.lod for e in entries], np.int32)
+    lo = np.array([e.aabb_min for e in entries], np.float32).reshape(-1)
+    hi = np.array([e.aabb_max for e in entries], np.float32).reshape(-1)
+    zt = np.ascontiguousarray(ztops, np.float64)
+    thr = np.ascontiguousarray(thresholds, np.float64)
+    out = np.zeros(cap, np.int32)
+    vs = make_view(view)
+    m = lib().orc_select(C.byref(vs), n, _ptr(ids), _ptr(lods), _ptr(lo), _ptr(hi), _ptr(zt), _ptr(thr),
+                         len(thr), int(cull), _ptr(out), cap)
+    if m < 0:
+        raise KeyError("selected (block, LOD) not loaded")
+    return out[:m]
+
+
+def mlp(w, x):
+    out = np.zeros(3)
+    lib().orc_mlp(_ptr(np.ascontiguousarray(w, np.float64)), _ptr(np.ascontiguousarray(x, np.float64)),
+                  _ptr(out))
+    return out
+
+
+def field(ob, k, pts):
+    """Pre-activation features (8 channels, fp64) at world points pts[n][3]."""
+    pts = np.ascontiguousarray(pts, np.float32)
+    out = np.zeros((pts.shape[0], 8))
+    lib().orc_field(C.byref(ob.arr[k]), pts.shape[0], _ptr(pts), _ptr(out))
+    return out

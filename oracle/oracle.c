@@ -1,0 +1,779 @@
+/*
+ * CPU oracle for block-merged ray marching (City-on-Web, arXiv 2312.16457).
+ *
+ * TEST INFRASTRUCTURE ONLY -- see oracle.h.  Written for plain readability:
+ * one ray at a time, every sample tested by its definition, no blocking,
+ * no skipping structure beyond the occupancy bit the method itself defines.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off (no fast-math), so every float
+ * operation below is one correctly rounded IEEE fp32 operation.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NCH 8
+
+/* ---------------------------------------------------------------------- */
+/* Discrete decisions in exact fp32                                         */
+/* ---------------------------------------------------------------------- */
+
+/* Pixel ray r(t) = o + t d (Sec. 3): o is the eye; d is the normalised
+ * camera-to-world rotation of the pixel-centre direction (x, y, 1). */
+static void ray_dir(const orc_view* v, int i, int j, float d[3]) {
+    float x = ((float)i + 0.5f - v->cx) / v->fx;
+    float y = ((float)j + 0.5f - v->cy) / v->fy;
+    float u[3];
+    for (int c = 0; c < 3; ++c) {
+        float a = v->R[3 * c + 0] * x;
+        float b = v->R[3 * c + 1] * y;
+        u[c] = (a + b) + v->R[3 * c + 2];
+    }
+    float n = sqrtf((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+    for (int c = 0; c < 3; ++c) d[c] = u[c] / n;
+}
+
+static void position(const float o[3], const float d[3], float t, float p[3]) {
+    for (int c = 0; c < 3; ++c) {
+        float td = t * d[c];
+        p[c] = o[c] + td;
+    }
+}
+
+static int inside(const float p[3], const float lo[3], const float hi[3]) {
+    for (int c = 0; c < 3; ++c)
+        if (!(lo[c] <= p[c] && p[c] < hi[c])) return 0;
+    return 1;
+}
+
+/* slab intersection in fp32 with the closed box; t_near clamped at 0 */
+static int slab32(const float o[3], const float d[3], const float lo[3], const float hi[3],
+                  float* tn, float* tf) {
+    float t0 = 0.0f, t1 = INFINITY;
+    for (int c = 0; c < 3; ++c) {
+        if (d[c] == 0.0f) {
+            if (o[c] < lo[c] || o[c] > hi[c]) return 0;
+            continue;
+        }
+        float inv = 1.0f / d[c];
+        float a = (lo[c] - o[c]) * inv;
+        float b = (hi[c] - o[c]) * inv;
+        float mn = a < b ? a : b, mx = a < b ? b : a;
+        if (mn > t0) t0 = mn;
+        if (mx < t1) t1 = mx;
+    }
+    *tn = t0;
+    *tf = t1;
+    return t0 < t1;
+}
+
+/* occupancy cell of a sample in block b (fp32 local coordinate) */
+static int occ_cell(const orc_block* b, const float p[3], float q[3]) {
+    int cell[3];
+    for (int c = 0; c < 3; ++c) {
+        q[c] = p[c] - b->lo[c];
+        float s = q[c] * (float)b->O;
+        int k = (int)floorf(s);
+        if (k < 0) k = 0;
+        if (k > b->O - 1) k = b->O - 1;
+        cell[c] = k;
+    }
+    return (cell[2] * b->O + cell[1]) * b->O + cell[0];
+}
+
+/* ---------------------------------------------------------------------- */
+/* Texture access                                                           */
+/* ---------------------------------------------------------------------- */
+
+static double texel(const orc_block* b, int tex, long idx, int ch) {
+    if (b->dtype == ORC_U8) {
+        const unsigned char* src = tex == 0 ? b->g8 : b->p8[tex - 1];
+        return (double)src[idx * NCH + ch] * (double)b->scale[tex][ch] + (double)b->offset[tex][ch];
+    }
+    const double* src = tex == 0 ? b->gf : b->pf[tex - 1];
+    return src[idx * NCH + ch];
+}
+
+/* texel value as the fp32 decision sees it: fl(fl(q*s)+o), or the stored value */
+static float texel32(const orc_block* b, int tex, long idx, int ch) {
+    if (b->dtype == ORC_U8) {
+        const unsigned char* src = tex == 0 ? b->g8 : b->p8[tex - 1];
+        float m = (float)src[idx * NCH + ch] * b->scale[tex][ch];
+        return m + b->offset[tex][ch];
+    }
+    const double* src = tex == 0 ? b->gf : b->pf[tex - 1];
+    return (float)src[idx * NCH + ch];
+}
+
+static int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
+
+/* cell-centred linear interpolation taps with clamp-to-edge: u = q*R - 1/2 */
+static void lin_taps(double q, int R, int idx[2], double w[2]) {
+    double u = q * (double)R - 0.5;
+    double f0 = floor(u);
+    double f = u - f0;
+    int a = (int)f0;
+    idx[0] = clampi(a, 0, R - 1);
+    idx[1] = clampi(a + 1, 0, R - 1);
+    w[0] = 1.0 - f;
+    w[1] = f;
+}
+
+typedef struct tap {
+    int tex;
+    long idx;
+    double w;
+} tap;
+
+/* raw features = grid trilinear + three bilinear planes, summed ((G+XY)+XZ)+YZ.
+ * taps (20 entries) receive the texel index and interpolation weight of each
+ * texture sample, for the adjoint. */
+static void eval_raw(const orc_block* b, const float q32[3], double raw[NCH], tap* taps) {
+    double q[3] = {q32[0], q32[1], q32[2]};
+    int gi[3][2], pi[3][2];
+    double gw[3][2], pw[3][2];
+    for (int c = 0; c < 3; ++c) {
+        lin_taps(q[c], b->R, gi[c], gw[c]);
+        lin_taps(q[c], b->Rp, pi[c], pw[c]);
+    }
+    double part[4][NCH];
+    memset(part, 0, sizeof(part));
+    int nt = 0;
+    /* grid [z][y][x] */
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                long idx = ((long)gi[2][dz] * b->R + gi[1][dy]) * b->R + gi[0][dx];
+                double w = gw[2][dz] * gw[1][dy] * gw[0][dx];
+                for (int ch = 0; ch < NCH; ++ch) part[0][ch] += w * texel(b, 0, idx, ch);
+                if (taps) taps[nt++] = (tap){0, idx, w};
+            }
+    /* planes: xy -> (x, y), xz -> (x, z), yz -> (y, z); index [v][u] */
+    static const int axes[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int pl = 0; pl < 3; ++pl) {
+        int au = axes[pl][0], av = axes[pl][1];
+        for (int dv = 0; dv < 2; ++dv)
+            for (int du = 0; du < 2; ++du) {
+                long idx = (long)pi[av][dv] * b->Rp + pi[au][du];
+                double w = pw[av][dv] * pw[au][du];
+                for (int ch = 0; ch < NCH; ++ch) part[1 + pl][ch] += w * texel(b, 1 + pl, idx, ch);
+                if (taps) taps[nt++] = (tap){1 + pl, idx, w};
+            }
+    }
+    for (int ch = 0; ch < NCH; ++ch) raw[ch] = ((part[0][ch] + part[1][ch]) + part[2][ch]) + part[3][ch];
+}
+
+static double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* ---------------------------------------------------------------------- */
+/* Occupancy: conservative max-bound of the interpolated density           */
+/* ---------------------------------------------------------------------- */
+
+int orc_occupancy(const orc_block* b, unsigned char* out) {
+    const float thresh = (float)log(0.01); /* density 0.01 in pre-activation units */
+    int O = b->O, R = b->R, Rp = b->Rp;
+    if (O <= 0 || R % O || Rp % O) return -1;
+    int s = R / O, sp = Rp / O;
+    for (int cz = 0; cz < O; ++cz)
+        for (int cy = 0; cy < O; ++cy)
+            for (int cx = 0; cx < O; ++cx) {
+                int c3[3] = {cx, cy, cz};
+                int glo[3], ghi[3], plo[3], phi[3];
+                for (int a = 0; a < 3; ++a) {
+                    glo[a] = clampi(c3[a] * s - 1, 0, R - 1);
+                    ghi[a] = clampi((c3[a] + 1) * s, 0, R - 1);
+                    plo[a] = clampi(c3[a] * sp - 1, 0, Rp - 1);
+                    phi[a] = clampi((c3[a] + 1) * sp, 0, Rp - 1);
+                }
+                float mg = -INFINITY;
+                for (int z = glo[2]; z <= ghi[2]; ++z)
+                    for (int y = glo[1]; y <= ghi[1]; ++y)
+                        for (int x = glo[0]; x <= ghi[0]; ++x) {
+                            float v = texel32(b, 0, ((long)z * R + y) * R + x, 0);
+                            if (v > mg) mg = v;
+                        }
+                static const int axes[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+                float mp[3];
+                for (int pl = 0; pl < 3; ++pl) {
+                    int au = axes[pl][0], av = axes[pl][1];
+                    float m = -INFINITY;
+                    for (int vv = plo[av]; vv <= phi[av]; ++vv)
+                        for (int uu = plo[au]; uu <= phi[au]; ++uu) {
+                            float val = texel32(b, 1 + pl, (long)vv * Rp + uu, 0);
+                            if (val > m) m = val;
+                        }
+                    mp[pl] = m;
+                }
+                float bound = ((mg + mp[0]) + mp[1]) + mp[2];
+                out[(cz * O + cy) * O + cx] = bound > thresh ? 1 : 0;
+            }
+    return 0;
+}
+
+double orc_ztop(const orc_block* b, const unsigned char* occ) {
+    int O = b->O, top = -1;
+    for (int z = 0; z < O; ++z)
+        for (int i = 0; i < O * O; ++i)
+            if (occ[z * O * O + i]) top = z;
+    double ext = (double)b->hi[2] - (double)b->lo[2];
+    return (double)b->lo[2] + (double)(top + 1) / (double)O * ext;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Sample enumeration                                                      */
+/* ---------------------------------------------------------------------- */
+
+typedef struct sample {
+    int set_pos;   /* position in the view's set */
+    long k;        /* global (mode 1) or per-block (mode 0) step index */
+    float q[3];    /* fp32 local coordinate */
+    double delta;
+    int occupied;
+} sample;
+
+static int cmp_tin(const void* a, const void* b) {
+    const double* x = (const double*)a;
+    const double* y = (const double*)b;
+    if (x[0] < y[0]) return -1;
+    if (x[0] > y[0]) return 1;
+    return x[1] < y[1] ? -1 : (x[1] > y[1]);
+}
+
+/* Enumerate the samples of one ray in compositing order (front to back).
+ * Returns the number written (<= cap).  Empty samples (no block in the set,
+ * or outside every block) are not listed; unoccupied ones are, with
+ * occupied = 0. */
+static long enumerate(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
+                      const orc_view* v, const int* set, int nset, const orc_params* p,
+                      int i, int j, sample* out, long cap, float dir[3]) {
+    float d[3];
+    ray_dir(v, i, j, d);
+    if (dir) memcpy(dir, d, sizeof(d));
+    const float* o = v->eye;
+    long n = 0;
+    if (p->mode == 0) {
+        /* per-block chord, n_steps midpoints; blocks in order of entry t */
+        double* ord = (double*)malloc(sizeof(double) * 4 * (nset > 0 ? nset : 1));
+        int nh = 0;
+        for (int s = 0; s < nset; ++s) {
+            const orc_block* b = &blocks[set[s]];
+            float tn, tf;
+            if (!slab32(o, d, b->lo, b->hi, &tn, &tf)) continue;
+            ord[4 * nh + 0] = tn;
+            ord[4 * nh + 1] = b->block_id;
+            ord[4 * nh + 2] = s;
+            ord[4 * nh + 3] = tf;
+            ++nh;
+        }
+        qsort(ord, nh, sizeof(double) * 4, cmp_tin);
+        for (int h = 0; h < nh; ++h) {
+            int s = (int)ord[4 * h + 2];
+            const orc_block* b = &blocks[set[s]];
+            float tn = (float)ord[4 * h + 0], tf = (float)ord[4 * h + 3];
+            float dr = (tf - tn) / (float)p->n_steps;
+            for (int k = 0; k < p->n_steps; ++k) {
+                float t = tn + ((float)k + 0.5f) * dr;
+                float pt[3];
+                position(o, d, t, pt);
+                if (!inside(pt, b->lo, b->hi)) continue;
+                if (n >= cap) break;
+                sample* sm = &out[n++];
+                sm->set_pos = s;
+                sm->k = k;
+                sm->delta = dr;
+                int cell = occ_cell(b, pt, sm->q);
+                sm->occupied = occ[set[s]][cell] != 0;
+            }
+        }
+        free(ord);
+        return n;
+    }
+    /* mode 1: camera-anchored grid t_k = (k + 1/2) delta; window of max_steps
+     * steps from the first sample inside the scene box */
+    float slo[3] = {INFINITY, INFINITY, INFINITY}, shi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = 0; b < nblocks; ++b)
+        for (int c = 0; c < 3; ++c) {
+            if (blocks[b].lo[c] < slo[c]) slo[c] = blocks[b].lo[c];
+            if (blocks[b].hi[c] > shi[c]) shi[c] = blocks[b].hi[c];
+        }
+    /* scan bound from an fp64 slab test of the box grown by 1e-3 */
+    double tfar = INFINITY, tnear = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double lo = (double)slo[c] - 1e-3, hi = (double)shi[c] + 1e-3, oc = o[c], dc = d[c];
+        if (dc == 0.0) {
+            if (oc < lo || oc > hi) return 0;
+            continue;
+        }
+        double a = (lo - oc) / dc, bb = (hi - oc) / dc;
+        double mn = a < bb ? a : bb, mx = a < bb ? bb : a;
+        if (mn > tnear) tnear = mn;
+        if (mx < tfar) tfar = mx;
+    }
+    if (!(tnear <= tfar)) return 0;
+    long kmax = (long)ceil(tfar / (double)p->delta) + 8;
+    long k0 = -1;
+    for (long k = 0; k <= kmax; ++k) {
+        float t = ((float)k + 0.5f) * p->delta;
+        float pt[3];
+        position(o, d, t, pt);
+        if (inside(pt, slo, shi)) {
+            k0 = k;
+            break;
+        }
+    }
+    if (k0 < 0) return 0;
+    for (long k = k0; k < k0 + p->max_steps; ++k) {
+        float t = ((float)k + 0.5f) * p->delta;
+        float pt[3];
+        position(o, d, t, pt);
+        int s_hit = -1;
+        for (int s = 0; s < nset; ++s)
+            if (inside(pt, blocks[set[s]].lo, blocks[set[s]].hi)) {
+                s_hit = s;
+                break;
+            }
+        if (s_hit < 0) continue;
+        if (n >= cap) break;
+        sample* sm = &out[n++];
+        sm->set_pos = s_hit;
+        sm->k = k;
+        sm->delta = p->delta;
+        int cell = occ_cell(&blocks[set[s_hit]], pt, sm->q);
+        sm->occupied = occ[set[s_hit]][cell] != 0;
+    }
+    return n;
+}
+
+static long sample_cap(const orc_params* p, int nset) {
+    return p->mode == 0 ? (long)p->n_steps * (nset > 0 ? nset : 1) : (long)p->max_steps;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Deferred MLP (Eq. "deferred")                                            */
+/* ---------------------------------------------------------------------- */
+
+typedef struct mlp_trace {
+    double x[10], pre1[16], h1[16], pre2[16], h2[16], z[3], s[3];
+} mlp_trace;
+
+static void mlp_fwd(const double* w, const double* x, mlp_trace* tr) {
+    const double *W1 = w, *b1 = w + 160, *W2 = w + 176, *b2 = w + 432, *W3 = w + 448, *b3 = w + 496;
+    memcpy(tr->x, x, sizeof(double) * 10);
+    for (int o = 0; o < 16; ++o) {
+        double a = b1[o];
+        for (int i = 0; i < 10; ++i) a += W1[o * 10 + i] * x[i];
+        tr->pre1[o] = a;
+        tr->h1[o] = a > 0.0 ? a : 0.0;
+    }
+    for (int o = 0; o < 16; ++o) {
+        double a = b2[o];
+        for (int i = 0; i < 16; ++i) a += W2[o * 16 + i] * tr->h1[i];
+        tr->pre2[o] = a;
+        tr->h2[o] = a > 0.0 ? a : 0.0;
+    }
+    for (int o = 0; o < 3; ++o) {
+        double a = b3[o];
+        for (int i = 0; i < 16; ++i) a += W3[o * 16 + i] * tr->h2[i];
+        tr->z[o] = a;
+        tr->s[o] = sigm(a);
+    }
+}
+
+void orc_field(const orc_block* b, int n, const float* pts, double* raw) {
+    for (int k = 0; k < n; ++k) {
+        float q[3];
+        for (int c = 0; c < 3; ++c) q[c] = pts[3 * k + c] - b->lo[c];
+        eval_raw(b, q, raw + NCH * k, NULL);
+    }
+}
+
+void orc_mlp(const double* mlp, const double* x, double* out) {
+    mlp_trace tr;
+    mlp_fwd(mlp, x, &tr);
+    for (int c = 0; c < 3; ++c) out[c] = tr.s[c];
+}
+
+/* ---------------------------------------------------------------------- */
+/* Rendering                                                               */
+/* ---------------------------------------------------------------------- */
+
+typedef struct pt_val {
+    double sigma, v[7];
+} pt_val;
+
+static void shade(const orc_block* b, const float q[3], pt_val* pv, double raw[NCH], tap* taps) {
+    eval_raw(b, q, raw, taps);
+    pv->sigma = exp(raw[0]);
+    for (int c = 0; c < 7; ++c) pv->v[c] = sigm(raw[1 + c]);
+}
+
+static void render_one(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
+                       const orc_view* v, const int* set, int nset, const orc_params* p,
+                       const double* mlp, int i, int j, int composite, sample* buf, long cap,
+                       double rgb[3], double* trans, double aux[8], long long* ne,
+                       long long* nm, int* ook) {
+    float d[3];
+    long n = enumerate(blocks, nblocks, occ, v, set, nset, p, i, j, buf, cap, d);
+    /* block runs in ray order */
+    int* run_pos = (int*)malloc(sizeof(int) * (n + 1));
+    int nrun = 0, ordered = 1;
+    long long eval = 0;
+    for (long s = 0; s < n; ++s) {
+        if (s == 0 || buf[s].set_pos != buf[s - 1].set_pos) {
+            for (int r = 0; r < nrun; ++r)
+                if (run_pos[r] == buf[s].set_pos) ordered = 0; /* block re-entered */
+            if (nrun > 0 && buf[s].set_pos < run_pos[nrun - 1]) ordered = 0;
+            run_pos[nrun++] = buf[s].set_pos;
+        }
+        eval += buf[s].occupied;
+    }
+    double A[7] = {0}, T = 1.0;
+    if (composite == ORC_MONOLITHIC) {
+        for (long s = 0; s < n; ++s) {
+            if (!buf[s].occupied) continue;
+            pt_val pv;
+            double raw[NCH];
+            shade(&blocks[set[buf[s].set_pos]], buf[s].q, &pv, raw, NULL);
+            double sd = pv.sigma * buf[s].delta;
+            double alpha = -expm1(-sd);
+            double w = T * alpha;
+            for (int c = 0; c < 7; ++c) A[c] += w * pv.v[c];
+            T *= exp(-sd);
+        }
+    } else {
+        /* per-block composite (Eq. "volume rendering inside blocks") */
+        double* Ak = (double*)calloc((size_t)(nrun + 1) * 8, sizeof(double));
+        int r = -1;
+        for (long s = 0; s < n; ++s) {
+            if (s == 0 || buf[s].set_pos != buf[s - 1].set_pos) {
+                ++r;
+                Ak[r * 8 + 7] = 1.0;
+            }
+            if (!buf[s].occupied) continue;
+            pt_val pv;
+            double raw[NCH];
+            shade(&blocks[set[buf[s].set_pos]], buf[s].q, &pv, raw, NULL);
+            double sd = pv.sigma * buf[s].delta;
+            double alpha = -expm1(-sd);
+            double w = Ak[r * 8 + 7] * alpha;
+            for (int c = 0; c < 7; ++c) Ak[r * 8 + c] += w * pv.v[c];
+            Ak[r * 8 + 7] *= exp(-sd);
+        }
+        if (composite == ORC_ALPHA_NORM) {
+            double asum = 0.0;
+            for (int q = 0; q < nrun; ++q) asum += 1.0 - Ak[q * 8 + 7];
+            for (int q = 0; q < nrun; ++q) {
+                double wgt = asum > 0.0 ? (1.0 - Ak[q * 8 + 7]) / asum : 0.0;
+                for (int c = 0; c < 7; ++c) A[c] += wgt * Ak[q * 8 + c];
+                T *= Ak[q * 8 + 7];
+            }
+        } else {
+            /* merge front to back (Eq. "volume rendering across blocks"), with
+             * the block transmittance carried as the product of (1 - alpha_i) */
+            int* ordr = (int*)malloc(sizeof(int) * (nrun + 1));
+            for (int q = 0; q < nrun; ++q) ordr[q] = q;
+            if (composite == ORC_REVERSED)
+                for (int q = 0; q < nrun; ++q) ordr[q] = nrun - 1 - q;
+            if (composite == ORC_BY_ID) /* insertion sort of runs by block id */
+                for (int a = 1; a < nrun; ++a)
+                    for (int b = a; b > 0; --b) {
+                        int ia = blocks[set[run_pos[ordr[b]]]].block_id;
+                        int ib = blocks[set[run_pos[ordr[b - 1]]]].block_id;
+                        if (ia < ib) {
+                            int t = ordr[b];
+                            ordr[b] = ordr[b - 1];
+                            ordr[b - 1] = t;
+                        }
+                    }
+            for (int q = 0; q < nrun; ++q) {
+                int rr = ordr[q];
+                for (int c = 0; c < 7; ++c) A[c] += T * Ak[rr * 8 + c];
+                T *= Ak[rr * 8 + 7];
+            }
+            free(ordr);
+        }
+        free(Ak);
+    }
+    free(run_pos);
+    double x[10];
+    for (int c = 0; c < 7; ++c) x[c] = A[c];
+    for (int c = 0; c < 3; ++c) x[7 + c] = d[c];
+    mlp_trace tr;
+    mlp_fwd(mlp, x, &tr);
+    for (int c = 0; c < 3; ++c) rgb[c] = A[c] + tr.s[c];
+    *trans = T;
+    for (int c = 0; c < 7; ++c) aux[c] = A[c];
+    aux[7] = T;
+    *ne = eval;
+    *nm = n;
+    *ook = ordered;
+}
+
+int orc_render(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
+               const orc_view* v, const int* set, int nset, const orc_params* p,
+               const double* mlp, const int* pix, int npix, int composite,
+               double* rgb, double* trans, double* aux, long long* n_eval,
+               long long* n_march, int* order_ok, int nthreads) {
+    long cap = sample_cap(p, nset);
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        sample* buf = (sample*)malloc(sizeof(sample) * cap);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+        for (int q = 0; q < npix; ++q) {
+            double c3[3], t, a8[8];
+            long long ne, nm;
+            int ok;
+            render_one(blocks, nblocks, occ, v, set, nset, p, mlp, pix[2 * q], pix[2 * q + 1],
+                       composite, buf, cap, c3, &t, a8, &ne, &nm, &ok);
+            if (rgb) memcpy(rgb + 3 * q, c3, sizeof(c3));
+            if (trans) trans[q] = t;
+            if (aux) memcpy(aux + 8 * q, a8, sizeof(a8));
+            if (n_eval) n_eval[q] = ne;
+            if (n_march) n_march[q] = nm;
+            if (order_ok) order_ok[q] = ok;
+        }
+        free(buf);
+    }
+    (void)nthreads;
+    return 0;
+}
+
+int orc_ray_blocks(const orc_block* blocks, int nblocks, const orc_view* v, const int* set,
+                   int nset, const orc_params* p, int i, int j, int* out, int cap) {
+    /* occupancy is irrelevant for the order: use an all-occupied mask */
+    unsigned char one = 1;
+    const unsigned char** occ = (const unsigned char**)malloc(sizeof(void*) * nblocks);
+    unsigned char** full = (unsigned char**)malloc(sizeof(void*) * nblocks);
+    for (int b = 0; b < nblocks; ++b) {
+        long o3 = (long)blocks[b].O * blocks[b].O * blocks[b].O;
+        full[b] = (unsigned char*)malloc(o3);
+        memset(full[b], one, o3);
+        occ[b] = full[b];
+    }
+    long cap_s = sample_cap(p, nset);
+    sample* buf = (sample*)malloc(sizeof(sample) * cap_s);
+    long n = enumerate(blocks, nblocks, occ, v, set, nset, p, i, j, buf, cap_s, NULL);
+    int m = 0;
+    for (long s = 0; s < n; ++s)
+        if ((s == 0 || buf[s].set_pos != buf[s - 1].set_pos) && m < cap) out[m++] = set[buf[s].set_pos];
+    free(buf);
+    for (int b = 0; b < nblocks; ++b) free(full[b]);
+    free(full);
+    free(occ);
+    return m;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Adjoint (fp64)                                                          */
+/* ---------------------------------------------------------------------- */
+
+int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
+                const orc_view* v, const int* set, int nset, const orc_params* p,
+                const double* mlp, const int* pix, int npix, const double* grad_rgb,
+                const double* grad_trans, double* const* grad_grid, double* const* grad_plane,
+                double* grad_mlp) {
+    for (int s = 0; s < nset; ++s)
+        if (blocks[set[s]].dtype != ORC_F64) return -1;
+    long cap = sample_cap(p, nset);
+    sample* buf = (sample*)malloc(sizeof(sample) * cap);
+    pt_val* pv = (pt_val*)malloc(sizeof(pt_val) * cap);
+    tap* taps = (tap*)malloc(sizeof(tap) * 20 * cap);
+    double* wts = (double*)malloc(sizeof(double) * cap);
+    double* Tb = (double*)malloc(sizeof(double) * (cap + 1));
+    double* suf = (double*)malloc(sizeof(double) * 7 * (cap + 1));
+    long* ev = (long*)malloc(sizeof(long) * cap);
+    const double *W1 = mlp, *W2 = mlp + 176, *W3 = mlp + 448;
+    for (int q = 0; q < npix; ++q) {
+        float d[3];
+        long n = enumerate(blocks, nblocks, occ, v, set, nset, p, pix[2 * q], pix[2 * q + 1], buf,
+                           cap, d);
+        /* forward over the monolithic sequence (equal to the merged one) */
+        long m = 0;
+        double T = 1.0, A[7] = {0};
+        for (long s = 0; s < n; ++s) {
+            if (!buf[s].occupied) continue;
+            double raw[NCH];
+            shade(&blocks[set[buf[s].set_pos]], buf[s].q, &pv[m], raw, &taps[20 * m]);
+            double sd = pv[m].sigma * buf[s].delta;
+            double alpha = -expm1(-sd);
+            Tb[m] = T;
+            wts[m] = T * alpha;
+            for (int c = 0; c < 7; ++c) A[c] += wts[m] * pv[m].v[c];
+            T *= exp(-sd);
+            ev[m] = s;
+            ++m;
+        }
+        Tb[m] = T;
+        /* suffix sums S_i = sum_{j>i} w_j v_j */
+        for (int c = 0; c < 7; ++c) suf[7 * m + c] = 0.0;
+        if (m > 0)
+            for (int c = 0; c < 7; ++c) suf[7 * (m - 1) + c] = 0.0;
+        for (long s = m - 2; s >= 0; --s)
+            for (int c = 0; c < 7; ++c) suf[7 * s + c] = suf[7 * (s + 1) + c] + wts[s + 1] * pv[s + 1].v[c];
+        /* MLP backward */
+        double x[10];
+        for (int c = 0; c < 7; ++c) x[c] = A[c];
+        for (int c = 0; c < 3; ++c) x[7 + c] = d[c];
+        mlp_trace tr;
+        mlp_fwd(mlp, x, &tr);
+        const double* g = grad_rgb + 3 * q;
+        double dz[3], dh2[16], dh1[16], dx[10];
+        for (int o = 0; o < 3; ++o) dz[o] = g[o] * tr.s[o] * (1.0 - tr.s[o]);
+        for (int i = 0; i < 16; ++i) {
+            double a = 0.0;
+            for (int o = 0; o < 3; ++o) a += W3[o * 16 + i] * dz[o];
+            dh2[i] = tr.pre2[i] > 0.0 ? a : 0.0;
+        }
+        for (int i = 0; i < 16; ++i) {
+            double a = 0.0;
+            for (int o = 0; o < 16; ++o) a += W2[o * 16 + i] * dh2[o];
+            dh1[i] = tr.pre1[i] > 0.0 ? a : 0.0;
+        }
+        for (int i = 0; i < 10; ++i) {
+            double a = 0.0;
+            for (int o = 0; o < 16; ++o) a += W1[o * 10 + i] * dh1[o];
+            dx[i] = a;
+        }
+        if (grad_mlp) {
+            for (int o = 0; o < 16; ++o) {
+                for (int i = 0; i < 10; ++i) grad_mlp[o * 10 + i] += dh1[o] * tr.x[i];
+                grad_mlp[160 + o] += dh1[o];
+                for (int i = 0; i < 16; ++i) grad_mlp[176 + o * 16 + i] += dh2[o] * tr.h1[i];
+                grad_mlp[432 + o] += dh2[o];
+            }
+            for (int o = 0; o < 3; ++o) {
+                for (int i = 0; i < 16; ++i) grad_mlp[448 + o * 16 + i] += dz[o] * tr.h2[i];
+                grad_mlp[496 + o] += dz[o];
+            }
+        }
+        double u[7];
+        for (int c = 0; c < 7; ++c) u[c] = dx[c] + (c < 3 ? g[c] : 0.0);
+        double gT = grad_trans ? grad_trans[q] : 0.0;
+        /* per-sample adjoint */
+        for (long s = 0; s < m; ++s) {
+            const sample* sm = &buf[ev[s]];
+            double delta = sm->delta;
+            double uv = 0.0, us = 0.0;
+            for (int c = 0; c < 7; ++c) {
+                uv += u[c] * pv[s].v[c];
+                us += u[c] * suf[7 * s + c];
+            }
+            double dsig = delta * (Tb[s + 1] * uv - us) - delta * T * gT;
+            double draw[NCH];
+            draw[0] = pv[s].sigma * dsig;
+            for (int c = 0; c < 7; ++c) {
+                double sv = pv[s].v[c];
+                draw[1 + c] = wts[s] * u[c] * sv * (1.0 - sv);
+            }
+            int b = set[sm->set_pos];
+            for (int t = 0; t < 20; ++t) {
+                const tap* tp = &taps[20 * s + t];
+                double* dst = tp->tex == 0 ? grad_grid[b] : grad_plane[3 * b + tp->tex - 1];
+                if (!dst) continue;
+                for (int ch = 0; ch < NCH; ++ch) dst[tp->idx * NCH + ch] += tp->w * draw[ch];
+            }
+        }
+    }
+    free(buf);
+    free(pv);
+    free(taps);
+    free(wts);
+    free(Tb);
+    free(suf);
+    free(ev);
+    (void)nblocks;
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Selection (viewer: dynamic loading, LOD, depth sorting)                 */
+/* ---------------------------------------------------------------------- */
+
+static int culled(const orc_view* v, const double lo[3], const double hi[3]) {
+    double Rm[9], e[3];
+    for (int k = 0; k < 9; ++k) Rm[k] = v->R[k];
+    for (int k = 0; k < 3; ++k) e[k] = v->eye[k];
+    double xw0 = v->x0, xw1 = (double)v->x0 + v->w, yw0 = v->y0, yw1 = (double)v->y0 + v->h;
+    double fx = v->fx, fy = v->fy, cx = v->cx, cy = v->cy;
+    double planes[5][3] = {
+        {fx, 0.0, cx - xw0}, {-fx, 0.0, xw1 - cx}, {0.0, fy, cy - yw0}, {0.0, -fy, yw1 - cy}, {0.0, 0.0, 1.0}};
+    double X[8][3], nX[8];
+    for (int c = 0; c < 8; ++c) {
+        double P[3] = {(c & 1) ? hi[0] : lo[0], (c & 2) ? hi[1] : lo[1], (c & 4) ? hi[2] : lo[2]};
+        double w[3] = {P[0] - e[0], P[1] - e[1], P[2] - e[2]};
+        for (int a = 0; a < 3; ++a) X[c][a] = Rm[0 * 3 + a] * w[0] + Rm[1 * 3 + a] * w[1] + Rm[2 * 3 + a] * w[2];
+        nX[c] = sqrt(X[c][0] * X[c][0] + X[c][1] * X[c][1] + X[c][2] * X[c][2]);
+    }
+    for (int pl = 0; pl < 5; ++pl) {
+        double* n = planes[pl];
+        double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        int all_out = 1;
+        for (int c = 0; c < 8 && all_out; ++c) {
+            double s = (n[0] * X[c][0] + n[1] * X[c][1] + n[2] * X[c][2]) / nn;
+            if (!(s < -1e-5 * nX[c])) all_out = 0;
+        }
+        if (all_out) return 1;
+    }
+    return 0;
+}
+
+int orc_select(const orc_view* v, int nent, const int* ids, const int* lods, const float* lo,
+               const float* hi, const double* ztop, const double* thresholds, int n_thr,
+               int cull, int* out, int cap) {
+    int n = 0;
+    double* key = (double*)malloc(sizeof(double) * (nent + 1));
+    for (int e = 0; e < nent; ++e) {
+        if (lods[e] != 0) continue; /* one decision per block, made from its finest level */
+        double c[3] = {0.5 * ((double)lo[3 * e] + (double)hi[3 * e]),
+                       0.5 * ((double)lo[3 * e + 1] + (double)hi[3 * e + 1]), ztop[e]};
+        double dx = (double)v->eye[0] - c[0], dy = (double)v->eye[1] - c[1], dz = (double)v->eye[2] - c[2];
+        double dist = sqrt(dx * dx + dy * dy + dz * dz);
+        int lod = -1;
+        for (int l = 0; l < n_thr; ++l)
+            if (dist < thresholds[l]) {
+                lod = l;
+                break;
+            }
+        if (lod < 0) continue; /* beyond the far cut */
+        int chosen = -1;
+        for (int f = 0; f < nent; ++f)
+            if (ids[f] == ids[e] && lods[f] == lod) chosen = f;
+        if (chosen < 0) {
+            free(key);
+            return -2;
+        }
+        if (cull) {
+            double blo[3] = {lo[3 * chosen], lo[3 * chosen + 1], lo[3 * chosen + 2]};
+            double bhi[3] = {hi[3 * chosen], hi[3 * chosen + 1], ztop[chosen]};
+            if (culled(v, blo, bhi)) continue;
+        }
+        if (n >= cap) break;
+        out[n] = chosen;
+        key[n] = sqrt(dx * dx + dy * dy);
+        ++n;
+    }
+    /* insertion sort by xy distance, ties to the lower block id */
+    for (int a = 1; a < n; ++a)
+        for (int b = a; b > 0; --b) {
+            int swap = key[b] < key[b - 1] || (key[b] == key[b - 1] && ids[out[b]] < ids[out[b - 1]]);
+            if (!swap) break;
+            double tk = key[b];
+            key[b] = key[b - 1];
+            key[b - 1] = tk;
+            int to = out[b];
+            out[b] = out[b - 1];
+            out[b - 1] = to;
+        }
+    free(key);
+    return n;
+}

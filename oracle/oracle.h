@@ -1,0 +1,105 @@
+/*
+ * CPU oracle for block-merged ray marching (City-on-Web, arXiv 2312.16457).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, plainly written definition the
+ * GPU path is checked against.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load it; the renderer itself never does.
+ * It shares no code, header or constant table with the HIP library.
+ *
+ * Discrete decisions (ray direction, sample positions, sample -> block,
+ * occupancy cell, occupancy bit) are taken in IEEE fp32 exactly as specified
+ * below; all continuous arithmetic (interpolation, activations, compositing,
+ * MLP, adjoint) is fp64.
+ */
+#ifndef CITYWEB_ORACLE_H
+#define CITYWEB_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_U8 = 0, ORC_F64 = 1 };
+
+typedef struct orc_block {
+    int block_id, lod;
+    float lo[3], hi[3];      /* AABB; samples belong to [lo, hi) (half-open) */
+    int R, Rp, O;            /* grid, plane and occupancy resolution */
+    int dtype;               /* ORC_U8 or ORC_F64 */
+    const unsigned char* g8; /* [R][R][R][8]  z,y,x,ch */
+    const unsigned char* p8[3];
+    const double* gf;        /* same layouts, fp64 values */
+    const double* pf[3];
+    float scale[4][8];       /* uint8 decode q*scale+offset (tex 0 grid, 1 xy, 2 xz, 3 yz) */
+    float offset[4][8];
+} orc_block;
+
+typedef struct orc_view {
+    int W, H, x0, y0, w, h;  /* image size and crop window */
+    float eye[3];
+    float R[9];              /* camera-to-world, row-major; columns right, down, forward */
+    float fx, fy, cx, cy;
+} orc_view;
+
+typedef struct orc_params {
+    int mode;                /* 0: n_steps midpoints over each block chord; 1: global grid */
+    int n_steps;
+    float delta;             /* mode 1 step length */
+    int max_steps;           /* mode 1 cap counted from scene entry */
+} orc_params;
+
+enum {
+    ORC_MERGED = 0,          /* per-block composite, merged in per-ray entry order */
+    ORC_MONOLITHIC = 1,      /* one composite over the whole sample sequence */
+    ORC_REVERSED = 2,        /* negative control: merge in reverse entry order */
+    ORC_BY_ID = 3,           /* negative control: merge in block-id order */
+    ORC_ALPHA_NORM = 4       /* negative control: blend blocks with alpha^k / sum alpha^j */
+};
+
+/* occupancy bits [O][O][O] (z,y,x) of one block by the conservative max-bound rule */
+int orc_occupancy(const orc_block* b, unsigned char* out);
+
+/* top of the highest occupied cell (world z) */
+double orc_ztop(const orc_block* b, const unsigned char* occ);
+
+/* Render pixels (absolute image coordinates pix[2n], pix[2n+1]) of one view.
+ * blocks: every registered block (defines the scene box); occ[b]: its fixed
+ * occupancy; set: indices into blocks of the (block, LOD) entries that the
+ * view renders.  Any output pointer may be NULL. */
+int orc_render(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
+               const orc_view* v, const int* set, int nset, const orc_params* p,
+               const double* mlp, const int* pix, int npix, int composite,
+               double* rgb, double* trans, double* aux, long long* n_eval,
+               long long* n_march, int* order_ok, int nthreads);
+
+/* Entry order of blocks along one ray (block indices into `blocks`); returns count */
+int orc_ray_blocks(const orc_block* blocks, int nblocks, const orc_view* v, const int* set,
+                   int nset, const orc_params* p, int i, int j, int* out, int cap);
+
+/* fp64 adjoint.  grad_rgb[npix*3], grad_trans[npix] (nullable).  Gradients are
+ * ACCUMULATED into grad_grid[b] / grad_plane[3b+k] (NULL entries skipped) for
+ * every b in the set and into grad_mlp[499] (nullable).  fp64 blocks only. */
+int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
+                const orc_view* v, const int* set, int nset, const orc_params* p,
+                const double* mlp, const int* pix, int npix, const double* grad_rgb,
+                const double* grad_trans, double* const* grad_grid, double* const* grad_plane,
+                double* grad_mlp);
+
+/* Per-view block selection: LOD by eye-to-centre distance, frustum culling,
+ * front-to-back order by xy distance.  Inputs per distinct block entry k:
+ * ids[k], lods[k], lo/hi[3k..], ztop[k].  Writes chosen entry indices in order.
+ * Returns the count, or -2 if a chosen (block, LOD) is not among the entries. */
+int orc_select(const orc_view* v, int nent, const int* ids, const int* lods, const float* lo,
+               const float* hi, const double* ztop, const double* thresholds, int n_thr,
+               int cull, int* out, int cap);
+
+/* pre-activation features at n world points of block b (points outside the
+ * block are evaluated by the same clamped rule): raw[8n] */
+void orc_field(const orc_block* b, int n, const float* pts, double* raw);
+
+/* the MLP alone: x[10] -> out[3] = sigmoid(z) (before adding C_d) */
+void orc_mlp(const double* mlp, const double* x, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
