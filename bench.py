@@ -1,0 +1,187 @@
+"""Benchmark of the block-merged ray-march render path on one MI355X.
+
+Workload (N=1): 4x4 ground-partitioned uint8 blocks (128^3 grid + three
+1024^2 planes, 16^3 occupancy per block), one 1920x1080 view, camera-anchored
+steps of 1/512 block width, at most 2048 steps per ray, deferred MLP
+10->16->16->3.  One step = one full render of the frame (forward march with
+per-block composite and front-to-back merge, then the MFMA MLP pass), inputs
+resident in HBM.
+
+Prints one JSON line: metric/value (forward Msamples/s of evaluated samples),
+FPS, the roofline of the march kernel (timed with HIP events on its own
+stream inside the library), the CPU oracle baseline on a bounded sample, and
+optional extra measurements (backward, batched vs per-block launches).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+# MI355X published peaks
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+# algorithmic fp32 flops of one evaluated sample of the uint8 path:
+#   trilinear grid 8 taps x 8 ch x 2 = 128, three bilinear planes 3 x 4 x 8 x 2 = 192,
+#   interpolation weights 30, decode q*s+o 4 x 8 x 2 = 64, texture sum 3 x 8 = 24,
+#   activations (exp + 7 sigmoid) 22, alpha / weight / composite of 7 values / T 20
+FLOPS_PER_SAMPLE = 128 + 192 + 30 + 64 + 24 + 22 + 20  # 480
+BYTES_PER_SAMPLE_U8 = 160  # 20 texels x 8 uint8 channels gathered per evaluated sample
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extras", action="store_true", help="also time backward (C5) and batched C4")
+    ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU leg)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the render path shards by view or by block with no "
+              "inter-GPU exchange in the forward pass, and this build runs on a single MI355X.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import __graft_entry__
+    __graft_entry__._ensure_built()
+    from paper_2312_16457_amd import Renderer, scenegen as sg
+
+    t0 = time.time()
+    scene = sg.c2_scene()
+    view = sg.c2_view()
+    params = sg.cityb_params()
+    w = sg.xavier_mlp(1)
+    print(f"[bench] scene generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    r = Renderer(0)
+    r.load_blocks(scene.blocks)
+    sel = r.select(view, thresholds=(1e30,), cull=True)
+    mlp = torch.tensor(w, device="cuda")
+    # evaluated-sample count from the kernel's own counters (untimed run)
+    out = r.render([view], [sel], params, mlp, counts=True)
+    torch.cuda.synchronize()
+    n_eval = int(out["counts"][:, 0].sum().item())
+    n_march = int(out["counts"][:, 1].sum().item())
+    out = r.render([view], [sel], params, mlp, want_aux=False)
+    steps, warm = (3, 1) if args.profile else (args.steps, args.warmup)
+    for _ in range(warm):
+        r.render([view], [sel], params, mlp, out=out)
+    torch.cuda.synchronize()
+    # march-kernel duration: HIP events recorded by the library around the
+    # kernel on the call's stream
+    r.set_timing(True)
+    march_ms = []
+    for _ in range(steps):
+        r.render([view], [sel], params, mlp, out=out)
+        march_ms.append(r.last_timing()[0])
+    r.set_timing(False)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        r.render([view], [sel], params, mlp, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t_start) * 1e3 / steps
+    msamples = n_eval / (ms * 1e-3) / 1e6
+    fps = 1000.0 / ms
+    k_ms = float(np.mean(march_ms))
+    achieved = FLOPS_PER_SAMPLE * n_eval / (k_ms * 1e-3) / 1e12
+    res = {
+        "metric": "forward Msamples/s (evaluated samples), 4x4 uint8 blocks, 1920x1080",
+        "value": round(msamples, 2),
+        "unit": "Msamples/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "4x4 ground blocks, uint8 128^3 grid + 3x1024^2 planes, 16^3 occupancy, "
+                               "one 1920x1080 view, delta 1/512, <=2048 steps, MLP 10-16-16-3",
+                   "pixels": view.n_pixels, "evaluated_samples": n_eval, "marched_samples": n_march,
+                   "blocks": len(sel)},
+        "fps_1080p": round(fps, 2),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                     "kernel": "march_fwd_kernel<1,0,false>", "kernel_ms": round(k_ms, 4),
+                     "flops_per_sample": FLOPS_PER_SAMPLE,
+                     "gathered_GBps": round(BYTES_PER_SAMPLE_U8 * n_eval / (k_ms * 1e-3) / 1e9, 1)},
+    }
+    if not args.no_cpu_baseline and not args.profile:
+        res["cpu_baseline"] = cpu_baseline(scene, view, sel, params, w)
+    if args.extras and not args.profile:
+        res["extras"] = extras(torch, sg, Renderer)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(scene, view, sel, params, w):
+    """The CPU oracle, as it stands, on every 16th row of the same frame."""
+    import oracle as O
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    set_idx = [next(k for k, b in enumerate(scene.blocks) if (b.block_id, b.lod) == s) for s in sel]
+    rows = np.arange(0, view.H, 16)
+    pix = O.pixels_of(view, rows=rows)
+    threads = os.cpu_count() or 1
+    t = time.perf_counter()
+    ref = O.render(ob, occs, view, set_idx, params, w, pix=pix, nthreads=threads)
+    dt = time.perf_counter() - t
+    return {"value": round(ref["n_eval"].sum() / dt / 1e6, 3), "unit": "Msamples/s", "cores": threads,
+            "kind": "oracle", "sample": f"every 16th row of the 1920x1080 frame ({len(rows)} rows, "
+                                        f"{len(pix)} rays, {int(ref['n_eval'].sum())} evaluated samples), "
+                                        f"fp64, {dt:.1f}s"}
+
+
+def extras(torch, sg, Renderer):
+    """Backward throughput on the fp32 4x4 scene (8 views at 800x800) and the
+    batched-vs-per-block comparison on the 8x8x3-LOD scene (64 views)."""
+    from paper_2312_16457_amd import F_GRAPH, F_PER_BLOCK
+    ex = {}
+    # backward: 8 x 800^2 views
+    learn, _ = sg.c5_scenes()
+    views = sg.c5_views()
+    p = sg.cityb_params()
+    r = Renderer(0)
+    r.load_blocks(learn.blocks)
+    sets = [[(b.block_id, 0) for b in learn.blocks]] * len(views)
+    mlp = torch.tensor(sg.xavier_mlp(4), device="cuda")
+    out = r.render(views, sets, p, mlp, counts=True)
+    n_eval = int(out["counts"][:, 0].sum().item())
+    g = torch.randn_like(out["rgb"]) * 1e-3
+    gg = [torch.zeros_like(t[0]) for t in r.textures]
+    gp = [[torch.zeros_like(x) for x in t[1]] for t in r.textures]
+    gm = torch.zeros(499, device="cuda")
+    r.render_backward(views, sets, p, mlp, out["aux"], g, None, gg, gp, gm)
+    torch.cuda.synchronize()
+    r.set_timing(True)
+    bt = []
+    for _ in range(3):
+        r.render_backward(views, sets, p, mlp, out["aux"], g, None, gg, gp, gm)
+        bt.append(r.last_timing()[1])
+    r.set_timing(False)
+    t = time.perf_counter()
+    for _ in range(3):
+        r.render_backward(views, sets, p, mlp, out["aux"], g, None, gg, gp, gm)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / 3
+    ex["bwd"] = {"Msamples_per_s": round(n_eval / (ms * 1e-3) / 1e6, 2), "ms": round(ms, 3),
+                 "march_bwd_ms": round(float(np.mean(bt)), 3), "evaluated_samples": n_eval,
+                 "workload": "4x4 fp32 blocks 128^3 + 3x1024^2, 8 views 800x800"}
+    del r, gg, gp
+    torch.cuda.empty_cache()
+    return ex
+
+
+if __name__ == "__main__":
+    main()

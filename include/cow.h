@@ -1,0 +1,217 @@
+/*
+ * cow.h -- C ABI of the MI355X block-merged ray-march renderer
+ * (City-on-Web, arXiv 2312.16457).
+ *
+ * What it computes.  A scene is partitioned on the ground plane into
+ * axis-aligned unit blocks (Sec. 4.1, Eq. "blocks"); a sample point belongs
+ * to the block whose half-open box [lo, hi) contains it.  Each (block, LOD)
+ * holds a MERF-style baked representation (Sec. 3, Sec. 4.1 "Rendering
+ * Stage"): a low-res 3D feature grid, three high-res feature planes (xy, xz,
+ * yz) and an occupancy grid.  For every pixel ray the library
+ *   1. composites the samples of each block front to back (Eqs. "alpha
+ *      accumulation", "combined accumulation", "volume rendering inside
+ *      blocks"), giving per-block (C_d^k, F^k, T^k);
+ *   2. merges the blocks in depth order, A <- A + T * A^k, T <- T * T^k
+ *      (Eq. "volume rendering across blocks"; Appendix A shows
+ *      1 - alpha^k = prod_i (1 - alpha_i^k), so T^k is carried directly);
+ *   3. shades once with the tiny deferred MLP, C = C_d + sigmoid(Phi(C_d, F, d))
+ *      (Eq. "deferred"), with the unit world-space view direction d.
+ *
+ * Conventions.
+ *   Texture layouts are channels-last with 8 channels (0: pre-activation
+ *   density, exp; 1-3: diffuse, sigmoid; 4-7: specular features, sigmoid):
+ *     grid  [R][R][R][8]  indexed [z][y][x][c]
+ *     plane xy [Rp][Rp][8] indexed [y][x][c]; xz [z][x][c]; yz [z][y][c]
+ *   Texels are cell-centred with clamp-to-edge; raw features are
+ *   ((grid + xy) + xz) + yz.  uint8 texels decode to q * scale + offset per
+ *   (texture, channel), texture 0 = grid, 1 = xy, 2 = xz, 3 = yz.
+ *   Cameras use OpenCV axes; R is camera-to-world, row-major, with columns
+ *   (right, down, forward).  Pixel (i, j) has direction
+ *   normalize(R [(i + 1/2 - cx)/fx, (j + 1/2 - cy)/fy, 1]).
+ *   MLP weights: float[499] = W1[16][10], b1[16], W2[16][16], b2[16],
+ *   W3[3][16], b3[3] (row-major, out x in); input x = [C_d(3), F(4), d(3)].
+ *
+ * Memory ownership.  Every device buffer is owned by the caller.  The library
+ * keeps non-owning pointers to the textures passed to cow_load_blocks until
+ * the next cow_load_blocks or cow_destroy; the caller keeps them alive and
+ * may change their values (occupancy is not recomputed).  Workspaces are
+ * caller-allocated device memory sized by cow_query_workspace.
+ *
+ * Streams and threads.  Device work is enqueued on the given HIP stream and
+ * the call returns; outputs are valid after the stream synchronises.  A
+ * context is used from one host thread at a time.
+ *
+ * Errors.  Every entry point returns a cow_status.  Arguments are validated
+ * before anything is enqueued, so a failed call has no device side effects;
+ * cow_last_error gives the reason.  No C++ exception crosses this boundary.
+ */
+#ifndef COW_H
+#define COW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define COW_API __attribute__((visibility("default")))
+
+typedef enum cow_status {
+    COW_OK = 0,
+    COW_E_INVALID = 1,     /* bad argument (null pointer, size, range, NaN camera ...) */
+    COW_E_NOT_LOADED = 2,  /* a (block, LOD) in a set is not loaded */
+    COW_E_WORKSPACE = 3,   /* workspace smaller than cow_query_workspace asked for */
+    COW_E_UNSUPPORTED = 4, /* e.g. backward through uint8 textures */
+    COW_E_HIP = 5,         /* HIP runtime error; text in cow_last_error */
+    COW_E_INTERNAL = 6
+} cow_status;
+
+enum { COW_U8 = 0, COW_F32 = 1 };
+
+/* sampling modes */
+enum {
+    COW_MODE_CHORD = 0, /* n_steps midpoints over each block's ray chord (single-block scenes) */
+    COW_MODE_GRID = 1   /* t_k = (k + 1/2) delta from the eye; max_steps steps from scene entry */
+};
+
+/* render flags */
+enum {
+    COW_F_NONE = 0,
+    COW_F_GRAPH = 1,       /* replay a cached hipGraph of the launch sequence */
+    COW_F_PERSISTENT = 2,  /* persistent workgroups pulling ray packets from a counter */
+    COW_F_PER_BLOCK = 4,   /* baseline: one launch per view per block, blended in order */
+    COW_F_SPARSE = 8       /* read uint8 grids from the packed brick atlas (cow_pack_bricks) */
+};
+
+typedef struct cow_ctx cow_ctx;
+
+typedef struct cow_block_desc {
+    int32_t block_id, lod;
+    float aabb_min[3], aabb_max[3]; /* unit extent on every axis */
+    int32_t grid_res, plane_res, occ_res; /* powers of two, occ_res divides both */
+    int32_t dtype;                  /* COW_U8 or COW_F32 */
+    const void* grid;               /* device, [R][R][R][8] */
+    const void* plane[3];           /* device, xy, xz, yz: [Rp][Rp][8] */
+    float scale[4][8];              /* uint8 decode; ignored for COW_F32 */
+    float offset[4][8];
+} cow_block_desc;
+
+typedef struct cow_view {
+    int32_t W, H;                   /* image size */
+    int32_t crop_x0, crop_y0, crop_w, crop_h; /* rendered window */
+    float eye[3];
+    float R[9];
+    float fx, fy, cx, cy;
+} cow_view;
+
+typedef struct cow_block_ref {
+    int32_t block_id, lod;
+} cow_block_ref;
+
+typedef struct cow_block_set {
+    const cow_block_ref* refs;      /* host array, any order */
+    int32_t n;
+} cow_block_set;
+
+typedef struct cow_lod_policy {
+    double thresholds[3];           /* LOD l where distance < thresholds[l]; beyond the last: dropped */
+    int32_t n_thresholds;
+    int32_t cull;                   /* nonzero: frustum culling */
+} cow_lod_policy;
+
+typedef struct cow_render_params {
+    int32_t mode;                   /* COW_MODE_CHORD or COW_MODE_GRID */
+    int32_t n_steps;                /* chord mode */
+    float delta;                    /* grid mode step length (world units) */
+    int32_t max_steps;              /* grid mode cap, counted from scene entry */
+    int32_t flags;                  /* COW_F_* */
+    int64_t* counts;                /* device [P][2] (evaluated, marched) per pixel, or NULL */
+} cow_render_params;
+
+/* Create a context bound to HIP device `device` (host state only). */
+COW_API cow_status cow_create(cow_ctx** out, int device);
+COW_API cow_status cow_destroy(cow_ctx* ctx);
+
+/* Reason for the last failure on this context; valid until the next call. */
+COW_API const char* cow_last_error(const cow_ctx* ctx);
+
+/* Workspace sizes in bytes for loading `blocks` and for render / backward
+ * calls of up to max_views views and max_pixels pixels in total. */
+COW_API cow_status cow_query_workspace(cow_ctx* ctx, const cow_block_desc* blocks, int n_blocks,
+                               int max_views, int64_t max_pixels, size_t* load_bytes,
+                               size_t* render_bytes, size_t* backward_bytes);
+
+/* Register the blocks and build each one's occupancy grid (conservative
+ * max-bound rule: a cell is occupied iff the sum over the four textures of
+ * the largest density-channel texel in the cell's interpolation support
+ * exceeds ln 0.01, Sec. 4.5 "Baking") into load_ws.  Replaces any previous
+ * load.  Synchronises `stream` once (z_top of each block is read back). */
+COW_API cow_status cow_load_blocks(cow_ctx* ctx, const cow_block_desc* blocks, int n, void* load_ws,
+                           size_t load_bytes, hipStream_t stream);
+
+/* Copy one loaded block's occupancy [O][O][O] (z, y, x) to host memory. */
+COW_API cow_status cow_get_occupancy(cow_ctx* ctx, int block_id, int lod, uint8_t* host_out, size_t n);
+
+/* Per-view selection (Appendix D, "Dynamic Loading", "Depth sorting"):
+ * LOD by the distance from the eye to (centre_x, centre_y, z_top of the
+ * finest level), frustum culling of [x0,x1]x[y0,y1]x[z_lo, z_top(LOD)],
+ * front-to-back order by xy distance to the block centre (ties: lower id).
+ * All decisions in fp64.  Writes up to cap refs; *n_out = count. */
+COW_API cow_status cow_select_blocks(cow_ctx* ctx, const cow_view* view, const cow_lod_policy* policy,
+                             cow_block_ref* out, int cap, int* n_out);
+
+/* Sparse grid (Sec. 4.5 "block-sparse format"): pack the uint8 grid of every
+ * loaded uint8 block into bricks covering the interpolation support of its
+ * occupied cells.  cow_query_bricks gives the size after cow_load_blocks.
+ * Renders with COW_F_SPARSE then read the grid from the bricks (results are
+ * bitwise identical to the dense grid). */
+COW_API cow_status cow_query_bricks(cow_ctx* ctx, size_t* brick_bytes);
+COW_API cow_status cow_pack_bricks(cow_ctx* ctx, void* brick_ws, size_t brick_bytes, hipStream_t stream);
+
+/* Render n_views views.  Pixels are the views' crops concatenated in view
+ * order, row-major within each crop (P in total).  sets[v] lists the
+ * (block, LOD) entries view v renders; the library orders them front to back
+ * by xy distance.  mlp: device float[499].  Outputs (device): rgb [P][3],
+ * trans [P], aux [P][8] = (C_d, F, T) or NULL (required before a backward). */
+COW_API cow_status cow_render(cow_ctx* ctx, const cow_view* views, int n_views, const cow_block_set* sets,
+                      const cow_render_params* params, const float* mlp, float* rgb, float* trans,
+                      float* aux, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of cow_render for COW_F32 blocks.  grad_rgb [P][3] and grad_trans
+ * [P] (nullable) are dL/d outputs; aux is the forward's aux.  Gradients are
+ * ACCUMULATED into grad_grid[e] / grad_plane[3e + k] for loaded entry e (in
+ * load order; NULL entries skipped) and into grad_mlp[499]; fp32 atomics, so
+ * summation order varies run to run.  Per-ray samples are recomputed. */
+COW_API cow_status cow_render_backward(cow_ctx* ctx, const cow_view* views, int n_views,
+                               const cow_block_set* sets, const cow_render_params* params,
+                               const float* mlp, const float* aux, const float* grad_rgb,
+                               const float* grad_trans, float* const* grad_grid,
+                               float* const* grad_plane, float* grad_mlp, void* ws,
+                               size_t ws_bytes, hipStream_t stream);
+
+/* Time the launch configurations (ray-packet shape, waves per workgroup,
+ * persistent or not) on this workload and keep the fastest for later
+ * renders; reads/writes a JSON cache at cache_path (nullable).  The choice
+ * never changes results. */
+COW_API cow_status cow_autotune(cow_ctx* ctx, const cow_view* views, int n_views, const cow_block_set* sets,
+                        const cow_render_params* params, const float* mlp, void* ws,
+                        size_t ws_bytes, const char* cache_path, hipStream_t stream);
+
+/* Current launch configuration (packet width in pixels, waves per
+ * workgroup, persistent flag) and an explicit override. */
+COW_API cow_status cow_get_config(cow_ctx* ctx, int* tile_w, int* waves, int* persistent);
+COW_API cow_status cow_set_config(cow_ctx* ctx, int tile_w, int waves, int persistent);
+
+/* Instrumentation: when enabled, HIP events bracket the march kernel of
+ * each cow_render / cow_render_backward on the call's stream; the last
+ * call's forward and backward march durations in milliseconds. */
+COW_API cow_status cow_set_timing(cow_ctx* ctx, int enable);
+COW_API cow_status cow_last_timing(cow_ctx* ctx, float* fwd_march_ms, float* bwd_march_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

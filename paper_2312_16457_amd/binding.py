@@ -1,0 +1,355 @@
+"""ctypes binding of libcow.so (include/cow.h) with torch tensors as the
+device-memory and stream plumbing.  Argument marshalling only: every step of
+the render runs in the HIP library, and a missing library is an error."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcow.so")
+
+COW_OK, COW_E_INVALID, COW_E_NOT_LOADED, COW_E_WORKSPACE, COW_E_UNSUPPORTED, COW_E_HIP, COW_E_INTERNAL = range(7)
+COW_U8, COW_F32 = 0, 1
+MODE_CHORD, MODE_GRID = 0, 1
+F_NONE, F_GRAPH, F_PERSISTENT, F_PER_BLOCK, F_SPARSE = 0, 1, 2, 4, 8
+
+EXPORTS = ["cow_create", "cow_destroy", "cow_last_error", "cow_query_workspace", "cow_load_blocks",
+           "cow_get_occupancy", "cow_select_blocks", "cow_query_bricks", "cow_pack_bricks", "cow_render",
+           "cow_render_backward", "cow_autotune", "cow_get_config", "cow_set_config", "cow_set_timing",
+           "cow_last_timing"]
+
+
+class CowError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"cow status {status}: {msg}")
+        self.status = status
+
+
+class BlockDesc(C.Structure):
+    _fields_ = [("block_id", C.c_int32), ("lod", C.c_int32),
+                ("aabb_min", C.c_float * 3), ("aabb_max", C.c_float * 3),
+                ("grid_res", C.c_int32), ("plane_res", C.c_int32), ("occ_res", C.c_int32),
+                ("dtype", C.c_int32), ("grid", C.c_void_p), ("plane", C.c_void_p * 3),
+                ("scale", (C.c_float * 8) * 4), ("offset", (C.c_float * 8) * 4)]
+
+
+class View(C.Structure):
+    _fields_ = [("W", C.c_int32), ("H", C.c_int32), ("crop_x0", C.c_int32), ("crop_y0", C.c_int32),
+                ("crop_w", C.c_int32), ("crop_h", C.c_int32), ("eye", C.c_float * 3), ("R", C.c_float * 9),
+                ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float)]
+
+
+class BlockRef(C.Structure):
+    _fields_ = [("block_id", C.c_int32), ("lod", C.c_int32)]
+
+
+class BlockSet(C.Structure):
+    _fields_ = [("refs", C.POINTER(BlockRef)), ("n", C.c_int32)]
+
+
+class LodPolicy(C.Structure):
+    _fields_ = [("thresholds", C.c_double * 3), ("n_thresholds", C.c_int32), ("cull", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("n_steps", C.c_int32), ("delta", C.c_float), ("max_steps", C.c_int32),
+                ("flags", C.c_int32), ("counts", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the built library; raise if it is absent (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        P, vp = C.POINTER, C.c_void_p
+        L.cow_create.argtypes = [P(vp), C.c_int]
+        L.cow_destroy.argtypes = [vp]
+        L.cow_last_error.argtypes = [vp]
+        L.cow_last_error.restype = C.c_char_p
+        L.cow_query_workspace.argtypes = [vp, P(BlockDesc), C.c_int, C.c_int, C.c_int64, P(C.c_size_t),
+                                          P(C.c_size_t), P(C.c_size_t)]
+        L.cow_load_blocks.argtypes = [vp, P(BlockDesc), C.c_int, vp, C.c_size_t, vp]
+        L.cow_get_occupancy.argtypes = [vp, C.c_int, C.c_int, vp, C.c_size_t]
+        L.cow_select_blocks.argtypes = [vp, P(View), P(LodPolicy), P(BlockRef), C.c_int, P(C.c_int)]
+        L.cow_query_bricks.argtypes = [vp, P(C.c_size_t)]
+        L.cow_pack_bricks.argtypes = [vp, vp, C.c_size_t, vp]
+        L.cow_render.argtypes = [vp, P(View), C.c_int, P(BlockSet), P(Params), vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.cow_render_backward.argtypes = [vp, P(View), C.c_int, P(BlockSet), P(Params), vp, vp, vp, vp,
+                                          P(vp), P(vp), vp, vp, C.c_size_t, vp]
+        L.cow_autotune.argtypes = [vp, P(View), C.c_int, P(BlockSet), P(Params), vp, vp, C.c_size_t, C.c_char_p, vp]
+        L.cow_get_config.argtypes = [vp, P(C.c_int), P(C.c_int), P(C.c_int)]
+        L.cow_set_config.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+        L.cow_set_timing.argtypes = [vp, C.c_int]
+        L.cow_last_timing.argtypes = [vp, P(C.c_float), P(C.c_float)]
+        for name in EXPORTS:
+            if name != "cow_last_error":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def make_view(v):
+    s = View()
+    s.W, s.H = int(v.W), int(v.H)
+    s.crop_x0, s.crop_y0, s.crop_w, s.crop_h = (int(x) for x in v.crop)
+    s.eye[:] = [float(x) for x in np.asarray(v.eye, np.float32)]
+    s.R[:] = [float(x) for x in np.asarray(v.R, np.float32).reshape(-1)]
+    s.fx, s.fy, s.cx, s.cy = float(v.fx), float(v.fy), float(v.cx), float(v.cy)
+    return s
+
+
+def make_params(p, flags=0, counts=None):
+    s = Params()
+    s.mode, s.n_steps, s.delta, s.max_steps = int(p.mode), int(p.n_steps), float(p.delta), int(p.max_steps)
+    s.flags = int(flags)
+    s.counts = None if counts is None else counts.data_ptr()
+    return s
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Renderer:
+    """One library context on one GPU.  Device memory (textures, workspaces,
+    outputs) is held as torch tensors; the library only sees pointers."""
+
+    def __init__(self, device=0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.L = lib()
+        h = C.c_void_p()
+        st = self.L.cow_create(C.byref(h), int(device))
+        if st != COW_OK:
+            raise CowError(st, "cow_create failed")
+        self.h = h
+        self.blocks = []  # (block_id, lod) in load order
+        self.textures = []
+        self.load_ws = None
+        self.render_ws = None
+        self.bwd_ws = None
+        self.brick_ws = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.L.cow_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != COW_OK:
+            raise CowError(st, self.L.cow_last_error(self.h).decode())
+
+    # -- loading ----------------------------------------------------------------
+    def load_blocks(self, blocks):
+        """blocks: sequence of scenegen.BlockLod (numpy textures are copied to
+        the GPU) or of dicts with torch textures already on the device."""
+        torch = self.torch
+        descs = (BlockDesc * len(blocks))()
+        keep = []
+        self.blocks = []
+        for k, b in enumerate(blocks):
+            d = descs[k]
+            get = (lambda n: b[n]) if isinstance(b, dict) else (lambda n: getattr(b, n))
+            d.block_id, d.lod = int(get("block_id")), int(get("lod"))
+            d.aabb_min[:] = [float(x) for x in get("aabb_min")]
+            d.aabb_max[:] = [float(x) for x in get("aabb_max")]
+            d.grid_res, d.plane_res, d.occ_res = int(get("grid_res")), int(get("plane_res")), int(get("occ_res"))
+            d.dtype = int(get("dtype"))
+            g = get("grid")
+            ps = list(get("planes"))
+            if not torch.is_tensor(g):
+                g = torch.from_numpy(np.ascontiguousarray(g)).to(self.device)
+                ps = [torch.from_numpy(np.ascontiguousarray(p)).to(self.device) for p in ps]
+            want = torch.uint8 if d.dtype == COW_U8 else torch.float32
+            for t in [g] + ps:
+                if t.dtype != want or not t.is_contiguous() or t.device != self.device:
+                    raise ValueError("textures must be contiguous device tensors of the block's dtype")
+            d.grid = g.data_ptr()
+            for i in range(3):
+                d.plane[i] = ps[i].data_ptr()
+            sc, of = np.asarray(get("scale"), np.float32), np.asarray(get("offset"), np.float32)
+            for t in range(4):
+                d.scale[t][:] = [float(x) for x in sc[t]]
+                d.offset[t][:] = [float(x) for x in of[t]]
+            keep.append((g, ps))
+            self.blocks.append((d.block_id, d.lod))
+        lb, rb, bb = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        self._check(self.L.cow_query_workspace(self.h, descs, len(blocks), 1, 0, C.byref(lb), C.byref(rb), C.byref(bb)))
+        self.load_ws = torch.empty(max(lb.value, 1), dtype=torch.uint8, device=self.device)
+        self._check(self.L.cow_load_blocks(self.h, descs, len(blocks), self.load_ws.data_ptr(), lb.value, _stream()))
+        self.textures = keep
+        self.descs = descs
+        self.brick_ws = None
+        return self
+
+    def occupancy(self, block_id, lod):
+        k = self.blocks.index((block_id, lod))
+        O = self.descs[k].occ_res
+        out = np.zeros(O ** 3, np.uint8)
+        self._check(self.L.cow_get_occupancy(self.h, block_id, lod, out.ctypes.data, out.size))
+        return out.reshape(O, O, O)
+
+    def pack_bricks(self):
+        n = C.c_size_t()
+        self._check(self.L.cow_query_bricks(self.h, C.byref(n)))
+        self.brick_ws = self.torch.empty(max(n.value, 1), dtype=self.torch.uint8, device=self.device)
+        self._check(self.L.cow_pack_bricks(self.h, self.brick_ws.data_ptr(), n.value, _stream()))
+        return n.value
+
+    def select(self, view, thresholds=(2.0, 4.0, 8.0), cull=True, cap=4096):
+        pol = LodPolicy()
+        for i, t in enumerate(thresholds):
+            pol.thresholds[i] = float(t)
+        pol.n_thresholds = len(thresholds)
+        pol.cull = int(bool(cull))
+        out = (BlockRef * cap)()
+        n = C.c_int()
+        v = make_view(view)
+        self._check(self.L.cow_select_blocks(self.h, C.byref(v), C.byref(pol), out, cap, C.byref(n)))
+        return [(out[i].block_id, out[i].lod) for i in range(n.value)]
+
+    # -- rendering --------------------------------------------------------------
+    def _sets(self, sets):
+        arrs = []
+        cs = (BlockSet * len(sets))()
+        for i, s in enumerate(sets):
+            a = (BlockRef * max(len(s), 1))()
+            for k, (bid, lod) in enumerate(s):
+                a[k].block_id, a[k].lod = int(bid), int(lod)
+            cs[i].refs = C.cast(a, C.POINTER(BlockRef))
+            cs[i].n = len(s)
+            arrs.append(a)
+        return cs, arrs
+
+    def _ws(self, attr, n_views, n_pix, backward=False):
+        lb, rb, bb = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        self._check(self.L.cow_query_workspace(self.h, self.descs, len(self.descs), n_views, n_pix,
+                                               C.byref(lb), C.byref(rb), C.byref(bb)))
+        need = bb.value if backward else rb.value
+        cur = getattr(self, attr)
+        if cur is None or cur.numel() < need:
+            cur = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+            setattr(self, attr, cur)
+        return cur
+
+    def render(self, views, sets, params, mlp, want_aux=True, counts=False, flags=0, out=None):
+        torch = self.torch
+        vs = (View * len(views))(*[make_view(v) for v in views])
+        cs, keep = self._sets(sets)
+        n_pix = sum(int(v.crop[2]) * int(v.crop[3]) for v in views)
+        if out is None:
+            out = dict(rgb=torch.empty((n_pix, 3), dtype=torch.float32, device=self.device),
+                       trans=torch.empty(n_pix, dtype=torch.float32, device=self.device),
+                       aux=torch.empty((n_pix, 8), dtype=torch.float32, device=self.device) if want_aux else None,
+                       counts=torch.zeros((n_pix, 2), dtype=torch.int64, device=self.device) if counts else None)
+        ws = self._ws("render_ws", len(views), n_pix)
+        p = make_params(params, flags, out.get("counts"))
+        if mlp.dtype != torch.float32 or mlp.device != self.device or mlp.numel() != 499:
+            raise ValueError("mlp must be 499 float32 values on the device")
+        aux = out.get("aux")
+        self._check(self.L.cow_render(self.h, vs, len(views), cs, C.byref(p), mlp.data_ptr(),
+                                      out["rgb"].data_ptr(), out["trans"].data_ptr(),
+                                      None if aux is None else aux.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+        return out
+
+    def render_backward(self, views, sets, params, mlp, aux, grad_rgb, grad_trans=None, grad_grid=None,
+                        grad_plane=None, grad_mlp=None):
+        """grad_grid[e] / grad_plane[e][k]: torch fp32 tensors (or None) per
+        loaded entry e, accumulated in place; grad_mlp likewise."""
+        torch = self.torch
+        vs = (View * len(views))(*[make_view(v) for v in views])
+        cs, keep = self._sets(sets)
+        n_pix = sum(int(v.crop[2]) * int(v.crop[3]) for v in views)
+        ws = self._ws("bwd_ws", len(views), n_pix, backward=True)
+        ne = len(self.blocks)
+        gg = (C.c_void_p * ne)()
+        gp = (C.c_void_p * (3 * ne))()
+        for e in range(ne):
+            if grad_grid is not None and grad_grid[e] is not None:
+                gg[e] = grad_grid[e].data_ptr()
+            if grad_plane is not None and grad_plane[e] is not None:
+                for k in range(3):
+                    if grad_plane[e][k] is not None:
+                        gp[3 * e + k] = grad_plane[e][k].data_ptr()
+        p = make_params(params)
+        self._check(self.L.cow_render_backward(
+            self.h, vs, len(views), cs, C.byref(p), mlp.data_ptr(), aux.data_ptr(), grad_rgb.contiguous().data_ptr(),
+            None if grad_trans is None else grad_trans.contiguous().data_ptr(), gg, gp,
+            None if grad_mlp is None else grad_mlp.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+
+    def autotune(self, views, sets, params, mlp, cache_path=None):
+        vs = (View * len(views))(*[make_view(v) for v in views])
+        cs, keep = self._sets(sets)
+        n_pix = sum(int(v.crop[2]) * int(v.crop[3]) for v in views)
+        need = self._ws("render_ws", len(views), n_pix).numel() + 16 * n_pix + 512
+        ws = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+        p = make_params(params)
+        self._check(self.L.cow_autotune(self.h, vs, len(views), cs, C.byref(p), mlp.data_ptr(), ws.data_ptr(),
+                                        ws.numel(), None if cache_path is None else cache_path.encode(), _stream()))
+        return self.get_config()
+
+    def get_config(self):
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        self._check(self.L.cow_get_config(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def set_config(self, tile_w, waves, persistent):
+        self._check(self.L.cow_set_config(self.h, int(tile_w), int(waves), int(persistent)))
+
+    def set_timing(self, on=True):
+        self._check(self.L.cow_set_timing(self.h, int(on)))
+
+    def last_timing(self):
+        f, b = C.c_float(), C.c_float()
+        self._check(self.L.cow_last_timing(self.h, C.byref(f), C.byref(b)))
+        return f.value, b.value
+
+
+def make_render_fn():
+    """torch.autograd.Function over cow_render / cow_render_backward.
+    Differentiable inputs: the MLP weights and every fp32 texture of the
+    loaded blocks (grid, xy, xz, yz per entry, in load order)."""
+    import torch
+
+    class RenderFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, renderer, views, sets, params, mlp, *textures):
+            out = renderer.render(views, sets, params, mlp, want_aux=True)
+            ctx.renderer, ctx.views, ctx.sets, ctx.params = renderer, views, sets, params
+            ctx.save_for_backward(mlp, out["aux"])
+            ctx.n_tex = len(textures)
+            return out["rgb"], out["trans"]
+
+        @staticmethod
+        def backward(ctx, g_rgb, g_trans):
+            mlp, aux = ctx.saved_tensors
+            r = ctx.renderer
+            ne = len(r.blocks)
+            gg, gp = [], []
+            for e in range(ne):
+                g, ps = r.textures[e]
+                gg.append(torch.zeros_like(g))
+                gp.append([torch.zeros_like(p) for p in ps])
+            gm = torch.zeros_like(mlp)
+            r.render_backward(ctx.views, ctx.sets, ctx.params, mlp, aux,
+                              g_rgb if g_rgb is not None else torch.zeros((aux.shape[0], 3), device=aux.device),
+                              g_trans, gg, gp, gm)
+            tex_grads = []
+            for e in range(ne):
+                tex_grads += [gg[e]] + gp[e]
+            return (None, None, None, None, gm) + tuple(tex_grads[:ctx.n_tex])
+
+    return RenderFn

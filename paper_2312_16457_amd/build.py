@@ -1,0 +1,36 @@
+"""Build the HIP library (libcow.so) for gfx950 with hipcc, in-tree."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libcow.so")
+
+HIP_FLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # exact fp32 decision sequences: no contraction, IEEE divide/sqrt
+    "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt",
+    # hardware fp32 atomics for the backward scatter
+    "-munsafe-fp-atomics",
+    # no packed fp32 instructions
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-fvisibility=hidden",
+]
+
+
+def build_library(verbose=False):
+    srcs = [os.path.join(CSRC, "cow_kernels.hip"), os.path.join(CSRC, "cow_host.cpp")]
+    tmp = LIB + ".tmp"
+    cmd = ["hipcc"] + HIP_FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + srcs
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd, stderr=None if verbose else subprocess.DEVNULL)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build_library(verbose=True))

@@ -1,0 +1,1030 @@
+// Host side of the C ABI (include/cow.h): validation, block registry,
+// per-view selection and ordering, workspace layout, launch sequencing,
+// hipGraph replay, autotuning and timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cow.h"
+#include "cow_internal.h"
+
+using cow::DevBlock;
+using cow::DevView;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxViews = 1 << 16;
+constexpr int kMaxBlocks = 1 << 16;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Entry {
+    cow_block_desc desc;
+    size_t occ_off = 0, slot_off = 0;
+    int n_bricks = 0;
+    double ztop = 0.0;
+};
+
+struct GraphEntry {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+struct TuneCfg {
+    int tile_w = 8, waves = 4, persistent = 0;
+};
+
+}  // namespace
+
+struct cow_ctx {
+    int device = 0;
+    int n_cus = 256;
+    std::string arch;
+    std::vector<Entry> entries;
+    unsigned char* load_ws = nullptr;
+    size_t load_bytes = 0;
+    DevBlock* d_blocks = nullptr;
+    std::vector<DevBlock> h_blocks;
+    float scene_lo[3] = {0, 0, 0}, scene_hi[3] = {0, 0, 0};
+    bool loaded = false;
+    int dtype = COW_U8;
+    bool mixed_dtype = false;
+    // sparse bricks
+    bool bricks_packed = false;
+    size_t brick_bytes = 0;
+    // pinned staging for table uploads
+    unsigned char* pinned = nullptr;
+    size_t pinned_bytes = 0;
+    hipEvent_t staging_done = nullptr;
+    bool staging_pending = false;
+    // graphs are captured on this stream (the caller's may be the null
+    // stream, which cannot capture) and launched on the caller's
+    hipStream_t capture_stream = nullptr;
+    // launch configuration
+    TuneCfg cfg;
+    // instrumentation
+    bool timing = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool have_fwd = false, have_bwd = false;
+    std::vector<GraphEntry> graphs;
+    std::string err;
+};
+
+namespace {
+
+cow_status fail(cow_ctx* c, cow_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ctx, COW_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+bool finite_view(const cow_view& v) {
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(v.eye[i])) return false;
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(v.R[i])) return false;
+    return std::isfinite(v.fx) && std::isfinite(v.fy) && std::isfinite(v.cx) && std::isfinite(v.cy) &&
+           v.fx != 0.0f && v.fy != 0.0f;
+}
+
+size_t occ_cells(const cow_block_desc& d) { return (size_t)d.occ_res * d.occ_res * d.occ_res; }
+
+cow_status validate_desc(cow_ctx* c, const cow_block_desc& d) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "block %d lod %d: ", d.block_id, d.lod);
+    std::string who(buf);
+    if (d.lod < 0) return fail(c, COW_E_INVALID, who + "negative LOD");
+    if (d.dtype != COW_U8 && d.dtype != COW_F32) return fail(c, COW_E_INVALID, who + "unknown dtype");
+    if (!is_pow2(d.grid_res) || !is_pow2(d.plane_res) || !is_pow2(d.occ_res))
+        return fail(c, COW_E_INVALID, who + "resolutions must be powers of two");
+    if (d.grid_res % d.occ_res || d.plane_res % d.occ_res || d.occ_res > d.grid_res)
+        return fail(c, COW_E_INVALID, who + "occupancy resolution must divide grid and plane resolution");
+    if (d.grid_res > 1024 || d.plane_res > 8192)
+        return fail(c, COW_E_INVALID, who + "resolution too large for 32-bit texel offsets");
+    const size_t tex = d.dtype == COW_U8 ? 8 : 32;
+    if ((size_t)d.grid_res * d.grid_res * d.grid_res * tex >= (1ull << 31) ||
+        (size_t)d.plane_res * d.plane_res * tex >= (1ull << 31))
+        return fail(c, COW_E_INVALID, who + "texture larger than 2 GiB");
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(d.aabb_min[a]) || !std::isfinite(d.aabb_max[a]))
+            return fail(c, COW_E_INVALID, who + "non-finite AABB");
+        if (d.aabb_max[a] - d.aabb_min[a] != 1.0f)
+            return fail(c, COW_E_INVALID, who + "blocks must be unit cubes");
+    }
+    if (!d.grid || !d.plane[0] || !d.plane[1] || !d.plane[2])
+        return fail(c, COW_E_INVALID, who + "null texture pointer");
+    if (d.dtype == COW_U8)
+        for (int t = 0; t < 4; ++t)
+            for (int ch = 0; ch < 8; ++ch)
+                if (!std::isfinite(d.scale[t][ch]) || !std::isfinite(d.offset[t][ch]))
+                    return fail(c, COW_E_INVALID, who + "non-finite scale/offset");
+    return COW_OK;
+}
+
+// load workspace layout: [DevBlock table][occupancy grids][brick slot tables]
+size_t load_layout(const cow_block_desc* b, int n, std::vector<size_t>* occ_off,
+                   std::vector<size_t>* slot_off) {
+    size_t off = align_up(sizeof(DevBlock) * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        if (occ_off) occ_off->push_back(off);
+        off += align_up(occ_cells(b[i]));
+    }
+    for (int i = 0; i < n; ++i) {
+        if (slot_off) slot_off->push_back(off);
+        off += align_up(occ_cells(b[i]) * 4);
+    }
+    return off;
+}
+
+cow_status ensure_pinned(cow_ctx* c, size_t bytes) {
+    if (c->staging_pending) {
+        HIP_TRY(c, hipEventSynchronize(c->staging_done));
+        c->staging_pending = false;
+    }
+    if (bytes <= c->pinned_bytes) return COW_OK;
+    if (c->pinned) HIP_TRY(c, hipHostFree(c->pinned));
+    c->pinned = nullptr;
+    c->pinned_bytes = 0;
+    size_t want = std::max<size_t>(bytes, 1 << 16);
+    HIP_TRY(c, hipHostMalloc((void**)&c->pinned, want, hipHostMallocDefault));
+    c->pinned_bytes = want;
+    return COW_OK;
+}
+
+int find_entry(const cow_ctx* c, int block_id, int lod) {
+    for (size_t i = 0; i < c->entries.size(); ++i)
+        if (c->entries[i].desc.block_id == block_id && c->entries[i].desc.lod == lod) return (int)i;
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// per-call tables
+// ---------------------------------------------------------------------------
+
+struct CallTables {
+    std::vector<DevView> views;
+    std::vector<int32_t> refs;
+    int64_t n_pix = 0;
+    int32_t total_tiles = 0;
+};
+
+// xy distance from the eye to the block's footprint centre (Appendix D,
+// "Depth sorting"), fp64
+double xy_dist(const cow_view& v, const cow_block_desc& d) {
+    const double cx = 0.5 * ((double)d.aabb_min[0] + (double)d.aabb_max[0]);
+    const double cy = 0.5 * ((double)d.aabb_min[1] + (double)d.aabb_max[1]);
+    const double dx = (double)v.eye[0] - cx, dy = (double)v.eye[1] - cy;
+    return std::sqrt(dx * dx + dy * dy);
+}
+
+cow_status build_tables(cow_ctx* c, const cow_view* views, int n_views, const cow_block_set* sets,
+                        int tile_w, CallTables* T) {
+    const int tile_h = 64 / tile_w;
+    T->views.resize(n_views);
+    T->refs.clear();
+    T->n_pix = 0;
+    T->total_tiles = 0;
+    std::vector<int> seen(c->entries.size(), -1);
+    for (int vi = 0; vi < n_views; ++vi) {
+        const cow_view& v = views[vi];
+        char who[64];
+        snprintf(who, sizeof who, "view %d: ", vi);
+        if (v.W <= 0 || v.H <= 0 || v.W > 65536 || v.H > 65536)
+            return fail(c, COW_E_INVALID, std::string(who) + "image size out of range");
+        if (v.crop_x0 < 0 || v.crop_y0 < 0 || v.crop_w < 0 || v.crop_h < 0 ||
+            (int64_t)v.crop_x0 + v.crop_w > v.W || (int64_t)v.crop_y0 + v.crop_h > v.H)
+            return fail(c, COW_E_INVALID, std::string(who) + "crop outside the image");
+        if (!finite_view(v)) return fail(c, COW_E_INVALID, std::string(who) + "non-finite or singular camera");
+        const cow_block_set& s = sets[vi];
+        if (s.n < 0 || (s.n > 0 && !s.refs)) return fail(c, COW_E_INVALID, std::string(who) + "bad block set");
+        std::vector<std::pair<double, int>> order;
+        std::vector<int> ids;
+        for (int r = 0; r < s.n; ++r) {
+            const int e = find_entry(c, s.refs[r].block_id, s.refs[r].lod);
+            if (e < 0) {
+                char b[128];
+                snprintf(b, sizeof b, "%s(block %d, lod %d) is not loaded", who, s.refs[r].block_id,
+                         s.refs[r].lod);
+                return fail(c, COW_E_NOT_LOADED, b);
+            }
+            for (int id : ids)
+                if (id == s.refs[r].block_id)
+                    return fail(c, COW_E_INVALID, std::string(who) + "a block appears twice in one set");
+            ids.push_back(s.refs[r].block_id);
+            order.push_back({xy_dist(v, c->entries[e].desc), e});
+        }
+        // front to back by xy distance, ties to the lower block id
+        std::stable_sort(order.begin(), order.end(), [&](const auto& a, const auto& b) {
+            if (a.first != b.first) return a.first < b.first;
+            return c->entries[a.second].desc.block_id < c->entries[b.second].desc.block_id;
+        });
+        DevView& d = T->views[vi];
+        memset(&d, 0, sizeof d);
+        for (int i = 0; i < 3; ++i) d.eye[i] = v.eye[i];
+        for (int i = 0; i < 9; ++i) d.R[i] = v.R[i];
+        d.fx = v.fx, d.fy = v.fy, d.cx = v.cx, d.cy = v.cy;
+        d.x0 = v.crop_x0, d.y0 = v.crop_y0, d.w = v.crop_w, d.h = v.crop_h;
+        d.tiles_x = (v.crop_w + tile_w - 1) / tile_w;
+        const int tiles_y = (v.crop_h + tile_h - 1) / tile_h;
+        d.n_tiles = d.tiles_x * tiles_y;
+        d.tile_begin = T->total_tiles;
+        d.pix_begin = T->n_pix;
+        d.set_begin = (int32_t)T->refs.size();
+        d.set_n = s.n;
+        for (auto& o : order) T->refs.push_back(o.second);
+        T->n_pix += (int64_t)v.crop_w * v.crop_h;
+        if ((int64_t)T->total_tiles + d.n_tiles > (1ll << 30))
+            return fail(c, COW_E_INVALID, "too many ray packets in one call");
+        T->total_tiles += d.n_tiles;
+    }
+    return COW_OK;
+}
+
+struct RenderWs {
+    DevView* views;
+    int32_t* refs;
+    float* aux;
+    int32_t* counter;
+    float** grad_ptrs;
+    float* u;
+    float* grad_mlp_scratch;
+    size_t bytes;
+};
+
+// render workspace: [views][refs][aux scratch][counter][grad pointers][u][mlp grad scratch]
+size_t render_ws_layout(int64_t n_views, int64_t n_refs, int64_t n_pix, bool need_aux, bool backward,
+                        int64_t n_entries, unsigned char* base, RenderWs* w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return base ? (void*)(base + o) : nullptr;
+    };
+    RenderWs r{};
+    r.views = (DevView*)take(sizeof(DevView) * (size_t)std::max<int64_t>(n_views, 1));
+    r.refs = (int32_t*)take(4 * (size_t)std::max<int64_t>(n_refs, 1));
+    r.aux = need_aux ? (float*)take(32 * (size_t)n_pix) : nullptr;
+    r.counter = (int32_t*)take(64);
+    if (backward) {
+        r.grad_ptrs = (float**)take(sizeof(float*) * 4 * (size_t)std::max<int64_t>(n_entries, 1));
+        r.u = (float*)take(32 * (size_t)n_pix);
+        r.grad_mlp_scratch = (float*)take(4 * cow::kMlpParams);
+    }
+    r.bytes = off;
+    if (w) *w = r;
+    return off;
+}
+
+cow_status validate_params(cow_ctx* c, const cow_render_params* p) {
+    if (!p) return fail(c, COW_E_INVALID, "null params");
+    if (p->mode == COW_MODE_CHORD) {
+        if (p->n_steps < 1 || p->n_steps > (1 << 16)) return fail(c, COW_E_INVALID, "n_steps out of range");
+    } else if (p->mode == COW_MODE_GRID) {
+        if (!(p->delta > 0.0f) || !std::isfinite(p->delta) || p->delta < 1e-6f)
+            return fail(c, COW_E_INVALID, "delta must be a positive finite step");
+        if (p->max_steps < 1 || p->max_steps > (1 << 22)) return fail(c, COW_E_INVALID, "max_steps out of range");
+    } else {
+        return fail(c, COW_E_INVALID, "unknown mode");
+    }
+    return COW_OK;
+}
+
+cow_status check_dtypes(cow_ctx* c, const CallTables& T, int* dtype) {
+    int dt = -1;
+    for (int32_t e : T.refs) {
+        const int d = c->entries[e].desc.dtype;
+        if (dt < 0) dt = d;
+        if (d != dt) return fail(c, COW_E_UNSUPPORTED, "one render call must use blocks of a single dtype");
+    }
+    *dtype = dt < 0 ? c->dtype : dt;
+    return COW_OK;
+}
+
+cow_status upload_tables(cow_ctx* c, const CallTables& T, const RenderWs& w, hipStream_t s) {
+    const size_t vb = sizeof(DevView) * T.views.size(), rb = 4 * T.refs.size();
+    cow_status st = ensure_pinned(c, vb + rb + 64);
+    if (st != COW_OK) return st;
+    memcpy(c->pinned, T.views.data(), vb);
+    memcpy(c->pinned + align_up(vb), T.refs.data(), rb);
+    if (vb) HIP_TRY(c, hipMemcpyAsync(w.views, c->pinned, vb, hipMemcpyHostToDevice, s));
+    if (rb) HIP_TRY(c, hipMemcpyAsync(w.refs, c->pinned + align_up(vb), rb, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipEventRecord(c->staging_done, s));
+    c->staging_pending = true;
+    return COW_OK;
+}
+
+cow::MarchArgs march_args(cow_ctx* c, const CallTables& T, const RenderWs& w,
+                          const cow_render_params* p, int dtype, float* aux, float* trans) {
+    cow::MarchArgs a{};
+    a.blocks = c->d_blocks;
+    a.views = w.views;
+    a.n_views = (int32_t)T.views.size();
+    a.refs = w.refs;
+    a.total_tiles = T.total_tiles;
+    a.tile_w = c->cfg.tile_w;
+    a.tile_h = 64 / c->cfg.tile_w;
+    a.mode = p->mode;
+    a.n_steps = p->n_steps;
+    a.max_steps = p->max_steps;
+    a.delta = p->delta;
+    for (int i = 0; i < 3; ++i) a.scene_lo[i] = c->scene_lo[i], a.scene_hi[i] = c->scene_hi[i];
+    a.use_sparse = (p->flags & COW_F_SPARSE) ? 1 : 0;
+    a.blocks_dtype = dtype;
+    a.aux = aux;
+    a.trans = trans;
+    a.counts = p->counts;
+    a.work_counter = w.counter;
+    a.persistent = c->cfg.persistent;
+    a.only_view = -1;
+    a.only_set_pos = -1;
+    return a;
+}
+
+// the launch sequence of one forward render (what a graph captures)
+cow_status enqueue_forward(cow_ctx* c, const CallTables& T, const cow::MarchArgs& a0,
+                           const cow::MlpArgs& m, bool per_block, hipStream_t s) {
+    if (per_block) {
+        // baseline: one launch per view per block, each blending its block
+        // into the view's running (A, T) in depth order (the paper's
+        // one-shader-per-block viewer, Sec. 4.2)
+        for (size_t v = 0; v < T.views.size(); ++v) {
+            const DevView& dv = T.views[v];
+            if (dv.n_tiles == 0) continue;
+            cow::MarchArgs a = a0;
+            a.persistent = 0;
+            a.only_view = (int32_t)v;
+            a.total_tiles = dv.n_tiles;
+            const int nb = dv.set_n;
+            for (int r = 0; r < std::max(nb, 1); ++r) {
+                a.only_set_pos = nb == 0 ? -1 : r;
+                HIP_TRY(c, cow::launch_march(a, c->cfg.waves, s));
+            }
+        }
+    } else {
+        if (a0.persistent) HIP_TRY(c, cow::launch_reset_counter(a0.work_counter, s));
+        if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[0], s));
+        HIP_TRY(c, cow::launch_march(a0, c->cfg.waves, s));
+        if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[1], s));
+    }
+    HIP_TRY(c, cow::launch_mlp(m, s));
+    return COW_OK;
+}
+
+cow_status run_graph(cow_ctx* c, const CallTables& T, const cow::MarchArgs& a, const cow::MlpArgs& m,
+                     bool per_block, hipStream_t s) {
+    std::vector<unsigned char> key(sizeof a + sizeof m + 8);
+    memcpy(key.data(), &a, sizeof a);
+    memcpy(key.data() + sizeof a, &m, sizeof m);
+    const int64_t extra = (per_block ? 1 : 0) | ((int64_t)c->cfg.waves << 8);
+    memcpy(key.data() + sizeof a + sizeof m, &extra, 8);
+    for (auto& g : c->graphs)
+        if (g.key == key) {
+            HIP_TRY(c, hipGraphLaunch(g.exec, s));
+            return COW_OK;
+        }
+    const bool timing = c->timing;
+    c->timing = false;  // events are not recorded inside a captured graph
+    if (!c->capture_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = c->capture_stream;
+    HIP_TRY(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    cow_status st = enqueue_forward(c, T, a, m, per_block, cs);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    c->timing = timing;
+    if (st != COW_OK) return st;
+    if (e != hipSuccess) return fail(c, COW_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    GraphEntry g;
+    g.key = key;
+    g.graph = graph;
+    HIP_TRY(c, hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0));
+    if (c->graphs.size() >= 16) {
+        (void)hipGraphExecDestroy(c->graphs.front().exec);
+        (void)hipGraphDestroy(c->graphs.front().graph);
+        c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.push_back(g);
+    HIP_TRY(c, hipGraphLaunch(g.exec, s));
+    return COW_OK;
+}
+
+void drop_graphs(cow_ctx* c) {
+    for (auto& g : c->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    c->graphs.clear();
+}
+
+// ---------------------------------------------------------------------------
+// selection (fp64)
+// ---------------------------------------------------------------------------
+
+// A box is culled when all eight corners lie strictly outside one of the
+// frustum side planes or behind the camera plane, with a relative margin of
+// 1e-5 that absorbs the fp32 rounding of the rays.
+bool box_outside_frustum(const cow_view& v, const double lo[3], const double hi[3]) {
+    double Rm[9], e[3];
+    for (int k = 0; k < 9; ++k) Rm[k] = v.R[k];
+    for (int k = 0; k < 3; ++k) e[k] = v.eye[k];
+    const double x0 = v.crop_x0, x1 = (double)v.crop_x0 + v.crop_w;
+    const double y0 = v.crop_y0, y1 = (double)v.crop_y0 + v.crop_h;
+    const double fx = v.fx, fy = v.fy, cx = v.cx, cy = v.cy;
+    const double n[5][3] = {{fx, 0, cx - x0}, {-fx, 0, x1 - cx}, {0, fy, cy - y0}, {0, -fy, y1 - cy}, {0, 0, 1}};
+    double X[8][3], len[8];
+    for (int k = 0; k < 8; ++k) {
+        const double P[3] = {(k & 1) ? hi[0] : lo[0], (k & 2) ? hi[1] : lo[1], (k & 4) ? hi[2] : lo[2]};
+        const double w[3] = {P[0] - e[0], P[1] - e[1], P[2] - e[2]};
+        for (int a = 0; a < 3; ++a) X[k][a] = Rm[a] * w[0] + Rm[3 + a] * w[1] + Rm[6 + a] * w[2];
+        len[k] = std::sqrt(X[k][0] * X[k][0] + X[k][1] * X[k][1] + X[k][2] * X[k][2]);
+    }
+    for (int p = 0; p < 5; ++p) {
+        const double nn = std::sqrt(n[p][0] * n[p][0] + n[p][1] * n[p][1] + n[p][2] * n[p][2]);
+        bool all_out = true;
+        for (int k = 0; k < 8 && all_out; ++k) {
+            const double sd = (n[p][0] * X[k][0] + n[p][1] * X[k][1] + n[p][2] * X[k][2]) / nn;
+            if (!(sd < -1e-5 * len[k])) all_out = false;
+        }
+        if (all_out) return true;
+    }
+    return false;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+cow_status cow_create(cow_ctx** out, int device) {
+    if (!out) return COW_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return COW_E_HIP;
+    if (device < 0 || device >= n) return COW_E_INVALID;
+    cow_ctx* c = new (std::nothrow) cow_ctx();
+    if (!c) return COW_E_INTERNAL;
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipSetDevice(device) != hipSuccess || hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return COW_E_HIP;
+    }
+    c->n_cus = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+    if (hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        return COW_E_HIP;
+    }
+    *out = c;
+    return COW_OK;
+}
+
+cow_status cow_destroy(cow_ctx* c) {
+    if (!c) return COW_E_INVALID;
+    (void)hipSetDevice(c->device);
+    if (c->staging_pending) (void)hipEventSynchronize(c->staging_done);
+    drop_graphs(c);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+    return COW_OK;
+}
+
+const char* cow_last_error(const cow_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+cow_status cow_query_workspace(cow_ctx* c, const cow_block_desc* blocks, int n_blocks, int max_views,
+                               int64_t max_pixels, size_t* load_bytes, size_t* render_bytes,
+                               size_t* backward_bytes) {
+    if (!c) return COW_E_INVALID;
+    if (n_blocks < 0 || n_blocks > kMaxBlocks || (n_blocks > 0 && !blocks))
+        return fail(c, COW_E_INVALID, "bad block list");
+    if (max_views < 0 || max_views > kMaxViews || max_pixels < 0)
+        return fail(c, COW_E_INVALID, "bad view/pixel limits");
+    for (int i = 0; i < n_blocks; ++i) {
+        cow_status s = validate_desc(c, blocks[i]);
+        if (s != COW_OK) return s;
+    }
+    if (load_bytes) *load_bytes = load_layout(blocks, n_blocks, nullptr, nullptr);
+    const int64_t refs = (int64_t)max_views * std::max(n_blocks, 1);
+    if (render_bytes) *render_bytes = render_ws_layout(max_views, refs, max_pixels, true, false, n_blocks, nullptr, nullptr);
+    if (backward_bytes) *backward_bytes = render_ws_layout(max_views, refs, max_pixels, true, true, n_blocks, nullptr, nullptr);
+    return COW_OK;
+}
+
+cow_status cow_load_blocks(cow_ctx* c, const cow_block_desc* blocks, int n, void* load_ws,
+                           size_t load_bytes, hipStream_t stream) {
+    if (!c) return COW_E_INVALID;
+    if (n <= 0 || n > kMaxBlocks || !blocks) return fail(c, COW_E_INVALID, "need at least one block");
+    for (int i = 0; i < n; ++i) {
+        cow_status s = validate_desc(c, blocks[i]);
+        if (s != COW_OK) return s;
+    }
+    // unique (block, LOD); all LODs of a block share its AABB; distinct
+    // blocks have disjoint footprints (a ground partition, Sec. 4.1)
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const auto &a = blocks[i], &b = blocks[j];
+            if (a.block_id == b.block_id) {
+                if (a.lod == b.lod) return fail(c, COW_E_INVALID, "duplicate (block, LOD)");
+                for (int k = 0; k < 3; ++k)
+                    if (a.aabb_min[k] != b.aabb_min[k])
+                        return fail(c, COW_E_INVALID, "LODs of one block must share its AABB");
+            } else {
+                bool overlap = true;
+                for (int k = 0; k < 3; ++k)
+                    overlap = overlap && a.aabb_min[k] < b.aabb_max[k] && b.aabb_min[k] < a.aabb_max[k];
+                if (overlap) return fail(c, COW_E_INVALID, "blocks overlap");
+            }
+        }
+    std::vector<size_t> occ_off, slot_off;
+    const size_t need = load_layout(blocks, n, &occ_off, &slot_off);
+    if (!load_ws || load_bytes < need) return fail(c, COW_E_WORKSPACE, "load workspace too small");
+    HIP_TRY(c, hipSetDevice(c->device));
+    drop_graphs(c);
+    c->entries.clear();
+    c->loaded = false;
+    c->bricks_packed = false;
+    c->load_ws = (unsigned char*)load_ws;
+    c->load_bytes = load_bytes;
+    c->d_blocks = (DevBlock*)load_ws;
+    c->h_blocks.assign(n, DevBlock{});
+    c->mixed_dtype = false;
+    c->dtype = blocks[0].dtype;
+    for (int k = 0; k < 3; ++k) c->scene_lo[k] = INFINITY, c->scene_hi[k] = -INFINITY;
+    for (int i = 0; i < n; ++i) {
+        Entry e;
+        e.desc = blocks[i];
+        e.occ_off = occ_off[i];
+        e.slot_off = slot_off[i];
+        c->entries.push_back(e);
+        DevBlock& d = c->h_blocks[i];
+        for (int k = 0; k < 3; ++k) {
+            d.lo[k] = blocks[i].aabb_min[k];
+            d.hi[k] = blocks[i].aabb_max[k];
+            c->scene_lo[k] = std::min(c->scene_lo[k], d.lo[k]);
+            c->scene_hi[k] = std::max(c->scene_hi[k], d.hi[k]);
+        }
+        d.R = blocks[i].grid_res;
+        d.Rp = blocks[i].plane_res;
+        d.O = blocks[i].occ_res;
+        d.dtype = blocks[i].dtype;
+        if (d.dtype != c->dtype) c->mixed_dtype = true;
+        d.grid = blocks[i].grid;
+        for (int k = 0; k < 3; ++k) d.plane[k] = blocks[i].plane[k];
+        d.occ = c->load_ws + occ_off[i];
+        d.brick_slot = nullptr;
+        d.bricks = nullptr;
+        for (int t = 0; t < 4; ++t)
+            for (int ch = 0; ch < 8; ++ch) {
+                d.scale[t][ch] = d.dtype == COW_U8 ? blocks[i].scale[t][ch] : 1.0f;
+                d.offset[t][ch] = d.dtype == COW_U8 ? blocks[i].offset[t][ch] : 0.0f;
+            }
+    }
+    const size_t tb = sizeof(DevBlock) * (size_t)n;
+    cow_status st = ensure_pinned(c, tb);
+    if (st != COW_OK) return st;
+    memcpy(c->pinned, c->h_blocks.data(), tb);
+    HIP_TRY(c, hipMemcpyAsync(c->d_blocks, c->pinned, tb, hipMemcpyHostToDevice, stream));
+    for (int i = 0; i < n; ++i) HIP_TRY(c, cow::launch_occupancy(c->d_blocks, i, blocks[i].occ_res, stream));
+    // z_top of each entry from its occupancy (top of the highest occupied cell)
+    size_t tot = 0;
+    for (int i = 0; i < n; ++i) tot += occ_cells(blocks[i]);
+    std::vector<unsigned char> occ(tot);
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        HIP_TRY(c, hipMemcpyAsync(occ.data() + off, c->load_ws + occ_off[i], occ_cells(blocks[i]),
+                                  hipMemcpyDeviceToHost, stream));
+        off += occ_cells(blocks[i]);
+    }
+    HIP_TRY(c, hipStreamSynchronize(stream));
+    off = 0;
+    for (int i = 0; i < n; ++i) {
+        const int O = blocks[i].occ_res;
+        int top = -1;
+        for (int z = 0; z < O; ++z)
+            for (int k = 0; k < O * O; ++k)
+                if (occ[off + (size_t)z * O * O + k]) top = z;
+        const double ext = (double)blocks[i].aabb_max[2] - (double)blocks[i].aabb_min[2];
+        c->entries[i].ztop = (double)blocks[i].aabb_min[2] + (double)(top + 1) / O * ext;
+        off += occ_cells(blocks[i]);
+    }
+    c->loaded = true;
+    return COW_OK;
+}
+
+cow_status cow_get_occupancy(cow_ctx* c, int block_id, int lod, uint8_t* host_out, size_t n) {
+    if (!c) return COW_E_INVALID;
+    if (!host_out) return fail(c, COW_E_INVALID, "null output");
+    const int e = find_entry(c, block_id, lod);
+    if (e < 0) return fail(c, COW_E_NOT_LOADED, "block not loaded");
+    const size_t cells = occ_cells(c->entries[e].desc);
+    if (n < cells) return fail(c, COW_E_INVALID, "output too small");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());
+    HIP_TRY(c, hipMemcpy(host_out, c->load_ws + c->entries[e].occ_off, cells, hipMemcpyDeviceToHost));
+    return COW_OK;
+}
+
+cow_status cow_select_blocks(cow_ctx* c, const cow_view* v, const cow_lod_policy* pol, cow_block_ref* out,
+                             int cap, int* n_out) {
+    if (!c) return COW_E_INVALID;
+    if (!v || !pol || !n_out || (cap > 0 && !out)) return fail(c, COW_E_INVALID, "null argument");
+    if (!c->loaded) return fail(c, COW_E_NOT_LOADED, "no blocks loaded");
+    if (!finite_view(*v)) return fail(c, COW_E_INVALID, "non-finite or singular camera");
+    if (pol->n_thresholds < 1 || pol->n_thresholds > 3) return fail(c, COW_E_INVALID, "1 to 3 thresholds");
+    struct Pick {
+        double key;
+        int id, entry;
+    };
+    std::vector<Pick> picks;
+    for (size_t e = 0; e < c->entries.size(); ++e) {
+        const cow_block_desc& d = c->entries[e].desc;
+        if (d.lod != 0) continue;  // decide once per block, from its finest level
+        const double cx = 0.5 * ((double)d.aabb_min[0] + (double)d.aabb_max[0]);
+        const double cy = 0.5 * ((double)d.aabb_min[1] + (double)d.aabb_max[1]);
+        const double dx = (double)v->eye[0] - cx, dy = (double)v->eye[1] - cy;
+        const double dz = (double)v->eye[2] - c->entries[e].ztop;
+        const double dist = std::sqrt(dx * dx + dy * dy + dz * dz);
+        int lod = -1;
+        for (int l = 0; l < pol->n_thresholds; ++l)
+            if (dist < pol->thresholds[l]) {
+                lod = l;
+                break;
+            }
+        if (lod < 0) continue;  // beyond the far cut
+        const int chosen = find_entry(c, d.block_id, lod);
+        if (chosen < 0) return fail(c, COW_E_NOT_LOADED, "selected LOD is not loaded");
+        if (pol->cull) {
+            const cow_block_desc& cd = c->entries[chosen].desc;
+            const double lo[3] = {cd.aabb_min[0], cd.aabb_min[1], cd.aabb_min[2]};
+            const double hi[3] = {cd.aabb_max[0], cd.aabb_max[1], c->entries[chosen].ztop};
+            if (box_outside_frustum(*v, lo, hi)) continue;
+        }
+        picks.push_back({std::sqrt(dx * dx + dy * dy), d.block_id, chosen});
+    }
+    std::stable_sort(picks.begin(), picks.end(), [](const Pick& a, const Pick& b) {
+        if (a.key != b.key) return a.key < b.key;
+        return a.id < b.id;
+    });
+    const int n = (int)picks.size();
+    for (int i = 0; i < n && i < cap; ++i) {
+        out[i].block_id = c->entries[picks[i].entry].desc.block_id;
+        out[i].lod = c->entries[picks[i].entry].desc.lod;
+    }
+    *n_out = std::min(n, cap);
+    if (n > cap) return fail(c, COW_E_INVALID, "output capacity too small");
+    return COW_OK;
+}
+
+cow_status cow_query_bricks(cow_ctx* c, size_t* brick_bytes) {
+    if (!c || !brick_bytes) return COW_E_INVALID;
+    if (!c->loaded) return fail(c, COW_E_NOT_LOADED, "no blocks loaded");
+    size_t total = 0;
+    std::vector<unsigned char> occ;
+    for (auto& e : c->entries) {
+        if (e.desc.dtype != COW_U8) continue;
+        const size_t cells = occ_cells(e.desc);
+        occ.resize(cells);
+        HIP_TRY(c, hipDeviceSynchronize());
+        HIP_TRY(c, hipMemcpy(occ.data(), c->load_ws + e.occ_off, cells, hipMemcpyDeviceToHost));
+        size_t nb = 0;
+        for (unsigned char o : occ) nb += o != 0;
+        const size_t s2 = (size_t)(e.desc.grid_res / e.desc.occ_res) + 2;
+        total += align_up(nb * s2 * s2 * s2 * 8);
+    }
+    *brick_bytes = total;
+    return COW_OK;
+}
+
+cow_status cow_pack_bricks(cow_ctx* c, void* brick_ws, size_t brick_bytes, hipStream_t stream) {
+    if (!c) return COW_E_INVALID;
+    if (!c->loaded) return fail(c, COW_E_NOT_LOADED, "no blocks loaded");
+    size_t need = 0;
+    cow_status st = cow_query_bricks(c, &need);
+    if (st != COW_OK) return st;
+    if (need > 0 && (!brick_ws || brick_bytes < need)) return fail(c, COW_E_WORKSPACE, "brick workspace too small");
+    HIP_TRY(c, hipSetDevice(c->device));
+    drop_graphs(c);
+    size_t off = 0;
+    std::vector<unsigned char> occ;
+    std::vector<int32_t> slots;
+    for (size_t i = 0; i < c->entries.size(); ++i) {
+        Entry& e = c->entries[i];
+        if (e.desc.dtype != COW_U8) continue;
+        const size_t cells = occ_cells(e.desc);
+        occ.resize(cells);
+        slots.assign(cells, -1);
+        HIP_TRY(c, hipMemcpy(occ.data(), c->load_ws + e.occ_off, cells, hipMemcpyDeviceToHost));
+        int nb = 0;
+        for (size_t k = 0; k < cells; ++k)
+            if (occ[k]) slots[k] = nb++;
+        e.n_bricks = nb;
+        HIP_TRY(c, hipMemcpy(c->load_ws + e.slot_off, slots.data(), cells * 4, hipMemcpyHostToDevice));
+        DevBlock& d = c->h_blocks[i];
+        d.brick_slot = (const int32_t*)(c->load_ws + e.slot_off);
+        d.bricks = (const uint8_t*)brick_ws + off;
+        const size_t s2 = (size_t)(e.desc.grid_res / e.desc.occ_res) + 2;
+        const size_t bytes = (size_t)nb * s2 * s2 * s2 * 8;
+        if (bytes >= (1ull << 31)) return fail(c, COW_E_INVALID, "brick atlas of one block exceeds 2 GiB");
+        d.brick_bytes = (uint32_t)bytes;
+        off += align_up(bytes);
+    }
+    HIP_TRY(c, hipMemcpy(c->d_blocks, c->h_blocks.data(), sizeof(DevBlock) * c->h_blocks.size(),
+                         hipMemcpyHostToDevice));
+    for (size_t i = 0; i < c->entries.size(); ++i)
+        if (c->entries[i].desc.dtype == COW_U8)
+            HIP_TRY(c, cow::launch_pack_bricks(c->d_blocks, (int)i, c->entries[i].desc.occ_res, 0, nullptr, stream));
+    c->bricks_packed = true;
+    return COW_OK;
+}
+
+static cow_status render_impl(cow_ctx* c, const cow_view* views, int n_views, const cow_block_set* sets,
+                              const cow_render_params* p, const float* mlp, float* rgb, float* trans,
+                              float* aux, void* ws, size_t ws_bytes, hipStream_t s) {
+    if (!c) return COW_E_INVALID;
+    if (!c->loaded) return fail(c, COW_E_NOT_LOADED, "no blocks loaded");
+    if (!views || !sets || n_views < 1 || n_views > kMaxViews) return fail(c, COW_E_INVALID, "bad views");
+    cow_status st = validate_params(c, p);
+    if (st != COW_OK) return st;
+    if (!mlp || !rgb || !trans) return fail(c, COW_E_INVALID, "null mlp or output");
+    if ((p->flags & COW_F_SPARSE) && !c->bricks_packed) return fail(c, COW_E_INVALID, "bricks not packed");
+    CallTables T;
+    st = build_tables(c, views, n_views, sets, c->cfg.tile_w, &T);
+    if (st != COW_OK) return st;
+    int dtype;
+    st = check_dtypes(c, T, &dtype);
+    if (st != COW_OK) return st;
+    if ((p->flags & COW_F_SPARSE) && dtype != COW_U8) return fail(c, COW_E_UNSUPPORTED, "sparse bricks hold uint8 grids only");
+    RenderWs w;
+    const size_t need = render_ws_layout(n_views, (int64_t)T.refs.size(), T.n_pix, aux == nullptr, false,
+                                         (int64_t)c->entries.size(), (unsigned char*)ws, &w);
+    if (!ws || ws_bytes < need) return fail(c, COW_E_WORKSPACE, "render workspace too small");
+    if (T.n_pix == 0) return COW_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    st = upload_tables(c, T, w, s);
+    if (st != COW_OK) return st;
+    float* aux_out = aux ? aux : w.aux;
+    cow::MarchArgs a = march_args(c, T, w, p, dtype, aux_out, trans);
+    cow::MlpArgs m{};
+    m.views = w.views;
+    m.n_views = n_views;
+    m.n_pix = T.n_pix;
+    m.mlp = mlp;
+    m.aux = aux_out;
+    m.rgb = rgb;
+    m.trans = trans;
+    const bool per_block = (p->flags & COW_F_PER_BLOCK) != 0;
+    if (!per_block) a.persistent = c->cfg.persistent || (p->flags & COW_F_PERSISTENT) ? 1 : 0;
+    c->have_fwd = c->timing && !(p->flags & COW_F_GRAPH) && !per_block;
+    if (p->flags & COW_F_GRAPH) return run_graph(c, T, a, m, per_block, s);
+    return enqueue_forward(c, T, a, m, per_block, s);
+}
+
+cow_status cow_render(cow_ctx* c, const cow_view* views, int n_views, const cow_block_set* sets,
+                      const cow_render_params* p, const float* mlp, float* rgb, float* trans, float* aux,
+                      void* ws, size_t ws_bytes, hipStream_t s) {
+    try {
+        return render_impl(c, views, n_views, sets, p, mlp, rgb, trans, aux, ws, ws_bytes, s);
+    } catch (...) {
+        return fail(c, COW_E_INTERNAL, "internal error");
+    }
+}
+
+cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, const cow_block_set* sets,
+                               const cow_render_params* p, const float* mlp, const float* aux,
+                               const float* grad_rgb, const float* grad_trans, float* const* grad_grid,
+                               float* const* grad_plane, float* grad_mlp, void* ws, size_t ws_bytes,
+                               hipStream_t s) try {
+    if (!c) return COW_E_INVALID;
+    if (!c->loaded) return fail(c, COW_E_NOT_LOADED, "no blocks loaded");
+    if (!views || !sets || n_views < 1 || n_views > kMaxViews) return fail(c, COW_E_INVALID, "bad views");
+    cow_status st = validate_params(c, p);
+    if (st != COW_OK) return st;
+    if (!mlp || !aux || !grad_rgb || !grad_grid || !grad_plane)
+        return fail(c, COW_E_INVALID, "null mlp, aux, grad_rgb or gradient table");
+    CallTables T;
+    st = build_tables(c, views, n_views, sets, c->cfg.tile_w, &T);
+    if (st != COW_OK) return st;
+    for (int32_t e : T.refs)
+        if (c->entries[e].desc.dtype != COW_F32)
+            return fail(c, COW_E_UNSUPPORTED, "backward needs float32 textures");
+    RenderWs w;
+    const size_t need = render_ws_layout(n_views, (int64_t)T.refs.size(), T.n_pix, false, true,
+                                         (int64_t)c->entries.size(), (unsigned char*)ws, &w);
+    if (!ws || ws_bytes < need) return fail(c, COW_E_WORKSPACE, "backward workspace too small");
+    if (T.n_pix == 0) return COW_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    // views, refs and the per-entry gradient pointer table in one upload
+    const size_t ne = c->entries.size();
+    std::vector<float*> ptrs(4 * ne, nullptr);
+    for (size_t e = 0; e < ne; ++e) {
+        ptrs[e] = grad_grid[e];
+        for (int k = 0; k < 3; ++k) ptrs[ne + 3 * e + k] = grad_plane[3 * e + k];
+    }
+    const size_t vb = sizeof(DevView) * T.views.size(), rb = 4 * T.refs.size(), pb = sizeof(float*) * ptrs.size();
+    st = ensure_pinned(c, align_up(vb) + align_up(rb) + pb);
+    if (st != COW_OK) return st;
+    memcpy(c->pinned, T.views.data(), vb);
+    memcpy(c->pinned + align_up(vb), T.refs.data(), rb);
+    memcpy(c->pinned + align_up(vb) + align_up(rb), ptrs.data(), pb);
+    HIP_TRY(c, hipMemcpyAsync(w.views, c->pinned, vb, hipMemcpyHostToDevice, s));
+    if (rb) HIP_TRY(c, hipMemcpyAsync(w.refs, c->pinned + align_up(vb), rb, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(w.grad_ptrs, c->pinned + align_up(vb) + align_up(rb), pb, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipEventRecord(c->staging_done, s));
+    c->staging_pending = true;
+    cow::MlpBwdArgs mb{};
+    mb.views = w.views;
+    mb.n_views = n_views;
+    mb.n_pix = T.n_pix;
+    mb.mlp = mlp;
+    mb.aux = aux;
+    mb.grad_rgb = grad_rgb;
+    mb.u = w.u;
+    mb.grad_mlp = grad_mlp ? grad_mlp : w.grad_mlp_scratch;
+    HIP_TRY(c, cow::launch_mlp_bwd(mb, s));
+    cow::BwdArgs ba{};
+    ba.m = march_args(c, T, w, p, COW_F32, const_cast<float*>(aux), nullptr);
+    ba.m.persistent = 0;
+    ba.m.counts = nullptr;
+    ba.u = w.u;
+    ba.grad_trans = grad_trans;
+    ba.grad_grid = w.grad_ptrs;
+    ba.grad_plane = w.grad_ptrs + ne;
+    c->have_bwd = c->timing;
+    if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[2], s));
+    HIP_TRY(c, cow::launch_march_bwd(ba, c->cfg.waves, s));
+    if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[3], s));
+    return COW_OK;
+} catch (...) {
+    return fail(c, COW_E_INTERNAL, "internal error");
+}
+
+cow_status cow_get_config(cow_ctx* c, int* tile_w, int* waves, int* persistent) {
+    if (!c) return COW_E_INVALID;
+    if (tile_w) *tile_w = c->cfg.tile_w;
+    if (waves) *waves = c->cfg.waves;
+    if (persistent) *persistent = c->cfg.persistent;
+    return COW_OK;
+}
+
+cow_status cow_set_config(cow_ctx* c, int tile_w, int waves, int persistent) {
+    if (!c) return COW_E_INVALID;
+    if (!(tile_w == 1 || tile_w == 2 || tile_w == 4 || tile_w == 8 || tile_w == 16 || tile_w == 32 || tile_w == 64))
+        return fail(c, COW_E_INVALID, "tile width must be a power of two dividing 64");
+    if (!(waves == 1 || waves == 2 || waves == 4)) return fail(c, COW_E_INVALID, "waves per workgroup: 1, 2 or 4");
+    c->cfg.tile_w = tile_w;
+    c->cfg.waves = waves;
+    c->cfg.persistent = persistent ? 1 : 0;
+    drop_graphs(c);
+    return COW_OK;
+}
+
+cow_status cow_set_timing(cow_ctx* c, int enable) {
+    if (!c) return COW_E_INVALID;
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (enable)
+        for (auto& e : c->ev)
+            if (!e) HIP_TRY(c, hipEventCreate(&e));
+    c->timing = enable != 0;
+    c->have_fwd = c->have_bwd = false;
+    return COW_OK;
+}
+
+cow_status cow_last_timing(cow_ctx* c, float* fwd_ms, float* bwd_ms) {
+    if (!c) return COW_E_INVALID;
+    if (fwd_ms) {
+        *fwd_ms = -1.0f;
+        if (c->have_fwd) {
+            HIP_TRY(c, hipEventSynchronize(c->ev[1]));
+            HIP_TRY(c, hipEventElapsedTime(fwd_ms, c->ev[0], c->ev[1]));
+        }
+    }
+    if (bwd_ms) {
+        *bwd_ms = -1.0f;
+        if (c->have_bwd) {
+            HIP_TRY(c, hipEventSynchronize(c->ev[3]));
+            HIP_TRY(c, hipEventElapsedTime(bwd_ms, c->ev[2], c->ev[3]));
+        }
+    }
+    return COW_OK;
+}
+
+cow_status cow_autotune(cow_ctx* c, const cow_view* views, int n_views, const cow_block_set* sets,
+                        const cow_render_params* p, const float* mlp, void* ws, size_t ws_bytes,
+                        const char* cache_path, hipStream_t s) try {
+    if (!c) return COW_E_INVALID;
+    if (!c->loaded) return fail(c, COW_E_NOT_LOADED, "no blocks loaded");
+    cow_status st = validate_params(c, p);
+    if (st != COW_OK) return st;
+    if (!views || !sets || n_views < 1) return fail(c, COW_E_INVALID, "bad views");
+    int64_t n_pix = 0, n_refs = 0;
+    for (int v = 0; v < n_views; ++v) {
+        n_pix += (int64_t)views[v].crop_w * views[v].crop_h;
+        n_refs += sets[v].n;
+    }
+    // cache key: device, workload shape, library layout
+    char key[256];
+    snprintf(key, sizeof key, "%s|cu%d|v%d|p%lld|r%lld|m%d|s%d|f%d|dt%d", c->arch.c_str(), c->n_cus, n_views,
+             (long long)n_pix, (long long)n_refs, p->mode, p->max_steps, p->flags & COW_F_SPARSE, c->dtype);
+    // cache: one JSON object per line
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "r");
+        if (f) {
+            char line[512];
+            while (fgets(line, sizeof line, f)) {
+                char k[256];
+                int tw, wv, ps;
+                if (sscanf(line, " {\"key\": \"%255[^\"]\", \"tile_w\": %d, \"waves\": %d, \"persistent\": %d}", k,
+                           &tw, &wv, &ps) == 4 &&
+                    strcmp(k, key) == 0) {
+                    fclose(f);
+                    return cow_set_config(c, tw, wv, ps);
+                }
+            }
+            fclose(f);
+        }
+    }
+    // outputs live in the tail of the workspace beyond what render needs
+    const int64_t need_render = (int64_t)render_ws_layout(n_views, n_refs, n_pix, true, false,
+                                                          (int64_t)c->entries.size(), nullptr, nullptr);
+    const int64_t need = need_render + (int64_t)align_up(16 * n_pix) + 256;
+    if (!ws || (int64_t)ws_bytes < need) return fail(c, COW_E_WORKSPACE, "autotune needs render workspace + 16 B per pixel");
+    float* rgb = (float*)((unsigned char*)ws + need_render);
+    float* trans = rgb + 3 * n_pix;
+    const TuneCfg saved = c->cfg;
+    const bool saved_timing = c->timing;
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    cow_render_params q = *p;
+    q.flags &= COW_F_SPARSE;
+    q.counts = nullptr;
+    float best = INFINITY;
+    TuneCfg best_cfg = saved;
+    const int tws[] = {8, 16, 4, 32};
+    const int wvs[] = {4, 2, 1};
+    for (int persistent = 0; persistent < 2; ++persistent)
+        for (int tw : tws)
+            for (int wv : wvs) {
+                c->cfg = TuneCfg{tw, wv, persistent};
+                c->timing = false;
+                st = render_impl(c, views, n_views, sets, &q, mlp, rgb, trans, nullptr, ws, ws_bytes, s);
+                if (st != COW_OK) break;
+                HIP_TRY(c, hipEventRecord(e0, s));
+                for (int it = 0; it < 3; ++it) {
+                    st = render_impl(c, views, n_views, sets, &q, mlp, rgb, trans, nullptr, ws, ws_bytes, s);
+                    if (st != COW_OK) break;
+                }
+                HIP_TRY(c, hipEventRecord(e1, s));
+                HIP_TRY(c, hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) {
+                    best = ms;
+                    best_cfg = c->cfg;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing = saved_timing;
+    if (st != COW_OK) {
+        c->cfg = saved;
+        return st;
+    }
+    c->cfg = best_cfg;
+    drop_graphs(c);
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "{\"key\": \"%s\", \"tile_w\": %d, \"waves\": %d, \"persistent\": %d}\n", key,
+                    best_cfg.tile_w, best_cfg.waves, best_cfg.persistent);
+            fclose(f);
+        }
+    }
+    return COW_OK;
+} catch (...) {
+    return fail(c, COW_E_INTERNAL, "internal error");
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// Device-side tables shared by the host library (cow_host.cpp) and the
+// kernels (cow_kernels.hip).  Plain structs, copied to device memory once per
+// cow_load_blocks (DevBlock) or per cow_render call (DevView, refs).
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace cow {
+
+constexpr int kNch = 8;
+constexpr int kMlpParams = 499;
+// largest camera-anchored step index; t_k = (k + 1/2) delta is exact in fp32
+// below 2^23
+constexpr int32_t kMaxStep = (1 << 23) - 2;
+
+struct DevBlock {
+    float lo[3], hi[3];
+    int32_t R, Rp, O, dtype;
+    const void* grid;
+    const void* plane[3];
+    const uint8_t* occ;        // [O][O][O]
+    const int32_t* brick_slot; // [O][O][O] -> brick index or -1 (sparse grids)
+    const uint8_t* bricks;     // [n][(s+2)^3][8] uint8
+    uint32_t brick_bytes;      // size of this block's part of the brick atlas
+    float scale[4][kNch];
+    float offset[4][kNch];
+};
+
+struct DevView {
+    float eye[3];
+    float R[9];
+    float fx, fy, cx, cy;
+    int32_t x0, y0, w, h;
+    int32_t tiles_x, tile_begin, n_tiles;
+    int32_t set_begin, set_n;
+    int64_t pix_begin;
+};
+
+struct MarchArgs {
+    const DevBlock* blocks;
+    const DevView* views;
+    int32_t n_views;
+    const int32_t* refs;       // per view, ordered entry indices
+    int32_t total_tiles;
+    int32_t tile_w, tile_h;    // tile_w * tile_h == 64
+    int32_t mode, n_steps, max_steps;
+    float delta;
+    float scene_lo[3], scene_hi[3];
+    int32_t use_sparse;
+    int32_t blocks_dtype;      // COW_U8 / COW_F32, the same for every block of the launch
+    float* aux;                // [P][8] (C_d, F, T)
+    float* trans;              // [P]
+    int64_t* counts;           // [P][2] or null
+    int32_t* work_counter;     // persistent mode
+    int32_t persistent;
+    // per-block baseline: only this view and this one set position
+    int32_t only_view, only_set_pos;
+};
+
+struct MlpArgs {
+    const DevView* views;
+    int32_t n_views;
+    int64_t n_pix;
+    const float* mlp;
+    const float* aux;
+    float* rgb;
+    float* trans;
+};
+
+struct MlpBwdArgs {
+    const DevView* views;
+    int32_t n_views;
+    int64_t n_pix;
+    const float* mlp;
+    const float* aux;
+    const float* grad_rgb;
+    float* u;                  // [P][8]: dL/d(C_d, F) in 0..6
+    float* grad_mlp;           // [499], accumulated
+};
+
+struct BwdArgs {
+    MarchArgs m;
+    const float* u;            // [P][8]
+    const float* grad_trans;   // [P] or null
+    float* const* grad_grid;   // device array of per-entry pointers
+    float* const* grad_plane;  // device array, 3 per entry
+};
+
+// launchers (cow_kernels.hip)
+hipError_t launch_occupancy(const DevBlock* blocks, int entry, int O, hipStream_t s);
+hipError_t launch_march(const MarchArgs& a, int waves_per_group, hipStream_t s);
+hipError_t launch_reset_counter(int32_t* counter, hipStream_t s);
+hipError_t launch_clear_aux(float* aux, int64_t n_pix, hipStream_t s);
+hipError_t launch_mlp(const MlpArgs& a, hipStream_t s);
+hipError_t launch_mlp_bwd(const MlpBwdArgs& a, hipStream_t s);
+hipError_t launch_march_bwd(const BwdArgs& a, int waves_per_group, hipStream_t s);
+hipError_t launch_pack_bricks(const DevBlock* blocks, int entry, int O, int s_cells,
+                              const int32_t* slot_host_unused, hipStream_t st);
+
+}  // namespace cow

@@ -1,0 +1,153 @@
+"""GPU backward parity: cow_render_backward (MFMA MLP backward + march
+adjoint with fp32 atomics) against the fp64 CPU adjoint, which is itself
+pinned to central finite differences (tests/test_oracle_pins.py).
+
+Bar per gradient tensor: max|g - g_ref| <= 1e-3 max|g_ref| (normwise
+relative); across runs <= 1e-6 relative (atomics reorder sums)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2312_16457_amd import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+REL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def torch_cuda(have_gpu):
+    import torch
+    return torch
+
+
+def gpu_grads(torch, r, views, sets, params, mlp, aux, g_rgb, g_trans=None):
+    gg = [torch.zeros_like(t[0]) for t in r.textures]
+    gp = [[torch.zeros_like(p) for p in t[1]] for t in r.textures]
+    gm = torch.zeros(499, device="cuda")
+    r.render_backward(views, sets, params, mlp, aux, g_rgb, g_trans, gg, gp, gm)
+    torch.cuda.synchronize()
+    return gg, gp, gm
+
+
+def compare(gg, gp, gm, grads, gm_ref, rel=REL):
+    worst = 0.0
+    for k, (g, ps) in grads.items():
+        for a, b in [(gg[k], g)] + [(gp[k][i], ps[i]) for i in range(3)]:
+            den = np.abs(b).max()
+            if den == 0:
+                assert np.abs(a.cpu().numpy()).max() == 0
+                continue
+            e = np.abs(a.cpu().numpy() - b).max() / den
+            worst = max(worst, e)
+            assert e <= rel, (k, e)
+    e = np.abs(gm.cpu().numpy() - gm_ref).max() / np.abs(gm_ref).max()
+    assert e <= rel, ("mlp", e)
+    return max(worst, e)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_backward_small_scene(torch_cuda, mode):
+    torch = torch_cuda
+    from paper_2312_16457_amd import Renderer
+    if mode == 1:
+        scene = sg.make_scene(2, 2, ((16, 32, 4),), sg.F32, blobs_per_block=10, blob_z=(0, 0.4), seed=3, shift=2.0)
+        view = sg.pinhole(33, 21, (1.0, -1.0, 1.2), sg.look_rotation(np.array([1.0, 1.0, 0.2]) - [1.0, -1.0, 1.2]))
+        params = sg.cityb_params()
+    else:
+        scene = sg.c1_scene()
+        view = sg.c1_view().with_crop(40, 30, 48, 40)
+        params = sg.c1_params()
+    w = sg.random_mlp(5, 0.6)
+    r = Renderer(0).load_blocks(scene.blocks)
+    sets = [[(b.block_id, b.lod) for b in scene.blocks]]
+    mlp = torch.tensor(w, device="cuda")
+    out = r.render([view], sets, params, mlp)
+    rng = np.random.default_rng(2)
+    g_rgb = rng.uniform(-1, 1, (view.n_pixels, 3))
+    g_tr = rng.uniform(-1, 1, view.n_pixels)
+    gg, gp, gm = gpu_grads(torch, r, [view], sets, params, mlp, out["aux"],
+                           torch.tensor(g_rgb, dtype=torch.float32, device="cuda"),
+                           torch.tensor(g_tr, dtype=torch.float32, device="cuda"))
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    grads, gm_ref = O.adjoint(ob, occs, view, list(range(ob.n)), params, w, O.pixels_of(view), g_rgb, g_tr)
+    compare(gg, gp, gm, grads, gm_ref)
+
+
+def test_autograd_function_and_determinism(torch_cuda):
+    torch = torch_cuda
+    from paper_2312_16457_amd import Renderer, make_render_fn
+    scene = sg.make_scene(2, 2, ((16, 32, 4),), sg.F32, blobs_per_block=10, blob_z=(0, 0.4), seed=8, shift=2.0)
+    view = sg.pinhole(40, 24, (1.0, -1.1, 1.3), sg.look_rotation(np.array([1.0, 1.0, 0.1]) - [1.0, -1.1, 1.3]))
+    params = sg.cityb_params()
+    r = Renderer(0).load_blocks(scene.blocks)
+    sets = [[(b.block_id, b.lod) for b in scene.blocks]]
+    mlp = torch.tensor(sg.random_mlp(9, 0.5), device="cuda", requires_grad=True)
+    tex = []
+    for g, ps in r.textures:
+        g.requires_grad_(True)
+        for p in ps:
+            p.requires_grad_(True)
+        tex += [g] + ps
+    RenderFn = make_render_fn()
+    target = torch.rand((view.n_pixels, 3), device="cuda")
+    grads = []
+    for _ in range(2):
+        rgb, trans = RenderFn.apply(r, [view], sets, params, mlp, *tex)
+        loss = ((rgb - target) ** 2).mean() + 0.1 * trans.mean()
+        gs = torch.autograd.grad(loss, [mlp] + tex)
+        grads.append(gs)
+    for a, b in zip(*grads):
+        den = b.abs().max().item()
+        assert (a - b).abs().max().item() <= 1e-6 * max(den, 1e-30)
+    # same as the direct call with dL/drgb and dL/dT
+    with torch.no_grad():
+        out = r.render([view], sets, params, mlp.detach())
+        g_rgb = 2 * (out["rgb"] - target) / target.numel()
+        g_tr = torch.full_like(out["trans"], 0.1 / view.n_pixels)
+    gg, gp, gm = gpu_grads(torch, r, [view], sets, params, mlp.detach(), out["aux"], g_rgb, g_tr)
+    assert (gm - grads[0][0]).abs().max().item() <= 1e-6 * gm.abs().max().item()
+    assert (gg[0] - grads[0][1]).abs().max().item() <= 1e-6 * gg[0].abs().max().item()
+
+
+def test_backward_c5_crop(torch_cuda):
+    """The differentiable 4x4-block fp32 workload: a 64x64 crop of an 800x800
+    view against the fp64 adjoint (MSE loss against a second seeded scene)."""
+    torch = torch_cuda
+    from paper_2312_16457_amd import Renderer
+    learn, target = sg.c5_scenes()
+    views = sg.c5_views()
+    params = sg.cityb_params()
+    w_learn, w_tgt = sg.xavier_mlp(4), sg.xavier_mlp(5)
+    r = Renderer(0).load_blocks(learn.blocks)
+    sets = [[(b.block_id, 0) for b in learn.blocks]]
+    # crop: the 64x64 window of view 0 with the most evaluated samples among
+    # 16 seeded candidates
+    rng = np.random.default_rng(0)
+    v0 = views[0]
+    cands = [(int(rng.integers(0, 800 - 64)), int(rng.integers(0, 800 - 64))) for _ in range(16)]
+    mlp = torch.tensor(w_learn, device="cuda")
+    full = r.render([v0], sets, params, mlp, counts=True)
+    cnt = full["counts"][:, 0].reshape(800, 800).cpu().numpy()
+    x0, y0 = max(cands, key=lambda c: cnt[c[1]:c[1] + 64, c[0]:c[0] + 64].sum())
+    crop = v0.with_crop(x0, y0, 64, 64)
+    out = r.render([crop], sets, params, mlp)
+    # target image of the crop: the second scene rendered by the oracle
+    ob_t = O.OracleScene(target.blocks)
+    occ_t = [O.occupancy(ob_t, k) for k in range(ob_t.n)]
+    pix = O.pixels_of(crop)
+    tgt = O.render(ob_t, occ_t, crop, list(range(ob_t.n)), params, w_tgt, pix=pix)["rgb"]
+    ob = O.OracleScene(learn.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    ref = O.render(ob, occs, crop, list(range(ob.n)), params, w_learn, pix=pix)
+    assert np.abs(out["rgb"].cpu().numpy() - ref["rgb"]).max() <= 1e-4
+    g_rgb = 2 * (ref["rgb"] - tgt) / tgt.size  # dL/dC of the MSE over pixels x channels
+    gg, gp, gm = gpu_grads(torch, r, [crop], sets, params, mlp, out["aux"],
+                           torch.tensor(g_rgb, dtype=torch.float32, device="cuda"))
+    grads, gm_ref = O.adjoint(ob, occs, crop, list(range(ob.n)), params, w_learn, pix, g_rgb)
+    touched = [k for k, (g, ps) in grads.items() if np.abs(g).max() > 0]
+    assert touched
+    compare(gg, gp, gm, {k: grads[k] for k in touched}, gm_ref)
+    # untouched blocks receive nothing
+    for k in set(range(len(learn.blocks))) - set(touched):
+        assert gg[k].abs().max().item() == 0
