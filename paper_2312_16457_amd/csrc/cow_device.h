@@ -1,0 +1,531 @@
+// Device helpers shared by the forward and backward march kernels:
+// exact fp32 decision sequences, the step-interval search, texture taps,
+// and wave-uniform block / view descriptors held in scalar registers.
+//
+// Every translation unit that includes this is compiled with
+// -ffp-contract=off and correctly rounded fp32 divide/sqrt, so each decision
+// below is one fixed sequence of IEEE fp32 operations; continuous arithmetic
+// asks for fusion explicitly with fmaf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cow_internal.h"
+
+namespace cow {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// wave-uniform values: readfirstlane puts them in scalar registers, so a
+// buffer resource built from them needs no per-lane waterfall
+// ---------------------------------------------------------------------------
+__device__ inline int ufl(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline float uff(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
+template <class T>
+__device__ inline T* ufp(T* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+// Buffer resource: base in scalar registers, 32-bit byte offsets per lane,
+// hardware range check (reads outside [0, bytes) return zero).
+__device__ inline __amdgpu_buffer_rsrc_t tex_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ inline uint2 ld8(__amdgpu_buffer_rsrc_t r, int byte_off) {
+    auto v = __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0);
+    return make_uint2(v[0], v[1]);
+}
+
+__device__ inline float4 ld16(__amdgpu_buffer_rsrc_t r, int byte_off) {
+    auto v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+    return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
+                       __uint_as_float(v[3]));
+}
+
+// ---------------------------------------------------------------------------
+// view (camera) of a ray packet
+// ---------------------------------------------------------------------------
+struct ViewU {
+    float eye[3], R[9], fx, fy, cx, cy;
+    int x0, y0, w, h, tiles_x, set_begin, set_n;
+    int64_t pix_begin;
+};
+
+__device__ inline void load_view(const DevView* V, ViewU& v) {
+    for (int c = 0; c < 3; ++c) v.eye[c] = uff(V->eye[c]);
+    for (int c = 0; c < 9; ++c) v.R[c] = uff(V->R[c]);
+    v.fx = uff(V->fx), v.fy = uff(V->fy), v.cx = uff(V->cx), v.cy = uff(V->cy);
+    v.x0 = ufl(V->x0), v.y0 = ufl(V->y0), v.w = ufl(V->w), v.h = ufl(V->h);
+    v.tiles_x = ufl(V->tiles_x), v.set_begin = ufl(V->set_begin), v.set_n = ufl(V->set_n);
+    const uint64_t pb = (uint64_t)V->pix_begin;
+    v.pix_begin = (int64_t)(((uint64_t)(uint32_t)ufl((int)(pb >> 32)) << 32) | (uint32_t)ufl((int)pb));
+}
+
+// Pixel ray r(t) = o + t d (Sec. 3): d is the normalised camera-to-world
+// rotation of (x, y, 1), x = (i + 1/2 - cx) / fx, y = (j + 1/2 - cy) / fy.
+template <class V>
+__device__ inline void ray_direction(const V& v, int i, int j, float d[3]) {
+    float x = ((float)i + 0.5f - v.cx) / v.fx;
+    float y = ((float)j + 0.5f - v.cy) / v.fy;
+    float u[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float a = v.R[3 * c + 0] * x;
+        float b = v.R[3 * c + 1] * y;
+        u[c] = (a + b) + v.R[3 * c + 2];
+    }
+    float n = sqrtf((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d[c] = u[c] / n;
+}
+
+// ---------------------------------------------------------------------------
+// camera-anchored steps and their block intervals
+// ---------------------------------------------------------------------------
+
+// t_k = (k + 1/2) delta, exact for k < 2^23 when delta is a power of two
+__device__ inline float step_t(int k, float delta) { return ((float)k + 0.5f) * delta; }
+
+// sample coordinate fl(o + fl(t d))
+__device__ inline float coord(float o, float t, float d) {
+    float td = t * d;
+    return o + td;
+}
+
+// Least k in [0, kMaxStep] with pred(k), pred monotone false -> true;
+// kMaxStep + 1 if none.  Exact whatever the guess: gallop from it, bisect.
+template <class Pred>
+__device__ inline int first_true(Pred pred, int guess) {
+    guess = guess < 0 ? 0 : (guess > kMaxStep ? kMaxStep : guess);
+    int lo, hi;  // pred(lo) false (lo may be -1), pred(hi) true (hi may be kMaxStep + 1)
+    if (pred(guess)) {
+        hi = guess;
+        int step = 1;
+        for (;;) {
+            const int c = hi - step;
+            if (c < 0) {
+                lo = -1;
+                break;
+            }
+            if (!pred(c)) {
+                lo = c;
+                break;
+            }
+            hi = c;
+            step <<= 1;
+        }
+    } else {
+        lo = guess;
+        int step = 1;
+        for (;;) {
+            const int c = lo + step;
+            if (c > kMaxStep) {
+                hi = kMaxStep + 1;
+                break;
+            }
+            if (pred(c)) {
+                hi = c;
+                break;
+            }
+            lo = c;
+            step <<= 1;
+        }
+    }
+    while (hi - lo > 1) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (pred(mid))
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return hi;
+}
+
+__device__ inline int guess_index(float g) {
+    if (!(g > 0.0f)) return 0;
+    if (g > (float)kMaxStep) return kMaxStep;
+    return (int)ceilf(g);
+}
+
+// Step indices k >= 0 whose fp32 sample position lies in the half-open box
+// [lo, hi) on every axis: [*ka, *kb) (empty when *ka >= *kb).  Each axis
+// predicate is monotone in k (t_k and both roundings are monotone), so the
+// set is an intersection of prefixes and suffixes.
+__device__ inline void box_interval(const float o[3], const float d[3], float delta, const float lo[3],
+                                          const float hi[3], int* ka, int* kb) {
+    const float inv_delta = 1.0f / delta;
+    int a = 0, b = kMaxStep + 1;
+    for (int c = 0; c < 3; ++c) {
+        const float oc = o[c], dc = d[c], l = lo[c], h = hi[c];
+        if (dc == 0.0f) {
+            if (!(l <= oc && oc < h)) b = 0;
+            continue;
+        }
+        const float r = __builtin_amdgcn_rcpf(dc);
+        const int gl = guess_index(((l - oc) * r) * inv_delta - 0.5f);
+        const int gh = guess_index(((h - oc) * r) * inv_delta - 0.5f);
+        int e, x;
+        if (dc > 0.0f) {
+            e = first_true([&](int k) { return coord(oc, step_t(k, delta), dc) >= l; }, gl);
+            x = first_true([&](int k) { return coord(oc, step_t(k, delta), dc) >= h; }, gh);
+        } else {
+            e = first_true([&](int k) { return coord(oc, step_t(k, delta), dc) < h; }, gh);
+            x = first_true([&](int k) { return coord(oc, step_t(k, delta), dc) < l; }, gl);
+        }
+        a = e > a ? e : a;
+        b = x < b ? x : b;
+    }
+    *ka = a;
+    *kb = b;
+}
+
+// slab test against the closed box, t_near clamped at 0 (chord mode)
+__device__ inline bool slab_exact(const float o[3], const float d[3], const float lo[3], const float hi[3],
+                                  float* tn, float* tf) {
+    float t0 = 0.0f, t1 = INFINITY;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if (d[c] == 0.0f) {
+            if (o[c] < lo[c] || o[c] > hi[c]) return false;
+            continue;
+        }
+        float inv = 1.0f / d[c];
+        float a = (lo[c] - o[c]) * inv;
+        float b = (hi[c] - o[c]) * inv;
+        float mn = a < b ? a : b, mx = a < b ? b : a;
+        if (mn > t0) t0 = mn;
+        if (mx < t1) t1 = mx;
+    }
+    *tn = t0;
+    *tf = t1;
+    return t0 < t1;
+}
+
+// ---------------------------------------------------------------------------
+// one (block, LOD) of the march, wave-uniform
+// ---------------------------------------------------------------------------
+struct BlockU {
+    __amdgpu_buffer_rsrc_t tex[4];  // grid, xy, xz, yz
+    __amdgpu_buffer_rsrc_t brick;   // packed grid bricks (sparse)
+    const uint8_t* occ;
+    const int32_t* slot;
+    int R, Rp, O;
+    float lo[3], hi[3];
+    float sc[4][kNch];              // uint8 decode scale per texture and channel
+    float osum[kNch];               // sum of the four textures' decode offsets
+};
+
+template <int DT>
+__device__ inline void load_block(const DevBlock* B, BlockU& b) {
+    b.R = ufl(B->R), b.Rp = ufl(B->Rp), b.O = ufl(B->O);
+    for (int c = 0; c < 3; ++c) b.lo[c] = uff(B->lo[c]), b.hi[c] = uff(B->hi[c]);
+    const uint32_t texel = DT == 0 ? 8u : 32u;
+    b.tex[0] = tex_rsrc(ufp(B->grid), (uint32_t)b.R * b.R * b.R * texel);
+    for (int p = 0; p < 3; ++p) b.tex[1 + p] = tex_rsrc(ufp(B->plane[p]), (uint32_t)b.Rp * b.Rp * texel);
+    b.occ = ufp(B->occ);
+    b.slot = ufp(B->brick_slot);
+    b.brick = tex_rsrc(ufp(B->bricks), (uint32_t)ufl((int)B->brick_bytes));
+    if (DT == 0) {
+        for (int t = 0; t < 4; ++t)
+            for (int c = 0; c < kNch; ++c) b.sc[t][c] = uff(B->scale[t][c]);
+        for (int c = 0; c < kNch; ++c)
+            b.osum[c] = uff(((B->offset[0][c] + B->offset[1][c]) + B->offset[2][c]) + B->offset[3][c]);
+    }
+}
+
+__device__ inline int occ_cell(const BlockU& b, const float q[3]) {
+    const float Of = (float)b.O;
+    int cell[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        int k = (int)floorf(q[c] * Of);
+        k = k < 0 ? 0 : k;
+        cell[c] = k > b.O - 1 ? b.O - 1 : k;
+    }
+    return (cell[2] * b.O + cell[1]) * b.O + cell[0];
+}
+
+// ---------------------------------------------------------------------------
+// feature gather: trilinear grid + three bilinear planes
+// ---------------------------------------------------------------------------
+struct Lin {
+    int i0, i1;
+    float w0, w1;
+};
+
+// cell-centred, clamp-to-edge linear taps: u = q R - 1/2
+__device__ inline Lin lin_taps(float q, int R) {
+    const float u = q * (float)R - 0.5f;
+    const float fl = floorf(u);
+    const int a = (int)fl;
+    Lin t;
+    t.w1 = u - fl;
+    t.w0 = 1.0f - t.w1;
+    t.i0 = a < 0 ? 0 : a;
+    t.i1 = a + 1 > R - 1 ? R - 1 : a + 1;
+    return t;
+}
+
+// texel indices and weights of one sample: 8 grid taps, then xy, xz, yz
+struct Taps {
+    int idx[20];
+    float w[20];
+};
+
+__device__ inline void sample_taps(int R, int Rp, const float q[3], Taps& T) {
+    const Lin gx = lin_taps(q[0], R), gy = lin_taps(q[1], R), gz = lin_taps(q[2], R);
+    const Lin px = lin_taps(q[0], Rp), py = lin_taps(q[1], Rp), pz = lin_taps(q[2], Rp);
+    const int zi[2] = {gz.i0, gz.i1}, yi[2] = {gy.i0, gy.i1}, xi[2] = {gx.i0, gx.i1};
+    const float zw[2] = {gz.w0, gz.w1}, yw[2] = {gy.w0, gy.w1}, xw[2] = {gx.w0, gx.w1};
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+            const int row = (zi[dz] * R + yi[dy]) * R;
+            const float wzy = zw[dz] * yw[dy];
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                T.idx[dz * 4 + dy * 2 + dx] = row + xi[dx];
+                T.w[dz * 4 + dy * 2 + dx] = wzy * xw[dx];
+            }
+        }
+    // planes are indexed [v][u]: xy (u=x, v=y), xz (u=x, v=z), yz (u=y, v=z)
+    const Lin U[3] = {px, px, py}, V[3] = {py, pz, pz};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const int v0 = V[p].i0 * Rp, v1 = V[p].i1 * Rp;
+        T.idx[8 + 4 * p + 0] = v0 + U[p].i0;
+        T.idx[8 + 4 * p + 1] = v0 + U[p].i1;
+        T.idx[8 + 4 * p + 2] = v1 + U[p].i0;
+        T.idx[8 + 4 * p + 3] = v1 + U[p].i1;
+        T.w[8 + 4 * p + 0] = V[p].w0 * U[p].w0;
+        T.w[8 + 4 * p + 1] = V[p].w0 * U[p].w1;
+        T.w[8 + 4 * p + 2] = V[p].w1 * U[p].w0;
+        T.w[8 + 4 * p + 3] = V[p].w1 * U[p].w1;
+    }
+}
+
+__device__ inline float ub(uint2 v, int c) {
+    const uint32_t w = c < 4 ? v.x : v.y;
+    return (float)((w >> (8 * (c & 3))) & 0xffu);
+}
+
+// raw[c] += scale[c] * (sum_k w_k q_k[c]) over N uint8 texels
+template <int N>
+__device__ inline void fold_u8(const uint2 (&t)[N], const float* w, const float* sc, float raw[kNch]) {
+#pragma unroll
+    for (int c = 0; c < kNch; ++c) {
+        float s = w[0] * ub(t[0], c);
+#pragma unroll
+        for (int k = 1; k < N; ++k) s = fmaf(w[k], ub(t[k], c), s);
+        raw[c] = fmaf(s, sc[c], raw[c]);
+    }
+}
+
+// Pre-activation features of a uint8 block at local coordinate q:
+// sum over the four textures of scale * interpolated q, plus the offsets.
+// Interpolating the bytes and decoding once equals decoding every texel
+// because the weights of each texture sum to one.
+template <bool SPARSE>
+__device__ inline void raw_u8(const BlockU& b, const float q[3], int cell, float raw[kNch]) {
+    Taps T;
+    sample_taps(b.R, b.Rp, q, T);
+    uint2 g[8], p0[4], p1[4], p2[4];
+    if (SPARSE) {
+        // brick of (s+2)^3 texels around the sample's occupancy cell; texel j
+        // of an axis holds grid index clamp(c s - 1 + j)
+        const int O = b.O, s = b.R / O, s2 = s + 2;
+        const int cx = cell % O, cy = (cell / O) % O, cz = cell / (O * O);
+        const int base = b.slot[cell] * (s2 * s2 * s2);
+        const Lin gx = lin_taps(q[0], b.R), gy = lin_taps(q[1], b.R), gz = lin_taps(q[2], b.R);
+        const int xs[2] = {gx.i0 - (cx * s - 1), gx.i1 - (cx * s - 1)};
+        const int ys[2] = {gy.i0 - (cy * s - 1), gy.i1 - (cy * s - 1)};
+        const int zs[2] = {gz.i0 - (cz * s - 1), gz.i1 - (cz * s - 1)};
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            g[k] = ld8(b.brick, 8 * (base + (zs[k >> 2] * s2 + ys[(k >> 1) & 1]) * s2 + xs[k & 1]));
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) g[k] = ld8(b.tex[0], 8 * T.idx[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        p0[k] = ld8(b.tex[1], 8 * T.idx[8 + k]);
+        p1[k] = ld8(b.tex[2], 8 * T.idx[12 + k]);
+        p2[k] = ld8(b.tex[3], 8 * T.idx[16 + k]);
+    }
+#pragma unroll
+    for (int c = 0; c < kNch; ++c) raw[c] = b.osum[c];
+    fold_u8<8>(g, T.w, b.sc[0], raw);
+    fold_u8<4>(p0, T.w + 8, b.sc[1], raw);
+    fold_u8<4>(p1, T.w + 12, b.sc[2], raw);
+    fold_u8<4>(p2, T.w + 16, b.sc[3], raw);
+}
+
+// fp32 block: a texel is two 16-byte halves (channels 0-3, 4-7); textures
+// are summed one at a time, ((G + XY) + XZ) + YZ
+__device__ inline void raw_f32(const BlockU& b, const Taps& T, float raw[kNch]) {
+#pragma unroll
+    for (int tex = 0; tex < 4; ++tex) {
+        const int k0 = tex == 0 ? 0 : 4 + 4 * tex, n = tex == 0 ? 8 : 4;
+        float a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            const float4 lo = ld16(b.tex[tex], 32 * T.idx[k0 + k]);
+            const float4 hi = ld16(b.tex[tex], 32 * T.idx[k0 + k] + 16);
+            const float w = T.w[k0 + k];
+            a[0] = fmaf(w, lo.x, a[0]);
+            a[1] = fmaf(w, lo.y, a[1]);
+            a[2] = fmaf(w, lo.z, a[2]);
+            a[3] = fmaf(w, lo.w, a[3]);
+            a[4] = fmaf(w, hi.x, a[4]);
+            a[5] = fmaf(w, hi.y, a[5]);
+            a[6] = fmaf(w, hi.z, a[6]);
+            a[7] = fmaf(w, hi.w, a[7]);
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) raw[c] = tex == 0 ? a[c] : raw[c] + a[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// activations and opacity
+// ---------------------------------------------------------------------------
+__device__ inline float sigmoidf_(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
+
+// alpha = 1 - exp(-x) for x = sigma delta >= 0 (Eq. "alpha accumulation"),
+// without the cancellation of forming 1 - exp(-x) when x is small: a
+// five-term series below 1/16 (truncation < 2e-9 relative).
+__device__ inline float alpha_of(float x) {
+    float t = fmaf(-x, 1.0f / 120.0f, 1.0f / 24.0f);
+    t = fmaf(-x, t, 1.0f / 6.0f);
+    t = fmaf(-x, t, 0.5f);
+    t = fmaf(-x, t, 1.0f);
+    const float series = x * t;
+    return x < 0.0625f ? series : 1.0f - __expf(-x);
+}
+
+// ---------------------------------------------------------------------------
+// packets: which tile of which view a wave marches
+// ---------------------------------------------------------------------------
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of packets (neighbouring pixels share its L2).
+__device__ inline int xcd_packet(int waves, int wave) {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int x = b & 7, q = nb >> 3, r = nb & 7;
+    const int lb = x * q + (x < r ? x : r) + (b >> 3);
+    return lb * waves + wave;
+}
+
+__device__ inline const DevView* find_view_by_tile(const DevView* views, int n_views, int packet) {
+    int lo = 0, hi = n_views - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_begin <= packet)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return views + lo;
+}
+
+__device__ inline int64_t view_of_pixel(const DevView* views, int n_views, int64_t p) {
+    int lo = 0, hi = n_views - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].pix_begin <= p)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline void pixel_direction(const DevView* views, int n_views, int64_t p, float d[3]) {
+    const DevView* V = views + view_of_pixel(views, n_views, p);
+    const int64_t li = p - V->pix_begin;
+    const int ly = (int)(li / V->w), lx = (int)(li - (int64_t)ly * V->w);
+    ray_direction(*V, V->x0 + lx, V->y0 + ly, d);
+}
+
+// A ray packet: lane -> pixel of a tile_w x tile_h tile of the view's crop.
+struct Ray {
+    float o[3], d[3];
+    int64_t pix;
+    bool active;
+};
+
+__device__ inline void packet_ray(const MarchArgs& a, const ViewU& v, int tile, int lane, Ray& r) {
+    const int tw = a.tile_w, th = a.tile_h;
+    const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
+    const int px = v.x0 + tx * tw + (lane % tw);
+    const int py = v.y0 + ty * th + (lane / tw);
+    r.active = px < v.x0 + v.w && py < v.y0 + v.h;
+    ray_direction(v, px, py, r.d);
+    r.o[0] = v.eye[0];
+    r.o[1] = v.eye[1];
+    r.o[2] = v.eye[2];
+    r.pix = v.pix_begin + (int64_t)(py - v.y0) * v.w + (px - v.x0);
+}
+
+// Samples of one block for one lane: grid mode, the block's step interval
+// clipped to the ray's window; chord mode, n_steps midpoints of the chord.
+struct Span {
+    int ka, kb;
+    float tn, dr, delta;
+};
+
+template <int MODE>
+__device__ inline Span block_span(const MarchArgs& a, const BlockU& b, const Ray& r, bool hit, int w0, int w1) {
+    Span s{0, 0, 0.0f, 0.0f, a.delta};
+    if (!hit) return s;
+    if (MODE == 1) {
+        box_interval(r.o, r.d, a.delta, b.lo, b.hi, &s.ka, &s.kb);
+        s.ka = s.ka > w0 ? s.ka : w0;
+        s.kb = s.kb < w1 ? s.kb : w1;
+    } else {
+        float tf;
+        if (slab_exact(r.o, r.d, b.lo, b.hi, &s.tn, &tf)) {
+            s.dr = (tf - s.tn) / (float)a.n_steps;
+            s.delta = s.dr;
+            s.kb = a.n_steps;
+        }
+    }
+    return s;
+}
+
+// Advance k to the next occupied sample of the span (or to kb).  Loads the
+// occupancy byte only when the sample's cell differs from the cached one.
+template <int MODE>
+__device__ inline bool next_occupied(const BlockU& b, const Ray& r, const Span& sp, float delta, int& k,
+                                     float q[3], int& cell, int& cur_cell, bool& cur_occ, int64_t& marched) {
+    while (k < sp.kb) {
+        const float t = MODE == 1 ? step_t(k, delta) : sp.tn + ((float)k + 0.5f) * sp.dr;
+        bool in = true;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float p = coord(r.o[c], t, r.d[c]);
+            if (MODE == 0) in = in && (b.lo[c] <= p && p < b.hi[c]);
+            q[c] = p - b.lo[c];
+        }
+        if (in) {
+            ++marched;
+            cell = occ_cell(b, q);
+            if (cell != cur_cell) {
+                cur_cell = cell;
+                cur_occ = b.occ[cell] != 0;
+            }
+            if (cur_occ) return true;
+        }
+        ++k;
+    }
+    return false;
+}
+
+}  // namespace cow

@@ -1,0 +1,265 @@
+// Forward march (per-block composite + front-to-back merge), occupancy
+// build and sparse-brick packing for gfx950 (City-on-Web, arXiv 2312.16457).
+#include <hip/hip_runtime.h>
+
+#include "cow_device.h"
+
+namespace cow {
+
+// Composite the samples of one block for one lane (Eqs. "alpha
+// accumulation", "combined accumulation", "volume rendering inside
+// blocks"): Ak = sum_i T_i alpha_i (c_i, f_i), Tk = prod_i (1 - alpha_i).
+// Lanes advance independently through their own spans; a wave iterates
+// while any lane still has an occupied sample.
+template <int DT, int MODE, bool SPARSE>
+__device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ray& r, const Span& sp,
+                                   float Ak[7], float& Tk, int64_t& n_eval, int64_t& n_march) {
+    int k = sp.ka;
+    int cur_cell = -1;
+    bool cur_occ = false;
+    for (;;) {
+        float q[3];
+        int cell = 0;
+        const bool have = next_occupied<MODE>(b, r, sp, sp.delta, k, q, cell, cur_cell, cur_occ, n_march);
+        if (!__any(have)) break;
+        if (have) {
+            float raw[8];
+            if (DT == 0) {
+                raw_u8<SPARSE>(b, q, cell, raw);
+            } else {
+                Taps T;
+                sample_taps(b.R, b.Rp, q, T);
+                raw_f32(b, T, raw);
+            }
+            const float sigma = __expf(raw[0]);
+            const float alpha = alpha_of(sigma * sp.delta);
+            const float w = Tk * alpha;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) Ak[c] = fmaf(w, sigmoidf_(raw[1 + c]), Ak[c]);
+            Tk *= 1.0f - alpha;
+            ++n_eval;
+            ++k;
+        }
+    }
+}
+
+template <int MODE, int DT, bool SPARSE>
+__device__ void march_packet(const MarchArgs& a, const DevView* V, int tile, int lane) {
+    ViewU v;
+    load_view(V, v);
+    Ray r;
+    packet_ray(a, v, tile, lane, r);
+    bool hit = r.active;
+    int w0 = 0, w1 = 0;
+    if (MODE == 1 && r.active) {
+        int ka, kb;
+        box_interval(r.o, r.d, a.delta, a.scene_lo, a.scene_hi, &ka, &kb);
+        hit = ka < kb;
+        w0 = ka;
+        w1 = ka + a.max_steps;
+    }
+    int r0 = 0, r1 = v.set_n;
+    if (a.only_set_pos >= 0) r0 = a.only_set_pos, r1 = a.only_set_pos + 1;
+    float A[7] = {0, 0, 0, 0, 0, 0, 0}, T = 1.0f;
+    int64_t n_eval = 0, n_march = 0;
+    if (a.only_set_pos > 0 && r.active) {  // per-block baseline: continue the running blend
+        const float4 lo4 = reinterpret_cast<const float4*>(a.aux)[2 * r.pix];
+        const float4 hi4 = reinterpret_cast<const float4*>(a.aux)[2 * r.pix + 1];
+        A[0] = lo4.x, A[1] = lo4.y, A[2] = lo4.z, A[3] = lo4.w;
+        A[4] = hi4.x, A[5] = hi4.y, A[6] = hi4.z, T = hi4.w;
+        if (a.counts) n_eval = a.counts[2 * r.pix], n_march = a.counts[2 * r.pix + 1];
+    }
+    for (int j = r0; j < r1; ++j) {
+        const int e = ufl(a.refs[v.set_begin + j]);
+        BlockU b;
+        load_block<DT>(a.blocks + e, b);
+        const Span sp = block_span<MODE>(a, b, r, hit, w0, w1);
+        if (!__any(sp.ka < sp.kb)) continue;
+        float Ak[7] = {0, 0, 0, 0, 0, 0, 0}, Tk = 1.0f;
+        march_block<DT, MODE, SPARSE>(a, b, r, sp, Ak, Tk, n_eval, n_march);
+        // merge front to back (Eq. "volume rendering across blocks"), with
+        // the block's transmittance prod(1 - alpha_i) carried directly
+#pragma unroll
+        for (int c = 0; c < 7; ++c) A[c] = fmaf(T, Ak[c], A[c]);
+        T *= Tk;
+    }
+    if (r.active) {
+        float4* aux4 = reinterpret_cast<float4*>(a.aux);
+        aux4[2 * r.pix] = make_float4(A[0], A[1], A[2], A[3]);
+        aux4[2 * r.pix + 1] = make_float4(A[4], A[5], A[6], T);
+        a.trans[r.pix] = T;
+        if (a.counts) {
+            a.counts[2 * r.pix] = n_eval;
+            a.counts[2 * r.pix + 1] = n_march;
+        }
+    }
+}
+
+// All blocks of one launch share a texture dtype (checked on the host).
+template <int MODE, int DT, bool SPARSE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void march_fwd_kernel(MarchArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    const int wave = ufl(threadIdx.x >> 6);
+    if (a.persistent) {
+        for (;;) {
+            int p = 0;
+            if (lane == 0) p = atomicAdd(a.work_counter, 1);
+            p = ufl(__shfl(p, 0));
+            if (p >= a.total_tiles) break;
+            const DevView* V = find_view_by_tile(a.views, a.n_views, p);
+            march_packet<MODE, DT, SPARSE>(a, V, p - ufl(V->tile_begin), lane);
+        }
+        return;
+    }
+    const int packet = ufl(xcd_packet(waves, wave));
+    if (packet >= a.total_tiles) return;
+    if (a.only_view >= 0) {
+        march_packet<MODE, DT, SPARSE>(a, a.views + a.only_view, packet, lane);
+        return;
+    }
+    const DevView* V = find_view_by_tile(a.views, a.n_views, packet);
+    march_packet<MODE, DT, SPARSE>(a, V, packet - ufl(V->tile_begin), lane);
+}
+
+hipError_t launch_march(const MarchArgs& a, int waves, hipStream_t s) {
+    if (a.total_tiles <= 0) return hipSuccess;
+    dim3 block(64 * waves);
+    dim3 grid;
+    if (a.persistent) {
+        int dev = 0, cus = 256;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        grid = dim3(cus * (16 / waves));  // four waves per SIMD
+    } else {
+        grid = dim3((a.total_tiles + waves - 1) / waves);
+    }
+    const int dt = a.blocks_dtype;
+#define COW_LAUNCH(M, D, S) hipLaunchKernelGGL((march_fwd_kernel<M, D, S>), grid, block, 0, s, a)
+    if (a.mode == 1) {
+        if (dt == 1)
+            COW_LAUNCH(1, 1, false);
+        else if (a.use_sparse)
+            COW_LAUNCH(1, 0, true);
+        else
+            COW_LAUNCH(1, 0, false);
+    } else {
+        if (dt == 1)
+            COW_LAUNCH(0, 1, false);
+        else if (a.use_sparse)
+            COW_LAUNCH(0, 0, true);
+        else
+            COW_LAUNCH(0, 0, false);
+    }
+#undef COW_LAUNCH
+    return hipGetLastError();
+}
+
+__global__ void reset_counter_kernel(int32_t* c) {
+    if (threadIdx.x == 0) c[0] = 0;
+}
+
+hipError_t launch_reset_counter(int32_t* counter, hipStream_t s) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
+    return hipGetLastError();
+}
+
+__global__ void clear_aux_kernel(float4* aux, int64_t n_pix) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_pix) {
+        aux[2 * i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        aux[2 * i + 1] = make_float4(0.f, 0.f, 0.f, 1.f);
+    }
+}
+
+hipError_t launch_clear_aux(float* aux, int64_t n_pix, hipStream_t s) {
+    if (n_pix <= 0) return hipSuccess;
+    hipLaunchKernelGGL(clear_aux_kernel, dim3((unsigned)((n_pix + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<float4*>(aux), n_pix);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// occupancy: conservative max-bound of the interpolated density
+// ---------------------------------------------------------------------------
+
+// density-channel texel as the decision sees it: fl(fl(q s) + o), or the
+// stored fp32 value
+__device__ inline float texel0(const DevBlock* B, int tex, int idx) {
+    const void* base = tex == 0 ? B->grid : B->plane[tex - 1];
+    if (B->dtype == 0) {
+        const float q = (float)reinterpret_cast<const uint8_t*>(base)[(size_t)idx * 8];
+        const float m = q * B->scale[tex][0];
+        return m + B->offset[tex][0];
+    }
+    return reinterpret_cast<const float*>(base)[(size_t)idx * 8];
+}
+
+// A cell is occupied iff the largest density texel of each texture over the
+// cell's interpolation support, summed ((G + XY) + XZ) + YZ, exceeds ln 0.01:
+// every sample of an unoccupied cell then has density <= 0.01 (interpolation
+// is a convex combination and exp is monotone), and such cells are skipped.
+__global__ void occupancy_kernel(const DevBlock* blocks, int entry) {
+    const DevBlock* B = blocks + entry;
+    const int O = B->O, R = B->R, Rp = B->Rp;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= O * O * O) return;
+    const int c3[3] = {cell % O, (cell / O) % O, cell / (O * O)};
+    const int s = R / O, sp = Rp / O;
+    int glo[3], ghi[3], plo[3], phi[3];
+    for (int a = 0; a < 3; ++a) {
+        glo[a] = max(c3[a] * s - 1, 0);
+        ghi[a] = min((c3[a] + 1) * s, R - 1);
+        plo[a] = max(c3[a] * sp - 1, 0);
+        phi[a] = min((c3[a] + 1) * sp, Rp - 1);
+    }
+    float mg = -INFINITY;
+    for (int z = glo[2]; z <= ghi[2]; ++z)
+        for (int y = glo[1]; y <= ghi[1]; ++y)
+            for (int x = glo[0]; x <= ghi[0]; ++x) mg = fmaxf(mg, texel0(B, 0, (z * R + y) * R + x));
+    const int au[3] = {0, 0, 1}, av[3] = {1, 2, 2};
+    float mp[3];
+    for (int p = 0; p < 3; ++p) {
+        float m = -INFINITY;
+        for (int v = plo[av[p]]; v <= phi[av[p]]; ++v)
+            for (int u = plo[au[p]]; u <= phi[au[p]]; ++u) m = fmaxf(m, texel0(B, 1 + p, v * Rp + u));
+        mp[p] = m;
+    }
+    const float thresh = -0x1.26bb1cp+2f;  // fp32 nearest to ln(0.01)
+    const float bound = ((mg + mp[0]) + mp[1]) + mp[2];
+    const_cast<uint8_t*>(B->occ)[cell] = bound > thresh ? 1 : 0;
+}
+
+hipError_t launch_occupancy(const DevBlock* blocks, int entry, int O, hipStream_t s) {
+    const int n = O * O * O;
+    hipLaunchKernelGGL(occupancy_kernel, dim3((n + 63) / 64), dim3(64), 0, s, blocks, entry);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// sparse grid: copy each occupied cell's interpolation support to a brick
+// ---------------------------------------------------------------------------
+__global__ void pack_bricks_kernel(const DevBlock* blocks, int entry) {
+    const DevBlock* B = blocks + entry;
+    const int O = B->O, R = B->R, s = R / O, s2 = s + 2;
+    const int cell = blockIdx.x;
+    const int slot = B->brick_slot[cell];
+    if (slot < 0) return;
+    const int cx = cell % O, cy = (cell / O) % O, cz = cell / (O * O);
+    const uint2* G = reinterpret_cast<const uint2*>(B->grid);
+    uint2* dst = reinterpret_cast<uint2*>(const_cast<uint8_t*>(B->bricks)) + (size_t)slot * (s2 * s2 * s2);
+    for (int t = threadIdx.x; t < s2 * s2 * s2; t += blockDim.x) {
+        const int bx = t % s2, by = (t / s2) % s2, bz = t / (s2 * s2);
+        const int x = min(max(cx * s - 1 + bx, 0), R - 1);
+        const int y = min(max(cy * s - 1 + by, 0), R - 1);
+        const int z = min(max(cz * s - 1 + bz, 0), R - 1);
+        dst[t] = G[(z * R + y) * R + x];
+    }
+}
+
+hipError_t launch_pack_bricks(const DevBlock* blocks, int entry, int O, int, const int32_t*, hipStream_t st) {
+    hipLaunchKernelGGL(pack_bricks_kernel, dim3(O * O * O), dim3(256), 0, st, blocks, entry);
+    return hipGetLastError();
+}
+
+}  // namespace cow

@@ -1,0 +1,136 @@
+// March adjoint of the block-merged render for gfx950 (City-on-Web,
+// arXiv 2312.16457): per-ray recomputation of the samples, fp32 atomic
+// scatter of texel gradients.
+#include <hip/hip_runtime.h>
+
+#include "cow_device.h"
+
+namespace cow {
+
+// One ray per lane, samples recomputed in the forward order.  With
+// v_k = (c_k, f_k), u = dL/dA, A the ray's final (C_d, F), A_{<=k} the
+// running prefix and T_{k+1} the transmittance after sample k:
+//   dL/dsigma_k = delta (T_{k+1} u.v_k - u.(A - A_{<=k})) - delta T_N dL/dT_N
+//   dL/draw_0   = sigma_k dL/dsigma_k
+//   dL/draw_c   = w_k u_c s (1 - s)        (c >= 1, s = sigmoid(raw_c))
+// and each texel receives its interpolation weight times dL/draw.  The
+// merged composite equals the monolithic one over the same sequence
+// (Appendix A), so one running prefix serves all blocks in order.
+template <int MODE>
+__device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, int lane) {
+    const MarchArgs& a = ba.m;
+    ViewU v;
+    load_view(V, v);
+    Ray r;
+    packet_ray(a, v, tile, lane, r);
+    bool hit = r.active;
+    int w0 = 0, w1 = 0;
+    if (MODE == 1 && r.active) {
+        int ka, kb;
+        box_interval(r.o, r.d, a.delta, a.scene_lo, a.scene_hi, &ka, &kb);
+        hit = ka < kb;
+        w0 = ka;
+        w1 = ka + a.max_steps;
+    }
+    float Af[7] = {0, 0, 0, 0, 0, 0, 0}, TN = 1.0f, u[7] = {0, 0, 0, 0, 0, 0, 0}, gT = 0.0f;
+    if (r.active) {
+        const float4 lo = reinterpret_cast<const float4*>(a.aux)[2 * r.pix];
+        const float4 hi = reinterpret_cast<const float4*>(a.aux)[2 * r.pix + 1];
+        Af[0] = lo.x, Af[1] = lo.y, Af[2] = lo.z, Af[3] = lo.w, Af[4] = hi.x, Af[5] = hi.y, Af[6] = hi.z;
+        TN = hi.w;
+        const float4 ulo = reinterpret_cast<const float4*>(ba.u)[2 * r.pix];
+        const float4 uhi = reinterpret_cast<const float4*>(ba.u)[2 * r.pix + 1];
+        u[0] = ulo.x, u[1] = ulo.y, u[2] = ulo.z, u[3] = ulo.w, u[4] = uhi.x, u[5] = uhi.y, u[6] = uhi.z;
+        if (ba.grad_trans) gT = ba.grad_trans[r.pix];
+    }
+    float Ap[7] = {0, 0, 0, 0, 0, 0, 0}, Tg = 1.0f;
+    const float tn_term = TN * gT;
+    int64_t unused = 0;
+    for (int j = 0; j < v.set_n; ++j) {
+        const int e = ufl(a.refs[v.set_begin + j]);
+        BlockU b;
+        load_block<1>(a.blocks + e, b);
+        float* gg = ufp(ba.grad_grid[e]);
+        float* gp[3] = {ufp(ba.grad_plane[3 * e + 0]), ufp(ba.grad_plane[3 * e + 1]), ufp(ba.grad_plane[3 * e + 2])};
+        const Span sp = block_span<MODE>(a, b, r, hit, w0, w1);
+        if (!__any(sp.ka < sp.kb)) continue;
+        int k = sp.ka;
+        int cur_cell = -1;
+        bool cur_occ = false;
+        for (;;) {
+            float q[3];
+            int cell = 0;
+            const bool have = next_occupied<MODE>(b, r, sp, sp.delta, k, q, cell, cur_cell, cur_occ, unused);
+            if (!__any(have)) break;
+            if (have) {
+                Taps T;
+                sample_taps(b.R, b.Rp, q, T);
+                float raw[8];
+                raw_f32(b, T, raw);
+                const float sigma = __expf(raw[0]);
+                const float alpha = alpha_of(sigma * sp.delta);
+                const float w = Tg * alpha;
+                float vv[7];
+                float uv = 0.0f, us = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 7; ++c) {
+                    vv[c] = sigmoidf_(raw[1 + c]);
+                    Ap[c] = fmaf(w, vv[c], Ap[c]);
+                    uv = fmaf(u[c], vv[c], uv);
+                    us = fmaf(u[c], Af[c] - Ap[c], us);
+                }
+                const float Tn = Tg * (1.0f - alpha);
+                const float dsig = sp.delta * (Tn * uv - us) - sp.delta * tn_term;
+                float draw[8];
+                draw[0] = sigma * dsig;
+#pragma unroll
+                for (int c = 0; c < 7; ++c) draw[1 + c] = w * u[c] * vv[c] * (1.0f - vv[c]);
+                if (gg) {
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        float* dst = gg + (size_t)T.idx[t] * 8;
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) atomicAdd(dst + c, T.w[t] * draw[c]);
+                    }
+                }
+#pragma unroll
+                for (int pl = 0; pl < 3; ++pl) {
+                    if (!gp[pl]) continue;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        float* dst = gp[pl] + (size_t)T.idx[8 + 4 * pl + t] * 8;
+                        const float wt = T.w[8 + 4 * pl + t];
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) atomicAdd(dst + c, wt * draw[c]);
+                    }
+                }
+                Tg = Tn;
+                ++k;
+            }
+        }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void march_bwd_kernel(BwdArgs ba) {
+    const MarchArgs& a = ba.m;
+    const int lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    const int wave = ufl(threadIdx.x >> 6);
+    const int packet = ufl(xcd_packet(waves, wave));
+    if (packet >= a.total_tiles) return;
+    const DevView* V = find_view_by_tile(a.views, a.n_views, packet);
+    march_bwd_packet<MODE>(ba, V, packet - ufl(V->tile_begin), lane);
+}
+
+hipError_t launch_march_bwd(const BwdArgs& a, int waves, hipStream_t s) {
+    if (a.m.total_tiles <= 0) return hipSuccess;
+    dim3 block(64 * waves), grid((a.m.total_tiles + waves - 1) / waves);
+    if (a.m.mode == 1)
+        hipLaunchKernelGGL(march_bwd_kernel<1>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(march_bwd_kernel<0>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace cow
