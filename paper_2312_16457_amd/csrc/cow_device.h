@@ -215,6 +215,7 @@ struct BlockU {
     const uint8_t* occ;
     const int32_t* slot;
     int R, Rp, O;
+    int lR, lRp, lO;                // log2 of the (power-of-two) resolutions
     float lo[3], hi[3];
     float sc[4][kNch];              // uint8 decode scale per texture and channel
     float osum[kNch];               // sum of the four textures' decode offsets
@@ -223,6 +224,8 @@ struct BlockU {
 template <int DT>
 __device__ inline void load_block(const DevBlock* B, BlockU& b) {
     b.R = ufl(B->R), b.Rp = ufl(B->Rp), b.O = ufl(B->O);
+    b.lR = 31 - __builtin_clz((unsigned)b.R), b.lRp = 31 - __builtin_clz((unsigned)b.Rp);
+    b.lO = 31 - __builtin_clz((unsigned)b.O);
     for (int c = 0; c < 3; ++c) b.lo[c] = uff(B->lo[c]), b.hi[c] = uff(B->hi[c]);
     const uint32_t texel = DT == 0 ? 8u : 32u;
     b.tex[0] = tex_rsrc(ufp(B->grid), (uint32_t)b.R * b.R * b.R * texel);
@@ -247,7 +250,7 @@ __device__ inline int occ_cell(const BlockU& b, const float q[3]) {
         k = k < 0 ? 0 : k;
         cell[c] = k > b.O - 1 ? b.O - 1 : k;
     }
-    return (cell[2] * b.O + cell[1]) * b.O + cell[0];
+    return (((cell[2] << b.lO) + cell[1]) << b.lO) + cell[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -277,7 +280,8 @@ struct Taps {
     float w[20];
 };
 
-__device__ inline void sample_taps(int R, int Rp, const float q[3], Taps& T) {
+__device__ inline void sample_taps(const BlockU& b, const float q[3], Taps& T) {
+    const int R = b.R, Rp = b.Rp, lR = b.lR, lRp = b.lRp;
     const Lin gx = lin_taps(q[0], R), gy = lin_taps(q[1], R), gz = lin_taps(q[2], R);
     const Lin px = lin_taps(q[0], Rp), py = lin_taps(q[1], Rp), pz = lin_taps(q[2], Rp);
     const int zi[2] = {gz.i0, gz.i1}, yi[2] = {gy.i0, gy.i1}, xi[2] = {gx.i0, gx.i1};
@@ -286,7 +290,7 @@ __device__ inline void sample_taps(int R, int Rp, const float q[3], Taps& T) {
     for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy) {
-            const int row = (zi[dz] * R + yi[dy]) * R;
+            const int row = ((zi[dz] << lR) + yi[dy]) << lR;
             const float wzy = zw[dz] * yw[dy];
 #pragma unroll
             for (int dx = 0; dx < 2; ++dx) {
@@ -298,7 +302,7 @@ __device__ inline void sample_taps(int R, int Rp, const float q[3], Taps& T) {
     const Lin U[3] = {px, px, py}, V[3] = {py, pz, pz};
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-        const int v0 = V[p].i0 * Rp, v1 = V[p].i1 * Rp;
+        const int v0 = V[p].i0 << lRp, v1 = V[p].i1 << lRp;
         T.idx[8 + 4 * p + 0] = v0 + U[p].i0;
         T.idx[8 + 4 * p + 1] = v0 + U[p].i1;
         T.idx[8 + 4 * p + 2] = v1 + U[p].i0;
@@ -334,7 +338,7 @@ __device__ inline void fold_u8(const uint2 (&t)[N], const float* w, const float*
 template <bool SPARSE>
 __device__ inline void raw_u8(const BlockU& b, const float q[3], int cell, float raw[kNch]) {
     Taps T;
-    sample_taps(b.R, b.Rp, q, T);
+    sample_taps(b, q, T);
     uint2 g[8], p0[4], p1[4], p2[4];
     if (SPARSE) {
         // brick of (s+2)^3 texels around the sample's occupancy cell; texel j

@@ -28,7 +28,7 @@ __device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ra
                 raw_u8<SPARSE>(b, q, cell, raw);
             } else {
                 Taps T;
-                sample_taps(b.R, b.Rp, q, T);
+                sample_taps(b, q, T);
                 raw_f32(b, T, raw);
             }
             const float sigma = __expf(raw[0]);

@@ -64,7 +64,7 @@ __device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, 
             if (!__any(have)) break;
             if (have) {
                 Taps T;
-                sample_taps(b.R, b.Rp, q, T);
+                sample_taps(b, q, T);
                 float raw[8];
                 raw_f32(b, T, raw);
                 const float sigma = __expf(raw[0]);

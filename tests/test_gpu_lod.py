@@ -136,4 +136,3 @@ def test_autotune_invariance(c3):
     assert torch.equal(base["rgb"], tuned["rgb"]) and torch.equal(base["aux"], tuned["aux"])
     r.set_config(8, 4, 0)
     print("autotuned config", cfg)
-EOF
