@@ -40,8 +40,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", action="store_true", help="also time backward (C5) and batched C4")
-    ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU leg)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched measurements")
+    ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU leg, no extras)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a 1 GiB device copy, to scale HBM byte counters")
     return ap.parse_args()
 
 
@@ -52,6 +54,14 @@ def main():
               "inter-GPU exchange in the forward pass, and this build runs on a single MI355X.", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_each_way": src.numel() * 4, "launches": 3}))
+        return
     import __graft_entry__
     __graft_entry__._ensure_built()
     from paper_2312_16457_amd import Renderer, scenegen as sg
@@ -61,7 +71,7 @@ def main():
     view = sg.c2_view()
     params = sg.cityb_params()
     w = sg.xavier_mlp(1)
-    print(f"[bench] scene generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    log(f"scene generated in {time.time() - t0:.1f}s")
     r = Renderer(0)
     r.load_blocks(scene.blocks)
     sel = r.select(view, thresholds=(1e30,), cull=True)
@@ -115,14 +125,42 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
                      "kernel": "march_fwd_kernel<1,0,false>", "kernel_ms": round(k_ms, 4),
+                     "algorithmic_tflop_per_launch": round(FLOPS_PER_SAMPLE * n_eval / 1e12, 4),
                      "flops_per_sample": FLOPS_PER_SAMPLE,
                      "gathered_GBps": round(BYTES_PER_SAMPLE_U8 * n_eval / (k_ms * 1e-3) / 1e9, 1)},
     }
+    log(f"forward {ms:.2f} ms per frame")
     if not args.no_cpu_baseline and not args.profile:
         res["cpu_baseline"] = cpu_baseline(scene, view, sel, params, w)
-    if args.extras and not args.profile:
+        log("cpu baseline done")
+    res["roofline"]["traffic"] = recorded_traffic()
+    if not args.no_extras and not args.profile:
+        del r, out
+        torch.cuda.empty_cache()
         res["extras"] = extras(torch, sg, Renderer)
     print(json.dumps(res), flush=True)
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2312_16457_amd", "csrc")
+    for f in ("cow_internal.h", "cow_device.h", "cow_march.hip"):  # the march kernel's sources
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per march launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (scaled by a 1 GiB copy), or None when the kernel
+    sources changed since those counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_march_fwd_4x4_1080p.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(scene, view, sel, params, w):
@@ -143,12 +181,17 @@ def cpu_baseline(scene, view, sel, params, w):
                                         f"fp64, {dt:.1f}s"}
 
 
+def log(msg, t0=[time.time()]):
+    print(f"[bench {time.time() - t0[0]:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
 def extras(torch, sg, Renderer):
     """Backward throughput on the fp32 4x4 scene (8 views at 800x800) and the
     batched-vs-per-block comparison on the 8x8x3-LOD scene (64 views)."""
     from paper_2312_16457_amd import F_GRAPH, F_PER_BLOCK
     ex = {}
     # backward: 8 x 800^2 views
+    log("extras: generating the fp32 4x4 scene")
     learn, _ = sg.c5_scenes()
     views = sg.c5_views()
     p = sg.cityb_params()
@@ -156,29 +199,69 @@ def extras(torch, sg, Renderer):
     r.load_blocks(learn.blocks)
     sets = [[(b.block_id, 0) for b in learn.blocks]] * len(views)
     mlp = torch.tensor(sg.xavier_mlp(4), device="cuda")
+    log("extras: forward of 8 x 800^2")
     out = r.render(views, sets, p, mlp, counts=True)
     n_eval = int(out["counts"][:, 0].sum().item())
     g = torch.randn_like(out["rgb"]) * 1e-3
+    log(f"extras: first backward ({n_eval} samples)")
     gg = [torch.zeros_like(t[0]) for t in r.textures]
     gp = [[torch.zeros_like(x) for x in t[1]] for t in r.textures]
     gm = torch.zeros(499, device="cuda")
     r.render_backward(views, sets, p, mlp, out["aux"], g, None, gg, gp, gm)
     torch.cuda.synchronize()
+    log("extras: timing backward")
     r.set_timing(True)
     bt = []
-    for _ in range(3):
+    for _ in range(2):
         r.render_backward(views, sets, p, mlp, out["aux"], g, None, gg, gp, gm)
         bt.append(r.last_timing()[1])
     r.set_timing(False)
     t = time.perf_counter()
-    for _ in range(3):
+    for _ in range(2):
         r.render_backward(views, sets, p, mlp, out["aux"], g, None, gg, gp, gm)
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t) * 1e3 / 3
+    ms = (time.perf_counter() - t) * 1e3 / 2
     ex["bwd"] = {"Msamples_per_s": round(n_eval / (ms * 1e-3) / 1e6, 2), "ms": round(ms, 3),
                  "march_bwd_ms": round(float(np.mean(bt)), 3), "evaluated_samples": n_eval,
                  "workload": "4x4 fp32 blocks 128^3 + 3x1024^2, 8 views 800x800"}
-    del r, gg, gp
+    del r, gg, gp, out, g
+    torch.cuda.empty_cache()
+    # batched: 64 views of mixed resolution over the 8x8x3-LOD scene in one
+    # graph-replayed launch vs one launch per view per block
+    log(f"extras: backward {ms:.1f} ms; generating the 8x8x3-LOD scene")
+    scene = sg.c3_scene()
+    views = sg.c4_views()
+    p = sg.cityb_params()
+    r = Renderer(0)
+    r.load_blocks(scene.blocks)
+    sets = [r.select(v, thresholds=(2.0, 4.0, 8.0), cull=True) for v in views]
+    mlp = torch.tensor(sg.xavier_mlp(3), device="cuda")
+    log("extras: counting samples of the 64-view batch")
+    cnt = r.render(views, sets, p, mlp, counts=True)
+    n_eval = int(cnt["counts"][:, 0].sum().item())
+    n_pix = cnt["rgb"].shape[0]
+    del cnt
+    out = r.render(views, sets, p, mlp, want_aux=False)
+    timings = {}
+    for name, flags in (("batched_graph", F_GRAPH), ("per_block_launches", F_PER_BLOCK)):
+        log(f"extras: timing {name}")
+        r.render(views, sets, p, mlp, out=out, flags=flags)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(2):
+            r.render(views, sets, p, mlp, out=out, flags=flags)
+        torch.cuda.synchronize()
+        timings[name] = (time.perf_counter() - t) * 1e3 / 2
+    tb = timings["batched_graph"]
+    ex["batched"] = {"views": len(views), "pixels": n_pix, "evaluated_samples": n_eval,
+                     "blocks_per_view": [min(len(s) for s in sets), max(len(s) for s in sets)],
+                     "launches_per_block_mode": sum(max(len(s), 1) for s in sets) + 1,
+                     "ms_batched": round(tb, 2), "ms_per_block": round(timings["per_block_launches"], 2),
+                     "speedup_vs_per_block": round(timings["per_block_launches"] / tb, 3),
+                     "Msamples_per_s": round(n_eval / (tb * 1e-3) / 1e6, 1),
+                     "fps_1080p_equivalent": round(n_pix / (tb * 1e-3) / 2073600, 2),
+                     "workload": "8x8 blocks x 3 LODs uint8, 64 views {256^2, 800^2, 1280x720, 1920x1080}"}
+    del r, out
     torch.cuda.empty_cache()
     return ex
 

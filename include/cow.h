@@ -127,6 +127,8 @@ typedef struct cow_render_params {
     int32_t n_steps;                /* chord mode */
     float delta;                    /* grid mode step length (world units) */
     int32_t max_steps;              /* grid mode cap, counted from scene entry */
+    float t_min;                    /* early ray termination: a ray stops after the first evaluated
+                                       sample at which its transmittance drops below t_min (0: off) */
     int32_t flags;                  /* COW_F_* */
     int64_t* counts;                /* device [P][2] (evaluated, marched) per pixel, or NULL */
 } cow_render_params;

@@ -52,7 +52,8 @@ class _View(C.Structure):
 
 
 class _Params(C.Structure):
-    _fields_ = [("mode", C.c_int), ("n_steps", C.c_int), ("delta", C.c_float), ("max_steps", C.c_int)]
+    _fields_ = [("mode", C.c_int), ("n_steps", C.c_int), ("delta", C.c_float), ("max_steps", C.c_int),
+                ("t_min", C.c_float)]
 
 
 _lib = None
@@ -101,6 +102,7 @@ def make_view(v):
 def make_params(p):
     s = _Params()
     s.mode, s.n_steps, s.delta, s.max_steps = int(p.mode), int(p.n_steps), float(p.delta), int(p.max_steps)
+    s.t_min = float(getattr(p, "t_min", 0.0))
     return s
 
 

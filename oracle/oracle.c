@@ -432,8 +432,14 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
         }
         eval += buf[s].occupied;
     }
+    /* early ray termination: the ray stops after the first evaluated sample
+     * at which its transmittance falls below t_min (applied in ray order, so
+     * to the monolithic and the merged composite alike) */
+    const double t_min = p->t_min;
+    long n_used = n; /* samples up to and including the terminating one */
     double A[7] = {0}, T = 1.0;
     if (composite == ORC_MONOLITHIC) {
+        eval = 0;
         for (long s = 0; s < n; ++s) {
             if (!buf[s].occupied) continue;
             pt_val pv;
@@ -444,9 +450,44 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
             double w = T * alpha;
             for (int c = 0; c < 7; ++c) A[c] += w * pv.v[c];
             T *= exp(-sd);
+            ++eval;
+            if (t_min > 0.0 && T < t_min) {
+                n_used = s + 1;
+                break;
+            }
+        }
+    } else if (composite == ORC_MERGED) {
+        /* per-block composite (Eq. "volume rendering inside blocks"), merged
+         * front to back in ray order (Eq. "volume rendering across blocks")
+         * with the block transmittance carried as the product of (1 - alpha_i) */
+        eval = 0;
+        long s = 0;
+        int stop = 0;
+        while (s < n && !stop) {
+            const int run = buf[s].set_pos;
+            double Ak[7] = {0}, Tk = 1.0;
+            for (; s < n && buf[s].set_pos == run; ++s) {
+                if (!buf[s].occupied) continue;
+                pt_val pv;
+                double raw[NCH];
+                shade(&blocks[set[run]], buf[s].q, &pv, raw, NULL);
+                double sd = pv.sigma * buf[s].delta;
+                double alpha = -expm1(-sd);
+                double w = Tk * alpha;
+                for (int c = 0; c < 7; ++c) Ak[c] += w * pv.v[c];
+                Tk *= exp(-sd);
+                ++eval;
+                if (t_min > 0.0 && T * Tk < t_min) {
+                    n_used = s + 1;
+                    stop = 1;
+                    break;
+                }
+            }
+            for (int c = 0; c < 7; ++c) A[c] += T * Ak[c];
+            T *= Tk;
         }
     } else {
-        /* per-block composite (Eq. "volume rendering inside blocks") */
+        /* negative controls: per-block composites combined some other way */
         double* Ak = (double*)calloc((size_t)(nrun + 1) * 8, sizeof(double));
         int r = -1;
         for (long s = 0; s < n; ++s) {
@@ -473,12 +514,8 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
                 T *= Ak[q * 8 + 7];
             }
         } else {
-            /* merge front to back (Eq. "volume rendering across blocks"), with
-             * the block transmittance carried as the product of (1 - alpha_i) */
             int* ordr = (int*)malloc(sizeof(int) * (nrun + 1));
-            for (int q = 0; q < nrun; ++q) ordr[q] = q;
-            if (composite == ORC_REVERSED)
-                for (int q = 0; q < nrun; ++q) ordr[q] = nrun - 1 - q;
+            for (int q = 0; q < nrun; ++q) ordr[q] = composite == ORC_REVERSED ? nrun - 1 - q : q;
             if (composite == ORC_BY_ID) /* insertion sort of runs by block id */
                 for (int a = 1; a < nrun; ++a)
                     for (int b = a; b > 0; --b) {
@@ -510,7 +547,7 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
     for (int c = 0; c < 7; ++c) aux[c] = A[c];
     aux[7] = T;
     *ne = eval;
-    *nm = n;
+    *nm = n_used;
     *ook = ordered;
 }
 
@@ -612,6 +649,7 @@ int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const
             T *= exp(-sd);
             ev[m] = s;
             ++m;
+            if (p->t_min > 0.0f && T < (double)p->t_min) break; /* early termination */
         }
         Tb[m] = T;
         /* suffix sums S_i = sum_{j>i} w_j v_j */

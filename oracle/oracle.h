@@ -45,6 +45,7 @@ typedef struct orc_params {
     int n_steps;
     float delta;             /* mode 1 step length */
     int max_steps;           /* mode 1 cap counted from scene entry */
+    float t_min;             /* stop a ray after the first evaluated sample with T < t_min (0: off) */
 } orc_params;
 
 enum {

@@ -56,7 +56,7 @@ class LodPolicy(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_steps", C.c_int32), ("delta", C.c_float), ("max_steps", C.c_int32),
-                ("flags", C.c_int32), ("counts", C.c_void_p)]
+                ("t_min", C.c_float), ("flags", C.c_int32), ("counts", C.c_void_p)]
 
 
 _lib = None
@@ -109,6 +109,7 @@ def make_view(v):
 def make_params(p, flags=0, counts=None):
     s = Params()
     s.mode, s.n_steps, s.delta, s.max_steps = int(p.mode), int(p.n_steps), float(p.delta), int(p.max_steps)
+    s.t_min = float(getattr(p, "t_min", 0.0))
     s.flags = int(flags)
     s.counts = None if counts is None else counts.data_ptr()
     return s

@@ -507,9 +507,9 @@ __device__ inline Span block_span(const MarchArgs& a, const BlockU& b, const Ray
 // Advance k to the next occupied sample of the span (or to kb).  Loads the
 // occupancy byte only when the sample's cell differs from the cached one.
 template <int MODE>
-__device__ inline bool next_occupied(const BlockU& b, const Ray& r, const Span& sp, float delta, int& k,
+__device__ inline bool next_occupied(const BlockU& b, const Ray& r, const Span& sp, int kb, float delta, int& k,
                                      float q[3], int& cell, int& cur_cell, bool& cur_occ, int64_t& marched) {
-    while (k < sp.kb) {
+    while (k < kb) {
         const float t = MODE == 1 ? step_t(k, delta) : sp.tn + ((float)k + 0.5f) * sp.dr;
         bool in = true;
 #pragma unroll

@@ -47,6 +47,7 @@ struct MarchArgs {
     int32_t tile_w, tile_h;    // tile_w * tile_h == 64
     int32_t mode, n_steps, max_steps;
     float delta;
+    float t_min;               // early ray termination threshold (0: off)
     float scene_lo[3], scene_hi[3];
     int32_t use_sparse;
     int32_t blocks_dtype;      // COW_U8 / COW_F32, the same for every block of the launch

@@ -11,16 +11,18 @@ namespace cow {
 // blocks"): Ak = sum_i T_i alpha_i (c_i, f_i), Tk = prod_i (1 - alpha_i).
 // Lanes advance independently through their own spans; a wave iterates
 // while any lane still has an occupied sample.
+// With early termination (t_min > 0) a lane stops after the first sample at
+// which its transmittance T_before * Tk falls below t_min.
 template <int DT, int MODE, bool SPARSE>
 __device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ray& r, const Span& sp,
-                                   float Ak[7], float& Tk, int64_t& n_eval, int64_t& n_march) {
-    int k = sp.ka;
+                                   float T_before, float Ak[7], float& Tk, int64_t& n_eval, int64_t& n_march) {
+    int k = sp.ka, kb = sp.kb;
     int cur_cell = -1;
     bool cur_occ = false;
     for (;;) {
         float q[3];
         int cell = 0;
-        const bool have = next_occupied<MODE>(b, r, sp, sp.delta, k, q, cell, cur_cell, cur_occ, n_march);
+        const bool have = next_occupied<MODE>(b, r, sp, kb, sp.delta, k, q, cell, cur_cell, cur_occ, n_march);
         if (!__any(have)) break;
         if (have) {
             float raw[8];
@@ -39,6 +41,7 @@ __device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ra
             Tk *= 1.0f - alpha;
             ++n_eval;
             ++k;
+            if (T_before * Tk < a.t_min) kb = k;  // early ray termination
         }
     }
 }
@@ -73,10 +76,11 @@ __device__ void march_packet(const MarchArgs& a, const DevView* V, int tile, int
         const int e = ufl(a.refs[v.set_begin + j]);
         BlockU b;
         load_block<DT>(a.blocks + e, b);
-        const Span sp = block_span<MODE>(a, b, r, hit, w0, w1);
+        const bool alive = hit && !(T < a.t_min);  // a terminated ray takes no more samples
+        const Span sp = block_span<MODE>(a, b, r, alive, w0, w1);
         if (!__any(sp.ka < sp.kb)) continue;
         float Ak[7] = {0, 0, 0, 0, 0, 0, 0}, Tk = 1.0f;
-        march_block<DT, MODE, SPARSE>(a, b, r, sp, Ak, Tk, n_eval, n_march);
+        march_block<DT, MODE, SPARSE>(a, b, r, sp, T, Ak, Tk, n_eval, n_march);
         // merge front to back (Eq. "volume rendering across blocks"), with
         // the block's transmittance prod(1 - alpha_i) carried directly
 #pragma unroll

@@ -44,23 +44,31 @@ __device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, 
         if (ba.grad_trans) gT = ba.grad_trans[r.pix];
     }
     float Ap[7] = {0, 0, 0, 0, 0, 0, 0}, Tg = 1.0f;
+    float T_blk = 1.0f;  // merged transmittance before the block, as the forward forms it
     const float tn_term = TN * gT;
     int64_t unused = 0;
     for (int j = 0; j < v.set_n; ++j) {
         const int e = ufl(a.refs[v.set_begin + j]);
         BlockU b;
         load_block<1>(a.blocks + e, b);
-        float* gg = ufp(ba.grad_grid[e]);
-        float* gp[3] = {ufp(ba.grad_plane[3 * e + 0]), ufp(ba.grad_plane[3 * e + 1]), ufp(ba.grad_plane[3 * e + 2])};
-        const Span sp = block_span<MODE>(a, b, r, hit, w0, w1);
+        // gradient tensors as buffer resources: base in scalar registers,
+        // no-return buffer_atomic_add_f32 with a 32-bit offset per lane
+        float* gptr[4] = {ufp(ba.grad_grid[e]), ufp(ba.grad_plane[3 * e + 0]), ufp(ba.grad_plane[3 * e + 1]),
+                          ufp(ba.grad_plane[3 * e + 2])};
+        __amdgpu_buffer_rsrc_t gr[4];
+        gr[0] = tex_rsrc(gptr[0], (uint32_t)b.R * b.R * b.R * 32u);
+        for (int t = 1; t < 4; ++t) gr[t] = tex_rsrc(gptr[t], (uint32_t)b.Rp * b.Rp * 32u);
+        const bool alive = hit && !(T_blk < a.t_min);
+        const Span sp = block_span<MODE>(a, b, r, alive, w0, w1);
         if (!__any(sp.ka < sp.kb)) continue;
-        int k = sp.ka;
+        int k = sp.ka, kb = sp.kb;
         int cur_cell = -1;
         bool cur_occ = false;
+        float Tk = 1.0f;  // block-local transmittance, for the same termination decision as the forward
         for (;;) {
             float q[3];
             int cell = 0;
-            const bool have = next_occupied<MODE>(b, r, sp, sp.delta, k, q, cell, cur_cell, cur_occ, unused);
+            const bool have = next_occupied<MODE>(b, r, sp, kb, sp.delta, k, q, cell, cur_cell, cur_occ, unused);
             if (!__any(have)) break;
             if (have) {
                 Taps T;
@@ -85,29 +93,26 @@ __device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, 
                 draw[0] = sigma * dsig;
 #pragma unroll
                 for (int c = 0; c < 7; ++c) draw[1 + c] = w * u[c] * vv[c] * (1.0f - vv[c]);
-                if (gg) {
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) {
-                        float* dst = gg + (size_t)T.idx[t] * 8;
+                for (int tex = 0; tex < 4; ++tex) {
+                    if (!gptr[tex]) continue;
+                    const int k0 = tex == 0 ? 0 : 4 + 4 * tex, n = tex == 0 ? 8 : 4;
 #pragma unroll
-                        for (int c = 0; c < 8; ++c) atomicAdd(dst + c, T.w[t] * draw[c]);
-                    }
-                }
+                    for (int t = 0; t < n; ++t) {
+                        const int off = T.idx[k0 + t] * 32;
+                        const float wt = T.w[k0 + t];
 #pragma unroll
-                for (int pl = 0; pl < 3; ++pl) {
-                    if (!gp[pl]) continue;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        float* dst = gp[pl] + (size_t)T.idx[8 + 4 * pl + t] * 8;
-                        const float wt = T.w[8 + 4 * pl + t];
-#pragma unroll
-                        for (int c = 0; c < 8; ++c) atomicAdd(dst + c, wt * draw[c]);
+                        for (int c = 0; c < 8; ++c)
+                            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(wt * draw[c], gr[tex], off + 4 * c, 0, 0);
                     }
                 }
                 Tg = Tn;
                 ++k;
+                Tk *= 1.0f - alpha;
+                if (T_blk * Tk < a.t_min) kb = k;  // early ray termination, as in the forward
             }
         }
+        T_blk *= Tk;
     }
 }
 
@@ -117,6 +122,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
     const int lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
     const int wave = ufl(threadIdx.x >> 6);
+    if (a.persistent) {
+        for (;;) {
+            int p = 0;
+            if (lane == 0) p = atomicAdd(a.work_counter, 1);
+            p = ufl(__shfl(p, 0));
+            if (p >= a.total_tiles) break;
+            const DevView* V = find_view_by_tile(a.views, a.n_views, p);
+            march_bwd_packet<MODE>(ba, V, p - ufl(V->tile_begin), lane);
+        }
+        return;
+    }
     const int packet = ufl(xcd_packet(waves, wave));
     if (packet >= a.total_tiles) return;
     const DevView* V = find_view_by_tile(a.views, a.n_views, packet);
@@ -126,6 +142,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
 hipError_t launch_march_bwd(const BwdArgs& a, int waves, hipStream_t s) {
     if (a.m.total_tiles <= 0) return hipSuccess;
     dim3 block(64 * waves), grid((a.m.total_tiles + waves - 1) / waves);
+    if (a.m.persistent) {
+        int dev = 0, cus = 256;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        grid = dim3(cus * (16 / waves));
+    }
     if (a.m.mode == 1)
         hipLaunchKernelGGL(march_bwd_kernel<1>, grid, block, 0, s, a);
     else

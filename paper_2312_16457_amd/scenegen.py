@@ -127,6 +127,7 @@ class RenderParams:
     n_steps: int = 128  # mode A
     delta: float = 1.0 / 512.0  # mode B step
     max_steps: int = 2048  # mode B cap, counted from scene entry
+    t_min: float = 0.0  # early ray termination threshold on the transmittance (0: off)
 
 
 # --------------------------------------------------------------------------

@@ -273,3 +273,34 @@ def test_invalid_arguments_have_no_side_effects(c2, torch_cuda):
     with pytest.raises(CowError) as ei:
         r.render_backward([v], [[(0, 0)]], sg.cityb_params(), mlp, out["aux"], torch.zeros_like(out["rgb"]))
     assert ei.value.status == COW_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_early_termination_parity(torch_cuda, mode):
+    """Opaque variant (density shift 0) with t_min = 1e-5: the kernel stops
+    each ray at the same sample as the oracle (fp32 vs fp64 transmittance may
+    differ by one sample where T meets t_min within rounding; the extra
+    contribution is below t_min)."""
+    torch = torch_cuda
+    scene = sg.make_scene(3, 3, ((16, 64, 8),), sg.U8, blobs_per_block=10, blob_z=(0, 0.3), seed=7, shift=0.0)
+    view = sg.pinhole(37, 29, (1.5, -1.1, 1.3), sg.look_rotation(np.array([1.5, 1.5, 0.1]) - [1.5, -1.1, 1.3]))
+    p = sg.RenderParams(mode=1, t_min=1e-5) if mode == 1 else sg.RenderParams(mode=0, n_steps=128, t_min=1e-5)
+    r = make_renderer(scene.blocks)
+    w = sg.random_mlp(2, 0.7)
+    refs = all_refs(scene)
+    mlp = torch.tensor(w, device="cuda")
+    out = r.render([view], [refs], p, mlp, counts=True)
+    full = r.render([view], [refs], sg.RenderParams(mode=p.mode, n_steps=p.n_steps), mlp, counts=True)
+    torch.cuda.synchronize()
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    ref = O.render(ob, occs, view, list(range(ob.n)), p, w)
+    cnt = out["counts"].cpu().numpy()
+    diff = cnt[:, 0] != ref["n_eval"]
+    assert diff.mean() <= 1e-3 and np.abs(cnt[:, 0] - ref["n_eval"]).max() <= 1
+    assert np.abs(out["rgb"].cpu().numpy() - ref["rgb"]).max() <= TOL
+    assert np.abs(out["trans"].cpu().numpy() - ref["trans"]).max() <= TOL
+    stopped = cnt[:, 0] < full["counts"].cpu().numpy()[:, 0]
+    assert stopped.mean() > 0.2  # the opaque scene does terminate rays early
+    gap = (out["aux"][:, :7] - full["aux"][:, :7]).abs().max(dim=1).values.cpu().numpy()
+    assert (gap <= out["trans"].cpu().numpy() + 1e-6).all()

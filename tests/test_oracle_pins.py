@@ -549,3 +549,38 @@ def test_adjoint_matches_finite_differences():
     arr[idx] = old
     fd = np.sum(g_tr * (Tp - Tm)) / (2 * h)
     assert abs(g[idx] - fd) <= 1e-4 * abs(fd) + 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Early ray termination: the ray stops after the first evaluated sample whose
+# transmittance is below t_min; what it skips is bounded by that transmittance
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", [0, 1])
+def test_early_termination_bound_and_equivalence(mode):
+    scene = tiny_city(shift=0.0, blobs=12, seed=17)  # opaque variant
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    v = tiny_view()
+    w = sg.random_mlp(3)
+    setv = list(range(ob.n))
+    base = sg.RenderParams(mode=1) if mode == 1 else sg.RenderParams(mode=0, n_steps=96)
+    full = O.render(ob, occs, v, setv, base, w)
+    t_min = 1e-3
+    p = sg.RenderParams(mode=base.mode, n_steps=base.n_steps, t_min=t_min)
+    term = O.render(ob, occs, v, setv, p, w)
+    mono = O.render(ob, occs, v, setv, p, w, composite=O.MONOLITHIC)
+    stopped = term["n_eval"] < full["n_eval"]
+    assert stopped.sum() > 50
+    # merged and monolithic composites stop at the same sample
+    assert np.array_equal(term["n_eval"], mono["n_eval"])
+    np.testing.assert_allclose(term["aux"], mono["aux"], atol=1e-12)
+    # a stopped ray ended below t_min; the skipped remainder is at most its T
+    assert (term["trans"][stopped] < t_min).all()
+    assert (term["trans"][~stopped] == full["trans"][~stopped]).all()
+    gap = np.abs(term["aux"][:, :7] - full["aux"][:, :7]).max(axis=1)
+    assert (gap <= term["trans"] + 1e-12).all()
+    # the stopping sample is the first below t_min: a threshold just under the
+    # final T of a stopped ray would have stopped it no later
+    lower = sg.RenderParams(mode=base.mode, n_steps=base.n_steps, t_min=t_min / 4)
+    later = O.render(ob, occs, v, setv, lower, w)
+    assert (later["n_eval"] >= term["n_eval"]).all() and (later["n_eval"] <= full["n_eval"]).all()
