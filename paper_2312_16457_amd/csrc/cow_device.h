@@ -418,12 +418,18 @@ __device__ inline float alpha_of(float x) {
 // packets: which tile of which view a wave marches
 // ---------------------------------------------------------------------------
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-// contiguous range of packets (neighbouring pixels share its L2).
+// Workgroups are dispatched round-robin over the 8 XCDs.  Hand each XCD
+// chunks of 16 consecutive workgroups' packets (neighbouring pixels share its
+// L2), with the chunks interleaved over the XCDs so that every XCD draws from
+// the whole image (a contiguous range per XCD leaves the XCDs of sky rows idle).
 __device__ inline int xcd_packet(int waves, int wave) {
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int x = b & 7, q = nb >> 3, r = nb & 7;
-    const int lb = x * q + (x < r ? x : r) + (b >> 3);
+    const int nb = gridDim.x, b = blockIdx.x, C = 16;
+    const int nfull = nb / (8 * C) * (8 * C);
+    int lb = b;  // tail workgroups keep their own index (still a bijection)
+    if (b < nfull) {
+        const int x = b & 7, j = b >> 3;
+        lb = ((j / C) * 8 + x) * C + (j % C);
+    }
     return lb * waves + wave;
 }
 

@@ -38,10 +38,11 @@ struct GraphEntry {
     hipGraph_t graph = nullptr;
 };
 
-// default launch: persistent waves pulling 16x4 ray packets from one queue
-// (measured fastest on the 4x4-block 1080p frame; the autotuner may change it)
+// default launch: 8x8 ray packets, four waves per workgroup, XCD-chunked
+// packet order (measured fastest on the 4x4-block 1080p frame; the
+// autotuner may change it)
 struct TuneCfg {
-    int tile_w = 16, waves = 4, persistent = 1;
+    int tile_w = 8, waves = 4, persistent = 0;
 };
 
 }  // namespace

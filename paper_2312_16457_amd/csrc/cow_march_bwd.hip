@@ -16,8 +16,55 @@ namespace cow {
 // and each texel receives its interpolation weight times dL/draw.  The
 // merged composite equals the monolithic one over the same sequence
 // (Appendix A), so one running prefix serves all blocks in order.
+// Texel-gradient scatter, one collective step per wave.  Each interpolation
+// tap pair (texels i0 and i0 + 1 along the fastest axis) of a lane is 16
+// contiguous floats (8 channels each) when i1 = i0 + 1.  The lanes stage
+// their pairs in LDS and read them back transposed, so that one atomic
+// instruction covers four lanes' 64-byte runs instead of 64 scattered texels:
+// far fewer cache-line requests for the L2 atomic units.
+struct ScatterLds {
+    float v[64][20];  // 16 values, byte offsets of the two texels (-1: none), pad
+};
+
+__device__ inline void scatter_pairs(ScatterLds& L, int lane, const Taps& T, const float draw[8],
+                                     float* const gptr[4], const __amdgpu_buffer_rsrc_t gr[4], bool have) {
+#pragma unroll
+    for (int pr = 0; pr < 10; ++pr) {
+        const int tex = pr < 4 ? 0 : 1 + (pr - 4) / 2;
+        if (!gptr[tex]) continue;
+        const int ka = 2 * pr, kb2 = 2 * pr + 1;  // taps 2pr, 2pr+1 differ by one texel along x / u
+        float* row = L.v[lane];
+        if (have) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                row[c] = T.w[ka] * draw[c];
+                row[8 + c] = T.w[kb2] * draw[c];
+            }
+            row[16] = __int_as_float(T.idx[ka] * 32);
+            row[17] = __int_as_float(T.idx[kb2] * 32);
+        } else {
+            row[16] = __int_as_float(-1);
+            row[17] = __int_as_float(-1);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int e = lane & 15, sub = lane >> 4;
+#pragma unroll 4
+        for (int j = 0; j < 16; ++j) {
+            const int src = 4 * j + sub;
+            const int off = __float_as_int(L.v[src][16 + (e >> 3)]);
+            const float val = L.v[src][e];
+            if (off >= 0) __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gr[tex], off + 4 * (e & 7), 0, 0);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 template <int MODE>
-__device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, int lane) {
+__device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, int lane, ScatterLds& lds) {
     const MarchArgs& a = ba.m;
     ViewU v;
     load_view(V, v);
@@ -70,8 +117,9 @@ __device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, 
             int cell = 0;
             const bool have = next_occupied<MODE>(b, r, sp, kb, sp.delta, k, q, cell, cur_cell, cur_occ, unused);
             if (!__any(have)) break;
+            Taps T;
+            float draw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             if (have) {
-                Taps T;
                 sample_taps(b, q, T);
                 float raw[8];
                 raw_f32(b, T, raw);
@@ -89,28 +137,16 @@ __device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, 
                 }
                 const float Tn = Tg * (1.0f - alpha);
                 const float dsig = sp.delta * (Tn * uv - us) - sp.delta * tn_term;
-                float draw[8];
                 draw[0] = sigma * dsig;
 #pragma unroll
                 for (int c = 0; c < 7; ++c) draw[1 + c] = w * u[c] * vv[c] * (1.0f - vv[c]);
-#pragma unroll
-                for (int tex = 0; tex < 4; ++tex) {
-                    if (!gptr[tex]) continue;
-                    const int k0 = tex == 0 ? 0 : 4 + 4 * tex, n = tex == 0 ? 8 : 4;
-#pragma unroll
-                    for (int t = 0; t < n; ++t) {
-                        const int off = T.idx[k0 + t] * 32;
-                        const float wt = T.w[k0 + t];
-#pragma unroll
-                        for (int c = 0; c < 8; ++c)
-                            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(wt * draw[c], gr[tex], off + 4 * c, 0, 0);
-                    }
-                }
                 Tg = Tn;
                 ++k;
                 Tk *= 1.0f - alpha;
                 if (T_blk * Tk < a.t_min) kb = k;  // early ray termination, as in the forward
             }
+            // collective over the wave: lanes without a sample take part with nothing to add
+            scatter_pairs(lds, lane, T, draw, gptr, gr, have);
         }
         T_blk *= Tk;
     }
@@ -119,6 +155,7 @@ __device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, 
 template <int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void march_bwd_kernel(BwdArgs ba) {
     const MarchArgs& a = ba.m;
+    __shared__ ScatterLds lds[4];
     const int lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
     const int wave = ufl(threadIdx.x >> 6);
@@ -129,14 +166,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
             p = ufl(__shfl(p, 0));
             if (p >= a.total_tiles) break;
             const DevView* V = find_view_by_tile(a.views, a.n_views, p);
-            march_bwd_packet<MODE>(ba, V, p - ufl(V->tile_begin), lane);
+            march_bwd_packet<MODE>(ba, V, p - ufl(V->tile_begin), lane, lds[wave]);
         }
         return;
     }
     const int packet = ufl(xcd_packet(waves, wave));
     if (packet >= a.total_tiles) return;
     const DevView* V = find_view_by_tile(a.views, a.n_views, packet);
-    march_bwd_packet<MODE>(ba, V, packet - ufl(V->tile_begin), lane);
+    march_bwd_packet<MODE>(ba, V, packet - ufl(V->tile_begin), lane, lds[wave]);
 }
 
 hipError_t launch_march_bwd(const BwdArgs& a, int waves, hipStream_t s) {
