@@ -75,8 +75,13 @@ def lib():
         L.orc_ray_blocks.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(_View), vp, C.c_int,
                                      C.POINTER(_Params), C.c_int, C.c_int, vp, C.c_int]
         L.orc_adjoint.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), C.POINTER(_View),
-                                  vp, C.c_int, C.POINTER(_Params), vp, vp, C.c_int, vp, vp,
+                                  vp, C.c_int, C.POINTER(_Params), vp, vp, C.c_int, vp, vp, vp,
                                   C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), vp]
+        L.orc_opacity.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), C.POINTER(_View),
+                                  vp, C.c_int, C.POINTER(_Params), vp, C.c_int, vp]
+        L.orc_sparsity.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), vp, C.c_int, vp,
+                                   C.c_int, C.c_double, C.c_double, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]
+        L.orc_sparsity.restype = C.c_double
         L.orc_select.argtypes = [C.POINTER(_View), C.c_int, vp, vp, vp, vp, vp, vp, C.c_int, C.c_int,
                                  vp, C.c_int]
         L.orc_mlp.argtypes = [vp, vp, vp]
@@ -216,7 +221,43 @@ def ray_blocks(ob, view, set_idx, params, i, j, cap=128):
     return out[:m]
 
 
-def adjoint(ob, occs, view, set_idx, params, mlp, pix, grad_rgb, grad_trans=None):
+def _grad_arrays(ob, idx):
+    grads = {}
+    gg = (C.c_void_p * ob.n)()
+    gp = (C.c_void_p * (3 * ob.n))()
+    for k in idx:
+        b = ob.blocks[k]
+        g = np.zeros(b.grid.shape, np.float64)
+        ps = [np.zeros(p.shape, np.float64) for p in b.planes]
+        grads[k] = (g, ps)
+        gg[k] = g.ctypes.data
+        for i in range(3):
+            gp[3 * k + i] = ps[i].ctypes.data
+    return grads, gg, gp
+
+
+def opacity(ob, occs, view, set_idx, params, pix):
+    """Per-ray block-opacity entropy."""
+    pix = np.ascontiguousarray(pix, np.int32)
+    setv = np.ascontiguousarray(set_idx, np.int32)
+    out = np.zeros(pix.shape[0])
+    vs, ps = make_view(view), make_params(params)
+    lib().orc_opacity(ob.arr, ob.n, _occ_ptrs(ob, occs), C.byref(vs), _ptr(setv), len(setv), C.byref(ps),
+                      _ptr(pix), pix.shape[0], _ptr(out))
+    return out
+
+
+def sparsity(ob, occs, set_idx, pts, delta, weight=1.0):
+    """L1 opacity sparsity at points; returns (loss, {block: (grad_grid, [grad_planes])})."""
+    setv = np.ascontiguousarray(set_idx, np.int32)
+    pts = np.ascontiguousarray(pts, np.float32)
+    grads, gg, gp = _grad_arrays(ob, set(int(s) for s in setv))
+    loss = lib().orc_sparsity(ob.arr, ob.n, _occ_ptrs(ob, occs), _ptr(setv), len(setv), _ptr(pts), pts.shape[0],
+                              float(delta), float(weight), gg, gp)
+    return loss, grads
+
+
+def adjoint(ob, occs, view, set_idx, params, mlp, pix, grad_rgb, grad_trans=None, w_opacity=None):
     """fp64 adjoint; returns ({block index: (grad_grid, [grad_planes])}, grad_mlp)."""
     L = lib()
     pix = np.ascontiguousarray(pix, np.int32)
@@ -235,10 +276,11 @@ def adjoint(ob, occs, view, set_idx, params, mlp, pix, grad_rgb, grad_trans=None
     gm = np.zeros(499, np.float64)
     gr = np.ascontiguousarray(grad_rgb, np.float64)
     gt = None if grad_trans is None else np.ascontiguousarray(grad_trans, np.float64)
+    wo = None if w_opacity is None else np.ascontiguousarray(w_opacity, np.float64)
     vs, ps_ = make_view(view), make_params(params)
     r = L.orc_adjoint(ob.arr, ob.n, _occ_ptrs(ob, occs), C.byref(vs), _ptr(setv), len(setv),
                       C.byref(ps_), _ptr(np.ascontiguousarray(mlp, np.float64)), _ptr(pix), pix.shape[0],
-                      _ptr(gr), _ptr(gt), gg, gp, _ptr(gm))
+                      _ptr(gr), _ptr(gt), _ptr(wo), gg, gp, _ptr(gm))
     if r != 0:
         raise ValueError("adjoint needs float blocks")
     return grads, gm

@@ -614,11 +614,22 @@ int orc_ray_blocks(const orc_block* blocks, int nblocks, const orc_view* v, cons
 /* Adjoint (fp64)                                                          */
 /* ---------------------------------------------------------------------- */
 
+/* entropy of a block's opacity and its derivative in the opacity */
+static const double OPAC_EPS = 1e-6;
+static double opac_h(double alpha) {
+    double a = alpha < OPAC_EPS ? OPAC_EPS : (alpha > 1.0 - OPAC_EPS ? 1.0 - OPAC_EPS : alpha);
+    return -(a * log(a) + (1.0 - a) * log(1.0 - a));
+}
+static double opac_dh(double alpha) {
+    if (!(alpha > OPAC_EPS && alpha < 1.0 - OPAC_EPS)) return 0.0; /* clamped */
+    return log((1.0 - alpha) / alpha);
+}
+
 int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
                 const orc_view* v, const int* set, int nset, const orc_params* p,
                 const double* mlp, const int* pix, int npix, const double* grad_rgb,
-                const double* grad_trans, double* const* grad_grid, double* const* grad_plane,
-                double* grad_mlp) {
+                const double* grad_trans, const double* w_opacity, double* const* grad_grid,
+                double* const* grad_plane, double* grad_mlp) {
     for (int s = 0; s < nset; ++s)
         if (blocks[set[s]].dtype != ORC_F64) return -1;
     long cap = sample_cap(p, nset);
@@ -652,6 +663,24 @@ int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const
             if (p->t_min > 0.0f && T < (double)p->t_min) break; /* early termination */
         }
         Tb[m] = T;
+        /* opacity term: per block (run) T^k over its evaluated samples;
+         * d/dsigma_i of -h(1 - T^k) weight = w dh/dalpha delta_i T^k */
+        double* opg = (double*)calloc((size_t)(m + 1), sizeof(double));
+        if (w_opacity && w_opacity[q] != 0.0) {
+            long s0 = 0;
+            while (s0 < m) {
+                long s1 = s0;
+                int run = buf[ev[s0]].set_pos;
+                double Tk = 1.0;
+                while (s1 < m && buf[ev[s1]].set_pos == run) {
+                    Tk *= exp(-pv[s1].sigma * buf[ev[s1]].delta);
+                    ++s1;
+                }
+                double g = w_opacity[q] * opac_dh(1.0 - Tk);
+                for (long s = s0; s < s1; ++s) opg[s] = g * buf[ev[s]].delta * Tk;
+                s0 = s1;
+            }
+        }
         /* suffix sums S_i = sum_{j>i} w_j v_j */
         for (int c = 0; c < 7; ++c) suf[7 * m + c] = 0.0;
         if (m > 0)
@@ -706,7 +735,7 @@ int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const
                 uv += u[c] * pv[s].v[c];
                 us += u[c] * suf[7 * s + c];
             }
-            double dsig = delta * (Tb[s + 1] * uv - us) - delta * T * gT;
+            double dsig = delta * (Tb[s + 1] * uv - us) - delta * T * gT + opg[s];
             double draw[NCH];
             draw[0] = pv[s].sigma * dsig;
             for (int c = 0; c < 7; ++c) {
@@ -721,6 +750,7 @@ int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const
                 for (int ch = 0; ch < NCH; ++ch) dst[tp->idx * NCH + ch] += tp->w * draw[ch];
             }
         }
+        free(opg);
     }
     free(buf);
     free(pv);
@@ -731,6 +761,78 @@ int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const
     free(ev);
     (void)nblocks;
     return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Regularisers of the training objective (Sec. 4.3)                       */
+/* ---------------------------------------------------------------------- */
+
+int orc_opacity(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
+                const orc_view* v, const int* set, int nset, const orc_params* p,
+                const int* pix, int npix, double* loss) {
+    long cap = sample_cap(p, nset);
+    sample* buf = (sample*)malloc(sizeof(sample) * cap);
+    for (int q = 0; q < npix; ++q) {
+        float d[3];
+        long n = enumerate(blocks, nblocks, occ, v, set, nset, p, pix[2 * q], pix[2 * q + 1], buf, cap, d);
+        double L = 0.0, T = 1.0;
+        long s = 0;
+        int stop = 0;
+        while (s < n && !stop) {
+            int run = buf[s].set_pos;
+            double Tk = 1.0;
+            for (; s < n && buf[s].set_pos == run; ++s) {
+                if (!buf[s].occupied) continue;
+                pt_val pv;
+                double raw[NCH];
+                shade(&blocks[set[run]], buf[s].q, &pv, raw, NULL);
+                Tk *= exp(-pv.sigma * buf[s].delta);
+                if (p->t_min > 0.0f && T * Tk < (double)p->t_min) {
+                    stop = 1;
+                    break;
+                }
+            }
+            L += opac_h(1.0 - Tk);
+            T *= Tk;
+        }
+        loss[q] = L;
+    }
+    free(buf);
+    return 0;
+}
+
+double orc_sparsity(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
+                    const int* set, int nset, const float* pts, int n, double delta, double weight,
+                    double* const* grad_grid, double* const* grad_plane) {
+    double loss = 0.0;
+    tap taps[20];
+    for (int i = 0; i < n; ++i) {
+        const float* pt = pts + 3 * i;
+        int s_hit = -1;
+        for (int s = 0; s < nset; ++s)
+            if (inside(pt, blocks[set[s]].lo, blocks[set[s]].hi)) {
+                s_hit = s;
+                break;
+            }
+        if (s_hit < 0) continue;
+        const orc_block* b = &blocks[set[s_hit]];
+        float q[3];
+        int cell = occ_cell(b, pt, q);
+        if (!occ[set[s_hit]][cell]) continue; /* density is zero in unoccupied cells */
+        double raw[NCH];
+        eval_raw(b, q, raw, taps);
+        double sigma = exp(raw[0]);
+        double alpha = -expm1(-sigma * delta);
+        loss += weight / n * alpha;
+        double draw0 = weight / n * delta * exp(-sigma * delta) * sigma;
+        int bi = set[s_hit];
+        for (int t = 0; t < 20; ++t) {
+            double* dst = taps[t].tex == 0 ? grad_grid[bi] : grad_plane[3 * bi + taps[t].tex - 1];
+            if (dst) dst[taps[t].idx * NCH] += taps[t].w * draw0;
+        }
+    }
+    (void)nblocks;
+    return loss;
 }
 
 /* ---------------------------------------------------------------------- */

@@ -76,14 +76,32 @@ int orc_render(const orc_block* blocks, int nblocks, const unsigned char* const*
 int orc_ray_blocks(const orc_block* blocks, int nblocks, const orc_view* v, const int* set,
                    int nset, const orc_params* p, int i, int j, int* out, int cap);
 
-/* fp64 adjoint.  grad_rgb[npix*3], grad_trans[npix] (nullable).  Gradients are
- * ACCUMULATED into grad_grid[b] / grad_plane[3b+k] (NULL entries skipped) for
- * every b in the set and into grad_mlp[499] (nullable).  fp64 blocks only. */
+/* fp64 adjoint.  grad_rgb[npix*3], grad_trans[npix] and w_opacity[npix] (the
+ * weight of each ray's block-opacity entropy, see orc_opacity) are nullable.
+ * Gradients are ACCUMULATED into grad_grid[b] / grad_plane[3b+k] (NULL
+ * entries skipped) for every b in the set and into grad_mlp[499] (nullable).
+ * fp64 blocks only. */
 int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
                 const orc_view* v, const int* set, int nset, const orc_params* p,
                 const double* mlp, const int* pix, int npix, const double* grad_rgb,
-                const double* grad_trans, double* const* grad_grid, double* const* grad_plane,
-                double* grad_mlp);
+                const double* grad_trans, const double* w_opacity, double* const* grad_grid,
+                double* const* grad_plane, double* grad_mlp);
+
+/* Block-opacity entropy of each ray (Eq. "opacity loss"):
+ * -sum_k (a log a + (1 - a) log(1 - a)), a = clamp(1 - T^k, 1e-6, 1 - 1e-6),
+ * over the blocks in which the ray marches at least one sample. */
+int orc_opacity(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
+                const orc_view* v, const int* set, int nset, const orc_params* p,
+                const int* pix, int npix, double* loss);
+
+/* L1 sparsity of opacity at given points (Eq. "sparse loss"):
+ * loss = weight / n * sum_i alpha(p_i), alpha = 1 - exp(-sigma(p_i) delta),
+ * sigma the render's density (zero in unoccupied cells, zero outside the
+ * set's blocks).  Returns the loss; accumulates its gradient into the
+ * density channel of grad_grid / grad_plane (fp64 blocks, NULL skipped). */
+double orc_sparsity(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
+                    const int* set, int nset, const float* pts, int n, double delta, double weight,
+                    double* const* grad_grid, double* const* grad_plane);
 
 /* Per-view block selection: LOD by eye-to-centre distance, frustum culling,
  * front-to-back order by xy distance.  Inputs per distinct block entry k:

@@ -584,3 +584,112 @@ def test_early_termination_bound_and_equivalence(mode):
     lower = sg.RenderParams(mode=base.mode, n_steps=base.n_steps, t_min=t_min / 4)
     later = O.render(ob, occs, v, setv, lower, w)
     assert (later["n_eval"] >= term["n_eval"]).all() and (later["n_eval"] <= full["n_eval"]).all()
+
+
+# ---------------------------------------------------------------------------
+# Regularisers (Sec. 4.3): the opacity loss of homogeneous blocks is the
+# binary entropy of exp(-sigma L); its gradient and the sparsity loss's match
+# finite differences; the sparsity loss of a homogeneous block is 1 - exp(-sigma delta)
+# ---------------------------------------------------------------------------
+def bernoulli_entropy(a):
+    from scipy.special import entr
+    return float(entr(a) + entr(1.0 - a))
+
+
+def test_opacity_closed_form_three_blocks():
+    sigmas = [0.7, 2.0, 30.0]  # the last is fully opaque: its entropy is the clamp's
+    blocks = [sg.homogeneous_block(sigma=s, block_id=k, origin=(k, 0, 0)) for k, s in enumerate(sigmas)]
+    ob = O.OracleScene(blocks)
+    occs = [O.occupancy(ob, k) for k in range(3)]
+    v = axis_view((-0.25, 0.5, 0.5), (1.0, 0.0, 0.0))
+    L = O.opacity(ob, occs, v, [0, 1, 2], sg.RenderParams(mode=1), O.pixels_of(v))[0]
+    want = 0.0
+    for b in blocks:
+        s, _, _ = stored_constants(b)
+        a = 1.0 - math.exp(-s)  # chord 1
+        want += bernoulli_entropy(min(max(a, 1e-6), 1 - 1e-6))
+    assert abs(L - want) < 1e-12
+    # the entropy vanishes only at the clamp: an opaque block contributes ~1.5e-5
+    assert bernoulli_entropy(1 - 1e-6) < 2e-5 and L > bernoulli_entropy(1 - math.exp(-0.7))
+
+
+def test_opacity_gradient_matches_finite_differences():
+    scene = tiny_city(nb=2, lods=((8, 16, 4),), shift=0.5, blobs=8, seed=21)
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    v = tiny_view(10, 8, eye=(1.0, -0.8, 1.1), target=(1.0, 1.0, 0.15))
+    p = sg.RenderParams(mode=1, delta=1.0 / 128, max_steps=4096)
+    w = kink_free_mlp(3)
+    setv = list(range(ob.n))
+    pix = O.pixels_of(v)
+    wo = np.random.default_rng(7).uniform(0.5, 1.5, len(pix))
+    L0 = O.opacity(ob, occs, v, setv, p, pix)
+    assert (L0 > 0.05).sum() > 10  # semi-transparent blocks are present
+    grads, gm = O.adjoint(ob, occs, v, setv, p, w, pix, np.zeros((len(pix), 3)), None, wo)
+    assert not gm.any()  # the opacity loss does not touch the MLP
+    gmax = max(np.abs(g).max() for g, _ in grads.values())
+    rng = np.random.default_rng(8)
+    h = 1e-4
+    checked = 0
+    for k, (g, ps) in grads.items():
+        for arr_i, arr_g in enumerate([g] + ps):
+            nz = np.argwhere(np.abs(arr_g) > 1e-3 * gmax)
+            if len(nz) == 0:
+                continue
+            assert not np.abs(arr_g[..., 1:]).any()  # density channel only
+            for _ in range(2):
+                idx = tuple(nz[rng.integers(len(nz))])
+                fg, fps = ob.f64[k]
+                arr = fg if arr_i == 0 else fps[arr_i - 1]
+                old = arr[idx]
+                arr[idx] = old + h
+                Lp = np.sum(wo * O.opacity(ob, occs, v, setv, p, pix))
+                arr[idx] = old - h
+                Lm = np.sum(wo * O.opacity(ob, occs, v, setv, p, pix))
+                arr[idx] = old
+                fd = (Lp - Lm) / (2 * h)
+                assert abs(arr_g[idx] - fd) <= 1e-4 * abs(fd) + 1e-6 * gmax, (k, arr_i, idx, arr_g[idx], fd)
+                checked += 1
+    assert checked >= 12
+
+
+def test_sparsity_closed_form_and_gradient():
+    b = sg.homogeneous_block(sigma=5.0)
+    ob = O.OracleScene([b])
+    occ = O.occupancy(ob, 0)
+    rng = np.random.default_rng(9)
+    inside = rng.uniform(0.0, 1.0, (300, 3)).astype(np.float32)
+    outside = rng.uniform(1.0, 2.0, (100, 3)).astype(np.float32)
+    pts = np.concatenate([inside, outside])
+    delta = 1.0 / 512
+    L, _ = O.sparsity(ob, [occ], [0], pts, delta, weight=2.0)
+    s, _, _ = stored_constants(b)
+    assert abs(L - 2.0 * 300 / 400 * -math.expm1(-s * delta)) < 1e-15
+    # gradient against finite differences on a textured scene
+    scene = tiny_city(nb=2, lods=((8, 16, 4),), shift=0.5, blobs=8, seed=23)
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    pts = np.concatenate([rng.uniform(0, 2, (2000, 2)), rng.uniform(0, 1, (2000, 1))], 1).astype(np.float32)
+    setv = list(range(ob.n))
+    L, grads = O.sparsity(ob, occs, setv, pts, 1.0 / 64, weight=1.0)
+    assert L > 0
+    gmax = max(max(np.abs(g).max(), max(np.abs(q).max() for q in ps)) for g, ps in grads.values())
+    h = 1e-4
+    checked = 0
+    for k, (g, ps) in grads.items():
+        for arr_i, arr_g in enumerate([g] + ps):
+            assert not np.abs(arr_g[..., 1:]).any()
+            nz = np.argwhere(np.abs(arr_g) > 1e-3 * gmax)
+            idx = tuple(nz[rng.integers(len(nz))])
+            fg, fps = ob.f64[k]
+            arr = fg if arr_i == 0 else fps[arr_i - 1]
+            old = arr[idx]
+            arr[idx] = old + h
+            Lp, _ = O.sparsity(ob, occs, setv, pts, 1.0 / 64)
+            arr[idx] = old - h
+            Lm, _ = O.sparsity(ob, occs, setv, pts, 1.0 / 64)
+            arr[idx] = old
+            fd = (Lp - Lm) / (2 * h)
+            assert abs(arr_g[idx] - fd) <= 1e-5 * abs(fd) + 1e-8 * gmax, (k, arr_i, idx, arr_g[idx], fd)
+            checked += 1
+    assert checked == 4 * ob.n
