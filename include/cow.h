@@ -131,6 +131,12 @@ typedef struct cow_render_params {
                                        sample at which its transmittance drops below t_min (0: off) */
     int32_t flags;                  /* COW_F_* */
     int64_t* counts;                /* device [P][2] (evaluated, marched) per pixel, or NULL */
+    /* Opacity regulariser (Sec. 4.3, Eq. "opacity loss"): the entropy
+     * -(a log a + (1 - a) log(1 - a)) of each block's opacity a = 1 - T^k,
+     * with a clamped to [1e-6, 1 - 1e-6], summed over the blocks in which the
+     * ray marches at least one sample (up to its early termination). */
+    float* opacity;                 /* cow_render: device [P] per-ray entropy sum, or NULL */
+    const float* opacity_weight;    /* cow_render_backward: device [P] dL/d(that sum), or NULL */
 } cow_render_params;
 
 /* Create a context bound to HIP device `device` (host state only). */
@@ -183,7 +189,8 @@ COW_API cow_status cow_render(cow_ctx* ctx, const cow_view* views, int n_views, 
                       float* aux, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Adjoint of cow_render for COW_F32 blocks.  grad_rgb [P][3] and grad_trans
- * [P] (nullable) are dL/d outputs; aux is the forward's aux.  Gradients are
+ * [P] (nullable) are dL/d outputs, as is params->opacity_weight (nullable);
+ * aux is the forward's aux.  Gradients are
  * ACCUMULATED into grad_grid[e] / grad_plane[3e + k] for loaded entry e (in
  * load order; NULL entries skipped) and into grad_mlp[499]; fp32 atomics, so
  * summation order varies run to run.  Per-ray samples are recomputed. */
@@ -193,6 +200,22 @@ COW_API cow_status cow_render_backward(cow_ctx* ctx, const cow_view* views, int 
                                const float* grad_trans, float* const* grad_grid,
                                float* const* grad_plane, float* grad_mlp, void* ws,
                                size_t ws_bytes, hipStream_t stream);
+
+/* Sparsity regulariser (Sec. 4.3, Eq. "sparse loss"): the mean opacity
+ * alpha_i = 1 - exp(-sigma(p_i) delta) at n points, times weight.  sigma is
+ * the render's density: the point takes the first entry of `set` whose
+ * half-open box holds it, and is zero in an unoccupied cell or outside every
+ * entry.  pts: device float [n][3] (world).  alpha: device float [n] or NULL.
+ * loss: device float [1]; weight / n * sum alpha_i is ADDED to it (fp32
+ * atomics, order unspecified).  grad_grid / grad_plane: host tables of device
+ * pointers per loaded entry as in cow_render_backward, or NULL for no
+ * gradient; only the density channel (0) receives gradient, accumulated;
+ * gradients need COW_F32 entries.  ws: device workspace of at least
+ * 256 + 4 * set->n + 32 * (loaded entries) bytes (the backward workspace of
+ * cow_query_workspace always suffices). */
+COW_API cow_status cow_sparsity(cow_ctx* ctx, const cow_block_set* set, const float* pts, int64_t n, float delta,
+                                float weight, float* alpha, float* loss, float* const* grad_grid,
+                                float* const* grad_plane, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Time the launch configurations (ray-packet shape, waves per workgroup,
  * persistent or not) on this workload and keep the fastest for later

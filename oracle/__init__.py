@@ -80,7 +80,8 @@ def lib():
         L.orc_opacity.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), C.POINTER(_View),
                                   vp, C.c_int, C.POINTER(_Params), vp, C.c_int, vp]
         L.orc_sparsity.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), vp, C.c_int, vp,
-                                   C.c_int, C.c_double, C.c_double, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]
+                                   C.c_int, C.c_double, C.c_double, vp, C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_void_p)]
         L.orc_sparsity.restype = C.c_double
         L.orc_select.argtypes = [C.POINTER(_View), C.c_int, vp, vp, vp, vp, vp, vp, C.c_int, C.c_int,
                                  vp, C.c_int]
@@ -247,14 +248,20 @@ def opacity(ob, occs, view, set_idx, params, pix):
     return out
 
 
-def sparsity(ob, occs, set_idx, pts, delta, weight=1.0):
-    """L1 opacity sparsity at points; returns (loss, {block: (grad_grid, [grad_planes])})."""
+def sparsity(ob, occs, set_idx, pts, delta, weight=1.0, want_alpha=False, want_grad=True):
+    """L1 opacity sparsity at points; returns (loss, {block: (grad_grid,
+    [grad_planes])}), plus alpha per point with want_alpha.  Gradients need
+    fp64 blocks (want_grad=False for others)."""
     setv = np.ascontiguousarray(set_idx, np.int32)
     pts = np.ascontiguousarray(pts, np.float32)
-    grads, gg, gp = _grad_arrays(ob, set(int(s) for s in setv))
+    alpha = np.zeros(pts.shape[0])
+    if want_grad:
+        grads, gg, gp = _grad_arrays(ob, set(int(s) for s in setv))
+    else:
+        grads, gg, gp = {}, None, None
     loss = lib().orc_sparsity(ob.arr, ob.n, _occ_ptrs(ob, occs), _ptr(setv), len(setv), _ptr(pts), pts.shape[0],
-                              float(delta), float(weight), gg, gp)
-    return loss, grads
+                              float(delta), float(weight), _ptr(alpha), gg, gp)
+    return (loss, grads, alpha) if want_alpha else (loss, grads)
 
 
 def adjoint(ob, occs, view, set_idx, params, mlp, pix, grad_rgb, grad_trans=None, w_opacity=None):

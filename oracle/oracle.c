@@ -803,11 +803,12 @@ int orc_opacity(const orc_block* blocks, int nblocks, const unsigned char* const
 
 double orc_sparsity(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
                     const int* set, int nset, const float* pts, int n, double delta, double weight,
-                    double* const* grad_grid, double* const* grad_plane) {
+                    double* alpha_out, double* const* grad_grid, double* const* grad_plane) {
     double loss = 0.0;
     tap taps[20];
     for (int i = 0; i < n; ++i) {
         const float* pt = pts + 3 * i;
+        if (alpha_out) alpha_out[i] = 0.0;
         int s_hit = -1;
         for (int s = 0; s < nset; ++s)
             if (inside(pt, blocks[set[s]].lo, blocks[set[s]].hi)) {
@@ -823,11 +824,13 @@ double orc_sparsity(const orc_block* blocks, int nblocks, const unsigned char* c
         eval_raw(b, q, raw, taps);
         double sigma = exp(raw[0]);
         double alpha = -expm1(-sigma * delta);
+        if (alpha_out) alpha_out[i] = alpha;
         loss += weight / n * alpha;
         double draw0 = weight / n * delta * exp(-sigma * delta) * sigma;
         int bi = set[s_hit];
         for (int t = 0; t < 20; ++t) {
-            double* dst = taps[t].tex == 0 ? grad_grid[bi] : grad_plane[3 * bi + taps[t].tex - 1];
+            double* const* tab = taps[t].tex == 0 ? grad_grid : grad_plane;
+            double* dst = !tab ? NULL : (taps[t].tex == 0 ? tab[bi] : tab[3 * bi + taps[t].tex - 1]);
             if (dst) dst[taps[t].idx * NCH] += taps[t].w * draw0;
         }
     }

@@ -97,11 +97,13 @@ int orc_opacity(const orc_block* blocks, int nblocks, const unsigned char* const
 /* L1 sparsity of opacity at given points (Eq. "sparse loss"):
  * loss = weight / n * sum_i alpha(p_i), alpha = 1 - exp(-sigma(p_i) delta),
  * sigma the render's density (zero in unoccupied cells, zero outside the
- * set's blocks).  Returns the loss; accumulates its gradient into the
- * density channel of grad_grid / grad_plane (fp64 blocks, NULL skipped). */
+ * set's blocks; a point takes the first entry of the set whose half-open
+ * box holds it).  Returns the loss; writes alpha[n] (nullable); accumulates
+ * its gradient into the density channel of grad_grid / grad_plane (fp64
+ * blocks, NULL skipped). */
 double orc_sparsity(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
                     const int* set, int nset, const float* pts, int n, double delta, double weight,
-                    double* const* grad_grid, double* const* grad_plane);
+                    double* alpha, double* const* grad_grid, double* const* grad_plane);
 
 /* Per-view block selection: LOD by eye-to-centre distance, frustum culling,
  * front-to-back order by xy distance.  Inputs per distinct block entry k:

@@ -18,8 +18,8 @@ F_NONE, F_GRAPH, F_PERSISTENT, F_PER_BLOCK, F_SPARSE = 0, 1, 2, 4, 8
 
 EXPORTS = ["cow_create", "cow_destroy", "cow_last_error", "cow_query_workspace", "cow_load_blocks",
            "cow_get_occupancy", "cow_select_blocks", "cow_query_bricks", "cow_pack_bricks", "cow_render",
-           "cow_render_backward", "cow_autotune", "cow_get_config", "cow_set_config", "cow_set_timing",
-           "cow_last_timing"]
+           "cow_render_backward", "cow_sparsity", "cow_autotune", "cow_get_config", "cow_set_config",
+           "cow_set_timing", "cow_last_timing"]
 
 
 class CowError(RuntimeError):
@@ -56,7 +56,8 @@ class LodPolicy(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_steps", C.c_int32), ("delta", C.c_float), ("max_steps", C.c_int32),
-                ("t_min", C.c_float), ("flags", C.c_int32), ("counts", C.c_void_p)]
+                ("t_min", C.c_float), ("flags", C.c_int32), ("counts", C.c_void_p), ("opacity", C.c_void_p),
+                ("opacity_weight", C.c_void_p)]
 
 
 _lib = None
@@ -84,6 +85,8 @@ def lib():
         L.cow_render.argtypes = [vp, P(View), C.c_int, P(BlockSet), P(Params), vp, vp, vp, vp, vp, C.c_size_t, vp]
         L.cow_render_backward.argtypes = [vp, P(View), C.c_int, P(BlockSet), P(Params), vp, vp, vp, vp,
                                           P(vp), P(vp), vp, vp, C.c_size_t, vp]
+        L.cow_sparsity.argtypes = [vp, P(BlockSet), vp, C.c_int64, C.c_float, C.c_float, vp, vp, vp, vp, vp,
+                                   C.c_size_t, vp]
         L.cow_autotune.argtypes = [vp, P(View), C.c_int, P(BlockSet), P(Params), vp, vp, C.c_size_t, C.c_char_p, vp]
         L.cow_get_config.argtypes = [vp, P(C.c_int), P(C.c_int), P(C.c_int)]
         L.cow_set_config.argtypes = [vp, C.c_int, C.c_int, C.c_int]
@@ -106,12 +109,14 @@ def make_view(v):
     return s
 
 
-def make_params(p, flags=0, counts=None):
+def make_params(p, flags=0, counts=None, opacity=None, opacity_weight=None):
     s = Params()
     s.mode, s.n_steps, s.delta, s.max_steps = int(p.mode), int(p.n_steps), float(p.delta), int(p.max_steps)
     s.t_min = float(getattr(p, "t_min", 0.0))
     s.flags = int(flags)
     s.counts = None if counts is None else counts.data_ptr()
+    s.opacity = None if opacity is None else opacity.data_ptr()
+    s.opacity_weight = None if opacity_weight is None else opacity_weight.data_ptr()
     return s
 
 
@@ -246,7 +251,7 @@ class Renderer:
             setattr(self, attr, cur)
         return cur
 
-    def render(self, views, sets, params, mlp, want_aux=True, counts=False, flags=0, out=None):
+    def render(self, views, sets, params, mlp, want_aux=True, counts=False, flags=0, out=None, opacity=False):
         torch = self.torch
         vs = (View * len(views))(*[make_view(v) for v in views])
         cs, keep = self._sets(sets)
@@ -255,9 +260,10 @@ class Renderer:
             out = dict(rgb=torch.empty((n_pix, 3), dtype=torch.float32, device=self.device),
                        trans=torch.empty(n_pix, dtype=torch.float32, device=self.device),
                        aux=torch.empty((n_pix, 8), dtype=torch.float32, device=self.device) if want_aux else None,
-                       counts=torch.zeros((n_pix, 2), dtype=torch.int64, device=self.device) if counts else None)
+                       counts=torch.zeros((n_pix, 2), dtype=torch.int64, device=self.device) if counts else None,
+                       opacity=torch.zeros(n_pix, dtype=torch.float32, device=self.device) if opacity else None)
         ws = self._ws("render_ws", len(views), n_pix)
-        p = make_params(params, flags, out.get("counts"))
+        p = make_params(params, flags, out.get("counts"), out.get("opacity"))
         if mlp.dtype != torch.float32 or mlp.device != self.device or mlp.numel() != 499:
             raise ValueError("mlp must be 499 float32 values on the device")
         aux = out.get("aux")
@@ -266,15 +272,7 @@ class Renderer:
                                       None if aux is None else aux.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
         return out
 
-    def render_backward(self, views, sets, params, mlp, aux, grad_rgb, grad_trans=None, grad_grid=None,
-                        grad_plane=None, grad_mlp=None):
-        """grad_grid[e] / grad_plane[e][k]: torch fp32 tensors (or None) per
-        loaded entry e, accumulated in place; grad_mlp likewise."""
-        torch = self.torch
-        vs = (View * len(views))(*[make_view(v) for v in views])
-        cs, keep = self._sets(sets)
-        n_pix = sum(int(v.crop[2]) * int(v.crop[3]) for v in views)
-        ws = self._ws("bwd_ws", len(views), n_pix, backward=True)
+    def _grad_tables(self, grad_grid, grad_plane):
         ne = len(self.blocks)
         gg = (C.c_void_p * ne)()
         gp = (C.c_void_p * (3 * ne))()
@@ -285,11 +283,49 @@ class Renderer:
                 for k in range(3):
                     if grad_plane[e][k] is not None:
                         gp[3 * e + k] = grad_plane[e][k].data_ptr()
-        p = make_params(params)
+        return gg, gp
+
+    def render_backward(self, views, sets, params, mlp, aux, grad_rgb, grad_trans=None, grad_grid=None,
+                        grad_plane=None, grad_mlp=None, opacity_weight=None):
+        """grad_grid[e] / grad_plane[e][k]: torch fp32 tensors (or None) per
+        loaded entry e, accumulated in place; grad_mlp likewise.
+        opacity_weight: per-pixel dL/d(opacity regulariser) or None."""
+        vs = (View * len(views))(*[make_view(v) for v in views])
+        cs, keep = self._sets(sets)
+        n_pix = sum(int(v.crop[2]) * int(v.crop[3]) for v in views)
+        ws = self._ws("bwd_ws", len(views), n_pix, backward=True)
+        gg, gp = self._grad_tables(grad_grid, grad_plane)
+        ow = None if opacity_weight is None else opacity_weight.contiguous()
+        p = make_params(params, opacity_weight=ow)
         self._check(self.L.cow_render_backward(
             self.h, vs, len(views), cs, C.byref(p), mlp.data_ptr(), aux.data_ptr(), grad_rgb.contiguous().data_ptr(),
             None if grad_trans is None else grad_trans.contiguous().data_ptr(), gg, gp,
             None if grad_mlp is None else grad_mlp.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+
+    def sparsity(self, refs, pts, delta, weight=1.0, loss=None, alpha=False, grad_grid=None, grad_plane=None):
+        """Sparsity regulariser at points pts [n][3] (device fp32) over the
+        (block, lod) entries `refs` (first match wins).  Adds the loss to
+        `loss` (a device fp32 scalar tensor, created if None) and returns
+        (loss, alpha or None); gradients accumulate into grad_grid/plane."""
+        torch = self.torch
+        pts = pts.contiguous()
+        if pts.dtype != torch.float32 or pts.device != self.device or pts.dim() != 2 or pts.shape[1] != 3:
+            raise ValueError("pts must be [n][3] float32 on the device")
+        n = pts.shape[0]
+        if loss is None:
+            loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        a = torch.empty(n, dtype=torch.float32, device=self.device) if alpha else None
+        cs, keep = self._sets([refs])
+        ws = self._ws("bwd_ws", 1, 1, backward=True)
+        if ws.numel() < 256 + 4 * len(refs) + 32 * len(self.blocks):
+            ws = self.torch.empty(256 + 4 * len(refs) + 32 * len(self.blocks), dtype=torch.uint8, device=self.device)
+        gg = gp = None
+        if grad_grid is not None or grad_plane is not None:
+            gg, gp = self._grad_tables(grad_grid, grad_plane)
+        self._check(self.L.cow_sparsity(self.h, cs, pts.data_ptr(), n, float(delta), float(weight),
+                                        None if a is None else a.data_ptr(), loss.data_ptr(), gg, gp,
+                                        ws.data_ptr(), ws.numel(), _stream()))
+        return loss, a
 
     def autotune(self, views, sets, params, mlp, cache_path=None):
         vs = (View * len(views))(*[make_view(v) for v in views])
@@ -319,38 +355,77 @@ class Renderer:
         return f.value, b.value
 
 
-def make_render_fn():
+def _zero_grads(torch, r):
+    gg, gp = [], []
+    for e in range(len(r.blocks)):
+        g, ps = r.textures[e]
+        gg.append(torch.zeros_like(g))
+        gp.append([torch.zeros_like(p) for p in ps])
+    return gg, gp
+
+
+def _tex_grads(gg, gp, n_tex):
+    out = []
+    for e in range(len(gg)):
+        out += [gg[e]] + gp[e]
+    return tuple(out[:n_tex])
+
+
+def make_render_fn(with_opacity=False):
     """torch.autograd.Function over cow_render / cow_render_backward.
     Differentiable inputs: the MLP weights and every fp32 texture of the
-    loaded blocks (grid, xy, xz, yz per entry, in load order)."""
+    loaded blocks (grid, xy, xz, yz per entry, in load order).  Outputs rgb
+    and trans, plus the per-ray opacity regulariser with with_opacity."""
     import torch
 
     class RenderFn(torch.autograd.Function):
         @staticmethod
         def forward(ctx, renderer, views, sets, params, mlp, *textures):
-            out = renderer.render(views, sets, params, mlp, want_aux=True)
+            out = renderer.render(views, sets, params, mlp, want_aux=True, opacity=with_opacity)
             ctx.renderer, ctx.views, ctx.sets, ctx.params = renderer, views, sets, params
             ctx.save_for_backward(mlp, out["aux"])
             ctx.n_tex = len(textures)
+            if with_opacity:
+                return out["rgb"], out["trans"], out["opacity"]
             return out["rgb"], out["trans"]
 
         @staticmethod
-        def backward(ctx, g_rgb, g_trans):
+        def backward(ctx, g_rgb, g_trans, g_opacity=None):
             mlp, aux = ctx.saved_tensors
             r = ctx.renderer
-            ne = len(r.blocks)
-            gg, gp = [], []
-            for e in range(ne):
-                g, ps = r.textures[e]
-                gg.append(torch.zeros_like(g))
-                gp.append([torch.zeros_like(p) for p in ps])
+            gg, gp = _zero_grads(torch, r)
             gm = torch.zeros_like(mlp)
             r.render_backward(ctx.views, ctx.sets, ctx.params, mlp, aux,
                               g_rgb if g_rgb is not None else torch.zeros((aux.shape[0], 3), device=aux.device),
-                              g_trans, gg, gp, gm)
-            tex_grads = []
-            for e in range(ne):
-                tex_grads += [gg[e]] + gp[e]
-            return (None, None, None, None, gm) + tuple(tex_grads[:ctx.n_tex])
+                              g_trans, gg, gp, gm, opacity_weight=g_opacity)
+            return (None, None, None, None, gm) + _tex_grads(gg, gp, ctx.n_tex)
 
     return RenderFn
+
+
+def make_sparsity_fn():
+    """torch.autograd.Function over cow_sparsity: the scalar sparsity loss of
+    points pts over entries refs; differentiable in the fp32 textures."""
+    import torch
+
+    class SparsityFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, renderer, refs, pts, delta, weight, *textures):
+            loss, _ = renderer.sparsity(refs, pts, delta, weight)
+            ctx.renderer, ctx.refs, ctx.delta, ctx.weight = renderer, refs, delta, weight
+            ctx.save_for_backward(pts)
+            ctx.n_tex = len(textures)
+            return loss[0]
+
+        @staticmethod
+        def backward(ctx, g_loss):
+            (pts,) = ctx.saved_tensors
+            r = ctx.renderer
+            gg, gp = _zero_grads(torch, r)
+            # the loss is linear in its weight: d(g L)/dtheta = gradient of weight g
+            scratch = torch.zeros(1, dtype=torch.float32, device=pts.device)
+            r.sparsity(ctx.refs, pts, ctx.delta, float(ctx.weight) * float(g_loss), loss=scratch,
+                       grad_grid=gg, grad_plane=gp)
+            return (None, None, None, None, None) + _tex_grads(gg, gp, ctx.n_tex)
+
+    return SparsityFn

@@ -41,6 +41,10 @@ __device__ inline uint2 ld8(__amdgpu_buffer_rsrc_t r, int byte_off) {
     return make_uint2(v[0], v[1]);
 }
 
+__device__ inline float ld4(__amdgpu_buffer_rsrc_t r, int byte_off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+
 __device__ inline float4 ld16(__amdgpu_buffer_rsrc_t r, int byte_off) {
     auto v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
     return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]),
@@ -371,30 +375,54 @@ __device__ inline void raw_u8(const BlockU& b, const float q[3], int cell, float
     fold_u8<4>(p2, T.w + 16, b.sc[3], raw);
 }
 
-// fp32 block: a texel is two 16-byte halves (channels 0-3, 4-7); textures
-// are summed one at a time, ((G + XY) + XZ) + YZ
+// fp32 block: a texel is two 16-byte halves (channels 0-3, 4-7).  All 40
+// loads are issued before any is consumed, so one sample's memory latency is
+// paid once; the four textures are then summed ((G + XY) + XZ) + YZ.
 __device__ inline void raw_f32(const BlockU& b, const Taps& T, float raw[kNch]) {
+    float4 lo[20], hi[20];
+#pragma unroll
+    for (int k = 0; k < 20; ++k) {
+        const int tex = k < 8 ? 0 : 1 + (k - 8) / 4;
+        lo[k] = ld16(b.tex[tex], 32 * T.idx[k]);
+        hi[k] = ld16(b.tex[tex], 32 * T.idx[k] + 16);
+    }
 #pragma unroll
     for (int tex = 0; tex < 4; ++tex) {
         const int k0 = tex == 0 ? 0 : 4 + 4 * tex, n = tex == 0 ? 8 : 4;
         float a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-        for (int k = 0; k < n; ++k) {
-            const float4 lo = ld16(b.tex[tex], 32 * T.idx[k0 + k]);
-            const float4 hi = ld16(b.tex[tex], 32 * T.idx[k0 + k] + 16);
-            const float w = T.w[k0 + k];
-            a[0] = fmaf(w, lo.x, a[0]);
-            a[1] = fmaf(w, lo.y, a[1]);
-            a[2] = fmaf(w, lo.z, a[2]);
-            a[3] = fmaf(w, lo.w, a[3]);
-            a[4] = fmaf(w, hi.x, a[4]);
-            a[5] = fmaf(w, hi.y, a[5]);
-            a[6] = fmaf(w, hi.z, a[6]);
-            a[7] = fmaf(w, hi.w, a[7]);
+        for (int k = k0; k < k0 + n; ++k) {
+            const float w = T.w[k];
+            a[0] = fmaf(w, lo[k].x, a[0]);
+            a[1] = fmaf(w, lo[k].y, a[1]);
+            a[2] = fmaf(w, lo[k].z, a[2]);
+            a[3] = fmaf(w, lo[k].w, a[3]);
+            a[4] = fmaf(w, hi[k].x, a[4]);
+            a[5] = fmaf(w, hi[k].y, a[5]);
+            a[6] = fmaf(w, hi[k].z, a[6]);
+            a[7] = fmaf(w, hi[k].w, a[7]);
         }
 #pragma unroll
         for (int c = 0; c < 8; ++c) raw[c] = tex == 0 ? a[c] : raw[c] + a[c];
     }
+}
+
+// Density channel alone of an fp32 block: the same operations, in the same
+// order, as channel 0 of raw_f32, so the two agree bit for bit.
+__device__ inline float raw0_f32(const BlockU& b, const Taps& T) {
+    float v[20];
+#pragma unroll
+    for (int k = 0; k < 20; ++k) v[k] = ld4(b.tex[k < 8 ? 0 : 1 + (k - 8) / 4], 32 * T.idx[k]);
+    float raw = 0.0f;
+#pragma unroll
+    for (int tex = 0; tex < 4; ++tex) {
+        const int k0 = tex == 0 ? 0 : 4 + 4 * tex, n = tex == 0 ? 8 : 4;
+        float a = 0.0f;
+#pragma unroll
+        for (int k = k0; k < k0 + n; ++k) a = fmaf(T.w[k], v[k], a);
+        raw = tex == 0 ? a : raw + a;
+    }
+    return raw;
 }
 
 // ---------------------------------------------------------------------------
@@ -412,6 +440,22 @@ __device__ inline float alpha_of(float x) {
     t = fmaf(-x, t, 1.0f);
     const float series = x * t;
     return x < 0.0625f ? series : 1.0f - __expf(-x);
+}
+
+// Binary entropy of a block's opacity a = 1 - Tk (Eq. "opacity loss"), with
+// a clamped to [1e-6, 1 - 1e-6] so that both logarithms stay finite; 1 - a
+// is taken as Tk itself (no cancellation).  The derivative in a is
+// log((1 - a) / a), zero where the clamp holds.
+constexpr float kOpacityEps = 1e-6f;
+__device__ inline float opacity_entropy(float Tk) {
+    const float lo = kOpacityEps, hi = 1.0f - kOpacityEps;
+    const float a = fminf(fmaxf(1.0f - Tk, lo), hi);
+    const float b = fminf(fmaxf(Tk, lo), hi);
+    return -(a * logf(a) + b * logf(b));
+}
+__device__ inline float opacity_dentropy(float Tk) {
+    const float a = 1.0f - Tk;
+    return (a > kOpacityEps && a < 1.0f - kOpacityEps) ? logf(Tk / a) : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -536,6 +580,35 @@ __device__ inline bool next_occupied(const BlockU& b, const Ray& r, const Span& 
         ++k;
     }
     return false;
+}
+
+// Transmittance prod(1 - alpha_i) of one block for one lane of an fp32
+// march, density channel only, with the forward's early-termination rule:
+// the value the forward's composite of the block forms.  A lane with
+// want == false marches nothing and gets 1.
+template <int MODE>
+__device__ inline float block_trans_f32(const BlockU& b, const Ray& r, const Span& sp, float T_before,
+                                        float t_min, bool want) {
+    int k = sp.ka, kb = want ? sp.kb : sp.ka;
+    int cur_cell = -1;
+    bool cur_occ = false;
+    int64_t unused = 0;
+    float Tk = 1.0f;
+    for (;;) {
+        float q[3];
+        int cell = 0;
+        const bool have = next_occupied<MODE>(b, r, sp, kb, sp.delta, k, q, cell, cur_cell, cur_occ, unused);
+        if (!__any(have)) break;
+        if (have) {
+            Taps T;
+            sample_taps(b, q, T);
+            const float sigma = __expf(raw0_f32(b, T));
+            Tk *= 1.0f - alpha_of(sigma * sp.delta);
+            ++k;
+            if (T_before * Tk < t_min) kb = k;
+        }
+    }
+    return Tk;
 }
 
 }  // namespace cow

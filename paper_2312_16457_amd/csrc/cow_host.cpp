@@ -354,6 +354,7 @@ cow::MarchArgs march_args(cow_ctx* c, const CallTables& T, const RenderWs& w,
     a.aux = aux;
     a.trans = trans;
     a.counts = p->counts;
+    a.opacity = p->opacity;
     a.work_counter = w.counter;
     a.persistent = c->cfg.persistent;
     a.only_view = -1;
@@ -872,8 +873,10 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     ba.m = march_args(c, T, w, p, COW_F32, const_cast<float*>(aux), nullptr);
     ba.m.persistent = c->cfg.persistent;
     ba.m.counts = nullptr;
+    ba.m.opacity = nullptr;
     ba.u = w.u;
     ba.grad_trans = grad_trans;
+    ba.w_opacity = p->opacity_weight;
     ba.grad_grid = w.grad_ptrs;
     ba.grad_plane = w.grad_ptrs + ne;
     c->have_bwd = c->timing;
@@ -881,6 +884,70 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[2], s));
     HIP_TRY(c, cow::launch_march_bwd(ba, c->cfg.waves, s));
     if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[3], s));
+    return COW_OK;
+} catch (...) {
+    return fail(c, COW_E_INTERNAL, "internal error");
+}
+
+cow_status cow_sparsity(cow_ctx* c, const cow_block_set* set, const float* pts, int64_t n, float delta,
+                        float weight, float* alpha, float* loss, float* const* grad_grid,
+                        float* const* grad_plane, void* ws, size_t ws_bytes, hipStream_t s) try {
+    if (!c) return COW_E_INVALID;
+    if (!c->loaded) return fail(c, COW_E_NOT_LOADED, "no blocks loaded");
+    if (!set || set->n < 0 || (set->n > 0 && !set->refs)) return fail(c, COW_E_INVALID, "bad block set");
+    if (n < 0 || (n > 0 && !pts) || !loss) return fail(c, COW_E_INVALID, "null points or loss");
+    if (n > (int64_t)1 << 31) return fail(c, COW_E_INVALID, "too many points");
+    if (!(delta > 0.0f) || !std::isfinite(delta)) return fail(c, COW_E_INVALID, "delta must be positive and finite");
+    if (!std::isfinite(weight)) return fail(c, COW_E_INVALID, "weight must be finite");
+    if ((grad_grid == nullptr) != (grad_plane == nullptr))
+        return fail(c, COW_E_INVALID, "gradient tables must be both given or both NULL");
+    std::vector<int32_t> idx((size_t)set->n);
+    int dtype = -1;
+    for (int r = 0; r < set->n; ++r) {
+        const int e = find_entry(c, set->refs[r].block_id, set->refs[r].lod);
+        if (e < 0) return fail(c, COW_E_INVALID, "set names a (block, lod) that is not loaded");
+        idx[r] = e;
+        const int d = c->entries[e].desc.dtype;
+        if (dtype >= 0 && d != dtype) return fail(c, COW_E_UNSUPPORTED, "one call must use blocks of a single dtype");
+        dtype = d;
+    }
+    if (grad_grid && dtype == COW_U8) return fail(c, COW_E_UNSUPPORTED, "gradients need float32 textures");
+    const size_t ne = c->entries.size();
+    const size_t ib = align_up(4 * (size_t)std::max(set->n, 1)), pb = sizeof(float*) * 4 * ne;
+    if (!ws || ws_bytes < ib + pb) return fail(c, COW_E_WORKSPACE, "sparsity workspace too small");
+    if (n == 0 || set->n == 0) {
+        if (n > 0 && alpha) HIP_TRY(c, hipMemsetAsync(alpha, 0, sizeof(float) * (size_t)n, s));
+        return COW_OK;
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    std::vector<float*> ptrs(4 * ne, nullptr);
+    if (grad_grid)
+        for (size_t e = 0; e < ne; ++e) {
+            ptrs[e] = grad_grid[e];
+            for (int k = 0; k < 3; ++k) ptrs[ne + 3 * e + k] = grad_plane[3 * e + k];
+        }
+    cow_status st = ensure_pinned(c, ib + pb);
+    if (st != COW_OK) return st;
+    memcpy(c->pinned, idx.data(), 4 * idx.size());
+    memcpy(c->pinned + ib, ptrs.data(), pb);
+    unsigned char* d = (unsigned char*)ws;
+    HIP_TRY(c, hipMemcpyAsync(d, c->pinned, ib + pb, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipEventRecord(c->staging_done, s));
+    c->staging_pending = true;
+    cow::SparsityArgs a{};
+    a.blocks = c->d_blocks;
+    a.set = (const int32_t*)d;
+    a.n_set = set->n;
+    a.dtype = dtype;
+    a.pts = pts;
+    a.n = n;
+    a.delta = delta;
+    a.scale = (float)((double)weight / (double)n);
+    a.alpha = alpha;
+    a.loss = loss;
+    a.grad_grid = grad_grid ? (float* const*)(d + ib) : nullptr;
+    a.grad_plane = grad_grid ? (float* const*)(d + ib) + ne : nullptr;
+    HIP_TRY(c, cow::launch_sparsity(a, s));
     return COW_OK;
 } catch (...) {
     return fail(c, COW_E_INTERNAL, "internal error");

@@ -1,5 +1,5 @@
 // Device-side tables shared by the host library (cow_host.cpp) and the
-// kernels (cow_kernels.hip).  Plain structs, copied to device memory once per
+// kernels (the .hip sources).  Plain structs, copied to device memory once per
 // cow_load_blocks (DevBlock) or per cow_render call (DevView, refs).
 #pragma once
 
@@ -54,6 +54,7 @@ struct MarchArgs {
     float* aux;                // [P][8] (C_d, F, T)
     float* trans;              // [P]
     int64_t* counts;           // [P][2] or null
+    float* opacity;            // [P] per-ray block-opacity entropy, or null
     int32_t* work_counter;     // persistent mode
     int32_t persistent;
     // per-block baseline: only this view and this one set position
@@ -85,11 +86,28 @@ struct BwdArgs {
     MarchArgs m;
     const float* u;            // [P][8]
     const float* grad_trans;   // [P] or null
+    const float* w_opacity;    // [P] dL/d(per-ray opacity entropy), or null
     float* const* grad_grid;   // device array of per-entry pointers
     float* const* grad_plane;  // device array, 3 per entry
 };
 
-// launchers (cow_kernels.hip)
+// sparsity regulariser at given points
+struct SparsityArgs {
+    const DevBlock* blocks;
+    const int32_t* set;        // entry indices, first match wins
+    int32_t n_set;
+    int32_t dtype;             // COW_U8 / COW_F32, the same for every entry of the set
+    const float* pts;          // [n][3]
+    int64_t n;
+    float delta;
+    float scale;               // weight / n
+    float* alpha;              // [n] or null
+    float* loss;               // [1], accumulated
+    float* const* grad_grid;   // device array of per-entry pointers, or null
+    float* const* grad_plane;  // device array, 3 per entry, or null
+};
+
+// launchers
 hipError_t launch_occupancy(const DevBlock* blocks, int entry, int O, hipStream_t s);
 hipError_t launch_march(const MarchArgs& a, int waves_per_group, hipStream_t s);
 hipError_t launch_reset_counter(int32_t* counter, hipStream_t s);
@@ -97,6 +115,7 @@ hipError_t launch_clear_aux(float* aux, int64_t n_pix, hipStream_t s);
 hipError_t launch_mlp(const MlpArgs& a, hipStream_t s);
 hipError_t launch_mlp_bwd(const MlpBwdArgs& a, hipStream_t s);
 hipError_t launch_march_bwd(const BwdArgs& a, int waves_per_group, hipStream_t s);
+hipError_t launch_sparsity(const SparsityArgs& a, hipStream_t s);
 hipError_t launch_pack_bricks(const DevBlock* blocks, int entry, int O, int s_cells,
                               const int32_t* slot_host_unused, hipStream_t st);
 

@@ -63,7 +63,7 @@ __device__ void march_packet(const MarchArgs& a, const DevView* V, int tile, int
     }
     int r0 = 0, r1 = v.set_n;
     if (a.only_set_pos >= 0) r0 = a.only_set_pos, r1 = a.only_set_pos + 1;
-    float A[7] = {0, 0, 0, 0, 0, 0, 0}, T = 1.0f;
+    float A[7] = {0, 0, 0, 0, 0, 0, 0}, T = 1.0f, H = 0.0f;
     int64_t n_eval = 0, n_march = 0;
     if (a.only_set_pos > 0 && r.active) {  // per-block baseline: continue the running blend
         const float4 lo4 = reinterpret_cast<const float4*>(a.aux)[2 * r.pix];
@@ -71,6 +71,7 @@ __device__ void march_packet(const MarchArgs& a, const DevView* V, int tile, int
         A[0] = lo4.x, A[1] = lo4.y, A[2] = lo4.z, A[3] = lo4.w;
         A[4] = hi4.x, A[5] = hi4.y, A[6] = hi4.z, T = hi4.w;
         if (a.counts) n_eval = a.counts[2 * r.pix], n_march = a.counts[2 * r.pix + 1];
+        if (a.opacity) H = a.opacity[r.pix];
     }
     for (int j = r0; j < r1; ++j) {
         const int e = ufl(a.refs[v.set_begin + j]);
@@ -80,7 +81,11 @@ __device__ void march_packet(const MarchArgs& a, const DevView* V, int tile, int
         const Span sp = block_span<MODE>(a, b, r, alive, w0, w1);
         if (!__any(sp.ka < sp.kb)) continue;
         float Ak[7] = {0, 0, 0, 0, 0, 0, 0}, Tk = 1.0f;
+        const int64_t marched_before = n_march;
         march_block<DT, MODE, SPARSE>(a, b, r, sp, T, Ak, Tk, n_eval, n_march);
+        // opacity regulariser: entropy of the block's opacity 1 - Tk, for
+        // every block the ray marches (Eq. "opacity loss")
+        if (a.opacity && n_march > marched_before) H += opacity_entropy(Tk);
         // merge front to back (Eq. "volume rendering across blocks"), with
         // the block's transmittance prod(1 - alpha_i) carried directly
 #pragma unroll
@@ -92,6 +97,7 @@ __device__ void march_packet(const MarchArgs& a, const DevView* V, int tile, int
         aux4[2 * r.pix] = make_float4(A[0], A[1], A[2], A[3]);
         aux4[2 * r.pix + 1] = make_float4(A[4], A[5], A[6], T);
         a.trans[r.pix] = T;
+        if (a.opacity) a.opacity[r.pix] = H;
         if (a.counts) {
             a.counts[2 * r.pix] = n_eval;
             a.counts[2 * r.pix + 1] = n_march;
@@ -99,9 +105,11 @@ __device__ void march_packet(const MarchArgs& a, const DevView* V, int tile, int
     }
 }
 
-// All blocks of one launch share a texture dtype (checked on the host).
+// All blocks of one launch share a texture dtype (checked on the host).  The
+// uint8 kernel runs four waves per SIMD; the fp32 one keeps its 40 texel
+// loads (160 registers) in flight with two.
 template <int MODE, int DT, bool SPARSE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void march_fwd_kernel(MarchArgs a) {
+__device__ inline void march_fwd_body(const MarchArgs& a) {
     const int lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
     const int wave = ufl(threadIdx.x >> 6);
@@ -126,6 +134,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void m
     march_packet<MODE, DT, SPARSE>(a, V, packet - ufl(V->tile_begin), lane);
 }
 
+template <int MODE, bool SPARSE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void march_fwd_kernel(MarchArgs a) {
+    march_fwd_body<MODE, 0, SPARSE>(a);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void march_fwd_f32_kernel(MarchArgs a) {
+    march_fwd_body<MODE, 1, false>(a);
+}
+
 hipError_t launch_march(const MarchArgs& a, int waves, hipStream_t s) {
     if (a.total_tiles <= 0) return hipSuccess;
     dim3 block(64 * waves);
@@ -139,21 +157,22 @@ hipError_t launch_march(const MarchArgs& a, int waves, hipStream_t s) {
         grid = dim3((a.total_tiles + waves - 1) / waves);
     }
     const int dt = a.blocks_dtype;
-#define COW_LAUNCH(M, D, S) hipLaunchKernelGGL((march_fwd_kernel<M, D, S>), grid, block, 0, s, a)
-    if (a.mode == 1) {
-        if (dt == 1)
-            COW_LAUNCH(1, 1, false);
-        else if (a.use_sparse)
-            COW_LAUNCH(1, 0, true);
+#define COW_LAUNCH(M, S) hipLaunchKernelGGL((march_fwd_kernel<M, S>), grid, block, 0, s, a)
+    if (dt == 1) {
+        if (a.mode == 1)
+            hipLaunchKernelGGL(march_fwd_f32_kernel<1>, grid, block, 0, s, a);
         else
-            COW_LAUNCH(1, 0, false);
+            hipLaunchKernelGGL(march_fwd_f32_kernel<0>, grid, block, 0, s, a);
+    } else if (a.mode == 1) {
+        if (a.use_sparse)
+            COW_LAUNCH(1, true);
+        else
+            COW_LAUNCH(1, false);
     } else {
-        if (dt == 1)
-            COW_LAUNCH(0, 1, false);
-        else if (a.use_sparse)
-            COW_LAUNCH(0, 0, true);
+        if (a.use_sparse)
+            COW_LAUNCH(0, true);
         else
-            COW_LAUNCH(0, 0, false);
+            COW_LAUNCH(0, false);
     }
 #undef COW_LAUNCH
     return hipGetLastError();

@@ -14,6 +14,9 @@ namespace cow {
 //   dL/draw_0   = sigma_k dL/dsigma_k
 //   dL/draw_c   = w_k u_c s (1 - s)        (c >= 1, s = sigmoid(raw_c))
 // and each texel receives its interpolation weight times dL/draw.  The
+// opacity regulariser H = sum_k h(1 - T^k) with per-ray weight g adds
+// g h'(1 - T^k) delta_i T^k to dL/dsigma_i for every sample i of block k;
+// T^k comes from a density-only pre-march of the block.  The
 // merged composite equals the monolithic one over the same sequence
 // (Appendix A), so one running prefix serves all blocks in order.
 // Texel-gradient scatter, one collective step per wave.  Each interpolation
@@ -63,7 +66,7 @@ __device__ inline void scatter_pairs(ScatterLds& L, int lane, const Taps& T, con
     }
 }
 
-template <int MODE>
+template <int MODE, bool OPAC>
 __device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, int lane, ScatterLds& lds) {
     const MarchArgs& a = ba.m;
     ViewU v;
@@ -90,6 +93,7 @@ __device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, 
         u[0] = ulo.x, u[1] = ulo.y, u[2] = ulo.z, u[3] = ulo.w, u[4] = uhi.x, u[5] = uhi.y, u[6] = uhi.z;
         if (ba.grad_trans) gT = ba.grad_trans[r.pix];
     }
+    const float w_op = (OPAC && r.active) ? ba.w_opacity[r.pix] : 0.0f;
     float Ap[7] = {0, 0, 0, 0, 0, 0, 0}, Tg = 1.0f;
     float T_blk = 1.0f;  // merged transmittance before the block, as the forward forms it
     const float tn_term = TN * gT;
@@ -108,6 +112,11 @@ __device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, 
         const bool alive = hit && !(T_blk < a.t_min);
         const Span sp = block_span<MODE>(a, b, r, alive, w0, w1);
         if (!__any(sp.ka < sp.kb)) continue;
+        float g_op = 0.0f;  // dL/dsigma_i of the opacity term, per unit step length
+        if (OPAC && __any(w_op != 0.0f)) {
+            const float Tkf = block_trans_f32<MODE>(b, r, sp, T_blk, a.t_min, w_op != 0.0f);
+            g_op = w_op * opacity_dentropy(Tkf) * Tkf;
+        }
         int k = sp.ka, kb = sp.kb;
         int cur_cell = -1;
         bool cur_occ = false;
@@ -136,7 +145,7 @@ __device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, 
                     us = fmaf(u[c], Af[c] - Ap[c], us);
                 }
                 const float Tn = Tg * (1.0f - alpha);
-                const float dsig = sp.delta * (Tn * uv - us) - sp.delta * tn_term;
+                const float dsig = sp.delta * (Tn * uv - us) - sp.delta * tn_term + sp.delta * g_op;
                 draw[0] = sigma * dsig;
 #pragma unroll
                 for (int c = 0; c < 7; ++c) draw[1 + c] = w * u[c] * vv[c] * (1.0f - vv[c]);
@@ -152,7 +161,9 @@ __device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, 
     }
 }
 
-template <int MODE>
+// OPAC: with the opacity regulariser's pre-march (a separate instance keeps
+// the plain adjoint's register budget)
+template <int MODE, bool OPAC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void march_bwd_kernel(BwdArgs ba) {
     const MarchArgs& a = ba.m;
     __shared__ ScatterLds lds[4];
@@ -166,14 +177,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
             p = ufl(__shfl(p, 0));
             if (p >= a.total_tiles) break;
             const DevView* V = find_view_by_tile(a.views, a.n_views, p);
-            march_bwd_packet<MODE>(ba, V, p - ufl(V->tile_begin), lane, lds[wave]);
+            march_bwd_packet<MODE, OPAC>(ba, V, p - ufl(V->tile_begin), lane, lds[wave]);
         }
         return;
     }
     const int packet = ufl(xcd_packet(waves, wave));
     if (packet >= a.total_tiles) return;
     const DevView* V = find_view_by_tile(a.views, a.n_views, packet);
-    march_bwd_packet<MODE>(ba, V, packet - ufl(V->tile_begin), lane, lds[wave]);
+    march_bwd_packet<MODE, OPAC>(ba, V, packet - ufl(V->tile_begin), lane, lds[wave]);
 }
 
 hipError_t launch_march_bwd(const BwdArgs& a, int waves, hipStream_t s) {
@@ -185,10 +196,18 @@ hipError_t launch_march_bwd(const BwdArgs& a, int waves, hipStream_t s) {
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         grid = dim3(cus * (16 / waves));
     }
-    if (a.m.mode == 1)
-        hipLaunchKernelGGL(march_bwd_kernel<1>, grid, block, 0, s, a);
-    else
-        hipLaunchKernelGGL(march_bwd_kernel<0>, grid, block, 0, s, a);
+    const bool op = a.w_opacity != nullptr;
+    if (a.m.mode == 1) {
+        if (op)
+            hipLaunchKernelGGL((march_bwd_kernel<1, true>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((march_bwd_kernel<1, false>), grid, block, 0, s, a);
+    } else {
+        if (op)
+            hipLaunchKernelGGL((march_bwd_kernel<0, true>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((march_bwd_kernel<0, false>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -38,6 +38,20 @@ def test_header_declarations_exported(libcow):
     assert exported == names, "the library exports exactly the declared entry points"
 
 
+def test_every_export_has_a_ctypes_signature(libcow):
+    """Each entry point is called with declared argument types (floats and
+    64-bit sizes would otherwise be passed wrongly or rejected), and the
+    declared count matches the header's parameter list."""
+    from paper_2312_16457_amd import binding
+    src = open(HEADER).read()
+    for n in binding.EXPORTS:
+        f = getattr(libcow, n)
+        assert f.argtypes is not None, n
+        m = re.search(r"\b" + n + r"\s*\(([^)]*)\)", src)
+        params = [p for p in m.group(1).split(",") if p.strip() and p.strip() != "void"]
+        assert len(f.argtypes) == len(params), (n, len(f.argtypes), len(params))
+
+
 def test_struct_layouts_match_c():
     from paper_2312_16457_amd import binding as B
     prog = r"""
@@ -50,8 +64,9 @@ def test_struct_layouts_match_c():
       printf("%zu %zu %zu\n", sizeof(cow_view), offsetof(cow_view, eye), offsetof(cow_view, fx));
       printf("%zu %zu\n", sizeof(cow_block_ref), sizeof(cow_block_set));
       printf("%zu %zu\n", sizeof(cow_lod_policy), offsetof(cow_lod_policy, cull));
-      printf("%zu %zu %zu\n", sizeof(cow_render_params), offsetof(cow_render_params, flags),
-             offsetof(cow_render_params, counts));
+      printf("%zu %zu %zu %zu %zu\n", sizeof(cow_render_params), offsetof(cow_render_params, flags),
+             offsetof(cow_render_params, counts), offsetof(cow_render_params, opacity),
+             offsetof(cow_render_params, opacity_weight));
       return 0;
     }
     """
@@ -67,7 +82,8 @@ def test_struct_layouts_match_c():
     assert vals[1] == [C.sizeof(B.View), B.View.eye.offset, B.View.fx.offset]
     assert vals[2] == [C.sizeof(B.BlockRef), C.sizeof(B.BlockSet)]
     assert vals[3] == [C.sizeof(B.LodPolicy), B.LodPolicy.cull.offset]
-    assert vals[4] == [C.sizeof(B.Params), B.Params.flags.offset, B.Params.counts.offset]
+    assert vals[4] == [C.sizeof(B.Params), B.Params.flags.offset, B.Params.counts.offset, B.Params.opacity.offset,
+                       B.Params.opacity_weight.offset]
 
 
 def test_null_context_and_no_device(libcow):
