@@ -239,7 +239,7 @@ __device__ inline void load_block(const DevBlock* B, BlockU& b) {
     b.brick = tex_rsrc(ufp(B->bricks), (uint32_t)ufl((int)B->brick_bytes));
     if (DT == 0) {
         for (int t = 0; t < 4; ++t)
-            for (int c = 0; c < kNch; ++c) b.sc[t][c] = uff(B->scale[t][c]);
+            for (int c = 0; c < kNch; ++c) b.sc[t][c] = uff(B->scale[t][c]) * 16777216.0f;  // see bytes_h2
         for (int c = 0; c < kNch; ++c)
             b.osum[c] = uff(((B->offset[0][c] + B->offset[1][c]) + B->offset[2][c]) + B->offset[3][c]);
     }
@@ -260,79 +260,106 @@ __device__ inline int occ_cell(const BlockU& b, const float q[3]) {
 // ---------------------------------------------------------------------------
 // feature gather: trilinear grid + three bilinear planes
 // ---------------------------------------------------------------------------
+// Clamp-to-edge linear interpolation along one axis over cell-centred
+// texels (u = q R - 1/2), written as a pair of adjacent texels p, p + 1:
+// weights (1 - f, f) at p = floor(u) inside the texture, all weight on
+// texel 0 below the first centre and on texel R - 1 beyond the last.  The
+// pair is contiguous in memory along x (grid) and u (planes), so one 16-byte
+// load fetches both uint8 texels.  Needs R >= 2.
 struct Lin {
-    int i0, i1;
-    float w0, w1;
+    int p;
+    float w0, w1;  // weights of texels p and p + 1
 };
 
-// cell-centred, clamp-to-edge linear taps: u = q R - 1/2
-__device__ inline Lin lin_taps(float q, int R) {
+__device__ inline Lin lin_pair(float q, int R) {
     const float u = q * (float)R - 0.5f;
     const float fl = floorf(u);
     const int a = (int)fl;
+    const float f = u - fl;
     Lin t;
-    t.w1 = u - fl;
-    t.w0 = 1.0f - t.w1;
-    t.i0 = a < 0 ? 0 : a;
-    t.i1 = a + 1 > R - 1 ? R - 1 : a + 1;
+    const bool lo = a < 0, hi = a > R - 2;
+    t.p = lo ? 0 : (hi ? R - 2 : a);
+    t.w0 = lo ? 1.0f : (hi ? 0.0f : 1.0f - f);
+    t.w1 = lo ? 0.0f : (hi ? 1.0f : f);
     return t;
 }
 
-// texel indices and weights of one sample: 8 grid taps, then xy, xz, yz
+// The taps of one sample as ten pairs: 0-3 the grid rows (z0,y0), (z0,y1),
+// (z1,y0), (z1,y1); 4-9 the plane rows xy v0, v1, xz v0, v1, yz v0, v1.
+// w[2j] and w[2j + 1] weight texels pidx[j] and pidx[j] + 1.
 struct Taps {
-    int idx[20];
+    int pidx[10];
     float w[20];
 };
 
+__device__ inline int pair_tex(int j) { return j < 4 ? 0 : 1 + (j - 4) / 2; }
+
 __device__ inline void sample_taps(const BlockU& b, const float q[3], Taps& T) {
     const int R = b.R, Rp = b.Rp, lR = b.lR, lRp = b.lRp;
-    const Lin gx = lin_taps(q[0], R), gy = lin_taps(q[1], R), gz = lin_taps(q[2], R);
-    const Lin px = lin_taps(q[0], Rp), py = lin_taps(q[1], Rp), pz = lin_taps(q[2], Rp);
-    const int zi[2] = {gz.i0, gz.i1}, yi[2] = {gy.i0, gy.i1}, xi[2] = {gx.i0, gx.i1};
-    const float zw[2] = {gz.w0, gz.w1}, yw[2] = {gy.w0, gy.w1}, xw[2] = {gx.w0, gx.w1};
+    const Lin gx = lin_pair(q[0], R), gy = lin_pair(q[1], R), gz = lin_pair(q[2], R);
+    const Lin px = lin_pair(q[0], Rp), py = lin_pair(q[1], Rp), pz = lin_pair(q[2], Rp);
+    const float zw[2] = {gz.w0, gz.w1}, yw[2] = {gy.w0, gy.w1};
 #pragma unroll
     for (int dz = 0; dz < 2; ++dz)
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy) {
-            const int row = ((zi[dz] << lR) + yi[dy]) << lR;
+            const int j = dz * 2 + dy;
             const float wzy = zw[dz] * yw[dy];
-#pragma unroll
-            for (int dx = 0; dx < 2; ++dx) {
-                T.idx[dz * 4 + dy * 2 + dx] = row + xi[dx];
-                T.w[dz * 4 + dy * 2 + dx] = wzy * xw[dx];
-            }
+            T.pidx[j] = ((((gz.p + dz) << lR) + gy.p + dy) << lR) + gx.p;
+            T.w[2 * j] = wzy * gx.w0;
+            T.w[2 * j + 1] = wzy * gx.w1;
         }
     // planes are indexed [v][u]: xy (u=x, v=y), xz (u=x, v=z), yz (u=y, v=z)
     const Lin U[3] = {px, px, py}, V[3] = {py, pz, pz};
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
-        const int v0 = V[p].i0 << lRp, v1 = V[p].i1 << lRp;
-        T.idx[8 + 4 * p + 0] = v0 + U[p].i0;
-        T.idx[8 + 4 * p + 1] = v0 + U[p].i1;
-        T.idx[8 + 4 * p + 2] = v1 + U[p].i0;
-        T.idx[8 + 4 * p + 3] = v1 + U[p].i1;
-        T.w[8 + 4 * p + 0] = V[p].w0 * U[p].w0;
-        T.w[8 + 4 * p + 1] = V[p].w0 * U[p].w1;
-        T.w[8 + 4 * p + 2] = V[p].w1 * U[p].w0;
-        T.w[8 + 4 * p + 3] = V[p].w1 * U[p].w1;
+        const int j = 4 + 2 * p;
+        T.pidx[j] = (V[p].p << lRp) + U[p].p;
+        T.pidx[j + 1] = ((V[p].p + 1) << lRp) + U[p].p;
+        T.w[2 * j + 0] = V[p].w0 * U[p].w0;
+        T.w[2 * j + 1] = V[p].w0 * U[p].w1;
+        T.w[2 * j + 2] = V[p].w1 * U[p].w0;
+        T.w[2 * j + 3] = V[p].w1 * U[p].w1;
     }
 }
 
-__device__ inline float ub(uint2 v, int c) {
-    const uint32_t w = c < 4 ? v.x : v.y;
-    return (float)((w >> (8 * (c & 3))) & 0xffu);
+__device__ inline uint4 ld16u(__amdgpu_buffer_rsrc_t r, int byte_off) {
+    auto v = __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0);
+    return make_uint4(v[0], v[1], v[2], v[3]);
 }
 
-// raw[c] += scale[c] * (sum_k w_k q_k[c]) over N uint8 texels
+// Bytes 2i and 2i + 1 of a word as two fp16 subnormals, byte * 2^-24 exactly
+// (v_perm_b32): v_fma_mix_f32 then multiplies them by fp32 weights with no
+// separate conversion.  The 2^24 comes back, exactly, in the decode scale.
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+__device__ inline h2_t bytes_h2(uint32_t w, int i) {
+    return __builtin_bit_cast(h2_t, __builtin_amdgcn_perm(0u, w, i == 0 ? 0x0c010c00u : 0x0c030c02u));
+}
+
+// s[c] += w * byte c of one uint8 texel (two words), scaled by 2^-24
+__device__ inline void fold_texel(uint32_t x, uint32_t y, float w, float s[kNch]) {
+    const h2_t a = bytes_h2(x, 0), b = bytes_h2(x, 1), c = bytes_h2(y, 0), d = bytes_h2(y, 1);
+    s[0] = fmaf(w, (float)a.x, s[0]);
+    s[1] = fmaf(w, (float)a.y, s[1]);
+    s[2] = fmaf(w, (float)b.x, s[2]);
+    s[3] = fmaf(w, (float)b.y, s[3]);
+    s[4] = fmaf(w, (float)c.x, s[4]);
+    s[5] = fmaf(w, (float)c.y, s[5]);
+    s[6] = fmaf(w, (float)d.x, s[6]);
+    s[7] = fmaf(w, (float)d.y, s[7]);
+}
+
+// raw[c] += scale[c] * (sum over N pairs of w q[c]) for one texture
 template <int N>
-__device__ inline void fold_u8(const uint2 (&t)[N], const float* w, const float* sc, float raw[kNch]) {
+__device__ inline void fold_u8(const uint4 (&t)[N], const float* w, const float* sc, float raw[kNch]) {
+    float s[kNch] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int c = 0; c < kNch; ++c) {
-        float s = w[0] * ub(t[0], c);
-#pragma unroll
-        for (int k = 1; k < N; ++k) s = fmaf(w[k], ub(t[k], c), s);
-        raw[c] = fmaf(s, sc[c], raw[c]);
+    for (int k = 0; k < N; ++k) {
+        fold_texel(t[k].x, t[k].y, w[2 * k], s);
+        fold_texel(t[k].z, t[k].w, w[2 * k + 1], s);
     }
+#pragma unroll
+    for (int c = 0; c < kNch; ++c) raw[c] = fmaf(s[c], sc[c], raw[c]);
 }
 
 // Pre-activation features of a uint8 block at local coordinate q:
@@ -343,48 +370,51 @@ template <bool SPARSE>
 __device__ inline void raw_u8(const BlockU& b, const float q[3], int cell, float raw[kNch]) {
     Taps T;
     sample_taps(b, q, T);
-    uint2 g[8], p0[4], p1[4], p2[4];
+    uint4 g[4], p0[2], p1[2], p2[2];
     if (SPARSE) {
         // brick of (s+2)^3 texels around the sample's occupancy cell; texel j
-        // of an axis holds grid index clamp(c s - 1 + j)
+        // of an axis holds grid index clamp(c s - 1 + j), so the pair at grid
+        // index p sits at brick index p - (c s - 1) and the next one
         const int O = b.O, s = b.R / O, s2 = s + 2;
         const int cx = cell % O, cy = (cell / O) % O, cz = cell / (O * O);
         const int base = b.slot[cell] * (s2 * s2 * s2);
-        const Lin gx = lin_taps(q[0], b.R), gy = lin_taps(q[1], b.R), gz = lin_taps(q[2], b.R);
-        const int xs[2] = {gx.i0 - (cx * s - 1), gx.i1 - (cx * s - 1)};
-        const int ys[2] = {gy.i0 - (cy * s - 1), gy.i1 - (cy * s - 1)};
-        const int zs[2] = {gz.i0 - (cz * s - 1), gz.i1 - (cz * s - 1)};
+        const Lin gx = lin_pair(q[0], b.R), gy = lin_pair(q[1], b.R), gz = lin_pair(q[2], b.R);
+        const int xs = gx.p - (cx * s - 1), ys = gy.p - (cy * s - 1), zs = gz.p - (cz * s - 1);
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            g[k] = ld8(b.brick, 8 * (base + (zs[k >> 2] * s2 + ys[(k >> 1) & 1]) * s2 + xs[k & 1]));
+        for (int j = 0; j < 4; ++j)
+            g[j] = ld16u(b.brick, 8 * (base + ((zs + (j >> 1)) * s2 + ys + (j & 1)) * s2 + xs));
     } else {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) g[k] = ld8(b.tex[0], 8 * T.idx[k]);
+        for (int j = 0; j < 4; ++j) g[j] = ld16u(b.tex[0], 8 * T.pidx[j]);
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        p0[k] = ld8(b.tex[1], 8 * T.idx[8 + k]);
-        p1[k] = ld8(b.tex[2], 8 * T.idx[12 + k]);
-        p2[k] = ld8(b.tex[3], 8 * T.idx[16 + k]);
+    for (int j = 0; j < 2; ++j) {
+        p0[j] = ld16u(b.tex[1], 8 * T.pidx[4 + j]);
+        p1[j] = ld16u(b.tex[2], 8 * T.pidx[6 + j]);
+        p2[j] = ld16u(b.tex[3], 8 * T.pidx[8 + j]);
     }
 #pragma unroll
     for (int c = 0; c < kNch; ++c) raw[c] = b.osum[c];
-    fold_u8<8>(g, T.w, b.sc[0], raw);
-    fold_u8<4>(p0, T.w + 8, b.sc[1], raw);
-    fold_u8<4>(p1, T.w + 12, b.sc[2], raw);
-    fold_u8<4>(p2, T.w + 16, b.sc[3], raw);
+    fold_u8<4>(g, T.w, b.sc[0], raw);
+    fold_u8<2>(p0, T.w + 8, b.sc[1], raw);
+    fold_u8<2>(p1, T.w + 12, b.sc[2], raw);
+    fold_u8<2>(p2, T.w + 16, b.sc[3], raw);
 }
 
-// fp32 block: a texel is two 16-byte halves (channels 0-3, 4-7).  All 40
-// loads are issued before any is consumed, so one sample's memory latency is
-// paid once; the four textures are then summed ((G + XY) + XZ) + YZ.
+// fp32 block: a texel pair is 64 contiguous bytes (channels 0-3, 4-7 of each
+// texel).  All 40 loads are issued before any is consumed, so one sample's
+// memory latency is paid once; the four textures are then summed
+// ((G + XY) + XZ) + YZ.
 __device__ inline void raw_f32(const BlockU& b, const Taps& T, float raw[kNch]) {
     float4 lo[20], hi[20];
 #pragma unroll
-    for (int k = 0; k < 20; ++k) {
-        const int tex = k < 8 ? 0 : 1 + (k - 8) / 4;
-        lo[k] = ld16(b.tex[tex], 32 * T.idx[k]);
-        hi[k] = ld16(b.tex[tex], 32 * T.idx[k] + 16);
+    for (int j = 0; j < 10; ++j) {
+        const __amdgpu_buffer_rsrc_t r = b.tex[pair_tex(j)];
+        const int off = 32 * T.pidx[j];
+        lo[2 * j] = ld16(r, off);
+        hi[2 * j] = ld16(r, off + 16);
+        lo[2 * j + 1] = ld16(r, off + 32);
+        hi[2 * j + 1] = ld16(r, off + 48);
     }
 #pragma unroll
     for (int tex = 0; tex < 4; ++tex) {
@@ -412,7 +442,11 @@ __device__ inline void raw_f32(const BlockU& b, const Taps& T, float raw[kNch]) 
 __device__ inline float raw0_f32(const BlockU& b, const Taps& T) {
     float v[20];
 #pragma unroll
-    for (int k = 0; k < 20; ++k) v[k] = ld4(b.tex[k < 8 ? 0 : 1 + (k - 8) / 4], 32 * T.idx[k]);
+    for (int j = 0; j < 10; ++j) {
+        const __amdgpu_buffer_rsrc_t r = b.tex[pair_tex(j)];
+        v[2 * j] = ld4(r, 32 * T.pidx[j]);
+        v[2 * j + 1] = ld4(r, 32 * T.pidx[j] + 32);
+    }
     float raw = 0.0f;
 #pragma unroll
     for (int tex = 0; tex < 4; ++tex) {

@@ -118,6 +118,8 @@ cow_status validate_desc(cow_ctx* c, const cow_block_desc& d) {
         return fail(c, COW_E_INVALID, who + "resolutions must be powers of two");
     if (d.grid_res % d.occ_res || d.plane_res % d.occ_res || d.occ_res > d.grid_res)
         return fail(c, COW_E_INVALID, who + "occupancy resolution must divide grid and plane resolution");
+    if (d.grid_res < 2 || d.plane_res < 2)
+        return fail(c, COW_E_INVALID, who + "grid and plane resolution must be at least 2");
     if (d.grid_res > 1024 || d.plane_res > 8192)
         return fail(c, COW_E_INVALID, who + "resolution too large for 32-bit texel offsets");
     const size_t tex = d.dtype == COW_U8 ? 8 : 32;
@@ -135,8 +137,9 @@ cow_status validate_desc(cow_ctx* c, const cow_block_desc& d) {
     if (d.dtype == COW_U8)
         for (int t = 0; t < 4; ++t)
             for (int ch = 0; ch < 8; ++ch)
-                if (!std::isfinite(d.scale[t][ch]) || !std::isfinite(d.offset[t][ch]))
-                    return fail(c, COW_E_INVALID, who + "non-finite scale/offset");
+                if (!std::isfinite(d.scale[t][ch]) || !std::isfinite(d.offset[t][ch]) ||
+                    std::fabs(d.scale[t][ch]) > 1e30f)
+                    return fail(c, COW_E_INVALID, who + "non-finite or too large scale/offset");
     return COW_OK;
 }
 

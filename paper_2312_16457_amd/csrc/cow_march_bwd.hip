@@ -20,8 +20,8 @@ namespace cow {
 // merged composite equals the monolithic one over the same sequence
 // (Appendix A), so one running prefix serves all blocks in order.
 // Texel-gradient scatter, one collective step per wave.  Each interpolation
-// tap pair (texels i0 and i0 + 1 along the fastest axis) of a lane is 16
-// contiguous floats (8 channels each) when i1 = i0 + 1.  The lanes stage
+// tap pair (texels p and p + 1 along the fastest axis) of a lane is 16
+// contiguous floats (8 channels each).  The lanes stage
 // their pairs in LDS and read them back transposed, so that one atomic
 // instruction covers four lanes' 64-byte runs instead of 64 scattered texels:
 // far fewer cache-line requests for the L2 atomic units.
@@ -33,9 +33,9 @@ __device__ inline void scatter_pairs(ScatterLds& L, int lane, const Taps& T, con
                                      float* const gptr[4], const __amdgpu_buffer_rsrc_t gr[4], bool have) {
 #pragma unroll
     for (int pr = 0; pr < 10; ++pr) {
-        const int tex = pr < 4 ? 0 : 1 + (pr - 4) / 2;
+        const int tex = pair_tex(pr);
         if (!gptr[tex]) continue;
-        const int ka = 2 * pr, kb2 = 2 * pr + 1;  // taps 2pr, 2pr+1 differ by one texel along x / u
+        const int ka = 2 * pr, kb2 = 2 * pr + 1;  // taps of texels p and p + 1 along x / u
         float* row = L.v[lane];
         if (have) {
 #pragma unroll
@@ -43,8 +43,8 @@ __device__ inline void scatter_pairs(ScatterLds& L, int lane, const Taps& T, con
                 row[c] = T.w[ka] * draw[c];
                 row[8 + c] = T.w[kb2] * draw[c];
             }
-            row[16] = __int_as_float(T.idx[ka] * 32);
-            row[17] = __int_as_float(T.idx[kb2] * 32);
+            row[16] = __int_as_float(T.pidx[pr] * 32);
+            row[17] = __int_as_float(T.pidx[pr] * 32 + 32);
         } else {
             row[16] = __int_as_float(-1);
             row[17] = __int_as_float(-1);

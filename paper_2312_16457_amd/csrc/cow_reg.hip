@@ -59,8 +59,10 @@ __global__ __launch_bounds__(256) void sparsity_kernel(SparsityArgs s) {
             for (int t = 1; t < 4; ++t) gr[t] = tex_rsrc(gp[t], (uint32_t)b.Rp * b.Rp * 32u);
 #pragma unroll
             for (int k = 0; k < 20; ++k) {
-                const int tex = k < 8 ? 0 : 1 + (k - 8) / 4;
-                if (gp[tex]) __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(T.w[k] * g, gr[tex], 32 * T.idx[k], 0, 0);
+                const int tex = pair_tex(k >> 1);
+                if (gp[tex])
+                    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(T.w[k] * g, gr[tex], 32 * (T.pidx[k >> 1] + (k & 1)),
+                                                                    0, 0);
             }
         }
     }
