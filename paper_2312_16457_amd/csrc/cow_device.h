@@ -271,16 +271,17 @@ struct Lin {
     float w0, w1;  // weights of texels p and p + 1
 };
 
+// Clamping u to [0, R - 1] first gives both edge cases directly: p = 0 with
+// f = 0 below, p = R - 2 with f = 1 above; inside, f = u - floor(u).
 __device__ inline Lin lin_pair(float q, int R) {
     const float u = q * (float)R - 0.5f;
-    const float fl = floorf(u);
-    const int a = (int)fl;
-    const float f = u - fl;
+    const float uc = __builtin_amdgcn_fmed3f(u, 0.0f, (float)(R - 1));
+    const int a = (int)uc;
     Lin t;
-    const bool lo = a < 0, hi = a > R - 2;
-    t.p = lo ? 0 : (hi ? R - 2 : a);
-    t.w0 = lo ? 1.0f : (hi ? 0.0f : 1.0f - f);
-    t.w1 = lo ? 0.0f : (hi ? 1.0f : f);
+    t.p = a < R - 2 ? a : R - 2;
+    const float f = uc - (float)t.p;
+    t.w0 = 1.0f - f;
+    t.w1 = f;
     return t;
 }
 
