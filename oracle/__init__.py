@@ -21,7 +21,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 
-MERGED, MONOLITHIC, REVERSED, BY_ID, ALPHA_NORM = range(5)
+MERGED, MONOLITHIC, REVERSED, BY_ID, ALPHA_NORM, BLOCK_MLP = range(6)
 
 
 def build():
@@ -77,6 +77,9 @@ def lib():
         L.orc_adjoint.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), C.POINTER(_View),
                                   vp, C.c_int, C.POINTER(_Params), vp, vp, C.c_int, vp, vp, vp,
                                   C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), vp]
+        L.orc_adjoint_block_mlp.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), C.POINTER(_View),
+                                            vp, C.c_int, C.POINTER(_Params), vp, vp, C.c_int, vp, vp, vp,
+                                            C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), vp]
         L.orc_opacity.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), C.POINTER(_View),
                                   vp, C.c_int, C.POINTER(_Params), vp, C.c_int, vp]
         L.orc_sparsity.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), vp, C.c_int, vp,
@@ -202,6 +205,8 @@ def render(ob, occs, view, set_idx, params, mlp, pix=None, composite=MERGED, nth
     n = pix.shape[0]
     setv = np.ascontiguousarray(set_idx, np.int32)
     w = np.ascontiguousarray(mlp, np.float64)
+    if composite == BLOCK_MLP and w.size != 499 * ob.n:
+        raise ValueError("BLOCK_MLP needs one 499-weight MLP per entry of the scene")
     out = dict(rgb=np.zeros((n, 3)), trans=np.zeros(n), aux=np.zeros((n, 8)),
                n_eval=np.zeros(n, np.int64), n_march=np.zeros(n, np.int64),
                order_ok=np.zeros(n, np.int32))
@@ -291,6 +296,29 @@ def adjoint(ob, occs, view, set_idx, params, mlp, pix, grad_rgb, grad_trans=None
     if r != 0:
         raise ValueError("adjoint needs float blocks")
     return grads, gm
+
+
+def adjoint_block_mlp(ob, occs, view, set_idx, params, mlps, pix, grad_rgb, grad_trans=None, w_opacity=None):
+    """fp64 adjoint of the per-block deferred composite (BLOCK_MLP);
+    mlps [ob.n][499]; returns ({block: (grad_grid, [grad_planes])}, grad_mlps [ob.n][499])."""
+    L = lib()
+    pix = np.ascontiguousarray(pix, np.int32)
+    setv = np.ascontiguousarray(set_idx, np.int32)
+    grads, gg, gp = _grad_arrays(ob, set(int(s) for s in setv))
+    w = np.ascontiguousarray(mlps, np.float64).reshape(-1)
+    if w.size != 499 * ob.n:
+        raise ValueError("one 499-weight MLP per entry of the scene")
+    gm = np.zeros(499 * ob.n, np.float64)
+    gr = np.ascontiguousarray(grad_rgb, np.float64)
+    gt = None if grad_trans is None else np.ascontiguousarray(grad_trans, np.float64)
+    wo = None if w_opacity is None else np.ascontiguousarray(w_opacity, np.float64)
+    vs, ps_ = make_view(view), make_params(params)
+    r = L.orc_adjoint_block_mlp(ob.arr, ob.n, _occ_ptrs(ob, occs), C.byref(vs), _ptr(setv), len(setv),
+                                C.byref(ps_), _ptr(w), _ptr(pix), pix.shape[0], _ptr(gr), _ptr(gt), _ptr(wo),
+                                gg, gp, _ptr(gm))
+    if r != 0:
+        raise ValueError("adjoint needs float blocks")
+    return grads, gm.reshape(ob.n, 499)
 
 
 def select(view, entries, ztops, thresholds=(2.0, 4.0, 8.0), cull=True, cap=4096):

@@ -456,13 +456,16 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
                 break;
             }
         }
-    } else if (composite == ORC_MERGED) {
+    } else if (composite == ORC_MERGED || composite == ORC_BLOCK_MLP) {
         /* per-block composite (Eq. "volume rendering inside blocks"), merged
          * front to back in ray order (Eq. "volume rendering across blocks")
-         * with the block transmittance carried as the product of (1 - alpha_i) */
+         * with the block transmittance carried as the product of (1 - alpha_i).
+         * ORC_BLOCK_MLP shades each block with its own deferred MLP first and
+         * merges the colours C^k instead of (C_d^k, F^k) */
         eval = 0;
         long s = 0;
         int stop = 0;
+        double Cb[3] = {0, 0, 0};
         while (s < n && !stop) {
             const int run = buf[s].set_pos;
             double Ak[7] = {0}, Tk = 1.0;
@@ -483,8 +486,28 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
                     break;
                 }
             }
+            if (composite == ORC_BLOCK_MLP) {
+                double x[10];
+                for (int c = 0; c < 7; ++c) x[c] = Ak[c];
+                for (int c = 0; c < 3; ++c) x[7 + c] = d[c];
+                mlp_trace tr;
+                mlp_fwd(mlp + 499 * (long)set[run], x, &tr);
+                for (int c = 0; c < 3; ++c) Cb[c] += T * (Ak[c] + tr.s[c]);
+            }
             for (int c = 0; c < 7; ++c) A[c] += T * Ak[c];
             T *= Tk;
+        }
+        if (composite == ORC_BLOCK_MLP) {
+            free(run_pos);
+            for (int c = 0; c < 3; ++c) rgb[c] = Cb[c];
+            *trans = T;
+            for (int c = 0; c < 8; ++c) aux[c] = 0.0;
+            for (int c = 0; c < 3; ++c) aux[c] = Cb[c];
+            aux[7] = T;
+            *ne = eval;
+            *nm = n_used;
+            *ook = ordered;
+            return;
         }
     } else {
         /* negative controls: per-block composites combined some other way */
@@ -759,6 +782,163 @@ int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const
     free(Tb);
     free(suf);
     free(ev);
+    (void)nblocks;
+    return 0;
+}
+
+/* Adjoint of the per-block deferred composite.  Per block k (in ray order)
+ * with local composite (A^k, T^k), prefix transmittance P_k and colour
+ * C^k = A^k[0..2] + sigmoid(Phi^k(A^k, d)):
+ *   C = sum_k P_k C^k, T = prod_k T^k,
+ *   dL/dA^k = P_k (g on C_d) + P_k J_Phi^T (g * s (1 - s)),
+ *   T^k dL/dT^k = g . R_k + gT T with R_k = sum_{k'>k} P_k' C^k',
+ * and inside block k the single-chain adjoint with u = dL/dA^k. */
+int orc_adjoint_block_mlp(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
+                          const orc_view* v, const int* set, int nset, const orc_params* p,
+                          const double* mlp, const int* pix, int npix, const double* grad_rgb,
+                          const double* grad_trans, const double* w_opacity, double* const* grad_grid,
+                          double* const* grad_plane, double* grad_mlp) {
+    for (int s = 0; s < nset; ++s)
+        if (blocks[set[s]].dtype != ORC_F64) return -1;
+    long cap = sample_cap(p, nset);
+    sample* buf = (sample*)malloc(sizeof(sample) * cap);
+    pt_val* pv = (pt_val*)malloc(sizeof(pt_val) * cap);
+    tap* taps = (tap*)malloc(sizeof(tap) * 20 * cap);
+    double* Tl = (double*)malloc(sizeof(double) * (cap + 1)); /* local T before each sample */
+    long* ev = (long*)malloc(sizeof(long) * cap);
+    int nb_max = nset + 1;
+    long* rb = (long*)malloc(sizeof(long) * (nb_max + 1)); /* first evaluated sample of each run */
+    int* rpos = (int*)malloc(sizeof(int) * nb_max);
+    double* Ak = (double*)malloc(sizeof(double) * 7 * nb_max);
+    double* Tk = (double*)malloc(sizeof(double) * nb_max);
+    double* Pk = (double*)malloc(sizeof(double) * nb_max);
+    double* Ck = (double*)malloc(sizeof(double) * 3 * nb_max);
+    mlp_trace* tr = (mlp_trace*)malloc(sizeof(mlp_trace) * nb_max);
+    for (int q = 0; q < npix; ++q) {
+        float d[3];
+        long n = enumerate(blocks, nblocks, occ, v, set, nset, p, pix[2 * q], pix[2 * q + 1], buf, cap, d);
+        /* forward, run by run, with early termination */
+        int nr = 0;
+        long m = 0;
+        double P = 1.0;
+        long s = 0;
+        int stop = 0;
+        while (s < n && !stop) {
+            const int run = buf[s].set_pos;
+            rpos[nr] = run;
+            rb[nr] = m;
+            double A[7] = {0}, T = 1.0;
+            for (; s < n && buf[s].set_pos == run; ++s) {
+                if (!buf[s].occupied) continue;
+                double raw[NCH];
+                shade(&blocks[set[run]], buf[s].q, &pv[m], raw, &taps[20 * m]);
+                double sd = pv[m].sigma * buf[s].delta;
+                double alpha = -expm1(-sd);
+                Tl[m] = T;
+                for (int c = 0; c < 7; ++c) A[c] += T * alpha * pv[m].v[c];
+                T *= exp(-sd);
+                ev[m++] = s;
+                if (p->t_min > 0.0f && P * T < (double)p->t_min) {
+                    stop = 1;
+                    break;
+                }
+            }
+            for (int c = 0; c < 7; ++c) Ak[7 * nr + c] = A[c];
+            Tk[nr] = T;
+            Pk[nr] = P;
+            double x[10];
+            for (int c = 0; c < 7; ++c) x[c] = A[c];
+            for (int c = 0; c < 3; ++c) x[7 + c] = d[c];
+            mlp_fwd(mlp + 499 * (long)set[run], x, &tr[nr]);
+            for (int c = 0; c < 3; ++c) Ck[3 * nr + c] = A[c] + tr[nr].s[c];
+            P *= T;
+            ++nr;
+        }
+        rb[nr] = m;
+        const double Ttot = P;
+        const double* g = grad_rgb + 3 * q;
+        const double gT = grad_trans ? grad_trans[q] : 0.0;
+        double R[3] = {0, 0, 0}; /* sum over later blocks of P_k' C^k' */
+        for (int k = nr - 1; k >= 0; --k) {
+            const double* W1 = mlp + 499 * (long)set[rpos[k]];
+            const double *W2 = W1 + 176, *W3 = W1 + 448;
+            double dz[3], dh2[16], dh1[16], dx[10];
+            for (int o = 0; o < 3; ++o) dz[o] = Pk[k] * g[o] * tr[k].s[o] * (1.0 - tr[k].s[o]);
+            for (int i = 0; i < 16; ++i) {
+                double a = 0.0;
+                for (int o = 0; o < 3; ++o) a += W3[o * 16 + i] * dz[o];
+                dh2[i] = tr[k].pre2[i] > 0.0 ? a : 0.0;
+            }
+            for (int i = 0; i < 16; ++i) {
+                double a = 0.0;
+                for (int o = 0; o < 16; ++o) a += W2[o * 16 + i] * dh2[o];
+                dh1[i] = tr[k].pre1[i] > 0.0 ? a : 0.0;
+            }
+            for (int i = 0; i < 10; ++i) {
+                double a = 0.0;
+                for (int o = 0; o < 16; ++o) a += W1[o * 10 + i] * dh1[o];
+                dx[i] = a;
+            }
+            if (grad_mlp) {
+                double* gm = grad_mlp + 499 * (long)set[rpos[k]];
+                for (int o = 0; o < 16; ++o) {
+                    for (int i = 0; i < 10; ++i) gm[o * 10 + i] += dh1[o] * tr[k].x[i];
+                    gm[160 + o] += dh1[o];
+                    for (int i = 0; i < 16; ++i) gm[176 + o * 16 + i] += dh2[o] * tr[k].h1[i];
+                    gm[432 + o] += dh2[o];
+                }
+                for (int o = 0; o < 3; ++o) {
+                    for (int i = 0; i < 16; ++i) gm[448 + o * 16 + i] += dz[o] * tr[k].h2[i];
+                    gm[496 + o] += dz[o];
+                }
+            }
+            double u[7];
+            for (int c = 0; c < 7; ++c) u[c] = dx[c] + (c < 3 ? Pk[k] * g[c] : 0.0);
+            const double tT = g[0] * R[0] + g[1] * R[1] + g[2] * R[2] + gT * Ttot; /* T^k dL/dT^k */
+            /* opacity term of this block: w h'(1 - T^k) T^k per unit step */
+            double gop = 0.0;
+            if (w_opacity && w_opacity[q] != 0.0) gop = w_opacity[q] * opac_dh(1.0 - Tk[k]) * Tk[k];
+            /* inside the block: suffix sums of w_j v_j */
+            double S[7] = {0, 0, 0, 0, 0, 0, 0};
+            for (long e = rb[k + 1] - 1; e >= rb[k]; --e) {
+                const sample* sm = &buf[ev[e]];
+                double delta = sm->delta;
+                double alpha = -expm1(-pv[e].sigma * delta);
+                double w = Tl[e] * alpha;
+                double Tn = Tl[e] * exp(-pv[e].sigma * delta);
+                double uv = 0.0, us = 0.0;
+                for (int c = 0; c < 7; ++c) {
+                    uv += u[c] * pv[e].v[c];
+                    us += u[c] * S[c];
+                }
+                double dsig = delta * (Tn * uv - us) - delta * tT + delta * gop;
+                double draw[NCH];
+                draw[0] = pv[e].sigma * dsig;
+                for (int c = 0; c < 7; ++c) draw[1 + c] = w * u[c] * pv[e].v[c] * (1.0 - pv[e].v[c]);
+                int b = set[sm->set_pos];
+                for (int t = 0; t < 20; ++t) {
+                    const tap* tp = &taps[20 * e + t];
+                    double* dst = tp->tex == 0 ? grad_grid[b] : grad_plane[3 * b + tp->tex - 1];
+                    if (!dst) continue;
+                    for (int ch = 0; ch < NCH; ++ch) dst[tp->idx * NCH + ch] += tp->w * draw[ch];
+                }
+                for (int c = 0; c < 7; ++c) S[c] += w * pv[e].v[c];
+            }
+            for (int c = 0; c < 3; ++c) R[c] += Pk[k] * Ck[3 * k + c];
+        }
+    }
+    free(buf);
+    free(pv);
+    free(taps);
+    free(Tl);
+    free(ev);
+    free(rb);
+    free(rpos);
+    free(Ak);
+    free(Tk);
+    free(Pk);
+    free(Ck);
+    free(tr);
     (void)nblocks;
     return 0;
 }

@@ -53,7 +53,12 @@ enum {
     ORC_MONOLITHIC = 1,      /* one composite over the whole sample sequence */
     ORC_REVERSED = 2,        /* negative control: merge in reverse entry order */
     ORC_BY_ID = 3,           /* negative control: merge in block-id order */
-    ORC_ALPHA_NORM = 4       /* negative control: blend blocks with alpha^k / sum alpha^j */
+    ORC_ALPHA_NORM = 4,      /* negative control: blend blocks with alpha^k / sum alpha^j */
+    ORC_BLOCK_MLP = 5        /* per-block deferred shading before the merge (Eq. across as
+                                written): mlp holds one 499-weight MLP per entry of `blocks`;
+                                C = sum_k prod_{j<k} T^j (C_d^k + sigmoid(Phi^k(C_d^k, F^k, d)))
+                                over the blocks the ray marches at least one sample in;
+                                aux = (C, 0, 0, 0, 0, T) */
 };
 
 /* occupancy bits [O][O][O] (z,y,x) of one block by the conservative max-bound rule */
@@ -86,6 +91,15 @@ int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const
                 const double* mlp, const int* pix, int npix, const double* grad_rgb,
                 const double* grad_trans, const double* w_opacity, double* const* grad_grid,
                 double* const* grad_plane, double* grad_mlp);
+
+/* fp64 adjoint of the ORC_BLOCK_MLP composite: mlp[nblocks*499] per entry;
+ * gradients ACCUMULATED into grad_grid / grad_plane as in orc_adjoint and
+ * into grad_mlp[nblocks*499] (nullable).  grad_trans, w_opacity nullable. */
+int orc_adjoint_block_mlp(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
+                          const orc_view* v, const int* set, int nset, const orc_params* p,
+                          const double* mlp, const int* pix, int npix, const double* grad_rgb,
+                          const double* grad_trans, const double* w_opacity, double* const* grad_grid,
+                          double* const* grad_plane, double* grad_mlp);
 
 /* Block-opacity entropy of each ray (Eq. "opacity loss"):
  * -sum_k (a log a + (1 - a) log(1 - a)), a = clamp(1 - T^k, 1e-6, 1 - 1e-6),

@@ -693,3 +693,113 @@ def test_sparsity_closed_form_and_gradient():
             assert abs(arr_g[idx] - fd) <= 1e-5 * abs(fd) + 1e-8 * gmax, (k, arr_i, idx, arr_g[idx], fd)
             checked += 1
     assert checked == 4 * ob.n
+
+
+# ---------------------------------------------------------------------------
+# Per-block deferred shading before the merge (Eq. across as written, each
+# block with its own MLP): one block reduces to the single-MLP render;
+# homogeneous blocks with constant-output MLPs give the closed form
+# sum_k prod_{j<k} T^j ((1 - T^k) c^k + sigmoid(b3^k)); the adjoint matches
+# finite differences in textures and in every block's MLP weights
+# ---------------------------------------------------------------------------
+def constant_mlp(b3):
+    w = np.zeros(sg.MLP_NPARAM)
+    w[496:499] = b3
+    return w
+
+
+def test_block_mlp_single_block_equals_global():
+    scene = sg.c1_scene()
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, 0)]
+    v = sg.c1_view()
+    w = sg.random_mlp(3, 0.6).astype(np.float64)
+    g = O.render(ob, occs, v, [0], sg.c1_params(), w)
+    b = O.render(ob, occs, v, [0], sg.c1_params(), w.reshape(1, -1), composite=O.BLOCK_MLP)
+    hit = g["n_march"] > 0
+    assert hit.sum() > 1000 and (~hit).sum() > 100
+    np.testing.assert_allclose(b["rgb"][hit], g["rgb"][hit], atol=1e-13)
+    assert (b["rgb"][~hit] == 0).all() and (b["trans"] == g["trans"]).all()
+    assert np.abs(b["aux"][:, :3] - b["rgb"]).max() == 0 and (b["aux"][:, 7] == b["trans"]).all()
+
+
+def test_block_mlp_closed_form_three_blocks():
+    sig_col = [(0.7, (0.9, 0.1, 0.1)), (2.0, (0.1, 0.9, 0.1)), (0.4, (0.1, 0.1, 0.9))]
+    blocks = [sg.homogeneous_block(sigma=s, color=c, block_id=k, origin=(k, 0, 0)) for k, (s, c) in enumerate(sig_col)]
+    ob = O.OracleScene(blocks)
+    occs = [O.occupancy(ob, k) for k in range(3)]
+    v = axis_view((-0.25, 0.5, 0.5), (1.0, 0.0, 0.0))
+    b3 = np.array([[0.3, -1.0, 2.0], [-0.5, 0.5, 0.0], [1.5, 1.0, -2.0]])
+    mlps = np.stack([constant_mlp(b3[k]) for k in range(3)])
+    r = O.render(ob, occs, v, [2, 0, 1], sg.RenderParams(mode=1), mlps, composite=O.BLOCK_MLP)
+    C = np.zeros(3)
+    P = 1.0
+    for k, blk in enumerate(blocks):
+        s, c, _ = stored_constants(blk)
+        Tk = math.exp(-s)
+        C += P * ((1 - Tk) * c + sig(b3[k]))
+        P *= Tk
+    np.testing.assert_allclose(r["rgb"][0], C, atol=1e-12)
+    assert abs(r["trans"][0] - P) < 1e-12
+    # the single-MLP render of the same rays adds the specular term once, not per block
+    g = O.render(ob, occs, v, [2, 0, 1], sg.RenderParams(mode=1), mlps[0])
+    assert np.abs(g["rgb"][0] - r["rgb"][0]).max() > 0.1
+
+
+@pytest.mark.parametrize("extra", ["rgb", "trans_opacity"])
+def test_block_mlp_adjoint_matches_finite_differences(extra):
+    scene = tiny_city(nb=2, lods=((8, 16, 4),), shift=1.5, blobs=8, seed=13)
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    v = tiny_view(10, 8, eye=(1.0, -0.8, 1.1), target=(1.0, 1.0, 0.15))
+    p = sg.RenderParams(mode=1, delta=1.0 / 128, max_steps=4096)
+    mlps = np.stack([kink_free_mlp(20 + k) for k in range(ob.n)])
+    setv = list(range(ob.n))
+    pix = O.pixels_of(v)
+    rng = np.random.default_rng(4)
+    target = rng.uniform(0, 1, (len(pix), 3))
+    g_tr = rng.uniform(-0.5, 0.5, len(pix)) if extra != "rgb" else None
+    w_op = rng.uniform(0.1, 1.0, len(pix)) if extra != "rgb" else None
+
+    def loss():
+        r = O.render(ob, occs, v, setv, p, mlps, pix=pix, composite=O.BLOCK_MLP)
+        L = np.mean((r["rgb"] - target) ** 2)
+        if extra != "rgb":
+            L += np.sum(g_tr * r["trans"]) + np.sum(w_op * O.opacity(ob, occs, v, setv, p, pix))
+        return L, r
+
+    L0, r0 = loss()
+    g_rgb = 2 * (r0["rgb"] - target) / target.size
+    grads, gm = O.adjoint_block_mlp(ob, occs, v, setv, p, mlps, pix, g_rgb, g_tr, w_op)
+    gmax = max(max(np.abs(g).max(), max(np.abs(q).max() for q in ps)) for g, ps in grads.values())
+    h = 1e-4
+    checked = 0
+    for k, (g, ps) in grads.items():
+        for arr_i, arr_g in enumerate([g] + ps):
+            nz = np.argwhere(np.abs(arr_g) > 1e-3 * gmax)
+            for _ in range(2):
+                idx = tuple(nz[rng.integers(len(nz))])
+                fg, fps = ob.f64[k]
+                arr = fg if arr_i == 0 else fps[arr_i - 1]
+                old = arr[idx]
+                arr[idx] = old + h
+                Lp, _ = loss()
+                arr[idx] = old - h
+                Lm, _ = loss()
+                arr[idx] = old
+                fd = (Lp - Lm) / (2 * h)
+                assert abs(arr_g[idx] - fd) <= 1e-4 * abs(fd) + 1e-6 * gmax, (k, arr_i, idx, arr_g[idx], fd)
+                checked += 1
+    for k in range(ob.n):  # every block's own MLP
+        assert np.abs(gm[k]).max() > 0
+        for i in rng.choice(499, 6, replace=False):
+            old = mlps[k, i]
+            mlps[k, i] = old + h
+            Lp, _ = loss()
+            mlps[k, i] = old - h
+            Lm, _ = loss()
+            mlps[k, i] = old
+            fd = (Lp - Lm) / (2 * h)
+            assert abs(gm[k, i] - fd) <= 1e-4 * abs(fd) + 1e-8, (k, i, gm[k, i], fd)
+            checked += 1
+    assert checked >= 40
