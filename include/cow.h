@@ -137,6 +137,15 @@ typedef struct cow_render_params {
      * ray marches at least one sample (up to its early termination). */
     float* opacity;                 /* cow_render: device [P] per-ray entropy sum, or NULL */
     const float* opacity_weight;    /* cow_render_backward: device [P] dL/d(that sum), or NULL */
+    /* Per-block deferred shading (Sec. 4.2, the across-block equation as
+     * written): every block the ray marches at least one sample in is shaded
+     * with its own MLP, C^k = C_d^k + sigmoid(Phi^k(C_d^k, F^k, d)), and
+     * C = sum_k prod_{j<k} T^j C^k.  Device [loaded entries][499] in load
+     * order, or NULL for one MLP after the merge.  When set, the mlp argument
+     * of cow_render / cow_render_backward is unused (may be NULL) and aux
+     * holds (C, 0, 0, 0, 0, T). */
+    const float* block_mlp;
+    float* grad_block_mlp;          /* cow_render_backward: device [entries][499], accumulated, or NULL */
 } cow_render_params;
 
 /* Create a context bound to HIP device `device` (host state only). */

@@ -57,7 +57,7 @@ class LodPolicy(C.Structure):
 class Params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_steps", C.c_int32), ("delta", C.c_float), ("max_steps", C.c_int32),
                 ("t_min", C.c_float), ("flags", C.c_int32), ("counts", C.c_void_p), ("opacity", C.c_void_p),
-                ("opacity_weight", C.c_void_p)]
+                ("opacity_weight", C.c_void_p), ("block_mlp", C.c_void_p), ("grad_block_mlp", C.c_void_p)]
 
 
 _lib = None
@@ -109,7 +109,7 @@ def make_view(v):
     return s
 
 
-def make_params(p, flags=0, counts=None, opacity=None, opacity_weight=None):
+def make_params(p, flags=0, counts=None, opacity=None, opacity_weight=None, block_mlp=None, grad_block_mlp=None):
     s = Params()
     s.mode, s.n_steps, s.delta, s.max_steps = int(p.mode), int(p.n_steps), float(p.delta), int(p.max_steps)
     s.t_min = float(getattr(p, "t_min", 0.0))
@@ -117,6 +117,8 @@ def make_params(p, flags=0, counts=None, opacity=None, opacity_weight=None):
     s.counts = None if counts is None else counts.data_ptr()
     s.opacity = None if opacity is None else opacity.data_ptr()
     s.opacity_weight = None if opacity_weight is None else opacity_weight.data_ptr()
+    s.block_mlp = None if block_mlp is None else block_mlp.data_ptr()
+    s.grad_block_mlp = None if grad_block_mlp is None else grad_block_mlp.data_ptr()
     return s
 
 
@@ -251,7 +253,19 @@ class Renderer:
             setattr(self, attr, cur)
         return cur
 
-    def render(self, views, sets, params, mlp, want_aux=True, counts=False, flags=0, out=None, opacity=False):
+    def _check_block_mlp(self, block_mlp):
+        torch = self.torch
+        if block_mlp is None:
+            return None
+        if (block_mlp.dtype != torch.float32 or block_mlp.device != self.device
+                or block_mlp.numel() != 499 * len(self.blocks)):
+            raise ValueError("block_mlp must be [loaded entries][499] float32 on the device")
+        return block_mlp.contiguous()
+
+    def render(self, views, sets, params, mlp, want_aux=True, counts=False, flags=0, out=None, opacity=False,
+               block_mlp=None):
+        """block_mlp: [loaded entries][499] per-block deferred MLPs (shading
+        before the merge); mlp is then unused and may be None."""
         torch = self.torch
         vs = (View * len(views))(*[make_view(v) for v in views])
         cs, keep = self._sets(sets)
@@ -263,11 +277,13 @@ class Renderer:
                        counts=torch.zeros((n_pix, 2), dtype=torch.int64, device=self.device) if counts else None,
                        opacity=torch.zeros(n_pix, dtype=torch.float32, device=self.device) if opacity else None)
         ws = self._ws("render_ws", len(views), n_pix)
-        p = make_params(params, flags, out.get("counts"), out.get("opacity"))
-        if mlp.dtype != torch.float32 or mlp.device != self.device or mlp.numel() != 499:
+        bm = self._check_block_mlp(block_mlp)
+        p = make_params(params, flags, out.get("counts"), out.get("opacity"), block_mlp=bm)
+        if bm is None and (mlp is None or mlp.dtype != torch.float32 or mlp.device != self.device
+                           or mlp.numel() != 499):
             raise ValueError("mlp must be 499 float32 values on the device")
         aux = out.get("aux")
-        self._check(self.L.cow_render(self.h, vs, len(views), cs, C.byref(p), mlp.data_ptr(),
+        self._check(self.L.cow_render(self.h, vs, len(views), cs, C.byref(p), None if mlp is None else mlp.data_ptr(),
                                       out["rgb"].data_ptr(), out["trans"].data_ptr(),
                                       None if aux is None else aux.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
         return out
@@ -286,7 +302,7 @@ class Renderer:
         return gg, gp
 
     def render_backward(self, views, sets, params, mlp, aux, grad_rgb, grad_trans=None, grad_grid=None,
-                        grad_plane=None, grad_mlp=None, opacity_weight=None):
+                        grad_plane=None, grad_mlp=None, opacity_weight=None, block_mlp=None, grad_block_mlp=None):
         """grad_grid[e] / grad_plane[e][k]: torch fp32 tensors (or None) per
         loaded entry e, accumulated in place; grad_mlp likewise.
         opacity_weight: per-pixel dL/d(opacity regulariser) or None."""
@@ -296,9 +312,13 @@ class Renderer:
         ws = self._ws("bwd_ws", len(views), n_pix, backward=True)
         gg, gp = self._grad_tables(grad_grid, grad_plane)
         ow = None if opacity_weight is None else opacity_weight.contiguous()
-        p = make_params(params, opacity_weight=ow)
+        bm = self._check_block_mlp(block_mlp)
+        if grad_block_mlp is not None and grad_block_mlp.numel() != 499 * len(self.blocks):
+            raise ValueError("grad_block_mlp must be [loaded entries][499]")
+        p = make_params(params, opacity_weight=ow, block_mlp=bm, grad_block_mlp=grad_block_mlp)
         self._check(self.L.cow_render_backward(
-            self.h, vs, len(views), cs, C.byref(p), mlp.data_ptr(), aux.data_ptr(), grad_rgb.contiguous().data_ptr(),
+            self.h, vs, len(views), cs, C.byref(p), None if mlp is None else mlp.data_ptr(), aux.data_ptr(),
+            grad_rgb.contiguous().data_ptr(),
             None if grad_trans is None else grad_trans.contiguous().data_ptr(), gg, gp,
             None if grad_mlp is None else grad_mlp.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
 

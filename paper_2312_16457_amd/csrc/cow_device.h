@@ -477,6 +477,39 @@ __device__ inline float alpha_of(float x) {
     return x < 0.0625f ? series : 1.0f - __expf(-x);
 }
 
+// One block's deferred shading for one lane (Eq. "deferred" per block):
+// C = C_d + sigmoid(Phi(C_d, F, d)), Phi 10 -> 16 -> 16 -> 3 with ReLU, the
+// 499 weights laid out W1[16][10], b1, W2[16][16], b2, W3[3][16], b3 and read
+// through a wave-uniform pointer (scalar loads).
+__device__ inline void block_shade(const float* w, const float A[7], const float d[3], float C[3]) {
+    float x[10], h1[16], h2[16];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) x[c] = A[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[7 + c] = d[c];
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+        float a = w[160 + o];
+#pragma unroll
+        for (int i = 0; i < 10; ++i) a = fmaf(w[o * 10 + i], x[i], a);
+        h1[o] = fmaxf(a, 0.0f);
+    }
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+        float a = w[432 + o];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a = fmaf(w[176 + o * 16 + i], h1[i], a);
+        h2[o] = fmaxf(a, 0.0f);
+    }
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        float a = w[496 + o];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a = fmaf(w[448 + o * 16 + i], h2[i], a);
+        C[o] = A[o] + sigmoidf_(a);
+    }
+}
+
 // Binary entropy of a block's opacity a = 1 - Tk (Eq. "opacity loss"), with
 // a clamped to [1e-6, 1 - 1e-6] so that both logarithms stay finite; 1 - a
 // is taken as Tk itself (no cancellation).  The derivative in a is

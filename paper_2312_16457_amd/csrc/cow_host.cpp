@@ -358,6 +358,8 @@ cow::MarchArgs march_args(cow_ctx* c, const CallTables& T, const RenderWs& w,
     a.trans = trans;
     a.counts = p->counts;
     a.opacity = p->opacity;
+    a.block_mlp = p->block_mlp;
+    a.rgb = nullptr;
     a.work_counter = w.counter;
     a.persistent = c->cfg.persistent;
     a.only_view = -1;
@@ -391,7 +393,7 @@ cow_status enqueue_forward(cow_ctx* c, const CallTables& T, const cow::MarchArgs
         HIP_TRY(c, cow::launch_march(a0, c->cfg.waves, s));
         if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[1], s));
     }
-    HIP_TRY(c, cow::launch_mlp(m, s));
+    if (!a0.block_mlp) HIP_TRY(c, cow::launch_mlp(m, s));  // per-block shading ran in the march
     return COW_OK;
 }
 
@@ -776,7 +778,7 @@ static cow_status render_impl(cow_ctx* c, const cow_view* views, int n_views, co
     if (!views || !sets || n_views < 1 || n_views > kMaxViews) return fail(c, COW_E_INVALID, "bad views");
     cow_status st = validate_params(c, p);
     if (st != COW_OK) return st;
-    if (!mlp || !rgb || !trans) return fail(c, COW_E_INVALID, "null mlp or output");
+    if ((!mlp && !p->block_mlp) || !rgb || !trans) return fail(c, COW_E_INVALID, "null mlp or output");
     if ((p->flags & COW_F_SPARSE) && !c->bricks_packed) return fail(c, COW_E_INVALID, "bricks not packed");
     CallTables T;
     st = build_tables(c, views, n_views, sets, c->cfg.tile_w, &T);
@@ -795,6 +797,7 @@ static cow_status render_impl(cow_ctx* c, const cow_view* views, int n_views, co
     if (st != COW_OK) return st;
     float* aux_out = aux ? aux : w.aux;
     cow::MarchArgs a = march_args(c, T, w, p, dtype, aux_out, trans);
+    a.rgb = rgb;
     cow::MlpArgs m{};
     m.views = w.views;
     m.n_views = n_views;

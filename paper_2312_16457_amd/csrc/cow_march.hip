@@ -47,7 +47,8 @@ __device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ra
 }
 
 template <int MODE, int DT, bool SPARSE>
-__device__ void march_packet(const MarchArgs& a, const DevView* V, int tile, int lane) {
+__device__ __attribute__((always_inline)) inline void march_packet(const MarchArgs& a, const DevView* V, int tile,
+                                                                   int lane) {
     ViewU v;
     load_view(V, v);
     Ray r;
@@ -56,7 +57,9 @@ __device__ void march_packet(const MarchArgs& a, const DevView* V, int tile, int
     int w0 = 0, w1 = 0;
     if (MODE == 1 && r.active) {
         int ka, kb;
-        box_interval(r.o, r.d, a.delta, a.scene_lo, a.scene_hi, &ka, &kb);
+        const float slo[3] = {a.scene_lo[0], a.scene_lo[1], a.scene_lo[2]};
+        const float shi[3] = {a.scene_hi[0], a.scene_hi[1], a.scene_hi[2]};
+        box_interval(r.o, r.d, a.delta, slo, shi, &ka, &kb);
         hit = ka < kb;
         w0 = ka;
         w1 = ka + a.max_steps;
@@ -86,10 +89,21 @@ __device__ void march_packet(const MarchArgs& a, const DevView* V, int tile, int
         // opacity regulariser: entropy of the block's opacity 1 - Tk, for
         // every block the ray marches (Eq. "opacity loss")
         if (a.opacity && n_march > marched_before) H += opacity_entropy(Tk);
-        // merge front to back (Eq. "volume rendering across blocks"), with
-        // the block's transmittance prod(1 - alpha_i) carried directly
+        if (a.block_mlp) {
+            // per-block deferred shading before the merge: every block the
+            // ray marches adds its colour C^k under the prefix transmittance
+            if (n_march > marched_before) {
+                float Ck[3];
+                block_shade(ufp(a.block_mlp) + (size_t)e * kMlpParams, Ak, r.d, Ck);
 #pragma unroll
-        for (int c = 0; c < 7; ++c) A[c] = fmaf(T, Ak[c], A[c]);
+                for (int c = 0; c < 3; ++c) A[c] = fmaf(T, Ck[c], A[c]);
+            }
+        } else {
+            // merge front to back (Eq. "volume rendering across blocks"), with
+            // the block's transmittance prod(1 - alpha_i) carried directly
+#pragma unroll
+            for (int c = 0; c < 7; ++c) A[c] = fmaf(T, Ak[c], A[c]);
+        }
         T *= Tk;
     }
     if (r.active) {
@@ -97,6 +111,11 @@ __device__ void march_packet(const MarchArgs& a, const DevView* V, int tile, int
         aux4[2 * r.pix] = make_float4(A[0], A[1], A[2], A[3]);
         aux4[2 * r.pix + 1] = make_float4(A[4], A[5], A[6], T);
         a.trans[r.pix] = T;
+        if (a.block_mlp) {  // A[0..2] is the colour; A[3..6] stay zero
+            a.rgb[3 * r.pix + 0] = A[0];
+            a.rgb[3 * r.pix + 1] = A[1];
+            a.rgb[3 * r.pix + 2] = A[2];
+        }
         if (a.opacity) a.opacity[r.pix] = H;
         if (a.counts) {
             a.counts[2 * r.pix] = n_eval;
@@ -113,25 +132,29 @@ __device__ inline void march_fwd_body(const MarchArgs& a) {
     const int lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
     const int wave = ufl(threadIdx.x >> 6);
-    if (a.persistent) {
-        for (;;) {
-            int p = 0;
-            if (lane == 0) p = atomicAdd(a.work_counter, 1);
-            p = ufl(__shfl(p, 0));
-            if (p >= a.total_tiles) break;
-            const DevView* V = find_view_by_tile(a.views, a.n_views, p);
-            march_packet<MODE, DT, SPARSE>(a, V, p - ufl(V->tile_begin), lane);
+    // One call site of march_packet, so that it stays inlined with the
+    // arguments in scalar registers: a persistent wave takes packets from the
+    // counter until it runs dry, otherwise a wave marches its one packet.
+    int p = a.persistent ? 0 : ufl(xcd_packet(waves, wave));
+    for (;;) {
+        if (a.persistent) {
+            int q = 0;
+            if (lane == 0) q = atomicAdd(a.work_counter, 1);
+            p = ufl(__shfl(q, 0));
         }
-        return;
+        if (p >= a.total_tiles) return;
+        const DevView* V;
+        int tile;
+        if (a.only_view >= 0) {  // per-block baseline: one view per launch
+            V = a.views + a.only_view;
+            tile = p;
+        } else {
+            V = find_view_by_tile(a.views, a.n_views, p);
+            tile = p - ufl(V->tile_begin);
+        }
+        march_packet<MODE, DT, SPARSE>(a, V, tile, lane);
+        if (!a.persistent) return;
     }
-    const int packet = ufl(xcd_packet(waves, wave));
-    if (packet >= a.total_tiles) return;
-    if (a.only_view >= 0) {
-        march_packet<MODE, DT, SPARSE>(a, a.views + a.only_view, packet, lane);
-        return;
-    }
-    const DevView* V = find_view_by_tile(a.views, a.n_views, packet);
-    march_packet<MODE, DT, SPARSE>(a, V, packet - ufl(V->tile_begin), lane);
 }
 
 template <int MODE, bool SPARSE>
@@ -140,7 +163,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void m
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void march_fwd_f32_kernel(MarchArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void march_fwd_f32_kernel(MarchArgs a) {
     march_fwd_body<MODE, 1, false>(a);
 }
 

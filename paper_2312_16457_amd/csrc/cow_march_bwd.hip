@@ -67,7 +67,7 @@ __device__ inline void scatter_pairs(ScatterLds& L, int lane, const Taps& T, con
 }
 
 template <int MODE, bool OPAC>
-__device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, int lane, ScatterLds& lds) {
+__device__ __attribute__((always_inline)) inline void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, int lane, ScatterLds& lds) {
     const MarchArgs& a = ba.m;
     ViewU v;
     load_view(V, v);
@@ -77,7 +77,9 @@ __device__ void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, 
     int w0 = 0, w1 = 0;
     if (MODE == 1 && r.active) {
         int ka, kb;
-        box_interval(r.o, r.d, a.delta, a.scene_lo, a.scene_hi, &ka, &kb);
+        const float slo[3] = {a.scene_lo[0], a.scene_lo[1], a.scene_lo[2]};
+        const float shi[3] = {a.scene_hi[0], a.scene_hi[1], a.scene_hi[2]};
+        box_interval(r.o, r.d, a.delta, slo, shi, &ka, &kb);
         hit = ka < kb;
         w0 = ka;
         w1 = ka + a.max_steps;
@@ -170,21 +172,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
     const int lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
     const int wave = ufl(threadIdx.x >> 6);
-    if (a.persistent) {
-        for (;;) {
-            int p = 0;
-            if (lane == 0) p = atomicAdd(a.work_counter, 1);
-            p = ufl(__shfl(p, 0));
-            if (p >= a.total_tiles) break;
-            const DevView* V = find_view_by_tile(a.views, a.n_views, p);
-            march_bwd_packet<MODE, OPAC>(ba, V, p - ufl(V->tile_begin), lane, lds[wave]);
+    int p = a.persistent ? 0 : ufl(xcd_packet(waves, wave));  // one call site, as in the forward
+    for (;;) {
+        if (a.persistent) {
+            int q = 0;
+            if (lane == 0) q = atomicAdd(a.work_counter, 1);
+            p = ufl(__shfl(q, 0));
         }
-        return;
+        if (p >= a.total_tiles) return;
+        const DevView* V = find_view_by_tile(a.views, a.n_views, p);
+        march_bwd_packet<MODE, OPAC>(ba, V, p - ufl(V->tile_begin), lane, lds[wave]);
+        if (!a.persistent) return;
     }
-    const int packet = ufl(xcd_packet(waves, wave));
-    if (packet >= a.total_tiles) return;
-    const DevView* V = find_view_by_tile(a.views, a.n_views, packet);
-    march_bwd_packet<MODE, OPAC>(ba, V, packet - ufl(V->tile_begin), lane, lds[wave]);
 }
 
 hipError_t launch_march_bwd(const BwdArgs& a, int waves, hipStream_t s) {
