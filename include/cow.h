@@ -202,7 +202,11 @@ COW_API cow_status cow_render(cow_ctx* ctx, const cow_view* views, int n_views, 
  * aux is the forward's aux.  Gradients are
  * ACCUMULATED into grad_grid[e] / grad_plane[3e + k] for loaded entry e (in
  * load order; NULL entries skipped) and into grad_mlp[499]; fp32 atomics, so
- * summation order varies run to run.  Per-ray samples are recomputed. */
+ * summation order varies run to run.  Per-ray samples are recomputed.
+ * With params->block_mlp the weights' gradient goes to
+ * params->grad_block_mlp instead (grad_mlp and mlp unused, may be NULL): each
+ * lane re-composites a block, runs that block's MLP adjoint, and the wave's
+ * sum of the 499 weight gradients is added once per block and wave. */
 COW_API cow_status cow_render_backward(cow_ctx* ctx, const cow_view* views, int n_views,
                                const cow_block_set* sets, const cow_render_params* params,
                                const float* mlp, const float* aux, const float* grad_rgb,

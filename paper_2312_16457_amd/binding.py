@@ -391,17 +391,22 @@ def _tex_grads(gg, gp, n_tex):
     return tuple(out[:n_tex])
 
 
-def make_render_fn(with_opacity=False):
+def make_render_fn(with_opacity=False, per_block_mlp=False):
     """torch.autograd.Function over cow_render / cow_render_backward.
     Differentiable inputs: the MLP weights and every fp32 texture of the
     loaded blocks (grid, xy, xz, yz per entry, in load order).  Outputs rgb
-    and trans, plus the per-ray opacity regulariser with with_opacity."""
+    and trans, plus the per-ray opacity regulariser with with_opacity.  With
+    per_block_mlp the MLP input is [loaded entries][499], one deferred MLP
+    per block applied before the merge."""
     import torch
 
     class RenderFn(torch.autograd.Function):
         @staticmethod
         def forward(ctx, renderer, views, sets, params, mlp, *textures):
-            out = renderer.render(views, sets, params, mlp, want_aux=True, opacity=with_opacity)
+            if per_block_mlp:
+                out = renderer.render(views, sets, params, None, want_aux=True, opacity=with_opacity, block_mlp=mlp)
+            else:
+                out = renderer.render(views, sets, params, mlp, want_aux=True, opacity=with_opacity)
             ctx.renderer, ctx.views, ctx.sets, ctx.params = renderer, views, sets, params
             ctx.save_for_backward(mlp, out["aux"])
             ctx.n_tex = len(textures)
@@ -415,9 +420,13 @@ def make_render_fn(with_opacity=False):
             r = ctx.renderer
             gg, gp = _zero_grads(torch, r)
             gm = torch.zeros_like(mlp)
-            r.render_backward(ctx.views, ctx.sets, ctx.params, mlp, aux,
-                              g_rgb if g_rgb is not None else torch.zeros((aux.shape[0], 3), device=aux.device),
-                              g_trans, gg, gp, gm, opacity_weight=g_opacity)
+            g_rgb = g_rgb if g_rgb is not None else torch.zeros((aux.shape[0], 3), device=aux.device)
+            if per_block_mlp:
+                r.render_backward(ctx.views, ctx.sets, ctx.params, None, aux, g_rgb, g_trans, gg, gp, None,
+                                  opacity_weight=g_opacity, block_mlp=mlp, grad_block_mlp=gm)
+            else:
+                r.render_backward(ctx.views, ctx.sets, ctx.params, mlp, aux, g_rgb, g_trans, gg, gp, gm,
+                                  opacity_weight=g_opacity)
             return (None, None, None, None, gm) + _tex_grads(gg, gp, ctx.n_tex)
 
     return RenderFn

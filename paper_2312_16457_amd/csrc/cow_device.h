@@ -510,6 +510,105 @@ __device__ inline void block_shade(const float* w, const float A[7], const float
     }
 }
 
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Adjoint of block_shade for one lane: C = A + sigmoid(Phi(A, d)) weighted
+// by P in the merge, g = dL/dC of the ray.  Returns C and u = dL/dA (with
+// P folded in).  With want_gw, the gradient of the 499 weights is summed over
+// the wave and added once to gw (wave-collective: every lane calls it, an
+// inactive lane with zero weight).
+__device__ __attribute__((noinline)) void block_shade_adjoint(const float* w, const float A[7], const float d[3], float P,
+                                           const float g[3], bool active, float C[3], float u[7], bool want_gw,
+                                           __amdgpu_buffer_rsrc_t gw, int lane) {
+    float x[10], h1[16], h2[16], s[3];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) x[c] = A[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) x[7 + c] = d[c];
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+        float a = w[160 + o];
+#pragma unroll
+        for (int i = 0; i < 10; ++i) a = fmaf(w[o * 10 + i], x[i], a);
+        h1[o] = fmaxf(a, 0.0f);
+    }
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+        float a = w[432 + o];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a = fmaf(w[176 + o * 16 + i], h1[i], a);
+        h2[o] = fmaxf(a, 0.0f);
+    }
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        float a = w[496 + o];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a = fmaf(w[448 + o * 16 + i], h2[i], a);
+        s[o] = sigmoidf_(a);
+        C[o] = A[o] + s[o];
+    }
+    const float wP = active ? P : 0.0f;
+    float dz[3], dh2[16], dh1[16];
+#pragma unroll
+    for (int o = 0; o < 3; ++o) dz[o] = wP * g[o] * s[o] * (1.0f - s[o]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        float a = 0.0f;
+#pragma unroll
+        for (int o = 0; o < 3; ++o) a = fmaf(w[448 + o * 16 + i], dz[o], a);
+        dh2[i] = h2[i] > 0.0f ? a : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        float a = 0.0f;
+#pragma unroll
+        for (int o = 0; o < 16; ++o) a = fmaf(w[176 + o * 16 + i], dh2[o], a);
+        dh1[i] = h1[i] > 0.0f ? a : 0.0f;
+    }
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+        float a = c < 3 ? wP * g[c] : 0.0f;
+#pragma unroll
+        for (int o = 0; o < 16; ++o) a = fmaf(w[o * 10 + c], dh1[o], a);
+        u[c] = a;
+    }
+    if (!want_gw) return;
+    // weight gradient, in the weights' own layout: lane (i % 64) keeps the
+    // wave sum of entry i in acc[i / 64]
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#define COW_RED(idx, val)                                   \
+    {                                                       \
+        const float t_ = wave_sum(val);                     \
+        if (lane == ((idx) & 63)) acc[(idx) >> 6] = t_;     \
+    }
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+#pragma unroll
+        for (int i = 0; i < 10; ++i) COW_RED(o * 10 + i, dh1[o] * x[i]);
+        COW_RED(160 + o, dh1[o]);
+    }
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) COW_RED(176 + o * 16 + i, dh2[o] * h1[i]);
+        COW_RED(432 + o, dh2[o]);
+    }
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) COW_RED(448 + o * 16 + i, dz[o] * h2[i]);
+        COW_RED(496 + o, dz[o]);
+    }
+#undef COW_RED
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (q * 64 + lane < kMlpParams) __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(acc[q], gw, 4 * (q * 64 + lane), 0, 0);
+}
+
 // Binary entropy of a block's opacity a = 1 - Tk (Eq. "opacity loss"), with
 // a clamped to [1e-6, 1 - 1e-6] so that both logarithms stay finite; 1 - a
 // is taken as Tk itself (no cancellation).  The derivative in a is
@@ -648,6 +747,46 @@ __device__ inline bool next_occupied(const BlockU& b, const Ray& r, const Span& 
         ++k;
     }
     return false;
+}
+
+// Composite the samples of one block for one lane (Eqs. "alpha
+// accumulation", "combined accumulation", "volume rendering inside
+// blocks"): Ak = sum_i T_i alpha_i (c_i, f_i), Tk = prod_i (1 - alpha_i).
+// Lanes advance independently through their own spans; a wave iterates
+// while any lane still has an occupied sample.
+// With early termination (t_min > 0) a lane stops after the first sample at
+// which its transmittance T_before * Tk falls below t_min.
+template <int DT, int MODE, bool SPARSE>
+__device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ray& r, const Span& sp,
+                                   float T_before, float Ak[7], float& Tk, int64_t& n_eval, int64_t& n_march) {
+    int k = sp.ka, kb = sp.kb;
+    int cur_cell = -1;
+    bool cur_occ = false;
+    for (;;) {
+        float q[3];
+        int cell = 0;
+        const bool have = next_occupied<MODE>(b, r, sp, kb, sp.delta, k, q, cell, cur_cell, cur_occ, n_march);
+        if (!__any(have)) break;
+        if (have) {
+            float raw[8];
+            if (DT == 0) {
+                raw_u8<SPARSE>(b, q, cell, raw);
+            } else {
+                Taps T;
+                sample_taps(b, q, T);
+                raw_f32(b, T, raw);
+            }
+            const float sigma = __expf(raw[0]);
+            const float alpha = alpha_of(sigma * sp.delta);
+            const float w = Tk * alpha;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) Ak[c] = fmaf(w, sigmoidf_(raw[1 + c]), Ak[c]);
+            Tk *= 1.0f - alpha;
+            ++n_eval;
+            ++k;
+            if (T_before * Tk < a.t_min) kb = k;  // early ray termination
+        }
+    }
 }
 
 // Transmittance prod(1 - alpha_i) of one block for one lane of an fp32

@@ -833,7 +833,7 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     if (!views || !sets || n_views < 1 || n_views > kMaxViews) return fail(c, COW_E_INVALID, "bad views");
     cow_status st = validate_params(c, p);
     if (st != COW_OK) return st;
-    if (!mlp || !aux || !grad_rgb || !grad_grid || !grad_plane)
+    if ((!mlp && !p->block_mlp) || !aux || !grad_rgb || !grad_grid || !grad_plane)
         return fail(c, COW_E_INVALID, "null mlp, aux, grad_rgb or gradient table");
     CallTables T;
     st = build_tables(c, views, n_views, sets, c->cfg.tile_w, &T);
@@ -874,7 +874,7 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     mb.grad_rgb = grad_rgb;
     mb.u = w.u;
     mb.grad_mlp = grad_mlp ? grad_mlp : w.grad_mlp_scratch;
-    HIP_TRY(c, cow::launch_mlp_bwd(mb, s));
+    if (!p->block_mlp) HIP_TRY(c, cow::launch_mlp_bwd(mb, s));  // per-block MLPs: adjoint inside the march
     cow::BwdArgs ba{};
     ba.m = march_args(c, T, w, p, COW_F32, const_cast<float*>(aux), nullptr);
     ba.m.persistent = c->cfg.persistent;
@@ -883,6 +883,8 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     ba.u = w.u;
     ba.grad_trans = grad_trans;
     ba.w_opacity = p->opacity_weight;
+    ba.grad_rgb = grad_rgb;
+    ba.grad_block_mlp = p->grad_block_mlp;
     ba.grad_grid = w.grad_ptrs;
     ba.grad_plane = w.grad_ptrs + ne;
     c->have_bwd = c->timing;

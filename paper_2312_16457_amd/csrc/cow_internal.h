@@ -89,6 +89,8 @@ struct BwdArgs {
     const float* u;            // [P][8]
     const float* grad_trans;   // [P] or null
     const float* w_opacity;    // [P] dL/d(per-ray opacity entropy), or null
+    const float* grad_rgb;     // [P][3], read directly with per-block MLPs (m.block_mlp)
+    float* grad_block_mlp;     // [entries][499], accumulated, or null
     float* const* grad_grid;   // device array of per-entry pointers
     float* const* grad_plane;  // device array, 3 per entry
 };

@@ -6,46 +6,6 @@
 
 namespace cow {
 
-// Composite the samples of one block for one lane (Eqs. "alpha
-// accumulation", "combined accumulation", "volume rendering inside
-// blocks"): Ak = sum_i T_i alpha_i (c_i, f_i), Tk = prod_i (1 - alpha_i).
-// Lanes advance independently through their own spans; a wave iterates
-// while any lane still has an occupied sample.
-// With early termination (t_min > 0) a lane stops after the first sample at
-// which its transmittance T_before * Tk falls below t_min.
-template <int DT, int MODE, bool SPARSE>
-__device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ray& r, const Span& sp,
-                                   float T_before, float Ak[7], float& Tk, int64_t& n_eval, int64_t& n_march) {
-    int k = sp.ka, kb = sp.kb;
-    int cur_cell = -1;
-    bool cur_occ = false;
-    for (;;) {
-        float q[3];
-        int cell = 0;
-        const bool have = next_occupied<MODE>(b, r, sp, kb, sp.delta, k, q, cell, cur_cell, cur_occ, n_march);
-        if (!__any(have)) break;
-        if (have) {
-            float raw[8];
-            if (DT == 0) {
-                raw_u8<SPARSE>(b, q, cell, raw);
-            } else {
-                Taps T;
-                sample_taps(b, q, T);
-                raw_f32(b, T, raw);
-            }
-            const float sigma = __expf(raw[0]);
-            const float alpha = alpha_of(sigma * sp.delta);
-            const float w = Tk * alpha;
-#pragma unroll
-            for (int c = 0; c < 7; ++c) Ak[c] = fmaf(w, sigmoidf_(raw[1 + c]), Ak[c]);
-            Tk *= 1.0f - alpha;
-            ++n_eval;
-            ++k;
-            if (T_before * Tk < a.t_min) kb = k;  // early ray termination
-        }
-    }
-}
-
 template <int MODE, int DT, bool SPARSE>
 __device__ __attribute__((always_inline)) inline void march_packet(const MarchArgs& a, const DevView* V, int tile,
                                                                    int lane) {

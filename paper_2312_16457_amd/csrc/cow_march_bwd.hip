@@ -66,8 +66,15 @@ __device__ inline void scatter_pairs(ScatterLds& L, int lane, const Taps& T, con
     }
 }
 
-template <int MODE, bool OPAC>
-__device__ __attribute__((always_inline)) inline void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile, int lane, ScatterLds& lds) {
+// BMLP: per-block deferred MLPs before the merge.  Per block k with prefix
+// transmittance P, a first pass composites the block (A^k, T^k); the lane
+// then runs the block's MLP adjoint for u = dL/dA^k and takes
+// T^k dL/dT^k = g . R_k + gT T, with R_k = C - (colour merged up to block k)
+// the light of the later blocks; the sample adjoint inside the block is the
+// single-chain one with these per-block u and transmittance term.
+template <int MODE, bool OPAC, bool BMLP>
+__device__ __attribute__((always_inline)) inline void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile,
+                                                                       int lane, ScatterLds& lds) {
     const MarchArgs& a = ba.m;
     ViewU v;
     load_view(V, v);
@@ -85,20 +92,26 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
         w1 = ka + a.max_steps;
     }
     float Af[7] = {0, 0, 0, 0, 0, 0, 0}, TN = 1.0f, u[7] = {0, 0, 0, 0, 0, 0, 0}, gT = 0.0f;
+    float Cf[3] = {0, 0, 0}, g[3] = {0, 0, 0}, Cpre[3] = {0, 0, 0};  // per-block MLPs only
     if (r.active) {
         const float4 lo = reinterpret_cast<const float4*>(a.aux)[2 * r.pix];
         const float4 hi = reinterpret_cast<const float4*>(a.aux)[2 * r.pix + 1];
-        Af[0] = lo.x, Af[1] = lo.y, Af[2] = lo.z, Af[3] = lo.w, Af[4] = hi.x, Af[5] = hi.y, Af[6] = hi.z;
         TN = hi.w;
-        const float4 ulo = reinterpret_cast<const float4*>(ba.u)[2 * r.pix];
-        const float4 uhi = reinterpret_cast<const float4*>(ba.u)[2 * r.pix + 1];
-        u[0] = ulo.x, u[1] = ulo.y, u[2] = ulo.z, u[3] = ulo.w, u[4] = uhi.x, u[5] = uhi.y, u[6] = uhi.z;
+        if (BMLP) {  // aux = (C, 0, 0, 0, 0, T)
+            Cf[0] = lo.x, Cf[1] = lo.y, Cf[2] = lo.z;
+            for (int c = 0; c < 3; ++c) g[c] = ba.grad_rgb[3 * r.pix + c];
+        } else {
+            Af[0] = lo.x, Af[1] = lo.y, Af[2] = lo.z, Af[3] = lo.w, Af[4] = hi.x, Af[5] = hi.y, Af[6] = hi.z;
+            const float4 ulo = reinterpret_cast<const float4*>(ba.u)[2 * r.pix];
+            const float4 uhi = reinterpret_cast<const float4*>(ba.u)[2 * r.pix + 1];
+            u[0] = ulo.x, u[1] = ulo.y, u[2] = ulo.z, u[3] = ulo.w, u[4] = uhi.x, u[5] = uhi.y, u[6] = uhi.z;
+        }
         if (ba.grad_trans) gT = ba.grad_trans[r.pix];
     }
-    const float w_op = (OPAC && r.active) ? ba.w_opacity[r.pix] : 0.0f;
+    const float w_op = ((OPAC || BMLP) && r.active && ba.w_opacity) ? ba.w_opacity[r.pix] : 0.0f;
     float Ap[7] = {0, 0, 0, 0, 0, 0, 0}, Tg = 1.0f;
     float T_blk = 1.0f;  // merged transmittance before the block, as the forward forms it
-    const float tn_term = TN * gT;
+    float tn_term = TN * gT;
     int64_t unused = 0;
     for (int j = 0; j < v.set_n; ++j) {
         const int e = ufl(a.refs[v.set_begin + j]);
@@ -115,7 +128,30 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
         const Span sp = block_span<MODE>(a, b, r, alive, w0, w1);
         if (!__any(sp.ka < sp.kb)) continue;
         float g_op = 0.0f;  // dL/dsigma_i of the opacity term, per unit step length
-        if (OPAC && __any(w_op != 0.0f)) {
+        if (BMLP) {
+            float Tkf = 1.0f;
+            int64_t ne = 0, nm = 0;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) Af[c] = 0.0f;
+            march_block<1, MODE, false>(a, b, r, sp, T_blk, Af, Tkf, ne, nm);
+            float Ck[3];
+            __amdgpu_buffer_rsrc_t gw = tex_rsrc(ba.grad_block_mlp ? ufp(ba.grad_block_mlp) + (size_t)e * kMlpParams
+                                                                   : nullptr,
+                                                 4u * kMlpParams);
+            block_shade_adjoint(ufp(a.block_mlp) + (size_t)e * kMlpParams, Af, r.d, T_blk, g, nm > 0, Ck, u,
+                                ba.grad_block_mlp != nullptr, gw, lane);
+            float R = gT * TN;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (nm > 0) Cpre[c] = fmaf(T_blk, Ck[c], Cpre[c]);
+                R = fmaf(g[c], Cf[c] - Cpre[c], R);
+            }
+            tn_term = R;
+            if (w_op != 0.0f) g_op = w_op * opacity_dentropy(Tkf) * Tkf;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) Ap[c] = 0.0f;
+            Tg = 1.0f;
+        } else if (OPAC && __any(w_op != 0.0f)) {
             const float Tkf = block_trans_f32<MODE>(b, r, sp, T_blk, a.t_min, w_op != 0.0f);
             g_op = w_op * opacity_dentropy(Tkf) * Tkf;
         }
@@ -165,7 +201,7 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
 
 // OPAC: with the opacity regulariser's pre-march (a separate instance keeps
 // the plain adjoint's register budget)
-template <int MODE, bool OPAC>
+template <int MODE, bool OPAC, bool BMLP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void march_bwd_kernel(BwdArgs ba) {
     const MarchArgs& a = ba.m;
     __shared__ ScatterLds lds[4];
@@ -181,7 +217,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
         }
         if (p >= a.total_tiles) return;
         const DevView* V = find_view_by_tile(a.views, a.n_views, p);
-        march_bwd_packet<MODE, OPAC>(ba, V, p - ufl(V->tile_begin), lane, lds[wave]);
+        march_bwd_packet<MODE, OPAC, BMLP>(ba, V, p - ufl(V->tile_begin), lane, lds[wave]);
         if (!a.persistent) return;
     }
 }
@@ -195,18 +231,25 @@ hipError_t launch_march_bwd(const BwdArgs& a, int waves, hipStream_t s) {
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         grid = dim3(cus * (16 / waves));
     }
-    const bool op = a.w_opacity != nullptr;
+    const bool op = a.w_opacity != nullptr, bm = a.m.block_mlp != nullptr;
+    const size_t shm = 0;
+#define COW_LAUNCH(M, O, B) hipLaunchKernelGGL((march_bwd_kernel<M, O, B>), grid, block, shm, s, a)
     if (a.m.mode == 1) {
-        if (op)
-            hipLaunchKernelGGL((march_bwd_kernel<1, true>), grid, block, 0, s, a);
+        if (bm)
+            COW_LAUNCH(1, false, true);
+        else if (op)
+            COW_LAUNCH(1, true, false);
         else
-            hipLaunchKernelGGL((march_bwd_kernel<1, false>), grid, block, 0, s, a);
+            COW_LAUNCH(1, false, false);
     } else {
-        if (op)
-            hipLaunchKernelGGL((march_bwd_kernel<0, true>), grid, block, 0, s, a);
+        if (bm)
+            COW_LAUNCH(0, false, true);
+        else if (op)
+            COW_LAUNCH(0, true, false);
         else
-            hipLaunchKernelGGL((march_bwd_kernel<0, false>), grid, block, 0, s, a);
+            COW_LAUNCH(0, false, false);
     }
+#undef COW_LAUNCH
     return hipGetLastError();
 }
 

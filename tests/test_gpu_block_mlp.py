@@ -98,3 +98,86 @@ def test_block_mlp_c2_sampled_rows_and_variants(torch_cuda):
             o = r.render([view], [sel], p, None, flags=flags, block_mlp=bm)
             torch.cuda.synchronize()
             assert torch.equal(o["rgb"], base), flags
+
+
+@pytest.mark.parametrize("case", ["grid", "chord", "grid_trans_opacity_tmin"])
+def test_block_mlp_backward_parity(torch_cuda, case):
+    torch = torch_cuda
+    from paper_2312_16457_amd import Renderer
+    if case == "chord":
+        scene = sg.c1_scene()
+        view = sg.c1_view().with_crop(40, 30, 48, 40)
+        params = sg.c1_params()
+    else:
+        scene = small_scene(sg.F32, seed=5, shift=1.0)
+        view = small_view()
+        params = sg.RenderParams(mode=1, t_min=1e-3) if case.endswith("tmin") else sg.cityb_params()
+    n = len(scene.blocks)
+    mlps = block_mlps(n, 60)
+    r = Renderer(0).load_blocks(scene.blocks)
+    sets = [[(b.block_id, b.lod) for b in scene.blocks]]
+    bm = torch.tensor(mlps, device="cuda")
+    out = r.render([view], sets, params, None, block_mlp=bm)
+    rng = np.random.default_rng(8)
+    g_rgb = rng.uniform(-1, 1, (view.n_pixels, 3))
+    extra = case.startswith("grid_trans")
+    g_tr = rng.uniform(-1, 1, view.n_pixels) if extra else None
+    w_op = rng.uniform(0.2, 1.0, view.n_pixels) if extra else None
+    gg = [torch.zeros_like(t[0]) for t in r.textures]
+    gp = [[torch.zeros_like(q) for q in t[1]] for t in r.textures]
+    gbm = torch.zeros_like(bm)
+    r.render_backward([view], sets, params, None, out["aux"], torch.tensor(g_rgb, dtype=torch.float32, device="cuda"),
+                      None if g_tr is None else torch.tensor(g_tr, dtype=torch.float32, device="cuda"), gg, gp, None,
+                      opacity_weight=None if w_op is None else torch.tensor(w_op, dtype=torch.float32, device="cuda"),
+                      block_mlp=bm, grad_block_mlp=gbm)
+    torch.cuda.synchronize()
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    grads, gm_ref = O.adjoint_block_mlp(ob, occs, view, list(range(n)), params, mlps.astype(np.float64),
+                                        O.pixels_of(view), g_rgb, g_tr, w_op)
+    for k, (g, ps) in grads.items():
+        for a, b in [(gg[k], g)] + [(gp[k][i], ps[i]) for i in range(3)]:
+            den = np.abs(b).max()
+            e = np.abs(a.cpu().numpy() - b).max() / max(den, 1e-30)
+            assert e <= 1e-3, (k, e)
+    gbm_np = gbm.cpu().numpy()
+    for k in range(n):
+        den = np.abs(gm_ref[k]).max()
+        if den == 0:
+            assert not gbm_np[k].any()
+            continue
+        e = np.abs(gbm_np[k] - gm_ref[k]).max() / den
+        assert e <= 1e-3, ("mlp", k, e)
+
+
+def test_block_mlp_autograd(torch_cuda):
+    torch = torch_cuda
+    from paper_2312_16457_amd import Renderer, make_render_fn
+    scene = small_scene(sg.F32, seed=6, shift=1.0)
+    view = small_view(24, 16)
+    params = sg.cityb_params()
+    r = Renderer(0).load_blocks(scene.blocks)
+    sets = [[(b.block_id, b.lod) for b in scene.blocks]]
+    bm = torch.tensor(block_mlps(len(scene.blocks), 70), device="cuda", requires_grad=True)
+    tex = []
+    for g, ps in r.textures:
+        g.requires_grad_(True)
+        for q in ps:
+            q.requires_grad_(True)
+        tex += [g] + ps
+    fn = make_render_fn(per_block_mlp=True)
+    target = torch.rand((view.n_pixels, 3), device="cuda")
+    rgb, trans = fn.apply(r, [view], sets, params, bm, *tex)
+    loss = ((rgb - target) ** 2).mean()
+    gs = torch.autograd.grad(loss, [bm] + tex)
+    gg = [torch.zeros_like(t[0]) for t in r.textures]
+    gp = [[torch.zeros_like(q) for q in t[1]] for t in r.textures]
+    gbm = torch.zeros_like(bm)
+    with torch.no_grad():
+        out = r.render([view], sets, params, None, block_mlp=bm.detach())
+        r.render_backward([view], sets, params, None, out["aux"], 2 * (out["rgb"] - target) / target.numel(), None,
+                          gg, gp, None, block_mlp=bm.detach(), grad_block_mlp=gbm)
+    torch.cuda.synchronize()
+    assert gbm.abs().max().item() > 0
+    assert (gs[0] - gbm).abs().max().item() <= 1e-5 * gbm.abs().max().item()
+    assert (gs[1] - gg[0]).abs().max().item() <= 1e-5 * gg[0].abs().max().item()
