@@ -25,6 +25,7 @@ import numpy as np  # noqa: E402
 
 # MI355X published peaks
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # algorithmic fp32 flops of one evaluated sample of the uint8 path:
 #   trilinear grid 8 taps x 8 ch x 2 = 128, three bilinear planes 3 x 4 x 8 x 2 = 192,
@@ -127,9 +128,16 @@ def main():
                      "kernel": "march_fwd_kernel<1,false> (uint8, grid sampling)", "kernel_ms": round(k_ms, 4),
                      "algorithmic_tflop_per_launch": round(FLOPS_PER_SAMPLE * n_eval / 1e12, 4),
                      "flops_per_sample": FLOPS_PER_SAMPLE,
-                     "gathered_GBps": round(BYTES_PER_SAMPLE_U8 * n_eval / (k_ms * 1e-3) / 1e9, 1)},
+                     "gathered_GBps": round(BYTES_PER_SAMPLE_U8 * n_eval / (k_ms * 1e-3) / 1e9, 1),
+                     # ceiling without packed fp32 (not used: built with packed-fp32-ops off):
+                     # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+                     "peak_nonpacked_fp32": PEAK_FP32_NONPACKED_TFLOPS,
+                     "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4)},
     }
     log(f"forward {ms:.2f} ms per frame")
+    if not args.profile:
+        res["gather"] = gather_ceiling(torch, view, n_eval, res["roofline"]["gathered_GBps"])
+        log("gather probe done")
     if not args.no_cpu_baseline and not args.profile:
         res["cpu_baseline"] = cpu_baseline(scene, view, sel, params, w)
         log("cpu baseline done")
@@ -161,6 +169,32 @@ def recorded_traffic():
     if rec.get("source_digest") != source_digest():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def gather_ceiling(torch, view, n_eval, march_GBps):
+    """Achievable texel-gather rate for the march's access pattern: the
+    library's gather microbenchmark (the march's ten 16-byte pair loads per
+    sample, no arithmetic) on the same view, at the mean evaluated samples per
+    ray, over random uint8 textures of three footprints: L2-resident, Infinity
+    Cache-resident and the frame's own 640 MiB.  frac = the march's gathered
+    bytes per second over the probe's at the frame's footprint."""
+    from paper_2312_16457_amd import COW_U8
+    from paper_2312_16457_amd.binding import gather_probe
+    steps = max(1, int(round(n_eval / view.n_pixels)))
+    out = {"steps_per_ray": steps}
+    cases = (("l2_1block_32_128", 1, 32, 128), ("mall_2x2_64_512", 2, 64, 512), ("frame_4x4_128_1024", 4, 128, 1024))
+    for name, nb, R, Rp in cases:
+        nbytes = nb * nb * (R ** 3 + 3 * Rp * Rp) * 8
+        tex = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda")
+        gather_probe(view, tex, nb, nb, R, Rp, COW_U8, steps, 1.0 / 512)  # warm-up
+        best = min(gather_probe(view, tex, nb, nb, R, Rp, COW_U8, steps, 1.0 / 512)[0] for _ in range(3))
+        gbytes = view.n_pixels * steps * BYTES_PER_SAMPLE_U8
+        out[name] = {"footprint_MiB": round(nbytes / 2 ** 20, 1), "ms": round(best, 3),
+                     "GBps": round(gbytes / (best * 1e-3) / 1e9, 1)}
+        del tex
+    out["march_GBps"] = march_GBps
+    out["frac_of_frame_footprint"] = round(march_GBps / out["frame_4x4_128_1024"]["GBps"], 4)
+    return out
 
 
 def cpu_baseline(scene, view, sel, params, w):

@@ -249,6 +249,25 @@ COW_API cow_status cow_set_config(cow_ctx* ctx, int tile_w, int waves, int persi
 COW_API cow_status cow_set_timing(cow_ctx* ctx, int enable);
 COW_API cow_status cow_last_timing(cow_ctx* ctx, float* fwd_march_ms, float* bwd_march_ms);
 
+/* Texel-gather microbenchmark (a measurement aid, not a step of the render):
+ * the forward march's memory accesses without its arithmetic.  Each 8x8 tile
+ * of view's crop is one wave; a lane marches `steps` camera-anchored samples
+ * t_k = (k + 1/2) delta along its pixel ray through a field of
+ * blocks_x x blocks_y unit blocks that repeats in x, y and z, and per sample
+ * loads the ten texel pairs the march loads (four grid rows, two rows per
+ * plane; cell-centred, clamp-to-edge).  tex: device, blocks_x * blocks_y
+ * blocks of (grid_res^3 + 3 plane_res^2) texels of 8 bytes (COW_U8) or 32
+ * bytes (COW_F32) each, block (x, y) at index y * blocks_x + x, each laid
+ * out grid then the xy, xz, yz planes ([z][y][x] and [v][u], channels last).
+ * sink: device uint32 [tiles][64], one XOR of the loaded words per lane.
+ * ms_out (host): kernel time from HIP events; the call synchronises the
+ * stream.  Gathered bytes = tiles * 64 * steps * (160 or 640).
+ * COW_E_INVALID for a crop that is not a multiple of 8, non-power-of-two
+ * resolutions, or tex_bytes too small. */
+COW_API cow_status cow_gather_probe(const cow_view* view, const void* tex, size_t tex_bytes, int blocks_x,
+                                    int blocks_y, int grid_res, int plane_res, int dtype, int steps, float delta,
+                                    uint32_t* sink, float* ms_out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,7 +19,7 @@ F_NONE, F_GRAPH, F_PERSISTENT, F_PER_BLOCK, F_SPARSE = 0, 1, 2, 4, 8
 EXPORTS = ["cow_create", "cow_destroy", "cow_last_error", "cow_query_workspace", "cow_load_blocks",
            "cow_get_occupancy", "cow_select_blocks", "cow_query_bricks", "cow_pack_bricks", "cow_render",
            "cow_render_backward", "cow_sparsity", "cow_autotune", "cow_get_config", "cow_set_config",
-           "cow_set_timing", "cow_last_timing"]
+           "cow_set_timing", "cow_last_timing", "cow_gather_probe"]
 
 
 class CowError(RuntimeError):
@@ -92,6 +92,8 @@ def lib():
         L.cow_set_config.argtypes = [vp, C.c_int, C.c_int, C.c_int]
         L.cow_set_timing.argtypes = [vp, C.c_int]
         L.cow_last_timing.argtypes = [vp, P(C.c_float), P(C.c_float)]
+        L.cow_gather_probe.argtypes = [P(View), vp, C.c_size_t, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                       C.c_int, C.c_float, vp, P(C.c_float), vp]
         for name in EXPORTS:
             if name != "cow_last_error":
                 getattr(L, name).restype = C.c_int
@@ -458,3 +460,21 @@ def make_sparsity_fn():
             return (None, None, None, None, None) + _tex_grads(gg, gp, ctx.n_tex)
 
     return SparsityFn
+
+
+def gather_probe(view, tex, blocks_x, blocks_y, grid_res, plane_res, dtype, steps, delta):
+    """cow_gather_probe: the march's texel-pair loads without its arithmetic.
+    tex is a device uint8 tensor holding the block field; returns
+    (kernel ms, gathered bytes)."""
+    import torch
+    v = make_view(view)
+    tiles = (v.crop_w // 8) * (v.crop_h // 8)
+    sink = torch.empty(tiles * 64, dtype=torch.int32, device=tex.device)
+    ms = C.c_float(0.0)
+    st = lib().cow_gather_probe(C.byref(v), C.c_void_p(tex.data_ptr()), tex.numel() * tex.element_size(),
+                                int(blocks_x), int(blocks_y), int(grid_res), int(plane_res), int(dtype), int(steps),
+                                float(delta), C.c_void_p(sink.data_ptr()), C.byref(ms), _stream())
+    if st != COW_OK:
+        raise CowError(st, "cow_gather_probe: invalid arguments or HIP error")
+    per_sample = 160 if dtype == COW_U8 else 640
+    return float(ms.value), tiles * 64 * int(steps) * per_sample

@@ -22,7 +22,7 @@ HIP_FLAGS = [
 
 
 def build_library(verbose=False):
-    srcs = [os.path.join(CSRC, f) for f in ("cow_march.hip", "cow_march_bwd.hip", "cow_mlp.hip", "cow_reg.hip", "cow_host.cpp")]
+    srcs = [os.path.join(CSRC, f) for f in ("cow_march.hip", "cow_march_bwd.hip", "cow_mlp.hip", "cow_reg.hip", "cow_gather.hip", "cow_host.cpp")]
     tmp = LIB + ".tmp"
     cmd = ["hipcc"] + HIP_FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + srcs
     if verbose:
