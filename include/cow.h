@@ -156,7 +156,11 @@ COW_API cow_status cow_destroy(cow_ctx* ctx);
 COW_API const char* cow_last_error(const cow_ctx* ctx);
 
 /* Workspace sizes in bytes for loading `blocks` and for render / backward
- * calls of up to max_views views and max_pixels pixels in total. */
+ * calls of up to max_views views and max_pixels pixels in total.  The
+ * backward size includes a shadow of every float32 texture (its texel count
+ * plus one, 32 bytes each): texel pairs that start at an odd texel are
+ * accumulated there, one aligned 64-byte segment per pair, and folded into
+ * the caller's gradients at the end of the call. */
 COW_API cow_status cow_query_workspace(cow_ctx* ctx, const cow_block_desc* blocks, int n_blocks,
                                int max_views, int64_t max_pixels, size_t* load_bytes,
                                size_t* render_bytes, size_t* backward_bytes);
@@ -203,6 +207,8 @@ COW_API cow_status cow_render(cow_ctx* ctx, const cow_view* views, int n_views, 
  * ACCUMULATED into grad_grid[e] / grad_plane[3e + k] for loaded entry e (in
  * load order; NULL entries skipped) and into grad_mlp[499]; fp32 atomics, so
  * summation order varies run to run.  Per-ray samples are recomputed.
+ * Gradient buffers must be 16-byte aligned (COW_E_INVALID otherwise); at
+ * 64-byte alignment every texel pair is one 64-byte atomic segment.
  * With params->block_mlp the weights' gradient goes to
  * params->grad_block_mlp instead (grad_mlp and mlp unused, may be NULL): each
  * lane re-composites a block, runs that block's MLP adjoint, and the wave's

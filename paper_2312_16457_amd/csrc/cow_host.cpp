@@ -270,12 +270,28 @@ struct RenderWs {
     float** grad_ptrs;
     float* u;
     float* grad_mlp_scratch;
+    cow::FoldJob* jobs;
+    unsigned char* shadow;
     size_t bytes;
 };
 
-// render workspace: [views][refs][aux scratch][counter][grad pointers][u][mlp grad scratch]
+// shadow texture of a gradient texture of n texels: n + 1 texels of 32 bytes
+size_t shadow_bytes(int64_t n_texels) { return align_up((size_t)(n_texels + 1) * 32); }
+
+// shadows of every float32 entry: grid, then the three planes
+size_t shadow_total(const cow_block_desc* d, int64_t n) {
+    size_t t = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (d[i].dtype != COW_F32) continue;
+        const int64_t R = d[i].grid_res, Rp = d[i].plane_res;
+        t += shadow_bytes(R * R * R) + 3 * shadow_bytes(Rp * Rp);
+    }
+    return t;
+}
+
+// render workspace: [views][refs][aux scratch][counter][grad pointers][u][mlp grad scratch][fold jobs][shadows]
 size_t render_ws_layout(int64_t n_views, int64_t n_refs, int64_t n_pix, bool need_aux, bool backward,
-                        int64_t n_entries, unsigned char* base, RenderWs* w) {
+                        int64_t n_entries, size_t shadow, unsigned char* base, RenderWs* w) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -288,9 +304,12 @@ size_t render_ws_layout(int64_t n_views, int64_t n_refs, int64_t n_pix, bool nee
     r.aux = need_aux ? (float*)take(32 * (size_t)n_pix) : nullptr;
     r.counter = (int32_t*)take(64);
     if (backward) {
-        r.grad_ptrs = (float**)take(sizeof(float*) * 4 * (size_t)std::max<int64_t>(n_entries, 1));
+        // gradient pointers (4 per entry), then shadow pointers (4 per entry)
+        r.grad_ptrs = (float**)take(sizeof(float*) * 8 * (size_t)std::max<int64_t>(n_entries, 1));
         r.u = (float*)take(32 * (size_t)n_pix);
         r.grad_mlp_scratch = (float*)take(4 * cow::kMlpParams);
+        r.jobs = (cow::FoldJob*)take(sizeof(cow::FoldJob) * 4 * (size_t)std::max<int64_t>(n_entries, 1));
+        r.shadow = (unsigned char*)take(shadow);
     }
     r.bytes = off;
     if (w) *w = r;
@@ -538,8 +557,10 @@ cow_status cow_query_workspace(cow_ctx* c, const cow_block_desc* blocks, int n_b
     }
     if (load_bytes) *load_bytes = load_layout(blocks, n_blocks, nullptr, nullptr);
     const int64_t refs = (int64_t)max_views * std::max(n_blocks, 1);
-    if (render_bytes) *render_bytes = render_ws_layout(max_views, refs, max_pixels, true, false, n_blocks, nullptr, nullptr);
-    if (backward_bytes) *backward_bytes = render_ws_layout(max_views, refs, max_pixels, true, true, n_blocks, nullptr, nullptr);
+    if (render_bytes) *render_bytes = render_ws_layout(max_views, refs, max_pixels, true, false, n_blocks, 0, nullptr, nullptr);
+    if (backward_bytes)
+        *backward_bytes = render_ws_layout(max_views, refs, max_pixels, true, true, n_blocks,
+                                           shadow_total(blocks, n_blocks), nullptr, nullptr);
     return COW_OK;
 }
 
@@ -789,7 +810,7 @@ static cow_status render_impl(cow_ctx* c, const cow_view* views, int n_views, co
     if ((p->flags & COW_F_SPARSE) && dtype != COW_U8) return fail(c, COW_E_UNSUPPORTED, "sparse bricks hold uint8 grids only");
     RenderWs w;
     const size_t need = render_ws_layout(n_views, (int64_t)T.refs.size(), T.n_pix, aux == nullptr, false,
-                                         (int64_t)c->entries.size(), (unsigned char*)ws, &w);
+                                         (int64_t)c->entries.size(), 0, (unsigned char*)ws, &w);
     if (!ws || ws_bytes < need) return fail(c, COW_E_WORKSPACE, "render workspace too small");
     if (T.n_pix == 0) return COW_OK;
     HIP_TRY(c, hipSetDevice(c->device));
@@ -842,29 +863,61 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
         if (c->entries[e].desc.dtype != COW_F32)
             return fail(c, COW_E_UNSUPPORTED, "backward needs float32 textures");
     RenderWs w;
+    std::vector<cow_block_desc> descs;
+    for (const Entry& en : c->entries) descs.push_back(en.desc);
     const size_t need = render_ws_layout(n_views, (int64_t)T.refs.size(), T.n_pix, false, true,
-                                         (int64_t)c->entries.size(), (unsigned char*)ws, &w);
+                                         (int64_t)c->entries.size(), shadow_total(descs.data(), (int64_t)descs.size()),
+                                         (unsigned char*)ws, &w);
     if (!ws || ws_bytes < need) return fail(c, COW_E_WORKSPACE, "backward workspace too small");
+    const size_t ne = c->entries.size();
+    for (size_t e = 0; e < ne; ++e) {
+        if ((uintptr_t)grad_grid[e] % 16) return fail(c, COW_E_INVALID, "gradient buffers must be 16-byte aligned");
+        for (int k = 0; k < 3; ++k)
+            if ((uintptr_t)grad_plane[3 * e + k] % 16)
+                return fail(c, COW_E_INVALID, "gradient buffers must be 16-byte aligned");
+    }
     if (T.n_pix == 0) return COW_OK;
     HIP_TRY(c, hipSetDevice(c->device));
-    // views, refs and the per-entry gradient pointer table in one upload
-    const size_t ne = c->entries.size();
-    std::vector<float*> ptrs(4 * ne, nullptr);
+    // views, refs, the per-entry gradient and shadow pointer tables and the
+    // fold jobs (the textures of the entries this call renders) in one upload
+    std::vector<float*> ptrs(8 * ne, nullptr);
+    std::vector<char> used(ne, 0);
+    for (int32_t e : T.refs) used[e] = 1;
+    std::vector<cow::FoldJob> jobs;
+    int64_t max_texels = 0;
+    size_t sh_off = 0;
     for (size_t e = 0; e < ne; ++e) {
         ptrs[e] = grad_grid[e];
         for (int k = 0; k < 3; ++k) ptrs[ne + 3 * e + k] = grad_plane[3 * e + k];
+        if (descs[e].dtype != COW_F32) continue;
+        const int64_t R = descs[e].grid_res, Rp = descs[e].plane_res;
+        for (int t = 0; t < 4; ++t) {
+            const int64_t n = t == 0 ? R * R * R : Rp * Rp;
+            float* g = t == 0 ? grad_grid[e] : grad_plane[3 * e + t - 1];
+            float* sh = (float*)(w.shadow + sh_off);
+            sh_off += shadow_bytes(n);
+            if (!g || !used[e]) continue;
+            ptrs[4 * ne + 4 * e + t] = sh;
+            jobs.push_back(cow::FoldJob{g, sh, n});
+            max_texels = std::max(max_texels, n);
+        }
     }
     const size_t vb = sizeof(DevView) * T.views.size(), rb = 4 * T.refs.size(), pb = sizeof(float*) * ptrs.size();
-    st = ensure_pinned(c, align_up(vb) + align_up(rb) + pb);
+    const size_t jb = sizeof(cow::FoldJob) * jobs.size();
+    const size_t o_ref = align_up(vb), o_ptr = o_ref + align_up(rb), o_job = o_ptr + align_up(pb);
+    st = ensure_pinned(c, o_job + jb);
     if (st != COW_OK) return st;
     memcpy(c->pinned, T.views.data(), vb);
-    memcpy(c->pinned + align_up(vb), T.refs.data(), rb);
-    memcpy(c->pinned + align_up(vb) + align_up(rb), ptrs.data(), pb);
+    memcpy(c->pinned + o_ref, T.refs.data(), rb);
+    memcpy(c->pinned + o_ptr, ptrs.data(), pb);
+    if (jb) memcpy(c->pinned + o_job, jobs.data(), jb);
     HIP_TRY(c, hipMemcpyAsync(w.views, c->pinned, vb, hipMemcpyHostToDevice, s));
-    if (rb) HIP_TRY(c, hipMemcpyAsync(w.refs, c->pinned + align_up(vb), rb, hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipMemcpyAsync(w.grad_ptrs, c->pinned + align_up(vb) + align_up(rb), pb, hipMemcpyHostToDevice, s));
+    if (rb) HIP_TRY(c, hipMemcpyAsync(w.refs, c->pinned + o_ref, rb, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(w.grad_ptrs, c->pinned + o_ptr, pb, hipMemcpyHostToDevice, s));
+    if (jb) HIP_TRY(c, hipMemcpyAsync(w.jobs, c->pinned + o_job, jb, hipMemcpyHostToDevice, s));
     HIP_TRY(c, hipEventRecord(c->staging_done, s));
     c->staging_pending = true;
+    HIP_TRY(c, cow::launch_shadow_zero(w.jobs, (int)jobs.size(), max_texels, s));
     cow::MlpBwdArgs mb{};
     mb.views = w.views;
     mb.n_views = n_views;
@@ -887,11 +940,13 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     ba.grad_block_mlp = p->grad_block_mlp;
     ba.grad_grid = w.grad_ptrs;
     ba.grad_plane = w.grad_ptrs + ne;
+    ba.shadow = w.grad_ptrs + 4 * ne;
     c->have_bwd = c->timing;
     if (ba.m.persistent) HIP_TRY(c, cow::launch_reset_counter(ba.m.work_counter, s));
     if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[2], s));
     HIP_TRY(c, cow::launch_march_bwd(ba, c->cfg.waves, s));
     if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[3], s));
+    HIP_TRY(c, cow::launch_shadow_fold(w.jobs, (int)jobs.size(), max_texels, s));
     return COW_OK;
 } catch (...) {
     return fail(c, COW_E_INTERNAL, "internal error");
@@ -1048,7 +1103,7 @@ cow_status cow_autotune(cow_ctx* c, const cow_view* views, int n_views, const co
     }
     // outputs live in the tail of the workspace beyond what render needs
     const int64_t need_render = (int64_t)render_ws_layout(n_views, n_refs, n_pix, true, false,
-                                                          (int64_t)c->entries.size(), nullptr, nullptr);
+                                                          (int64_t)c->entries.size(), 0, nullptr, nullptr);
     const int64_t need = need_render + (int64_t)align_up(16 * n_pix) + 256;
     if (!ws || (int64_t)ws_bytes < need) return fail(c, COW_E_WORKSPACE, "autotune needs render workspace + 16 B per pixel");
     float* rgb = (float*)((unsigned char*)ws + need_render);

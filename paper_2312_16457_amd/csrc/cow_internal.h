@@ -93,6 +93,20 @@ struct BwdArgs {
     float* grad_block_mlp;     // [entries][499], accumulated, or null
     float* const* grad_grid;   // device array of per-entry pointers
     float* const* grad_plane;  // device array, 3 per entry
+    // Odd-pair gradients: a texel pair (p, p + 1) with p odd straddles two
+    // 64-byte segments of the gradient, so it is added to a shadow texture
+    // shifted by one texel instead (texel x at position x + 1), where it is
+    // one aligned segment; the shadow is folded into the gradient after the
+    // march.  Device array, 4 per entry (grid, xy, xz, yz; null: none).
+    float* const* shadow;
+};
+
+// zero the shadows, then (after the march) add shadow texel x + 1 into
+// gradient texel x
+struct FoldJob {
+    float* grad;      // [n_texels][8]
+    float* shadow;    // [n_texels + 1][8]
+    int64_t n_texels;
 };
 
 // sparsity regulariser at given points
@@ -119,6 +133,8 @@ hipError_t launch_clear_aux(float* aux, int64_t n_pix, hipStream_t s);
 hipError_t launch_mlp(const MlpArgs& a, hipStream_t s);
 hipError_t launch_mlp_bwd(const MlpBwdArgs& a, hipStream_t s);
 hipError_t launch_march_bwd(const BwdArgs& a, int waves_per_group, hipStream_t s);
+hipError_t launch_shadow_zero(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s);
+hipError_t launch_shadow_fold(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s);
 hipError_t launch_sparsity(const SparsityArgs& a, hipStream_t s);
 hipError_t launch_pack_bricks(const DevBlock* blocks, int entry, int O, int s_cells,
                               const int32_t* slot_host_unused, hipStream_t st);

@@ -24,45 +24,81 @@ namespace cow {
 // contiguous floats (8 channels each).  The lanes stage
 // their pairs in LDS and read them back transposed, so that one atomic
 // instruction covers four lanes' 64-byte runs instead of 64 scattered texels:
-// far fewer cache-line requests for the L2 atomic units.
+// far fewer cache-line requests for the L2 atomic units, whose request rate
+// bounds the adjoint.
 struct ScatterLds {
-    float v[64][20];  // 16 values, byte offsets of the two texels (-1: none), pad
+    float v[64][20];  // 16 values, byte offsets of the two texels (-1: none), target, pad
 };
 
-__device__ inline void scatter_pairs(ScatterLds& L, int lane, const Taps& T, const float draw[8],
-                                     float* const gptr[4], const __amdgpu_buffer_rsrc_t gr[4], bool have) {
+// Add vals[16] (texel p channels 0-7, texel p + 1 channels 0-7) for the pair
+// at texel index p (-1: nothing from this lane) of one gradient texture: an
+// even p into the gradient at byte 32 p, an odd p into its shadow at byte
+// 32 (p + 1), so every pair is one aligned 64-byte segment.
+__device__ inline void scatter_pair(ScatterLds& L, int lane, const float vals[16], int p,
+                                    const __amdgpu_buffer_rsrc_t& gr, const __amdgpu_buffer_rsrc_t& gs) {
+    float* row = L.v[lane];
 #pragma unroll
-    for (int pr = 0; pr < 10; ++pr) {
+    for (int c = 0; c < 16; ++c) row[c] = vals[c];
+    const int off = p < 0 ? -1 : 32 * (p + (p & 1));
+    row[16] = __int_as_float(off);
+    row[17] = __int_as_float(off < 0 ? -1 : off + 32);
+    row[18] = __int_as_float(p & 1);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int e = lane & 15, sub = lane >> 4;
+#pragma unroll 4
+    for (int j = 0; j < 16; ++j) {
+        const int src = 4 * j + sub;
+        const int o = __float_as_int(L.v[src][16 + (e >> 3)]);
+        const float val = L.v[src][e];
+        const bool odd = __float_as_int(L.v[src][18]) != 0;
+        if (o >= 0) {
+            if (odd)
+                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gs, o + 4 * (e & 7), 0, 0);
+            else
+                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gr, o + 4 * (e & 7), 0, 0);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Plane pairs (taps 4-9) of one sample: scattered at once.
+__device__ inline void scatter_planes(ScatterLds& L, int lane, const Taps& T, const float draw[8],
+                                      float* const gptr[4], const __amdgpu_buffer_rsrc_t gr[4],
+                                      const __amdgpu_buffer_rsrc_t gs[4], bool have) {
+#pragma unroll
+    for (int pr = 4; pr < 10; ++pr) {
         const int tex = pair_tex(pr);
         if (!gptr[tex]) continue;
-        const int ka = 2 * pr, kb2 = 2 * pr + 1;  // taps of texels p and p + 1 along x / u
-        float* row = L.v[lane];
-        if (have) {
+        float vals[16];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                row[c] = T.w[ka] * draw[c];
-                row[8 + c] = T.w[kb2] * draw[c];
-            }
-            row[16] = __int_as_float(T.pidx[pr] * 32);
-            row[17] = __int_as_float(T.pidx[pr] * 32 + 32);
-        } else {
-            row[16] = __int_as_float(-1);
-            row[17] = __int_as_float(-1);
+        for (int c = 0; c < 8; ++c) {
+            vals[c] = T.w[2 * pr] * draw[c];
+            vals[8 + c] = T.w[2 * pr + 1] * draw[c];
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int e = lane & 15, sub = lane >> 4;
-#pragma unroll 4
-        for (int j = 0; j < 16; ++j) {
-            const int src = 4 * j + sub;
-            const int off = __float_as_int(L.v[src][16 + (e >> 3)]);
-            const float val = L.v[src][e];
-            if (off >= 0) __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gr[tex], off + 4 * (e & 7), 0, 0);
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        scatter_pair(L, lane, vals, have ? T.pidx[pr] : -1, gr[tex], gs[tex]);
+    }
+}
+
+// Grid pairs (taps 0-3): consecutive samples of a ray often fall between the
+// same eight grid texels (a 128^3 grid cell spans about 2.7 steps of 1/512),
+// so a lane sums its grid gradient in registers while its cell stays the same
+// and scatters the sum when the cell changes or the block ends.  Only the
+// summation order differs from a per-sample scatter.
+struct GridAcc {
+    int cell;        // pair index of tap 0 of the pending cell, -1: none
+    float v[4][16];  // pending gradient of the cell's four pairs
+};
+
+__device__ inline void flush_grid(ScatterLds& L, int lane, GridAcc& g, bool flush, int lR,
+                                  const __amdgpu_buffer_rsrc_t& gr, const __amdgpu_buffer_rsrc_t& gs) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int pidx = g.cell + ((((j >> 1) << lR) + (j & 1)) << lR);
+        scatter_pair(L, lane, g.v[j], flush ? pidx : -1, gr, gs);
     }
 }
 
@@ -121,9 +157,11 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
         // no-return buffer_atomic_add_f32 with a 32-bit offset per lane
         float* gptr[4] = {ufp(ba.grad_grid[e]), ufp(ba.grad_plane[3 * e + 0]), ufp(ba.grad_plane[3 * e + 1]),
                           ufp(ba.grad_plane[3 * e + 2])};
-        __amdgpu_buffer_rsrc_t gr[4];
+        __amdgpu_buffer_rsrc_t gr[4], gs[4];
         gr[0] = tex_rsrc(gptr[0], (uint32_t)b.R * b.R * b.R * 32u);
         for (int t = 1; t < 4; ++t) gr[t] = tex_rsrc(gptr[t], (uint32_t)b.Rp * b.Rp * 32u);
+        gs[0] = tex_rsrc(ufp(ba.shadow[4 * e]), ((uint32_t)b.R * b.R * b.R + 1u) * 32u);
+        for (int t = 1; t < 4; ++t) gs[t] = tex_rsrc(ufp(ba.shadow[4 * e + t]), ((uint32_t)b.Rp * b.Rp + 1u) * 32u);
         const bool alive = hit && !(T_blk < a.t_min);
         const Span sp = block_span<MODE>(a, b, r, alive, w0, w1);
         if (!__any(sp.ka < sp.kb)) continue;
@@ -159,6 +197,13 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
         int cur_cell = -1;
         bool cur_occ = false;
         float Tk = 1.0f;  // block-local transmittance, for the same termination decision as the forward
+        GridAcc gacc;
+        gacc.cell = -1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int c = 0; c < 16; ++c) gacc.v[j][c] = 0.0f;
+        const bool want_grid = gptr[0] != nullptr;
         for (;;) {
             float q[3];
             int cell = 0;
@@ -193,8 +238,33 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
                 if (T_blk * Tk < a.t_min) kb = k;  // early ray termination, as in the forward
             }
             // collective over the wave: lanes without a sample take part with nothing to add
-            scatter_pairs(lds, lane, T, draw, gptr, gr, have);
+            if (want_grid) {
+                const int cell_now = have ? T.pidx[0] : -1;
+                const bool flush = have && gacc.cell >= 0 && cell_now != gacc.cell;
+                if (__any(flush)) {
+                    flush_grid(lds, lane, gacc, flush, b.lR, gr[0], gs[0]);
+                    if (flush) {
+                        gacc.cell = -1;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+#pragma unroll
+                            for (int c = 0; c < 16; ++c) gacc.v[j][c] = 0.0f;
+                    }
+                }
+                if (have) {
+                    gacc.cell = cell_now;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) {
+                            gacc.v[j][c] = fmaf(T.w[2 * j], draw[c], gacc.v[j][c]);
+                            gacc.v[j][8 + c] = fmaf(T.w[2 * j + 1], draw[c], gacc.v[j][8 + c]);
+                        }
+                }
+            }
+            scatter_planes(lds, lane, T, draw, gptr, gr, gs, have);
         }
+        if (want_grid && __any(gacc.cell >= 0)) flush_grid(lds, lane, gacc, gacc.cell >= 0, b.lR, gr[0], gs[0]);
         T_blk *= Tk;
     }
 }
@@ -220,6 +290,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
         march_bwd_packet<MODE, OPAC, BMLP>(ba, V, p - ufl(V->tile_begin), lane, lds[wave]);
         if (!a.persistent) return;
     }
+}
+
+// blockIdx.y: job; grid-stride over the job's floats
+__global__ __launch_bounds__(256) void shadow_zero_kernel(const FoldJob* jobs) {
+    const FoldJob j = jobs[blockIdx.y];
+    float4* sh = reinterpret_cast<float4*>(j.shadow);
+    const int64_t n = 2 * (j.n_texels + 1);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        sh[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+__global__ __launch_bounds__(256) void shadow_fold_kernel(const FoldJob* jobs) {
+    const FoldJob j = jobs[blockIdx.y];
+    float4* g = reinterpret_cast<float4*>(j.grad);
+    const float4* sh = reinterpret_cast<const float4*>(j.shadow) + 2;  // texel x + 1
+    const int64_t n = 2 * j.n_texels;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float4 a = g[i], b = sh[i];
+        g[i] = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+    }
+}
+
+static dim3 fold_grid(int n_jobs, int64_t max_texels) {
+    const int64_t blocks = (2 * (max_texels + 1) + 255) / 256;
+    return dim3((unsigned)(blocks < 2048 ? blocks : 2048), (unsigned)n_jobs);
+}
+
+hipError_t launch_shadow_zero(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s) {
+    if (n_jobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(shadow_zero_kernel, fold_grid(n_jobs, max_texels), dim3(256), 0, s, jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_shadow_fold(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s) {
+    if (n_jobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(shadow_fold_kernel, fold_grid(n_jobs, max_texels), dim3(256), 0, s, jobs);
+    return hipGetLastError();
 }
 
 hipError_t launch_march_bwd(const BwdArgs& a, int waves, hipStream_t s) {
