@@ -88,6 +88,7 @@ def lib():
         L.orc_sparsity.restype = C.c_double
         L.orc_select.argtypes = [C.POINTER(_View), C.c_int, vp, vp, vp, vp, vp, vp, C.c_int, C.c_int,
                                  vp, C.c_int]
+        L.orc_select_quadtree.argtypes = L.orc_select.argtypes
         L.orc_mlp.argtypes = [vp, vp, vp]
         L.orc_field.argtypes = [C.POINTER(_Block), C.c_int, vp, vp]
         _lib = L
@@ -165,9 +166,16 @@ class OracleScene:
         raise KeyError((block_id, lod))
 
 
+def dims(b, res):
+    """(z, y, x) texel or cell counts of a block: res per unit length times
+    the block's extent on each axis."""
+    ext = [int(round(float(b.aabb_max[c]) - float(b.aabb_min[c]))) for c in range(3)]
+    return (res * ext[2], res * ext[1], res * ext[0])
+
+
 def occupancy(ob, k):
     b = ob.blocks[k]
-    out = np.zeros((b.occ_res,) * 3, np.uint8)
+    out = np.zeros(dims(b, b.occ_res), np.uint8)
     r = lib().orc_occupancy(C.byref(ob.arr[k]), _ptr(out))
     if r != 0:
         raise ValueError("bad resolutions")
@@ -321,9 +329,10 @@ def adjoint_block_mlp(ob, occs, view, set_idx, params, mlps, pix, grad_rgb, grad
     return grads, gm.reshape(ob.n, 499)
 
 
-def select(view, entries, ztops, thresholds=(2.0, 4.0, 8.0), cull=True, cap=4096):
+def select(view, entries, ztops, thresholds=(2.0, 4.0, 8.0), cull=True, cap=4096, quadtree=False):
     """entries: list of BlockLod (or objects with block_id, lod, aabb_min, aabb_max);
-    ztops: per entry.  Returns chosen entry indices in front-to-back order."""
+    ztops: per entry.  Returns chosen entry indices in front-to-back order.
+    quadtree: entries of LOD l are merged assets over 2^l x 2^l blocks."""
     n = len(entries)
     ids = np.array([e.block_id for e in entries], np.int32)
     lods = np.array([e.lod for e in entries], np.int32)
@@ -333,8 +342,11 @@ def select(view, entries, ztops, thresholds=(2.0, 4.0, 8.0), cull=True, cap=4096
     thr = np.ascontiguousarray(thresholds, np.float64)
     out = np.zeros(cap, np.int32)
     vs = make_view(view)
-    m = lib().orc_select(C.byref(vs), n, _ptr(ids), _ptr(lods), _ptr(lo), _ptr(hi), _ptr(zt), _ptr(thr),
-                         len(thr), int(cull), _ptr(out), cap)
+    fn = lib().orc_select_quadtree if quadtree else lib().orc_select
+    m = fn(C.byref(vs), n, _ptr(ids), _ptr(lods), _ptr(lo), _ptr(hi), _ptr(zt), _ptr(thr),
+           len(thr), int(cull), _ptr(out), cap)
+    if m == -3:
+        raise ValueError("quadtree selection needs a threshold for every LOD below the coarsest")
     if m < 0:
         raise KeyError("selected (block, LOD) not loaded")
     return out[:m]

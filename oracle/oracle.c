@@ -72,6 +72,10 @@ static int slab32(const float o[3], const float d[3], const float lo[3], const f
     return t0 < t1;
 }
 
+/* Texels (or cells) along axis c of a block: the per-unit-length resolution
+ * times the block's extent on that axis (a whole power of two). */
+static int dim(const orc_block* b, int res, int c) { return res * (int)(b->hi[c] - b->lo[c]); }
+
 /* occupancy cell of a sample in block b (fp32 local coordinate) */
 static int occ_cell(const orc_block* b, const float p[3], float q[3]) {
     int cell[3];
@@ -80,10 +84,10 @@ static int occ_cell(const orc_block* b, const float p[3], float q[3]) {
         float s = q[c] * (float)b->O;
         int k = (int)floorf(s);
         if (k < 0) k = 0;
-        if (k > b->O - 1) k = b->O - 1;
+        if (k > dim(b, b->O, c) - 1) k = dim(b, b->O, c) - 1;
         cell[c] = k;
     }
-    return (cell[2] * b->O + cell[1]) * b->O + cell[0];
+    return (cell[2] * dim(b, b->O, 1) + cell[1]) * dim(b, b->O, 0) + cell[0];
 }
 
 /* ---------------------------------------------------------------------- */
@@ -112,14 +116,15 @@ static float texel32(const orc_block* b, int tex, long idx, int ch) {
 
 static int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
 
-/* cell-centred linear interpolation taps with clamp-to-edge: u = q*R - 1/2 */
-static void lin_taps(double q, int R, int idx[2], double w[2]) {
+/* cell-centred linear interpolation taps with clamp-to-edge: u = q*R - 1/2
+ * for R texels per unit length, D texels along the axis */
+static void lin_taps(double q, int R, int D, int idx[2], double w[2]) {
     double u = q * (double)R - 0.5;
     double f0 = floor(u);
     double f = u - f0;
     int a = (int)f0;
-    idx[0] = clampi(a, 0, R - 1);
-    idx[1] = clampi(a + 1, 0, R - 1);
+    idx[0] = clampi(a, 0, D - 1);
+    idx[1] = clampi(a + 1, 0, D - 1);
     w[0] = 1.0 - f;
     w[1] = f;
 }
@@ -138,8 +143,8 @@ static void eval_raw(const orc_block* b, const float q32[3], double raw[NCH], ta
     int gi[3][2], pi[3][2];
     double gw[3][2], pw[3][2];
     for (int c = 0; c < 3; ++c) {
-        lin_taps(q[c], b->R, gi[c], gw[c]);
-        lin_taps(q[c], b->Rp, pi[c], pw[c]);
+        lin_taps(q[c], b->R, dim(b, b->R, c), gi[c], gw[c]);
+        lin_taps(q[c], b->Rp, dim(b, b->Rp, c), pi[c], pw[c]);
     }
     double part[4][NCH];
     memset(part, 0, sizeof(part));
@@ -148,7 +153,7 @@ static void eval_raw(const orc_block* b, const float q32[3], double raw[NCH], ta
     for (int dz = 0; dz < 2; ++dz)
         for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx) {
-                long idx = ((long)gi[2][dz] * b->R + gi[1][dy]) * b->R + gi[0][dx];
+                long idx = ((long)gi[2][dz] * dim(b, b->R, 1) + gi[1][dy]) * dim(b, b->R, 0) + gi[0][dx];
                 double w = gw[2][dz] * gw[1][dy] * gw[0][dx];
                 for (int ch = 0; ch < NCH; ++ch) part[0][ch] += w * texel(b, 0, idx, ch);
                 if (taps) taps[nt++] = (tap){0, idx, w};
@@ -159,7 +164,7 @@ static void eval_raw(const orc_block* b, const float q32[3], double raw[NCH], ta
         int au = axes[pl][0], av = axes[pl][1];
         for (int dv = 0; dv < 2; ++dv)
             for (int du = 0; du < 2; ++du) {
-                long idx = (long)pi[av][dv] * b->Rp + pi[au][du];
+                long idx = (long)pi[av][dv] * dim(b, b->Rp, au) + pi[au][du];
                 double w = pw[av][dv] * pw[au][du];
                 for (int ch = 0; ch < NCH; ++ch) part[1 + pl][ch] += w * texel(b, 1 + pl, idx, ch);
                 if (taps) taps[nt++] = (tap){1 + pl, idx, w};
@@ -179,22 +184,28 @@ int orc_occupancy(const orc_block* b, unsigned char* out) {
     int O = b->O, R = b->R, Rp = b->Rp;
     if (O <= 0 || R % O || Rp % O) return -1;
     int s = R / O, sp = Rp / O;
-    for (int cz = 0; cz < O; ++cz)
-        for (int cy = 0; cy < O; ++cy)
-            for (int cx = 0; cx < O; ++cx) {
+    int G[3], P[3], C[3];
+    for (int a = 0; a < 3; ++a) {
+        G[a] = dim(b, R, a);
+        P[a] = dim(b, Rp, a);
+        C[a] = dim(b, O, a);
+    }
+    for (int cz = 0; cz < C[2]; ++cz)
+        for (int cy = 0; cy < C[1]; ++cy)
+            for (int cx = 0; cx < C[0]; ++cx) {
                 int c3[3] = {cx, cy, cz};
                 int glo[3], ghi[3], plo[3], phi[3];
                 for (int a = 0; a < 3; ++a) {
-                    glo[a] = clampi(c3[a] * s - 1, 0, R - 1);
-                    ghi[a] = clampi((c3[a] + 1) * s, 0, R - 1);
-                    plo[a] = clampi(c3[a] * sp - 1, 0, Rp - 1);
-                    phi[a] = clampi((c3[a] + 1) * sp, 0, Rp - 1);
+                    glo[a] = clampi(c3[a] * s - 1, 0, G[a] - 1);
+                    ghi[a] = clampi((c3[a] + 1) * s, 0, G[a] - 1);
+                    plo[a] = clampi(c3[a] * sp - 1, 0, P[a] - 1);
+                    phi[a] = clampi((c3[a] + 1) * sp, 0, P[a] - 1);
                 }
                 float mg = -INFINITY;
                 for (int z = glo[2]; z <= ghi[2]; ++z)
                     for (int y = glo[1]; y <= ghi[1]; ++y)
                         for (int x = glo[0]; x <= ghi[0]; ++x) {
-                            float v = texel32(b, 0, ((long)z * R + y) * R + x, 0);
+                            float v = texel32(b, 0, ((long)z * G[1] + y) * G[0] + x, 0);
                             if (v > mg) mg = v;
                         }
                 static const int axes[3][2] = {{0, 1}, {0, 2}, {1, 2}};
@@ -204,24 +215,24 @@ int orc_occupancy(const orc_block* b, unsigned char* out) {
                     float m = -INFINITY;
                     for (int vv = plo[av]; vv <= phi[av]; ++vv)
                         for (int uu = plo[au]; uu <= phi[au]; ++uu) {
-                            float val = texel32(b, 1 + pl, (long)vv * Rp + uu, 0);
+                            float val = texel32(b, 1 + pl, (long)vv * P[au] + uu, 0);
                             if (val > m) m = val;
                         }
                     mp[pl] = m;
                 }
                 float bound = ((mg + mp[0]) + mp[1]) + mp[2];
-                out[(cz * O + cy) * O + cx] = bound > thresh ? 1 : 0;
+                out[(cz * C[1] + cy) * C[0] + cx] = bound > thresh ? 1 : 0;
             }
     return 0;
 }
 
 double orc_ztop(const orc_block* b, const unsigned char* occ) {
-    int O = b->O, top = -1;
-    for (int z = 0; z < O; ++z)
-        for (int i = 0; i < O * O; ++i)
-            if (occ[z * O * O + i]) top = z;
+    int nz = dim(b, b->O, 2), nxy = dim(b, b->O, 0) * dim(b, b->O, 1), top = -1;
+    for (int z = 0; z < nz; ++z)
+        for (int i = 0; i < nxy; ++i)
+            if (occ[z * nxy + i]) top = z;
     double ext = (double)b->hi[2] - (double)b->lo[2];
-    return (double)b->lo[2] + (double)(top + 1) / (double)O * ext;
+    return (double)b->lo[2] + (double)(top + 1) / (double)nz * ext;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -615,7 +626,7 @@ int orc_ray_blocks(const orc_block* blocks, int nblocks, const orc_view* v, cons
     const unsigned char** occ = (const unsigned char**)malloc(sizeof(void*) * nblocks);
     unsigned char** full = (unsigned char**)malloc(sizeof(void*) * nblocks);
     for (int b = 0; b < nblocks; ++b) {
-        long o3 = (long)blocks[b].O * blocks[b].O * blocks[b].O;
+        long o3 = (long)dim(&blocks[b], blocks[b].O, 0) * dim(&blocks[b], blocks[b].O, 1) * dim(&blocks[b], blocks[b].O, 2);
         full[b] = (unsigned char*)malloc(o3);
         memset(full[b], one, o3);
         occ[b] = full[b];
@@ -1099,4 +1110,125 @@ int orc_select(const orc_view* v, int nent, const int* ids, const int* lods, con
         }
     free(key);
     return n;
+}
+
+/* Quadtree LOD selection (Appendix D "Dynamic Loading" with the merged LOD
+ * assets of Sec. 4.5 "Baking": an entry of LOD l covers 2^l x 2^l blocks).
+ * Coarse to fine: an entry of LOD l > 0 is drawn when every visible entry of
+ * LOD l - 1 inside it lies at distance >= thresholds[l - 1] (vacuously when
+ * none is visible); otherwise its visible children are examined in turn.
+ * Distance: eye to (centre x, centre y, highest finest-level top inside the
+ * entry).  Culling: the entry's box [lo, (hi_x, hi_y, its own ztop)].  Order:
+ * the coarsest entries by xy distance of their centres (ties: lower id), and
+ * inside an entry its children nearest quadrant first, then the two quadrants
+ * beside it (lower id first), then the opposite one: a straight ray crosses
+ * each of the two centre lines at most once, so it never meets them in
+ * another order.  A coarsest entry at distance >= thresholds[L] (when given)
+ * is not drawn. */
+typedef struct qt_state {
+    const orc_view* v;
+    int nent;
+    const int *ids, *lods;
+    const float *lo, *hi;
+    const double *ztop, *thr;
+    int n_thr, cull, *out, cap, n;
+} qt_state;
+
+static int xy_inside(const qt_state* q, int f, int e) {
+    return q->lo[3 * f] >= q->lo[3 * e] && q->hi[3 * f] <= q->hi[3 * e] && q->lo[3 * f + 1] >= q->lo[3 * e + 1] &&
+           q->hi[3 * f + 1] <= q->hi[3 * e + 1];
+}
+
+static double qt_dist(const qt_state* q, int e) {
+    double zf = -INFINITY;
+    for (int f = 0; f < q->nent; ++f)
+        if (q->lods[f] == 0 && xy_inside(q, f, e) && q->ztop[f] > zf) zf = q->ztop[f];
+    double cx = 0.5 * ((double)q->lo[3 * e] + (double)q->hi[3 * e]);
+    double cy = 0.5 * ((double)q->lo[3 * e + 1] + (double)q->hi[3 * e + 1]);
+    double dx = (double)q->v->eye[0] - cx, dy = (double)q->v->eye[1] - cy, dz = (double)q->v->eye[2] - zf;
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
+static int qt_visible(const qt_state* q, int e) {
+    if (!q->cull) return 1;
+    double blo[3] = {q->lo[3 * e], q->lo[3 * e + 1], q->lo[3 * e + 2]};
+    double bhi[3] = {q->hi[3 * e], q->hi[3 * e + 1], q->ztop[e]};
+    return !culled(q->v, blo, bhi);
+}
+
+static void qt_emit(qt_state* q, int e) {
+    if (q->n < q->cap) q->out[q->n] = e;
+    ++q->n;
+}
+
+static void qt_visit(qt_state* q, int e) {
+    int l = q->lods[e];
+    if (l == 0) {
+        qt_emit(q, e);
+        return;
+    }
+    int kid[64], rank[64], nk = 0, all_far = 1;
+    double cx = 0.5 * ((double)q->lo[3 * e] + (double)q->hi[3 * e]);
+    double cy = 0.5 * ((double)q->lo[3 * e + 1] + (double)q->hi[3 * e + 1]);
+    int ex = (double)q->v->eye[0] >= cx, ey = (double)q->v->eye[1] >= cy;
+    for (int f = 0; f < q->nent && nk < 64; ++f) {
+        if (q->lods[f] != l - 1 || !xy_inside(q, f, e) || !qt_visible(q, f)) continue;
+        if (qt_dist(q, f) < q->thr[l - 1]) all_far = 0;
+        double fx = 0.5 * ((double)q->lo[3 * f] + (double)q->hi[3 * f]);
+        double fy = 0.5 * ((double)q->lo[3 * f + 1] + (double)q->hi[3 * f + 1]);
+        rank[nk] = ((fx >= cx) != ex) + ((fy >= cy) != ey);
+        kid[nk++] = f;
+    }
+    if (all_far) {
+        qt_emit(q, e);
+        return;
+    }
+    for (int r = 0; r <= 2; ++r) {
+        /* children of this rank, lower id first */
+        int used[64] = {0};
+        for (;;) {
+            int best = -1;
+            for (int k = 0; k < nk; ++k)
+                if (!used[k] && rank[k] == r && (best < 0 || q->ids[kid[k]] < q->ids[kid[best]])) best = k;
+            if (best < 0) break;
+            used[best] = 1;
+            qt_visit(q, kid[best]);
+        }
+    }
+}
+
+int orc_select_quadtree(const orc_view* v, int nent, const int* ids, const int* lods, const float* lo,
+                        const float* hi, const double* ztop, const double* thresholds, int n_thr, int cull,
+                        int* out, int cap) {
+    int L = 0;
+    for (int e = 0; e < nent; ++e)
+        if (lods[e] > L) L = lods[e];
+    if (n_thr < L) return -3;
+    qt_state q = {v, nent, ids, lods, lo, hi, ztop, thresholds, n_thr, cull, out, cap, 0};
+    int* roots = (int*)malloc(sizeof(int) * (nent + 1));
+    double* key = (double*)malloc(sizeof(double) * (nent + 1));
+    int nr = 0;
+    for (int e = 0; e < nent; ++e) {
+        if (lods[e] != L || !qt_visible(&q, e)) continue;
+        if (n_thr > L && qt_dist(&q, e) >= thresholds[L]) continue;
+        double cx = 0.5 * ((double)lo[3 * e] + (double)hi[3 * e]), cy = 0.5 * ((double)lo[3 * e + 1] + (double)hi[3 * e + 1]);
+        double dx = (double)v->eye[0] - cx, dy = (double)v->eye[1] - cy;
+        roots[nr] = e;
+        key[nr++] = sqrt(dx * dx + dy * dy);
+    }
+    for (int a = 1; a < nr; ++a)
+        for (int b = a; b > 0; --b) {
+            int swap = key[b] < key[b - 1] || (key[b] == key[b - 1] && ids[roots[b]] < ids[roots[b - 1]]);
+            if (!swap) break;
+            double tk = key[b];
+            key[b] = key[b - 1];
+            key[b - 1] = tk;
+            int tr = roots[b];
+            roots[b] = roots[b - 1];
+            roots[b - 1] = tr;
+        }
+    for (int r = 0; r < nr; ++r) qt_visit(&q, roots[r]);
+    free(roots);
+    free(key);
+    return q.n > cap ? cap : q.n;
 }

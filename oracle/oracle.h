@@ -23,7 +23,9 @@ enum { ORC_U8 = 0, ORC_F64 = 1 };
 typedef struct orc_block {
     int block_id, lod;
     float lo[3], hi[3];      /* AABB; samples belong to [lo, hi) (half-open) */
-    int R, Rp, O;            /* grid, plane and occupancy resolution */
+    int R, Rp, O;            /* grid, plane and occupancy texels (cells) per unit length; a
+                                block spans hi - lo (whole powers of two per axis), so its
+                                grid holds R*(hi-lo) texels along each axis */
     int dtype;               /* ORC_U8 or ORC_F64 */
     const unsigned char* g8; /* [R][R][R][8]  z,y,x,ch */
     const unsigned char* p8[3];
@@ -126,6 +128,16 @@ double orc_sparsity(const orc_block* blocks, int nblocks, const unsigned char* c
 int orc_select(const orc_view* v, int nent, const int* ids, const int* lods, const float* lo,
                const float* hi, const double* ztop, const double* thresholds, int n_thr,
                int cull, int* out, int cap);
+
+/* Quadtree selection over merged LOD entries (an entry of LOD l covers
+ * 2^l x 2^l blocks): coarse to fine, an entry of LOD l > 0 is drawn when
+ * every visible LOD l-1 entry inside it is at distance >= thresholds[l-1];
+ * front-to-back order by recursive quadrants.  n_thr >= the coarsest LOD
+ * (-3 otherwise); thresholds[L], when given, drops far coarsest entries.
+ * Returns the count of chosen entry indices written to out. */
+int orc_select_quadtree(const orc_view* v, int nent, const int* ids, const int* lods, const float* lo,
+                        const float* hi, const double* ztop, const double* thresholds, int n_thr, int cull,
+                        int* out, int cap);
 
 /* pre-activation features at n world points of block b (points outside the
  * block are evaluated by the same clamped rule): raw[8n] */

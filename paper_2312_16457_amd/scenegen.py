@@ -16,7 +16,9 @@ and views are aerial.
 
 Conventions (shared by every consumer):
   * block (bx, by) is the unit cube [bx, bx+1] x [by, by+1] x [0, 1];
-    block_id = by * nbx + bx.
+    block_id = by * nbx + bx.  A merged LOD asset (quadtree LOD) spans
+    2^l x 2^l blocks; resolutions are texels per unit length, so a texture
+    holds R * extent texels along each axis (below, for a unit block).
   * grid texture  : array [R][R][R][8]  indexed [z][y][x][channel]
   * plane xy      : array [Rp][Rp][8]   indexed [y][x][channel]
   * plane xz      : array [Rp][Rp][8]   indexed [z][x][channel]
@@ -417,6 +419,77 @@ C4_TRAJECTORY = dict(xy=(3.0, 5.0), h=(1.2, 2.8), pitch=(45.0, 75.0))
 
 def c4_views(seed=3):
     return aerial_views(seed, 64, C4_RESOLUTIONS, **C4_TRAJECTORY)
+
+
+def _box_down(a, f, ndim):
+    """Box downsample of the first `ndim` axes by an integer factor f."""
+    if f == 1:
+        return a.astype(np.float32)
+    sh = []
+    for n in a.shape[:ndim]:
+        sh += [n // f, f]
+    b = a.reshape(*sh, a.shape[-1]).astype(np.float64)
+    return b.mean(axis=tuple(range(1, 2 * ndim, 2))).astype(np.float32)
+
+
+def merged_lods(finest, nbx, nby, n_lods, dtype=U8):
+    """Merged LOD assets (Sec. 4.4 LOD generation, Sec. 4.5 baking): the
+    entry of LOD l covers 2^l x 2^l blocks of the finest level, at 1/2^l of
+    its texel density, as one asset.  Its grid and xy plane are the 2^l box
+    downsample of the finest blocks' decoded textures laid side by side; its
+    xz (yz) plane is the mean over the blocks along y (x) of their
+    downsampled xz (yz) planes, laid side by side along x (y).  Resolutions
+    are per unit length; block_id is that of the asset's lowest block.
+    finest: the LOD-0 BlockLod of every block (block_id = by * nbx + bx)."""
+    by_id = {b.block_id: b for b in finest if b.lod == 0}
+    out = []
+    for l in range(1, n_lods):
+        f = 1 << l
+        for gy in range(0, nby, f):
+            for gx in range(0, nbx, f):
+                ids = [[(gy + j) * nbx + (gx + i) for i in range(f) if gx + i < nbx] for j in range(f) if gy + j < nby]
+                if len(ids) != f or any(len(r) != f for r in ids):
+                    continue  # an incomplete group at the edge of the grid has no merged asset
+                b0 = by_id[ids[0][0]]
+                R, Rp, O = b0.grid_res // f, b0.plane_res // f, b0.occ_res // f
+                dec = {i: by_id[i].decoded() for row in ids for i in row}
+                grid = np.concatenate([np.concatenate([_box_down(dec[i][0], f, 3) for i in row], axis=2)
+                                       for row in ids], axis=1)
+                xy = np.concatenate([np.concatenate([_box_down(dec[i][1][0], f, 2) for i in row], axis=1)
+                                     for row in ids], axis=0)
+                xz = np.concatenate([np.mean([_box_down(dec[ids[j][i]][1][1], f, 2) for j in range(f)], axis=0)
+                                     for i in range(f)], axis=1).astype(np.float32)
+                yz = np.concatenate([np.mean([_box_down(dec[ids[j][i]][1][2], f, 2) for i in range(f)], axis=0)
+                                     for j in range(f)], axis=1).astype(np.float32)
+                planes = [xy, xz, yz]
+                if dtype == U8:
+                    qg, sg, og = quantize(grid)
+                    qp = [quantize(p) for p in planes]
+                    scale = np.stack([sg] + [x[1] for x in qp]).astype(np.float32)
+                    offset = np.stack([og] + [x[2] for x in qp]).astype(np.float32)
+                    g_store, p_store = qg, [x[0] for x in qp]
+                else:
+                    scale = np.ones((4, NCH), np.float32)
+                    offset = np.zeros((4, NCH), np.float32)
+                    g_store, p_store = grid, planes
+                lo = np.array([gx, gy, 0], np.float32)
+                hi = np.array([gx + f, gy + f, 1], np.float32)
+                out.append(BlockLod(ids[0][0], l, lo, hi, R, Rp, O, dtype, np.ascontiguousarray(g_store),
+                                    [np.ascontiguousarray(p) for p in p_store], scale, offset))
+                del dec
+    return out
+
+
+def c3q_scene(seed=2):
+    """The 8x8 city with quadtree LODs: the finest blocks of the LOD city
+    (128^3 grid, 1024^2 planes, 16^3 occupancy per unit block) plus merged
+    assets of 2x2 blocks (LOD 1: 64 texels per unit, 128 x 128 x 64 grid) and
+    4x4 blocks (LOD 2: 32 per unit, 128 x 128 x 32), uint8."""
+    fine = city_scene(8, seed, U8, (C3_LODS[0],))
+    return Scene(8, 8, fine.blocks + merged_lods(fine.blocks, 8, 8, 3))
+
+
+QUADTREE_THRESHOLDS = (2.0, 4.0)
 
 
 def c5_scenes(seed=4, target_seed=5, lods=((128, 1024, 16),), nb=4):

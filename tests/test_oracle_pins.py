@@ -803,3 +803,156 @@ def test_block_mlp_adjoint_matches_finite_differences(extra):
             assert abs(gm[k, i] - fd) <= 1e-4 * abs(fd) + 1e-8, (k, i, gm[k, i], fd)
             checked += 1
     assert checked >= 40
+
+
+# ---------------------------------------------------------------------------
+# Quadtree LOD (Sec. 4.5 "Baking": an entry of LOD l is one asset over
+# 2^l x 2^l blocks; Appendix D: coarse-to-fine selection, depth order)
+# ---------------------------------------------------------------------------
+def merged_block(R=4, Rp=8, O=2, ext=(2, 2, 1), seed=0, dtype=sg.F32):
+    """A block of extent ext with random smooth textures (resolutions per unit length)."""
+    rng = np.random.default_rng(seed)
+    gx, gy, gz = (R * e for e in ext)
+    px, py, pz = (Rp * e for e in ext)
+    grid = rng.normal(0, 1, (gz, gy, gx, 8)).astype(np.float32)
+    planes = [rng.normal(0, 1, s + (8,)).astype(np.float32) for s in ((py, px), (pz, px), (pz, py))]
+    lo = np.zeros(3, np.float32)
+    return sg.BlockLod(0, 1, lo, lo + np.array(ext, np.float32), R, Rp, O, dtype, grid, planes,
+                       np.ones((4, 8), np.float32), np.zeros((4, 8), np.float32))
+
+
+def test_merged_block_field_against_scipy():
+    """Texture addressing of a non-cubic (4 x 2 x 1) asset: every texture is
+    interpolated at u = q R - 1/2 per unit length over its own extent, with
+    x (u) fastest; checked against scipy's map_coordinates."""
+    from scipy.ndimage import map_coordinates
+    b = merged_block(ext=(4, 2, 1))  # three different extents: a swapped row length fails
+    ob = O.OracleScene([b])
+    rng = np.random.default_rng(3)
+    pts = (rng.uniform(0, 1, (400, 3)) * np.array([4, 2, 1])).astype(np.float32)
+    raw = O.field(ob, 0, pts)
+    q = pts.astype(np.float64)
+    R, Rp = b.grid_res, b.plane_res
+    ref = np.zeros((400, 8))
+    for ch in range(8):
+        g = map_coordinates(b.grid[..., ch].astype(np.float64), [q[:, 2] * R - .5, q[:, 1] * R - .5,
+                                                                 q[:, 0] * R - .5], order=1, mode="nearest")
+        xy = map_coordinates(b.planes[0][..., ch].astype(np.float64), [q[:, 1] * Rp - .5, q[:, 0] * Rp - .5],
+                             order=1, mode="nearest")
+        xz = map_coordinates(b.planes[1][..., ch].astype(np.float64), [q[:, 2] * Rp - .5, q[:, 0] * Rp - .5],
+                             order=1, mode="nearest")
+        yz = map_coordinates(b.planes[2][..., ch].astype(np.float64), [q[:, 2] * Rp - .5, q[:, 1] * Rp - .5],
+                             order=1, mode="nearest")
+        ref[:, ch] = ((g + xy) + xz) + yz
+    np.testing.assert_allclose(raw, ref, atol=1e-9)
+
+
+def test_merged_block_occupancy_sound():
+    b = merged_block(R=8, Rp=16, O=2, seed=4)
+    b.grid[..., 0] = -9.0  # empty but for a few dense texels
+    b.grid[3, 5, 12, 0] = b.grid[6, 13, 2, 0] = 2.0
+    for p in b.planes:
+        p[..., 0] *= 0.1
+    ob = O.OracleScene([b])
+    occ = O.occupancy(ob, 0)
+    assert occ.shape == (2, 4, 4) and 0 < occ.mean() < 1
+    n = 9
+    g = (np.arange(n) / (n - 1)) * (1 - 1e-7)
+    worst = -np.inf
+    for cz, cy, cx in zip(*np.nonzero(occ == 0)):
+        zz, yy, xx = np.meshgrid((cz + g) / 2, (cy + g) / 2, (cx + g) / 2, indexing="ij")
+        pts = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], 1).astype(np.float32)
+        worst = max(worst, O.field(ob, 0, pts)[:, 0].max())
+    assert math.exp(worst) <= 0.01
+
+
+@pytest.fixture(scope="module")
+def quad_city():
+    fine = sg.city_scene(4, 7, sg.U8, ((16, 64, 4),), blobs_per_block=20)
+    scene = sg.Scene(4, 4, fine.blocks + sg.merged_lods(fine.blocks, 4, 4, 3))
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    zt = [O.ztop(ob, k, occs[k]) for k in range(ob.n)]
+    return scene, ob, occs, zt
+
+
+def quad_views():
+    views = sg.aerial_views(31, 6, [(40, 24)], xy=(0.0, 4.0), h=(1.0, 3.0), pitch=(30.0, 60.0))
+    views.append(sg.pinhole(48, 32, (1.0, -1.5, 2.0), sg.look_rotation(sg.yaw_pitch_forward(math.pi / 2.5, math.radians(40)))))
+    return views
+
+
+def test_merged_assets_are_downsampled_finest_level(quad_city):
+    """The LOD-1 asset over blocks (0,0)-(1,1) holds the 2x box downsample of
+    the four finest grids side by side (up to uint8 re-quantisation)."""
+    scene, ob, occs, zt = quad_city
+    a = scene.get(0, 1)
+    g, _ = a.decoded()
+    fine = {bid: scene.get(bid, 0).decoded()[0].astype(np.float64) for bid in (0, 1, 4, 5)}
+    def down(x):
+        r = x.shape[0] // 2
+        return x.reshape(r, 2, r, 2, r, 2, 8).mean(axis=(1, 3, 5))
+    ref = np.concatenate([np.concatenate([down(fine[0]), down(fine[1])], axis=2),
+                          np.concatenate([down(fine[4]), down(fine[5])], axis=2)], axis=1)
+    assert g.shape == ref.shape == (8, 16, 16, 8)
+    assert np.abs(g - ref).max() <= 0.51 * a.scale[0].max() + 1e-5
+
+
+def test_quadtree_selection_rule_and_partition(quad_city):
+    """Selected footprints are disjoint; without culling they tile the whole
+    scene; a chosen LOD-l entry (l > 0) has every child at distance >=
+    thresholds[l-1] and its parent has some child nearer (coarse to fine);
+    huge thresholds give every finest block, zero thresholds the roots."""
+    scene, ob, occs, zt = quad_city
+    B = scene.blocks
+
+    def dist(k):
+        e = B[k]
+        inside = [j for j, f in enumerate(B) if f.lod == 0 and f.aabb_min[0] >= e.aabb_min[0] and
+                  f.aabb_max[0] <= e.aabb_max[0] and f.aabb_min[1] >= e.aabb_min[1] and f.aabb_max[1] <= e.aabb_max[1]]
+        c = np.array([(e.aabb_min[0] + e.aabb_max[0]) / 2.0, (e.aabb_min[1] + e.aabb_max[1]) / 2.0,
+                      max(zt[j] for j in inside)], np.float64)
+        return float(np.linalg.norm(v.eye.astype(np.float64) - c))
+
+    def kids(k):
+        e = B[k]
+        return [j for j, f in enumerate(B) if f.lod == e.lod - 1 and f.aabb_min[0] >= e.aabb_min[0] and
+                f.aabb_max[0] <= e.aabb_max[0] and f.aabb_min[1] >= e.aabb_min[1] and f.aabb_max[1] <= e.aabb_max[1]]
+
+    thr = (1.8, 3.2)
+    mixed = 0
+    for v in quad_views():
+        sel = list(O.select(v, B, zt, thresholds=thr, cull=False, quadtree=True))
+        area = np.zeros((4, 4), np.int32)
+        for k in sel:
+            e = B[k]
+            area[int(e.aabb_min[1]):int(e.aabb_max[1]), int(e.aabb_min[0]):int(e.aabb_max[0])] += 1
+            if e.lod > 0:
+                assert all(dist(j) >= thr[e.lod - 1] for j in kids(k))
+            parent = [j for j, f in enumerate(B) if f.lod == e.lod + 1 and k in kids(j)]
+            for j in parent:
+                assert any(dist(i) < thr[e.lod] for i in kids(j))
+        assert (area == 1).all()
+        mixed += len({B[k].lod for k in sel}) > 1
+        assert [B[k].lod for k in O.select(v, B, zt, thresholds=(1e9, 1e9), cull=False, quadtree=True)] == [0] * 16
+        assert [B[k].lod for k in O.select(v, B, zt, thresholds=(0.0, 0.0), cull=False, quadtree=True)] == [2]
+    assert mixed >= 2
+
+
+def test_quadtree_order_is_per_ray_order_and_culling_exact(quad_city):
+    """On every pixel the per-view quadtree order equals the per-ray entry
+    order (so the block merge is the monolithic composite, Appendix A), and
+    culling removes only entries no ray reaches."""
+    scene, ob, occs, zt = quad_city
+    w = sg.xavier_mlp(3)
+    p = sg.cityb_params()
+    for v in quad_views():
+        sel = list(O.select(v, scene.blocks, zt, thresholds=(1.8, 3.2), cull=True, quadtree=True))
+        allb = list(O.select(v, scene.blocks, zt, thresholds=(1.8, 3.2), cull=False, quadtree=True))
+        a = O.render(ob, occs, v, sel, p, w)
+        assert a["order_ok"].all()
+        m = O.render(ob, occs, v, sel, p, w, composite=O.MONOLITHIC)
+        assert np.abs(a["rgb"] - m["rgb"]).max() < 1e-12 and np.abs(a["trans"] - m["trans"]).max() < 1e-12
+        if {scene.blocks[k].lod for k in sel} == {scene.blocks[k].lod for k in allb}:
+            b = O.render(ob, occs, v, allb, p, w)
+            assert np.array_equal(a["rgb"], b["rgb"])
