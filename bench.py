@@ -298,6 +298,40 @@ def extras(torch, sg, Renderer):
                      "workload": "8x8 blocks x 3 LODs uint8, 64 views {256^2, 800^2, 1280x720, 1920x1080}"}
     del r, out
     torch.cuda.empty_cache()
+    # the same 64 views over quadtree LODs: merged assets of 2x2 and 4x4 blocks
+    log("extras: building the quadtree-LOD city")
+    scene = sg.c3q_scene(lod_city=scene)
+    r = Renderer(0)
+    r.load_blocks(scene.blocks)
+    thr = sg.QUADTREE_THRESHOLDS
+    sets = [r.select(v, thresholds=thr, cull=True, quadtree=True) for v in views]
+    cnt = r.render(views, sets, p, mlp, counts=True)
+    n_eval = int(cnt["counts"][:, 0].sum().item())
+    del cnt
+    out = r.render(views, sets, p, mlp, want_aux=False)
+    timings = {}
+    for name, flags in (("batched_graph", F_GRAPH), ("per_block_launches", F_PER_BLOCK)):
+        log(f"extras: timing quadtree {name}")
+        r.render(views, sets, p, mlp, out=out, flags=flags)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(2):
+            r.render(views, sets, p, mlp, out=out, flags=flags)
+        torch.cuda.synchronize()
+        timings[name] = (time.perf_counter() - t) * 1e3 / 2
+    tb = timings["batched_graph"]
+    lods = [sum(1 for _, l in s if l == k) for s in sets for k in range(3)]
+    ex["quadtree"] = {"views": len(views), "pixels": n_pix, "evaluated_samples": n_eval,
+                      "entries_per_view": [min(len(s) for s in sets), max(len(s) for s in sets)],
+                      "entries_by_lod": [sum(lods[k::3]) for k in range(3)],
+                      "ms_batched": round(tb, 2), "ms_per_block": round(timings["per_block_launches"], 2),
+                      "speedup_vs_per_block": round(timings["per_block_launches"] / tb, 3),
+                      "Msamples_per_s": round(n_eval / (tb * 1e-3) / 1e6, 1),
+                      "fps_1080p_equivalent": round(n_pix / (tb * 1e-3) / 2073600, 2),
+                      "workload": "8x8 blocks, quadtree LODs (merged 2x2 and 4x4 assets) uint8, thresholds "
+                                  "2 and 4, the same 64 views"}
+    del r, out
+    torch.cuda.empty_cache()
     return ex
 
 

@@ -90,11 +90,15 @@ typedef struct cow_ctx cow_ctx;
 
 typedef struct cow_block_desc {
     int32_t block_id, lod;
-    float aabb_min[3], aabb_max[3]; /* unit extent on every axis */
-    int32_t grid_res, plane_res, occ_res; /* powers of two, occ_res divides both */
+    float aabb_min[3], aabb_max[3]; /* extent E_a = max - min on each axis: a whole power of two
+                                       (1 to 64); unit cubes for plain blocks, 2^l x 2^l x 1 for a
+                                       merged LOD-l asset */
+    int32_t grid_res, plane_res, occ_res; /* texels (cells) per unit length, powers of two,
+                                       occ_res divides both; a texture holds res * E_a texels
+                                       along axis a: G_a = grid_res E_a, P_a = plane_res E_a */
     int32_t dtype;                  /* COW_U8 or COW_F32 */
-    const void* grid;               /* device, [R][R][R][8] */
-    const void* plane[3];           /* device, xy, xz, yz: [Rp][Rp][8] */
+    const void* grid;               /* device, [G_z][G_y][G_x][8] */
+    const void* plane[3];           /* device, xy: [P_y][P_x][8], xz: [P_z][P_x][8], yz: [P_z][P_y][8] */
     float scale[4][8];              /* uint8 decode; ignored for COW_F32 */
     float offset[4][8];
 } cow_block_desc;
@@ -120,6 +124,8 @@ typedef struct cow_lod_policy {
     double thresholds[3];           /* LOD l where distance < thresholds[l]; beyond the last: dropped */
     int32_t n_thresholds;
     int32_t cull;                   /* nonzero: frustum culling */
+    int32_t quadtree;               /* nonzero: LOD l entries are merged assets over 2^l x 2^l blocks
+                                       (see cow_select_blocks) */
 } cow_lod_policy;
 
 typedef struct cow_render_params {
@@ -173,13 +179,23 @@ COW_API cow_status cow_query_workspace(cow_ctx* ctx, const cow_block_desc* block
 COW_API cow_status cow_load_blocks(cow_ctx* ctx, const cow_block_desc* blocks, int n, void* load_ws,
                            size_t load_bytes, hipStream_t stream);
 
-/* Copy one loaded block's occupancy [O][O][O] (z, y, x) to host memory. */
+/* Copy one loaded block's occupancy [Oz][Oy][Ox] (z, y, x; O per unit length
+ * times the extent on each axis) to host memory. */
 COW_API cow_status cow_get_occupancy(cow_ctx* ctx, int block_id, int lod, uint8_t* host_out, size_t n);
 
 /* Per-view selection (Appendix D, "Dynamic Loading", "Depth sorting"):
  * LOD by the distance from the eye to (centre_x, centre_y, z_top of the
  * finest level), frustum culling of [x0,x1]x[y0,y1]x[z_lo, z_top(LOD)],
  * front-to-back order by xy distance to the block centre (ties: lower id).
+ * With policy->quadtree (merged LOD assets, Sec. 4.5 "Baking": an entry of
+ * LOD l covers 2^l x 2^l blocks, aligned to its size): from the coarsest LOD
+ * down, an entry of LOD l > 0 is drawn when every visible LOD l-1 entry
+ * inside it is at distance >= thresholds[l-1] (vacuously when none is
+ * visible), else its visible children are examined; the distance uses the
+ * highest LOD-0 top inside the entry; thresholds[L] for the coarsest LOD L,
+ * when given, drops far coarsest entries; order: coarsest entries by xy
+ * distance, inside an entry its children by quadrant (the eye's, the two
+ * beside it, the opposite; ties: lower id).  n_thresholds must be >= L.
  * All decisions in fp64.  Writes up to cap refs; *n_out = count. */
 COW_API cow_status cow_select_blocks(cow_ctx* ctx, const cow_view* view, const cow_lod_policy* policy,
                              cow_block_ref* out, int cap, int* n_out);

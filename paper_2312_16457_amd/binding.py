@@ -51,7 +51,8 @@ class BlockSet(C.Structure):
 
 
 class LodPolicy(C.Structure):
-    _fields_ = [("thresholds", C.c_double * 3), ("n_thresholds", C.c_int32), ("cull", C.c_int32)]
+    _fields_ = [("thresholds", C.c_double * 3), ("n_thresholds", C.c_int32), ("cull", C.c_int32),
+                ("quadtree", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -124,6 +125,13 @@ def make_params(p, flags=0, counts=None, opacity=None, opacity_weight=None, bloc
     return s
 
 
+def _dims(d, res):
+    """(z, y, x) texel or cell counts of a block descriptor: res per unit
+    length times the extent on each axis."""
+    ext = [int(round(d.aabb_max[a] - d.aabb_min[a])) for a in range(3)]
+    return res * ext[2], res * ext[1], res * ext[0]
+
+
 def _stream():
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -187,6 +195,12 @@ class Renderer:
             for t in [g] + ps:
                 if t.dtype != want or not t.is_contiguous() or t.device != self.device:
                     raise ValueError("textures must be contiguous device tensors of the block's dtype")
+            gz, gy, gx = _dims(d, d.grid_res)
+            pz, py, px = _dims(d, d.plane_res)
+            sizes = [gz * gy * gx, py * px, pz * px, pz * py]
+            if [t.numel() for t in [g] + ps] != [8 * n for n in sizes]:
+                raise ValueError(f"block {d.block_id} lod {d.lod}: texture sizes do not match the "
+                                 f"resolutions times the block extents")
             d.grid = g.data_ptr()
             for i in range(3):
                 d.plane[i] = ps[i].data_ptr()
@@ -207,10 +221,10 @@ class Renderer:
 
     def occupancy(self, block_id, lod):
         k = self.blocks.index((block_id, lod))
-        O = self.descs[k].occ_res
-        out = np.zeros(O ** 3, np.uint8)
+        shape = _dims(self.descs[k], self.descs[k].occ_res)
+        out = np.zeros(int(np.prod(shape)), np.uint8)
         self._check(self.L.cow_get_occupancy(self.h, block_id, lod, out.ctypes.data, out.size))
-        return out.reshape(O, O, O)
+        return out.reshape(shape)
 
     def pack_bricks(self):
         n = C.c_size_t()
@@ -219,12 +233,13 @@ class Renderer:
         self._check(self.L.cow_pack_bricks(self.h, self.brick_ws.data_ptr(), n.value, _stream()))
         return n.value
 
-    def select(self, view, thresholds=(2.0, 4.0, 8.0), cull=True, cap=4096):
+    def select(self, view, thresholds=(2.0, 4.0, 8.0), cull=True, cap=4096, quadtree=False):
         pol = LodPolicy()
         for i, t in enumerate(thresholds):
             pol.thresholds[i] = float(t)
         pol.n_thresholds = len(thresholds)
         pol.cull = int(bool(cull))
+        pol.quadtree = int(bool(quadtree))
         out = (BlockRef * cap)()
         n = C.c_int()
         v = make_view(view)

@@ -218,22 +218,31 @@ struct BlockU {
     __amdgpu_buffer_rsrc_t brick;   // packed grid bricks (sparse)
     const uint8_t* occ;
     const int32_t* slot;
-    int R, Rp, O;
-    int lR, lRp, lO;                // log2 of the (power-of-two) resolutions
+    int R, Rp, O;                   // texels (cells) per unit length
+    int gd[3], pd[3], od[3];        // texels (cells) along x, y, z
+    int lgx, lgy, lpx, lpy, lox, loy;  // log2 of the row lengths used in indexing
     float lo[3], hi[3];
     float sc[4][kNch];              // uint8 decode scale per texture and channel
     float osum[kNch];               // sum of the four textures' decode offsets
 };
 
+__device__ inline uint32_t grid_texels(const BlockU& b) { return (uint32_t)b.gd[0] * b.gd[1] * b.gd[2]; }
+// planes xy, xz, yz: (u, v) = (x, y), (x, z), (y, z)
+__device__ inline uint32_t plane_texels(const BlockU& b, int p) {
+    return p == 0 ? (uint32_t)b.pd[0] * b.pd[1] : (p == 1 ? (uint32_t)b.pd[0] * b.pd[2] : (uint32_t)b.pd[1] * b.pd[2]);
+}
+
 template <int DT>
 __device__ inline void load_block(const DevBlock* B, BlockU& b) {
     b.R = ufl(B->R), b.Rp = ufl(B->Rp), b.O = ufl(B->O);
-    b.lR = 31 - __builtin_clz((unsigned)b.R), b.lRp = 31 - __builtin_clz((unsigned)b.Rp);
-    b.lO = 31 - __builtin_clz((unsigned)b.O);
+    for (int c = 0; c < 3; ++c) b.gd[c] = ufl(B->gd[c]), b.pd[c] = ufl(B->pd[c]), b.od[c] = ufl(B->od[c]);
+    b.lgx = 31 - __builtin_clz((unsigned)b.gd[0]), b.lgy = 31 - __builtin_clz((unsigned)b.gd[1]);
+    b.lpx = 31 - __builtin_clz((unsigned)b.pd[0]), b.lpy = 31 - __builtin_clz((unsigned)b.pd[1]);
+    b.lox = 31 - __builtin_clz((unsigned)b.od[0]), b.loy = 31 - __builtin_clz((unsigned)b.od[1]);
     for (int c = 0; c < 3; ++c) b.lo[c] = uff(B->lo[c]), b.hi[c] = uff(B->hi[c]);
     const uint32_t texel = DT == 0 ? 8u : 32u;
-    b.tex[0] = tex_rsrc(ufp(B->grid), (uint32_t)b.R * b.R * b.R * texel);
-    for (int p = 0; p < 3; ++p) b.tex[1 + p] = tex_rsrc(ufp(B->plane[p]), (uint32_t)b.Rp * b.Rp * texel);
+    b.tex[0] = tex_rsrc(ufp(B->grid), grid_texels(b) * texel);
+    for (int p = 0; p < 3; ++p) b.tex[1 + p] = tex_rsrc(ufp(B->plane[p]), plane_texels(b, p) * texel);
     b.occ = ufp(B->occ);
     b.slot = ufp(B->brick_slot);
     b.brick = tex_rsrc(ufp(B->bricks), (uint32_t)ufl((int)B->brick_bytes));
@@ -252,9 +261,9 @@ __device__ inline int occ_cell(const BlockU& b, const float q[3]) {
     for (int c = 0; c < 3; ++c) {
         int k = (int)floorf(q[c] * Of);
         k = k < 0 ? 0 : k;
-        cell[c] = k > b.O - 1 ? b.O - 1 : k;
+        cell[c] = k > b.od[c] - 1 ? b.od[c] - 1 : k;
     }
-    return (((cell[2] << b.lO) + cell[1]) << b.lO) + cell[0];
+    return (((cell[2] << b.loy) + cell[1]) << b.lox) + cell[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -271,14 +280,15 @@ struct Lin {
     float w0, w1;  // weights of texels p and p + 1
 };
 
-// Clamping u to [0, R - 1] first gives both edge cases directly: p = 0 with
-// f = 0 below, p = R - 2 with f = 1 above; inside, f = u - floor(u).
-__device__ inline Lin lin_pair(float q, int R) {
+// R texels per unit length, D texels along the axis.  Clamping u to
+// [0, D - 1] first gives both edge cases directly: p = 0 with f = 0 below,
+// p = D - 2 with f = 1 above; inside, f = u - floor(u).
+__device__ inline Lin lin_pair(float q, int R, int D) {
     const float u = q * (float)R - 0.5f;
-    const float uc = __builtin_amdgcn_fmed3f(u, 0.0f, (float)(R - 1));
+    const float uc = __builtin_amdgcn_fmed3f(u, 0.0f, (float)(D - 1));
     const int a = (int)uc;
     Lin t;
-    t.p = a < R - 2 ? a : R - 2;
+    t.p = a < D - 2 ? a : D - 2;
     const float f = uc - (float)t.p;
     t.w0 = 1.0f - f;
     t.w1 = f;
@@ -296,9 +306,9 @@ struct Taps {
 __device__ inline int pair_tex(int j) { return j < 4 ? 0 : 1 + (j - 4) / 2; }
 
 __device__ inline void sample_taps(const BlockU& b, const float q[3], Taps& T) {
-    const int R = b.R, Rp = b.Rp, lR = b.lR, lRp = b.lRp;
-    const Lin gx = lin_pair(q[0], R), gy = lin_pair(q[1], R), gz = lin_pair(q[2], R);
-    const Lin px = lin_pair(q[0], Rp), py = lin_pair(q[1], Rp), pz = lin_pair(q[2], Rp);
+    const int R = b.R, Rp = b.Rp;
+    const Lin gx = lin_pair(q[0], R, b.gd[0]), gy = lin_pair(q[1], R, b.gd[1]), gz = lin_pair(q[2], R, b.gd[2]);
+    const Lin px = lin_pair(q[0], Rp, b.pd[0]), py = lin_pair(q[1], Rp, b.pd[1]), pz = lin_pair(q[2], Rp, b.pd[2]);
     const float zw[2] = {gz.w0, gz.w1}, yw[2] = {gy.w0, gy.w1};
 #pragma unroll
     for (int dz = 0; dz < 2; ++dz)
@@ -306,17 +316,18 @@ __device__ inline void sample_taps(const BlockU& b, const float q[3], Taps& T) {
         for (int dy = 0; dy < 2; ++dy) {
             const int j = dz * 2 + dy;
             const float wzy = zw[dz] * yw[dy];
-            T.pidx[j] = ((((gz.p + dz) << lR) + gy.p + dy) << lR) + gx.p;
+            T.pidx[j] = ((((gz.p + dz) << b.lgy) + gy.p + dy) << b.lgx) + gx.p;
             T.w[2 * j] = wzy * gx.w0;
             T.w[2 * j + 1] = wzy * gx.w1;
         }
     // planes are indexed [v][u]: xy (u=x, v=y), xz (u=x, v=z), yz (u=y, v=z)
     const Lin U[3] = {px, px, py}, V[3] = {py, pz, pz};
+    const int lrow[3] = {b.lpx, b.lpx, b.lpy};  // row length of each plane: its u extent
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         const int j = 4 + 2 * p;
-        T.pidx[j] = (V[p].p << lRp) + U[p].p;
-        T.pidx[j + 1] = ((V[p].p + 1) << lRp) + U[p].p;
+        T.pidx[j] = (V[p].p << lrow[p]) + U[p].p;
+        T.pidx[j + 1] = ((V[p].p + 1) << lrow[p]) + U[p].p;
         T.w[2 * j + 0] = V[p].w0 * U[p].w0;
         T.w[2 * j + 1] = V[p].w0 * U[p].w1;
         T.w[2 * j + 2] = V[p].w1 * U[p].w0;
@@ -377,9 +388,9 @@ __device__ inline void raw_u8(const BlockU& b, const float q[3], int cell, float
         // of an axis holds grid index clamp(c s - 1 + j), so the pair at grid
         // index p sits at brick index p - (c s - 1) and the next one
         const int O = b.O, s = b.R / O, s2 = s + 2;
-        const int cx = cell % O, cy = (cell / O) % O, cz = cell / (O * O);
+        const int cx = cell & (b.od[0] - 1), cy = (cell >> b.lox) & (b.od[1] - 1), cz = cell >> (b.lox + b.loy);
         const int base = b.slot[cell] * (s2 * s2 * s2);
-        const Lin gx = lin_pair(q[0], b.R), gy = lin_pair(q[1], b.R), gz = lin_pair(q[2], b.R);
+        const Lin gx = lin_pair(q[0], b.R, b.gd[0]), gy = lin_pair(q[1], b.R, b.gd[1]), gz = lin_pair(q[2], b.R, b.gd[2]);
         const int xs = gx.p - (cx * s - 1), ys = gy.p - (cy * s - 1), zs = gz.p - (cz * s - 1);
 #pragma unroll
         for (int j = 0; j < 4; ++j)

@@ -66,8 +66,8 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
         }
         const int blk = wrap(cell[1], a.nby) * a.nbx + wrap(cell[0], a.nbx);
         const unsigned char* base = a.tex + (int64_t)blk * a.block_bytes;
-        const Lin gx = lin_pair(q[0], a.R), gy = lin_pair(q[1], a.R), gz = lin_pair(q[2], a.R);
-        const Lin ux = lin_pair(q[0], a.Rp), uy = lin_pair(q[1], a.Rp), uz = lin_pair(q[2], a.Rp);
+        const Lin gx = lin_pair(q[0], a.R, a.R), gy = lin_pair(q[1], a.R, a.R), gz = lin_pair(q[2], a.R, a.R);
+        const Lin ux = lin_pair(q[0], a.Rp, a.Rp), uy = lin_pair(q[1], a.Rp, a.Rp), uz = lin_pair(q[2], a.Rp, a.Rp);
         uint32_t x = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {

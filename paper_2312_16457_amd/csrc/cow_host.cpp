@@ -106,7 +106,28 @@ bool finite_view(const cow_view& v) {
            v.fx != 0.0f && v.fy != 0.0f;
 }
 
-size_t occ_cells(const cow_block_desc& d) { return (size_t)d.occ_res * d.occ_res * d.occ_res; }
+// extent of a block along axis a (a whole power of two, checked at load)
+int extent(const cow_block_desc& d, int a) { return (int)(d.aabb_max[a] - d.aabb_min[a]); }
+// texels (cells) along x, y, z: resolution per unit length times extent
+void dims(const cow_block_desc& d, int res, int out[3]) {
+    for (int a = 0; a < 3; ++a) out[a] = res * extent(d, a);
+}
+size_t grid_texels(const cow_block_desc& d) {
+    int g[3];
+    dims(d, d.grid_res, g);
+    return (size_t)g[0] * g[1] * g[2];
+}
+// planes xy, xz, yz: (u, v) = (x, y), (x, z), (y, z)
+size_t plane_texels(const cow_block_desc& d, int p) {
+    int q[3];
+    dims(d, d.plane_res, q);
+    return p == 0 ? (size_t)q[0] * q[1] : (p == 1 ? (size_t)q[0] * q[2] : (size_t)q[1] * q[2]);
+}
+size_t occ_cells(const cow_block_desc& d) {
+    int o[3];
+    dims(d, d.occ_res, o);
+    return (size_t)o[0] * o[1] * o[2];
+}
 
 cow_status validate_desc(cow_ctx* c, const cow_block_desc& d) {
     char buf[256];
@@ -120,18 +141,23 @@ cow_status validate_desc(cow_ctx* c, const cow_block_desc& d) {
         return fail(c, COW_E_INVALID, who + "occupancy resolution must divide grid and plane resolution");
     if (d.grid_res < 2 || d.plane_res < 2)
         return fail(c, COW_E_INVALID, who + "grid and plane resolution must be at least 2");
-    if (d.grid_res > 1024 || d.plane_res > 8192)
-        return fail(c, COW_E_INVALID, who + "resolution too large for 32-bit texel offsets");
-    const size_t tex = d.dtype == COW_U8 ? 8 : 32;
-    if ((size_t)d.grid_res * d.grid_res * d.grid_res * tex >= (1ull << 31) ||
-        (size_t)d.plane_res * d.plane_res * tex >= (1ull << 31))
-        return fail(c, COW_E_INVALID, who + "texture larger than 2 GiB");
     for (int a = 0; a < 3; ++a) {
         if (!std::isfinite(d.aabb_min[a]) || !std::isfinite(d.aabb_max[a]))
             return fail(c, COW_E_INVALID, who + "non-finite AABB");
-        if (d.aabb_max[a] - d.aabb_min[a] != 1.0f)
-            return fail(c, COW_E_INVALID, who + "blocks must be unit cubes");
+        const float e = d.aabb_max[a] - d.aabb_min[a];
+        if (!(e >= 1.0f && e <= 64.0f) || e != (float)(int)e || !is_pow2((int)e))
+            return fail(c, COW_E_INVALID, who + "block extents must be whole powers of two (1 to 64)");
     }
+    int g[3], q[3];
+    dims(d, d.grid_res, g);
+    dims(d, d.plane_res, q);
+    for (int a = 0; a < 3; ++a)
+        if (g[a] > 1024 || q[a] > 8192)
+            return fail(c, COW_E_INVALID, who + "resolution too large for 32-bit texel offsets");
+    const size_t tex = d.dtype == COW_U8 ? 8 : 32;
+    if (grid_texels(d) * tex >= (1ull << 31) || plane_texels(d, 0) * tex >= (1ull << 31) ||
+        plane_texels(d, 1) * tex >= (1ull << 31) || plane_texels(d, 2) * tex >= (1ull << 31))
+        return fail(c, COW_E_INVALID, who + "texture larger than 2 GiB");
     if (!d.grid || !d.plane[0] || !d.plane[1] || !d.plane[2])
         return fail(c, COW_E_INVALID, who + "null texture pointer");
     if (d.dtype == COW_U8)
@@ -199,6 +225,41 @@ double xy_dist(const cow_view& v, const cow_block_desc& d) {
     return std::sqrt(dx * dx + dy * dy);
 }
 
+// Front-to-back order of a set of ground squares of mixed power-of-two sizes
+// (merged LOD assets, each aligned to a multiple of its own size): recursive
+// quadrant subdivision of an aligned square that covers the set.  Inside a
+// square the quadrant on the eye's side of both centre lines goes first, the
+// two quadrants beside it next and the opposite one last: a straight ray
+// crosses each centre line at most once, so it can only meet the quadrants
+// in an order consistent with this (the xy-distance order of equal squares
+// does not extend to mixed sizes).
+struct QuadOrder {
+    const cow_ctx* c;
+    double ex, ey;
+    std::vector<int> in, out;
+    void visit(double x0, double y0, double S) {
+        std::vector<int> here;
+        for (int e : in) {
+            const cow_block_desc& d = c->entries[e].desc;
+            if (d.aabb_min[0] >= x0 && d.aabb_max[0] <= x0 + S && d.aabb_min[1] >= y0 && d.aabb_max[1] <= y0 + S)
+                here.push_back(e);
+        }
+        if (here.empty()) return;
+        for (int e : here) {
+            const cow_block_desc& d = c->entries[e].desc;
+            if (d.aabb_min[0] == x0 && d.aabb_min[1] == y0 && d.aabb_max[0] - d.aabb_min[0] == S) {
+                out.push_back(e);  // the square itself is an entry (a partition holds nothing else here)
+                return;
+            }
+        }
+        if (S <= 1.0) return;
+        const double h = 0.5 * S, cx = x0 + h, cy = y0 + h;
+        const int qx = ex >= cx, qy = ey >= cy;
+        const int seq[4][2] = {{qx, qy}, {1 - qx, qy}, {qx, 1 - qy}, {1 - qx, 1 - qy}};
+        for (auto& q : seq) visit(x0 + q[0] * h, y0 + q[1] * h, h);
+    }
+};
+
 cow_status build_tables(cow_ctx* c, const cow_view* views, int n_views, const cow_block_set* sets,
                         int tile_w, CallTables* T) {
     const int tile_h = 64 / tile_w;
@@ -235,11 +296,48 @@ cow_status build_tables(cow_ctx* c, const cow_view* views, int n_views, const co
             ids.push_back(s.refs[r].block_id);
             order.push_back({xy_dist(v, c->entries[e].desc), e});
         }
-        // front to back by xy distance, ties to the lower block id
-        std::stable_sort(order.begin(), order.end(), [&](const auto& a, const auto& b) {
-            if (a.first != b.first) return a.first < b.first;
-            return c->entries[a.second].desc.block_id < c->entries[b.second].desc.block_id;
-        });
+        // the set's footprints must not overlap (a sample belongs to one entry)
+        bool mixed = false;
+        for (size_t a = 0; a < order.size(); ++a) {
+            const cow_block_desc& da = c->entries[order[a].second].desc;
+            if (da.aabb_max[0] - da.aabb_min[0] != c->entries[order[0].second].desc.aabb_max[0] -
+                                                        c->entries[order[0].second].desc.aabb_min[0])
+                mixed = true;
+            for (size_t b = a + 1; b < order.size(); ++b) {
+                const cow_block_desc& db = c->entries[order[b].second].desc;
+                bool apart = false;
+                for (int k = 0; k < 3; ++k)
+                    apart = apart || da.aabb_max[k] <= db.aabb_min[k] || db.aabb_max[k] <= da.aabb_min[k];
+                if (!apart) return fail(c, COW_E_INVALID, std::string(who) + "two entries of a set overlap");
+            }
+        }
+        if (!mixed) {
+            // equal squares: front to back by xy distance (their columns are the
+            // Voronoi cells of their centres), ties to the lower block id
+            std::stable_sort(order.begin(), order.end(), [&](const auto& a, const auto& b) {
+                if (a.first != b.first) return a.first < b.first;
+                return c->entries[a.second].desc.block_id < c->entries[b.second].desc.block_id;
+            });
+        } else {
+            QuadOrder q{c, (double)v.eye[0], (double)v.eye[1], {}, {}};
+            double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY}, big = 1.0;
+            for (auto& o : order) {
+                const cow_block_desc& d = c->entries[o.second].desc;
+                q.in.push_back(o.second);
+                for (int k = 0; k < 2; ++k) lo[k] = std::min(lo[k], (double)d.aabb_min[k]), hi[k] = std::max(hi[k], (double)d.aabb_max[k]);
+                big = std::max(big, (double)(d.aabb_max[0] - d.aabb_min[0]));
+            }
+            // smallest aligned power-of-two square holding every footprint
+            double S = big, x0 = 0, y0 = 0;
+            for (;; S *= 2) {
+                x0 = std::floor(lo[0] / S) * S, y0 = std::floor(lo[1] / S) * S;
+                if (hi[0] <= x0 + S && hi[1] <= y0 + S) break;
+            }
+            q.visit(x0, y0, S);
+            if (q.out.size() != order.size())
+                return fail(c, COW_E_INVALID, std::string(who) + "entries of mixed sizes must be aligned to their own size");
+            for (size_t k = 0; k < order.size(); ++k) order[k].second = q.out[k];
+        }
         DevView& d = T->views[vi];
         memset(&d, 0, sizeof d);
         for (int i = 0; i < 3; ++i) d.eye[i] = v.eye[i];
@@ -283,8 +381,8 @@ size_t shadow_total(const cow_block_desc* d, int64_t n) {
     size_t t = 0;
     for (int64_t i = 0; i < n; ++i) {
         if (d[i].dtype != COW_F32) continue;
-        const int64_t R = d[i].grid_res, Rp = d[i].plane_res;
-        t += shadow_bytes(R * R * R) + 3 * shadow_bytes(Rp * Rp);
+        t += shadow_bytes((int64_t)grid_texels(d[i]));
+        for (int p = 0; p < 3; ++p) t += shadow_bytes((int64_t)plane_texels(d[i], p));
     }
     return t;
 }
@@ -495,6 +593,108 @@ bool box_outside_frustum(const cow_view& v, const double lo[3], const double hi[
     return false;
 }
 
+// Quadtree selection (Appendix D "Dynamic Loading" over the merged assets of
+// Sec. 4.5: an entry of LOD l covers 2^l x 2^l blocks).  From the coarsest
+// LOD down: an entry of LOD l > 0 is drawn when every visible LOD l-1 entry
+// inside it is at least thresholds[l-1] from the eye (vacuously when none is
+// visible), otherwise its visible children are examined.  Distance: eye to
+// (centre x, centre y, highest LOD-0 top inside the entry), fp64; culling of
+// [lo, (hi_x, hi_y, the entry's own top)].  Order: the coarsest entries by xy
+// distance (ties: lower id), inside an entry its children by quadrant (the
+// eye's quadrant, the two beside it, the opposite one; ties: lower id).
+struct QuadSelect {
+    cow_ctx* c;
+    const cow_view* v;
+    const cow_lod_policy* pol;
+    std::vector<std::vector<int>> kids;
+    std::vector<double> zfine;
+    std::vector<int> out;
+
+    static bool inside_xy(const cow_block_desc& a, const cow_block_desc& b) {
+        return a.aabb_min[0] >= b.aabb_min[0] && a.aabb_max[0] <= b.aabb_max[0] && a.aabb_min[1] >= b.aabb_min[1] &&
+               a.aabb_max[1] <= b.aabb_max[1];
+    }
+    double centre(int e, int k) const {
+        const cow_block_desc& d = c->entries[e].desc;
+        return 0.5 * ((double)d.aabb_min[k] + (double)d.aabb_max[k]);
+    }
+    double dist(int e) const {
+        const double dx = (double)v->eye[0] - centre(e, 0), dy = (double)v->eye[1] - centre(e, 1);
+        const double dz = (double)v->eye[2] - zfine[e];
+        return std::sqrt(dx * dx + dy * dy + dz * dz);
+    }
+    bool visible(int e) const {
+        if (!pol->cull) return true;
+        const cow_block_desc& d = c->entries[e].desc;
+        const double lo[3] = {d.aabb_min[0], d.aabb_min[1], d.aabb_min[2]};
+        const double hi[3] = {d.aabb_max[0], d.aabb_max[1], c->entries[e].ztop};
+        return !box_outside_frustum(*v, lo, hi);
+    }
+    void visit(int e) {
+        const int l = c->entries[e].desc.lod;
+        if (l == 0) {
+            out.push_back(e);
+            return;
+        }
+        std::vector<std::pair<int, int>> seen;  // (rank, entry)
+        bool far = true;
+        const bool ex = (double)v->eye[0] >= centre(e, 0), ey = (double)v->eye[1] >= centre(e, 1);
+        for (int f : kids[e]) {
+            if (!visible(f)) continue;
+            if (dist(f) < pol->thresholds[l - 1]) far = false;
+            const int rank = ((centre(f, 0) >= centre(e, 0)) != ex) + ((centre(f, 1) >= centre(e, 1)) != ey);
+            seen.push_back({rank, f});
+        }
+        if (far) {
+            out.push_back(e);
+            return;
+        }
+        std::stable_sort(seen.begin(), seen.end(), [&](const auto& a, const auto& b) {
+            if (a.first != b.first) return a.first < b.first;
+            return c->entries[a.second].desc.block_id < c->entries[b.second].desc.block_id;
+        });
+        for (auto& k : seen) visit(k.second);
+    }
+};
+
+cow_status select_quadtree(cow_ctx* c, const cow_view* v, const cow_lod_policy* pol, cow_block_ref* out, int cap,
+                           int* n_out) {
+    const int ne = (int)c->entries.size();
+    int L = 0;
+    for (auto& e : c->entries) L = std::max(L, e.desc.lod);
+    if (pol->n_thresholds < L) return fail(c, COW_E_INVALID, "quadtree selection needs a threshold per finer LOD");
+    QuadSelect q{c, v, pol, std::vector<std::vector<int>>(ne), std::vector<double>(ne, -INFINITY), {}};
+    for (int e = 0; e < ne; ++e) {
+        const cow_block_desc& d = c->entries[e].desc;
+        for (int f = 0; f < ne; ++f) {
+            const cow_block_desc& g = c->entries[f].desc;
+            if (!QuadSelect::inside_xy(g, d)) continue;
+            if (g.lod == 0) q.zfine[e] = std::max(q.zfine[e], c->entries[f].ztop);
+            if (d.lod > 0 && g.lod == d.lod - 1) q.kids[e].push_back(f);
+        }
+    }
+    std::vector<std::pair<double, int>> roots;
+    for (int e = 0; e < ne; ++e) {
+        if (c->entries[e].desc.lod != L || !q.visible(e)) continue;
+        if (pol->n_thresholds > L && q.dist(e) >= pol->thresholds[L]) continue;
+        const double dx = (double)v->eye[0] - q.centre(e, 0), dy = (double)v->eye[1] - q.centre(e, 1);
+        roots.push_back({std::sqrt(dx * dx + dy * dy), e});
+    }
+    std::stable_sort(roots.begin(), roots.end(), [&](const auto& a, const auto& b) {
+        if (a.first != b.first) return a.first < b.first;
+        return c->entries[a.second].desc.block_id < c->entries[b.second].desc.block_id;
+    });
+    for (auto& r : roots) q.visit(r.second);
+    const int n = (int)q.out.size();
+    for (int i = 0; i < n && i < cap; ++i) {
+        out[i].block_id = c->entries[q.out[i]].desc.block_id;
+        out[i].lod = c->entries[q.out[i]].desc.lod;
+    }
+    *n_out = std::min(n, cap);
+    if (n > cap) return fail(c, COW_E_INVALID, "output capacity too small");
+    return COW_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -572,8 +772,10 @@ cow_status cow_load_blocks(cow_ctx* c, const cow_block_desc* blocks, int n, void
         cow_status s = validate_desc(c, blocks[i]);
         if (s != COW_OK) return s;
     }
-    // unique (block, LOD); all LODs of a block share its AABB; distinct
-    // blocks have disjoint footprints (a ground partition, Sec. 4.1)
+    // unique (block, LOD); all LODs of a block share its AABB's lower corner;
+    // the entries of one LOD have disjoint boxes (a ground partition,
+    // Sec. 4.1); entries of different LODs may overlap (a merged LOD asset
+    // covers several finer blocks)
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j) {
             const auto &a = blocks[i], &b = blocks[j];
@@ -582,7 +784,7 @@ cow_status cow_load_blocks(cow_ctx* c, const cow_block_desc* blocks, int n, void
                 for (int k = 0; k < 3; ++k)
                     if (a.aabb_min[k] != b.aabb_min[k])
                         return fail(c, COW_E_INVALID, "LODs of one block must share its AABB");
-            } else {
+            } else if (a.lod == b.lod) {
                 bool overlap = true;
                 for (int k = 0; k < 3; ++k)
                     overlap = overlap && a.aabb_min[k] < b.aabb_max[k] && b.aabb_min[k] < a.aabb_max[k];
@@ -620,6 +822,9 @@ cow_status cow_load_blocks(cow_ctx* c, const cow_block_desc* blocks, int n, void
         d.R = blocks[i].grid_res;
         d.Rp = blocks[i].plane_res;
         d.O = blocks[i].occ_res;
+        dims(blocks[i], d.R, d.gd);
+        dims(blocks[i], d.Rp, d.pd);
+        dims(blocks[i], d.O, d.od);
         d.dtype = blocks[i].dtype;
         if (d.dtype != c->dtype) c->mixed_dtype = true;
         d.grid = blocks[i].grid;
@@ -638,7 +843,7 @@ cow_status cow_load_blocks(cow_ctx* c, const cow_block_desc* blocks, int n, void
     if (st != COW_OK) return st;
     memcpy(c->pinned, c->h_blocks.data(), tb);
     HIP_TRY(c, hipMemcpyAsync(c->d_blocks, c->pinned, tb, hipMemcpyHostToDevice, stream));
-    for (int i = 0; i < n; ++i) HIP_TRY(c, cow::launch_occupancy(c->d_blocks, i, blocks[i].occ_res, stream));
+    for (int i = 0; i < n; ++i) HIP_TRY(c, cow::launch_occupancy(c->d_blocks, i, (int)occ_cells(blocks[i]), stream));
     // z_top of each entry from its occupancy (top of the highest occupied cell)
     size_t tot = 0;
     for (int i = 0; i < n; ++i) tot += occ_cells(blocks[i]);
@@ -652,13 +857,15 @@ cow_status cow_load_blocks(cow_ctx* c, const cow_block_desc* blocks, int n, void
     HIP_TRY(c, hipStreamSynchronize(stream));
     off = 0;
     for (int i = 0; i < n; ++i) {
-        const int O = blocks[i].occ_res;
+        int o[3];
+        dims(blocks[i], blocks[i].occ_res, o);
+        const size_t layer = (size_t)o[0] * o[1];
         int top = -1;
-        for (int z = 0; z < O; ++z)
-            for (int k = 0; k < O * O; ++k)
-                if (occ[off + (size_t)z * O * O + k]) top = z;
+        for (int z = 0; z < o[2]; ++z)
+            for (size_t k = 0; k < layer; ++k)
+                if (occ[off + (size_t)z * layer + k]) top = z;
         const double ext = (double)blocks[i].aabb_max[2] - (double)blocks[i].aabb_min[2];
-        c->entries[i].ztop = (double)blocks[i].aabb_min[2] + (double)(top + 1) / O * ext;
+        c->entries[i].ztop = (double)blocks[i].aabb_min[2] + (double)(top + 1) / o[2] * ext;
         off += occ_cells(blocks[i]);
     }
     c->loaded = true;
@@ -685,6 +892,7 @@ cow_status cow_select_blocks(cow_ctx* c, const cow_view* v, const cow_lod_policy
     if (!c->loaded) return fail(c, COW_E_NOT_LOADED, "no blocks loaded");
     if (!finite_view(*v)) return fail(c, COW_E_INVALID, "non-finite or singular camera");
     if (pol->n_thresholds < 1 || pol->n_thresholds > 3) return fail(c, COW_E_INVALID, "1 to 3 thresholds");
+    if (pol->quadtree) return select_quadtree(c, v, pol, out, cap, n_out);
     struct Pick {
         double key;
         int id, entry;
@@ -786,7 +994,7 @@ cow_status cow_pack_bricks(cow_ctx* c, void* brick_ws, size_t brick_bytes, hipSt
                          hipMemcpyHostToDevice));
     for (size_t i = 0; i < c->entries.size(); ++i)
         if (c->entries[i].desc.dtype == COW_U8)
-            HIP_TRY(c, cow::launch_pack_bricks(c->d_blocks, (int)i, c->entries[i].desc.occ_res, 0, nullptr, stream));
+            HIP_TRY(c, cow::launch_pack_bricks(c->d_blocks, (int)i, (int)occ_cells(c->entries[i].desc), 0, nullptr, stream));
     c->bricks_packed = true;
     return COW_OK;
 }
@@ -890,9 +1098,8 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
         ptrs[e] = grad_grid[e];
         for (int k = 0; k < 3; ++k) ptrs[ne + 3 * e + k] = grad_plane[3 * e + k];
         if (descs[e].dtype != COW_F32) continue;
-        const int64_t R = descs[e].grid_res, Rp = descs[e].plane_res;
         for (int t = 0; t < 4; ++t) {
-            const int64_t n = t == 0 ? R * R * R : Rp * Rp;
+            const int64_t n = (int64_t)(t == 0 ? grid_texels(descs[e]) : plane_texels(descs[e], t - 1));
             float* g = t == 0 ? grad_grid[e] : grad_plane[3 * e + t - 1];
             float* sh = (float*)(w.shadow + sh_off);
             sh_off += shadow_bytes(n);

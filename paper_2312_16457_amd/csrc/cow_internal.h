@@ -17,7 +17,8 @@ constexpr int32_t kMaxStep = (1 << 23) - 2;
 
 struct DevBlock {
     float lo[3], hi[3];
-    int32_t R, Rp, O, dtype;
+    int32_t R, Rp, O, dtype;   // grid, plane, occupancy texels (cells) per unit length
+    int32_t gd[3], pd[3], od[3];  // texels (cells) along x, y, z: resolution x extent
     const void* grid;
     const void* plane[3];
     const uint8_t* occ;        // [O][O][O]
@@ -126,7 +127,7 @@ struct SparsityArgs {
 };
 
 // launchers
-hipError_t launch_occupancy(const DevBlock* blocks, int entry, int O, hipStream_t s);
+hipError_t launch_occupancy(const DevBlock* blocks, int entry, int n_cells, hipStream_t s);
 hipError_t launch_march(const MarchArgs& a, int waves_per_group, hipStream_t s);
 hipError_t launch_reset_counter(int32_t* counter, hipStream_t s);
 hipError_t launch_clear_aux(float* aux, int64_t n_pix, hipStream_t s);
@@ -136,7 +137,7 @@ hipError_t launch_march_bwd(const BwdArgs& a, int waves_per_group, hipStream_t s
 hipError_t launch_shadow_zero(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s);
 hipError_t launch_shadow_fold(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s);
 hipError_t launch_sparsity(const SparsityArgs& a, hipStream_t s);
-hipError_t launch_pack_bricks(const DevBlock* blocks, int entry, int O, int s_cells,
+hipError_t launch_pack_bricks(const DevBlock* blocks, int entry, int n_cells, int s_cells,
                               const int32_t* slot_host_unused, hipStream_t st);
 
 }  // namespace cow

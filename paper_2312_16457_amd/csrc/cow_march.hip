@@ -208,27 +208,30 @@ __device__ inline float texel0(const DevBlock* B, int tex, int idx) {
 __global__ void occupancy_kernel(const DevBlock* blocks, int entry) {
     const DevBlock* B = blocks + entry;
     const int O = B->O, R = B->R, Rp = B->Rp;
+    const int ox = B->od[0], oy = B->od[1], oz = B->od[2];
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= O * O * O) return;
-    const int c3[3] = {cell % O, (cell / O) % O, cell / (O * O)};
+    if (cell >= ox * oy * oz) return;
+    const int c3[3] = {cell % ox, (cell / ox) % oy, cell / (ox * oy)};
     const int s = R / O, sp = Rp / O;
     int glo[3], ghi[3], plo[3], phi[3];
     for (int a = 0; a < 3; ++a) {
         glo[a] = max(c3[a] * s - 1, 0);
-        ghi[a] = min((c3[a] + 1) * s, R - 1);
+        ghi[a] = min((c3[a] + 1) * s, B->gd[a] - 1);
         plo[a] = max(c3[a] * sp - 1, 0);
-        phi[a] = min((c3[a] + 1) * sp, Rp - 1);
+        phi[a] = min((c3[a] + 1) * sp, B->pd[a] - 1);
     }
+    const int gx = B->gd[0], gy = B->gd[1];
     float mg = -INFINITY;
     for (int z = glo[2]; z <= ghi[2]; ++z)
         for (int y = glo[1]; y <= ghi[1]; ++y)
-            for (int x = glo[0]; x <= ghi[0]; ++x) mg = fmaxf(mg, texel0(B, 0, (z * R + y) * R + x));
+            for (int x = glo[0]; x <= ghi[0]; ++x) mg = fmaxf(mg, texel0(B, 0, (z * gy + y) * gx + x));
     const int au[3] = {0, 0, 1}, av[3] = {1, 2, 2};
     float mp[3];
     for (int p = 0; p < 3; ++p) {
         float m = -INFINITY;
+        const int row = B->pd[au[p]];
         for (int v = plo[av[p]]; v <= phi[av[p]]; ++v)
-            for (int u = plo[au[p]]; u <= phi[au[p]]; ++u) m = fmaxf(m, texel0(B, 1 + p, v * Rp + u));
+            for (int u = plo[au[p]]; u <= phi[au[p]]; ++u) m = fmaxf(m, texel0(B, 1 + p, v * row + u));
         mp[p] = m;
     }
     const float thresh = -0x1.26bb1cp+2f;  // fp32 nearest to ln(0.01)
@@ -236,8 +239,8 @@ __global__ void occupancy_kernel(const DevBlock* blocks, int entry) {
     const_cast<uint8_t*>(B->occ)[cell] = bound > thresh ? 1 : 0;
 }
 
-hipError_t launch_occupancy(const DevBlock* blocks, int entry, int O, hipStream_t s) {
-    const int n = O * O * O;
+hipError_t launch_occupancy(const DevBlock* blocks, int entry, int n_cells, hipStream_t s) {
+    const int n = n_cells;
     hipLaunchKernelGGL(occupancy_kernel, dim3((n + 63) / 64), dim3(64), 0, s, blocks, entry);
     return hipGetLastError();
 }
@@ -248,23 +251,25 @@ hipError_t launch_occupancy(const DevBlock* blocks, int entry, int O, hipStream_
 __global__ void pack_bricks_kernel(const DevBlock* blocks, int entry) {
     const DevBlock* B = blocks + entry;
     const int O = B->O, R = B->R, s = R / O, s2 = s + 2;
+    const int ox = B->od[0], oy = B->od[1];
+    const int gx = B->gd[0], gy = B->gd[1], gz = B->gd[2];
     const int cell = blockIdx.x;
     const int slot = B->brick_slot[cell];
     if (slot < 0) return;
-    const int cx = cell % O, cy = (cell / O) % O, cz = cell / (O * O);
+    const int cx = cell % ox, cy = (cell / ox) % oy, cz = cell / (ox * oy);
     const uint2* G = reinterpret_cast<const uint2*>(B->grid);
     uint2* dst = reinterpret_cast<uint2*>(const_cast<uint8_t*>(B->bricks)) + (size_t)slot * (s2 * s2 * s2);
     for (int t = threadIdx.x; t < s2 * s2 * s2; t += blockDim.x) {
         const int bx = t % s2, by = (t / s2) % s2, bz = t / (s2 * s2);
-        const int x = min(max(cx * s - 1 + bx, 0), R - 1);
-        const int y = min(max(cy * s - 1 + by, 0), R - 1);
-        const int z = min(max(cz * s - 1 + bz, 0), R - 1);
-        dst[t] = G[(z * R + y) * R + x];
+        const int x = min(max(cx * s - 1 + bx, 0), gx - 1);
+        const int y = min(max(cy * s - 1 + by, 0), gy - 1);
+        const int z = min(max(cz * s - 1 + bz, 0), gz - 1);
+        dst[t] = G[((size_t)z * gy + y) * gx + x];
     }
 }
 
-hipError_t launch_pack_bricks(const DevBlock* blocks, int entry, int O, int, const int32_t*, hipStream_t st) {
-    hipLaunchKernelGGL(pack_bricks_kernel, dim3(O * O * O), dim3(256), 0, st, blocks, entry);
+hipError_t launch_pack_bricks(const DevBlock* blocks, int entry, int n_cells, int, const int32_t*, hipStream_t st) {
+    hipLaunchKernelGGL(pack_bricks_kernel, dim3(n_cells), dim3(256), 0, st, blocks, entry);
     return hipGetLastError();
 }
 

@@ -93,11 +93,11 @@ struct GridAcc {
     float v[4][16];  // pending gradient of the cell's four pairs
 };
 
-__device__ inline void flush_grid(ScatterLds& L, int lane, GridAcc& g, bool flush, int lR,
+__device__ inline void flush_grid(ScatterLds& L, int lane, GridAcc& g, bool flush, int lgx, int lgy,
                                   const __amdgpu_buffer_rsrc_t& gr, const __amdgpu_buffer_rsrc_t& gs) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int pidx = g.cell + ((((j >> 1) << lR) + (j & 1)) << lR);
+        const int pidx = g.cell + ((((j >> 1) << lgy) + (j & 1)) << lgx);
         scatter_pair(L, lane, g.v[j], flush ? pidx : -1, gr, gs);
     }
 }
@@ -158,10 +158,10 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
         float* gptr[4] = {ufp(ba.grad_grid[e]), ufp(ba.grad_plane[3 * e + 0]), ufp(ba.grad_plane[3 * e + 1]),
                           ufp(ba.grad_plane[3 * e + 2])};
         __amdgpu_buffer_rsrc_t gr[4], gs[4];
-        gr[0] = tex_rsrc(gptr[0], (uint32_t)b.R * b.R * b.R * 32u);
-        for (int t = 1; t < 4; ++t) gr[t] = tex_rsrc(gptr[t], (uint32_t)b.Rp * b.Rp * 32u);
-        gs[0] = tex_rsrc(ufp(ba.shadow[4 * e]), ((uint32_t)b.R * b.R * b.R + 1u) * 32u);
-        for (int t = 1; t < 4; ++t) gs[t] = tex_rsrc(ufp(ba.shadow[4 * e + t]), ((uint32_t)b.Rp * b.Rp + 1u) * 32u);
+        gr[0] = tex_rsrc(gptr[0], grid_texels(b) * 32u);
+        for (int t = 1; t < 4; ++t) gr[t] = tex_rsrc(gptr[t], plane_texels(b, t - 1) * 32u);
+        gs[0] = tex_rsrc(ufp(ba.shadow[4 * e]), (grid_texels(b) + 1u) * 32u);
+        for (int t = 1; t < 4; ++t) gs[t] = tex_rsrc(ufp(ba.shadow[4 * e + t]), (plane_texels(b, t - 1) + 1u) * 32u);
         const bool alive = hit && !(T_blk < a.t_min);
         const Span sp = block_span<MODE>(a, b, r, alive, w0, w1);
         if (!__any(sp.ka < sp.kb)) continue;
@@ -242,7 +242,7 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
                 const int cell_now = have ? T.pidx[0] : -1;
                 const bool flush = have && gacc.cell >= 0 && cell_now != gacc.cell;
                 if (__any(flush)) {
-                    flush_grid(lds, lane, gacc, flush, b.lR, gr[0], gs[0]);
+                    flush_grid(lds, lane, gacc, flush, b.lgx, b.lgy, gr[0], gs[0]);
                     if (flush) {
                         gacc.cell = -1;
 #pragma unroll
@@ -264,7 +264,7 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
             }
             scatter_planes(lds, lane, T, draw, gptr, gr, gs, have);
         }
-        if (want_grid && __any(gacc.cell >= 0)) flush_grid(lds, lane, gacc, gacc.cell >= 0, b.lR, gr[0], gs[0]);
+        if (want_grid && __any(gacc.cell >= 0)) flush_grid(lds, lane, gacc, gacc.cell >= 0, b.lgx, b.lgy, gr[0], gs[0]);
         T_blk *= Tk;
     }
 }

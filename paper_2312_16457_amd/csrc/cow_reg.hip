@@ -55,8 +55,8 @@ __global__ __launch_bounds__(256) void sparsity_kernel(SparsityArgs s) {
             float* gp[4] = {ufp(s.grad_grid[e]), ufp(s.grad_plane[3 * e]), ufp(s.grad_plane[3 * e + 1]),
                             ufp(s.grad_plane[3 * e + 2])};
             __amdgpu_buffer_rsrc_t gr[4];
-            gr[0] = tex_rsrc(gp[0], (uint32_t)b.R * b.R * b.R * 32u);
-            for (int t = 1; t < 4; ++t) gr[t] = tex_rsrc(gp[t], (uint32_t)b.Rp * b.Rp * 32u);
+            gr[0] = tex_rsrc(gp[0], grid_texels(b) * 32u);
+            for (int t = 1; t < 4; ++t) gr[t] = tex_rsrc(gp[t], plane_texels(b, t - 1) * 32u);
 #pragma unroll
             for (int k = 0; k < 20; ++k) {
                 const int tex = pair_tex(k >> 1);

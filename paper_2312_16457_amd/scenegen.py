@@ -428,8 +428,7 @@ def _box_down(a, f, ndim):
     sh = []
     for n in a.shape[:ndim]:
         sh += [n // f, f]
-    b = a.reshape(*sh, a.shape[-1]).astype(np.float64)
-    return b.mean(axis=tuple(range(1, 2 * ndim, 2))).astype(np.float32)
+    return a.reshape(*sh, a.shape[-1]).mean(axis=tuple(range(1, 2 * ndim, 2)), dtype=np.float32)
 
 
 def merged_lods(finest, nbx, nby, n_lods, dtype=U8):
@@ -441,52 +440,64 @@ def merged_lods(finest, nbx, nby, n_lods, dtype=U8):
     downsampled xz (yz) planes, laid side by side along x (y).  Resolutions
     are per unit length; block_id is that of the asset's lowest block.
     finest: the LOD-0 BlockLod of every block (block_id = by * nbx + bx)."""
+    from concurrent.futures import ThreadPoolExecutor
     by_id = {b.block_id: b for b in finest if b.lod == 0}
-    out = []
-    for l in range(1, n_lods):
+
+    def downs(bid):  # per level l >= 1: downsampled (grid, xy, xz, yz) of one block
+        g, ps = by_id[bid].decoded()
+        return [(_box_down(g, 1 << l, 3), [_box_down(p, 1 << l, 2) for p in ps]) for l in range(1, n_lods)]
+
+    workers = max(1, min(len(by_id), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(workers) as ex:
+        down = dict(zip(by_id, ex.map(downs, list(by_id))))
+
+    def asset(job):
+        l, gx, gy = job
         f = 1 << l
-        for gy in range(0, nby, f):
-            for gx in range(0, nbx, f):
-                ids = [[(gy + j) * nbx + (gx + i) for i in range(f) if gx + i < nbx] for j in range(f) if gy + j < nby]
-                if len(ids) != f or any(len(r) != f for r in ids):
-                    continue  # an incomplete group at the edge of the grid has no merged asset
-                b0 = by_id[ids[0][0]]
-                R, Rp, O = b0.grid_res // f, b0.plane_res // f, b0.occ_res // f
-                dec = {i: by_id[i].decoded() for row in ids for i in row}
-                grid = np.concatenate([np.concatenate([_box_down(dec[i][0], f, 3) for i in row], axis=2)
-                                       for row in ids], axis=1)
-                xy = np.concatenate([np.concatenate([_box_down(dec[i][1][0], f, 2) for i in row], axis=1)
-                                     for row in ids], axis=0)
-                xz = np.concatenate([np.mean([_box_down(dec[ids[j][i]][1][1], f, 2) for j in range(f)], axis=0)
-                                     for i in range(f)], axis=1).astype(np.float32)
-                yz = np.concatenate([np.mean([_box_down(dec[ids[j][i]][1][2], f, 2) for i in range(f)], axis=0)
-                                     for j in range(f)], axis=1).astype(np.float32)
-                planes = [xy, xz, yz]
-                if dtype == U8:
-                    qg, sg, og = quantize(grid)
-                    qp = [quantize(p) for p in planes]
-                    scale = np.stack([sg] + [x[1] for x in qp]).astype(np.float32)
-                    offset = np.stack([og] + [x[2] for x in qp]).astype(np.float32)
-                    g_store, p_store = qg, [x[0] for x in qp]
-                else:
-                    scale = np.ones((4, NCH), np.float32)
-                    offset = np.zeros((4, NCH), np.float32)
-                    g_store, p_store = grid, planes
-                lo = np.array([gx, gy, 0], np.float32)
-                hi = np.array([gx + f, gy + f, 1], np.float32)
-                out.append(BlockLod(ids[0][0], l, lo, hi, R, Rp, O, dtype, np.ascontiguousarray(g_store),
-                                    [np.ascontiguousarray(p) for p in p_store], scale, offset))
-                del dec
-    return out
+        ids = [[(gy + j) * nbx + (gx + i) for i in range(f)] for j in range(f)]
+        b0 = by_id[ids[0][0]]
+        R, Rp, O = b0.grid_res // f, b0.plane_res // f, b0.occ_res // f
+        d = {i: down[i][l - 1] for row in ids for i in row}
+        grid = np.concatenate([np.concatenate([d[i][0] for i in row], axis=2) for row in ids], axis=1)
+        xy = np.concatenate([np.concatenate([d[i][1][0] for i in row], axis=1) for row in ids], axis=0)
+        xz = np.concatenate([np.mean([d[ids[j][i]][1][1] for j in range(f)], axis=0, dtype=np.float32)
+                             for i in range(f)], axis=1)
+        yz = np.concatenate([np.mean([d[ids[j][i]][1][2] for i in range(f)], axis=0, dtype=np.float32)
+                             for j in range(f)], axis=1)
+        planes = [xy, xz, yz]
+        if dtype == U8:
+            qg, sg, og = quantize(grid)
+            qp = [quantize(p) for p in planes]
+            scale = np.stack([sg] + [x[1] for x in qp]).astype(np.float32)
+            offset = np.stack([og] + [x[2] for x in qp]).astype(np.float32)
+            g_store, p_store = qg, [x[0] for x in qp]
+        else:
+            scale = np.ones((4, NCH), np.float32)
+            offset = np.zeros((4, NCH), np.float32)
+            g_store, p_store = grid, planes
+        lo = np.array([gx, gy, 0], np.float32)
+        hi = np.array([gx + f, gy + f, 1], np.float32)
+        return BlockLod(ids[0][0], l, lo, hi, R, Rp, O, dtype, np.ascontiguousarray(g_store),
+                        [np.ascontiguousarray(p) for p in p_store], scale, offset)
+
+    # groups that fit the grid entirely (an incomplete group at the edge has no merged asset)
+    jobs = [(l, gx, gy) for l in range(1, n_lods) for gy in range(0, nby - (1 << l) + 1, 1 << l)
+            for gx in range(0, nbx - (1 << l) + 1, 1 << l)]
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(asset, jobs))
 
 
-def c3q_scene(seed=2):
+def c3q_scene(seed=2, lod_city=None):
     """The 8x8 city with quadtree LODs: the finest blocks of the LOD city
     (128^3 grid, 1024^2 planes, 16^3 occupancy per unit block) plus merged
     assets of 2x2 blocks (LOD 1: 64 texels per unit, 128 x 128 x 64 grid) and
-    4x4 blocks (LOD 2: 32 per unit, 128 x 128 x 32), uint8."""
-    fine = city_scene(8, seed, U8, (C3_LODS[0],))
-    return Scene(8, 8, fine.blocks + merged_lods(fine.blocks, 8, 8, 3))
+    4x4 blocks (LOD 2: 32 per unit, 128 x 128 x 32), uint8.  lod_city: an
+    already generated c3_scene(seed) whose finest level is reused."""
+    if lod_city is not None:
+        fine = [b for b in lod_city.blocks if b.lod == 0]
+    else:
+        fine = city_scene(8, seed, U8, (C3_LODS[0],)).blocks
+    return Scene(8, 8, fine + merged_lods(fine, 8, 8, 3))
 
 
 QUADTREE_THRESHOLDS = (2.0, 4.0)
