@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched measurements")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU leg, no extras)")
+    ap.add_argument("--leg", choices=["fwd", "bwd", "batched", "quadtree"], default="fwd",
+                    help="with --profile: the leg to run (one timed repetition of bwd / batched / quadtree)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a 1 GiB device copy, to scale HBM byte counters")
     return ap.parse_args()
@@ -66,6 +68,10 @@ def main():
     import __graft_entry__
     __graft_entry__._ensure_built()
     from paper_2312_16457_amd import Renderer, scenegen as sg
+    if args.profile and args.leg != "fwd":
+        fn = {"bwd": leg_backward, "batched": lambda *a, **k: leg_batched(*a, **k)[0], "quadtree": leg_quadtree}
+        print(json.dumps({"leg": args.leg, **fn[args.leg](torch, sg, Renderer, reps=1)}), flush=True)
+        return
 
     t0 = time.time()
     scene = sg.c2_scene()
@@ -220,13 +226,9 @@ def log(msg, t0=[time.time()]):
     print(f"[bench {time.time() - t0[0]:7.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
-def extras(torch, sg, Renderer):
-    """Backward throughput on the fp32 4x4 scene (8 views at 800x800) and the
-    batched-vs-per-block comparison on the 8x8x3-LOD scene (64 views)."""
-    from paper_2312_16457_amd import F_GRAPH, F_PER_BLOCK
-    ex = {}
-    # backward: 8 x 800^2 views
-    log("extras: generating the fp32 4x4 scene")
+def leg_backward(torch, sg, Renderer, reps=2):
+    """Backward throughput on the fp32 4x4 scene, 8 views at 800x800."""
+    log("backward: generating the fp32 4x4 scene")
     learn, _ = sg.c5_scenes()
     views = sg.c5_views()
     p = sg.cityb_params()
@@ -234,36 +236,55 @@ def extras(torch, sg, Renderer):
     r.load_blocks(learn.blocks)
     sets = [[(b.block_id, 0) for b in learn.blocks]] * len(views)
     mlp = torch.tensor(sg.xavier_mlp(4), device="cuda")
-    log("extras: forward of 8 x 800^2")
     out = r.render(views, sets, p, mlp, counts=True)
     n_eval = int(out["counts"][:, 0].sum().item())
     g = torch.randn_like(out["rgb"]) * 1e-3
-    log(f"extras: first backward ({n_eval} samples)")
+    log(f"backward: first call ({n_eval} samples)")
     gg = [torch.zeros_like(t[0]) for t in r.textures]
     gp = [[torch.zeros_like(x) for x in t[1]] for t in r.textures]
     gm = torch.zeros(499, device="cuda")
     r.render_backward(views, sets, p, mlp, out["aux"], g, None, gg, gp, gm)
     torch.cuda.synchronize()
-    log("extras: timing backward")
     r.set_timing(True)
     bt = []
-    for _ in range(2):
+    for _ in range(reps):
         r.render_backward(views, sets, p, mlp, out["aux"], g, None, gg, gp, gm)
         bt.append(r.last_timing()[1])
     r.set_timing(False)
     t = time.perf_counter()
-    for _ in range(2):
+    for _ in range(reps):
         r.render_backward(views, sets, p, mlp, out["aux"], g, None, gg, gp, gm)
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t) * 1e3 / 2
-    ex["bwd"] = {"Msamples_per_s": round(n_eval / (ms * 1e-3) / 1e6, 2), "ms": round(ms, 3),
-                 "march_bwd_ms": round(float(np.mean(bt)), 3), "evaluated_samples": n_eval,
-                 "workload": "4x4 fp32 blocks 128^3 + 3x1024^2, 8 views 800x800"}
+    ms = (time.perf_counter() - t) * 1e3 / reps
+    log(f"backward {ms:.1f} ms")
+    res = {"Msamples_per_s": round(n_eval / (ms * 1e-3) / 1e6, 2), "ms": round(ms, 3),
+           "march_bwd_ms": round(float(np.mean(bt)), 3), "evaluated_samples": n_eval,
+           "workload": "4x4 fp32 blocks 128^3 + 3x1024^2, 8 views 800x800"}
     del r, gg, gp, out, g
     torch.cuda.empty_cache()
-    # batched: 64 views of mixed resolution over the 8x8x3-LOD scene in one
-    # graph-replayed launch vs one launch per view per block
-    log(f"extras: backward {ms:.1f} ms; generating the 8x8x3-LOD scene")
+    return res
+
+
+def _time_launches(torch, r, views, sets, p, mlp, reps, tag):
+    from paper_2312_16457_amd import F_GRAPH, F_PER_BLOCK
+    out = r.render(views, sets, p, mlp, want_aux=False)
+    timings = {}
+    for name, flags in (("batched_graph", F_GRAPH), ("per_block_launches", F_PER_BLOCK)):
+        log(f"{tag}: timing {name}")
+        r.render(views, sets, p, mlp, out=out, flags=flags)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            r.render(views, sets, p, mlp, out=out, flags=flags)
+        torch.cuda.synchronize()
+        timings[name] = (time.perf_counter() - t) * 1e3 / reps
+    return timings
+
+
+def leg_batched(torch, sg, Renderer, reps=2):
+    """64 views of mixed resolution over the 8x8x3-LOD scene in one
+    graph-replayed launch vs one launch per view per block."""
+    log("batched: generating the 8x8x3-LOD scene")
     scene = sg.c3_scene()
     views = sg.c4_views()
     p = sg.cityb_params()
@@ -271,67 +292,62 @@ def extras(torch, sg, Renderer):
     r.load_blocks(scene.blocks)
     sets = [r.select(v, thresholds=(2.0, 4.0, 8.0), cull=True) for v in views]
     mlp = torch.tensor(sg.xavier_mlp(3), device="cuda")
-    log("extras: counting samples of the 64-view batch")
     cnt = r.render(views, sets, p, mlp, counts=True)
     n_eval = int(cnt["counts"][:, 0].sum().item())
     n_pix = cnt["rgb"].shape[0]
     del cnt
-    out = r.render(views, sets, p, mlp, want_aux=False)
-    timings = {}
-    for name, flags in (("batched_graph", F_GRAPH), ("per_block_launches", F_PER_BLOCK)):
-        log(f"extras: timing {name}")
-        r.render(views, sets, p, mlp, out=out, flags=flags)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(2):
-            r.render(views, sets, p, mlp, out=out, flags=flags)
-        torch.cuda.synchronize()
-        timings[name] = (time.perf_counter() - t) * 1e3 / 2
+    timings = _time_launches(torch, r, views, sets, p, mlp, reps, "batched")
     tb = timings["batched_graph"]
-    ex["batched"] = {"views": len(views), "pixels": n_pix, "evaluated_samples": n_eval,
-                     "blocks_per_view": [min(len(s) for s in sets), max(len(s) for s in sets)],
-                     "launches_per_block_mode": sum(max(len(s), 1) for s in sets) + 1,
-                     "ms_batched": round(tb, 2), "ms_per_block": round(timings["per_block_launches"], 2),
-                     "speedup_vs_per_block": round(timings["per_block_launches"] / tb, 3),
-                     "Msamples_per_s": round(n_eval / (tb * 1e-3) / 1e6, 1),
-                     "fps_1080p_equivalent": round(n_pix / (tb * 1e-3) / 2073600, 2),
-                     "workload": "8x8 blocks x 3 LODs uint8, 64 views {256^2, 800^2, 1280x720, 1920x1080}"}
-    del r, out
+    res = {"views": len(views), "pixels": n_pix, "evaluated_samples": n_eval,
+           "blocks_per_view": [min(len(s) for s in sets), max(len(s) for s in sets)],
+           "launches_per_block_mode": sum(max(len(s), 1) for s in sets) + 1,
+           "ms_batched": round(tb, 2), "ms_per_block": round(timings["per_block_launches"], 2),
+           "speedup_vs_per_block": round(timings["per_block_launches"] / tb, 3),
+           "Msamples_per_s": round(n_eval / (tb * 1e-3) / 1e6, 1),
+           "fps_1080p_equivalent": round(n_pix / (tb * 1e-3) / 2073600, 2),
+           "workload": "8x8 blocks x 3 LODs uint8, 64 views {256^2, 800^2, 1280x720, 1920x1080}"}
+    del r
     torch.cuda.empty_cache()
-    # the same 64 views over quadtree LODs: merged assets of 2x2 and 4x4 blocks
-    log("extras: building the quadtree-LOD city")
-    scene = sg.c3q_scene(lod_city=scene)
+    return res, scene
+
+
+def leg_quadtree(torch, sg, Renderer, lod_city=None, reps=2):
+    """The same 64 views over quadtree LODs: merged assets of 2x2 and 4x4 blocks."""
+    log("quadtree: building the quadtree-LOD city")
+    scene = sg.c3q_scene(lod_city=lod_city)
+    views = sg.c4_views()
+    p = sg.cityb_params()
     r = Renderer(0)
     r.load_blocks(scene.blocks)
     thr = sg.QUADTREE_THRESHOLDS
     sets = [r.select(v, thresholds=thr, cull=True, quadtree=True) for v in views]
+    mlp = torch.tensor(sg.xavier_mlp(3), device="cuda")
     cnt = r.render(views, sets, p, mlp, counts=True)
     n_eval = int(cnt["counts"][:, 0].sum().item())
+    n_pix = cnt["rgb"].shape[0]
     del cnt
-    out = r.render(views, sets, p, mlp, want_aux=False)
-    timings = {}
-    for name, flags in (("batched_graph", F_GRAPH), ("per_block_launches", F_PER_BLOCK)):
-        log(f"extras: timing quadtree {name}")
-        r.render(views, sets, p, mlp, out=out, flags=flags)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(2):
-            r.render(views, sets, p, mlp, out=out, flags=flags)
-        torch.cuda.synchronize()
-        timings[name] = (time.perf_counter() - t) * 1e3 / 2
+    timings = _time_launches(torch, r, views, sets, p, mlp, reps, "quadtree")
     tb = timings["batched_graph"]
-    lods = [sum(1 for _, l in s if l == k) for s in sets for k in range(3)]
-    ex["quadtree"] = {"views": len(views), "pixels": n_pix, "evaluated_samples": n_eval,
-                      "entries_per_view": [min(len(s) for s in sets), max(len(s) for s in sets)],
-                      "entries_by_lod": [sum(lods[k::3]) for k in range(3)],
-                      "ms_batched": round(tb, 2), "ms_per_block": round(timings["per_block_launches"], 2),
-                      "speedup_vs_per_block": round(timings["per_block_launches"] / tb, 3),
-                      "Msamples_per_s": round(n_eval / (tb * 1e-3) / 1e6, 1),
-                      "fps_1080p_equivalent": round(n_pix / (tb * 1e-3) / 2073600, 2),
-                      "workload": "8x8 blocks, quadtree LODs (merged 2x2 and 4x4 assets) uint8, thresholds "
-                                  "2 and 4, the same 64 views"}
-    del r, out
+    res = {"views": len(views), "pixels": n_pix, "evaluated_samples": n_eval,
+           "entries_per_view": [min(len(s) for s in sets), max(len(s) for s in sets)],
+           "entries_by_lod": [sum(1 for s in sets for _, l in s if l == k) for k in range(3)],
+           "ms_batched": round(tb, 2), "ms_per_block": round(timings["per_block_launches"], 2),
+           "speedup_vs_per_block": round(timings["per_block_launches"] / tb, 3),
+           "Msamples_per_s": round(n_eval / (tb * 1e-3) / 1e6, 1),
+           "fps_1080p_equivalent": round(n_pix / (tb * 1e-3) / 2073600, 2),
+           "workload": "8x8 blocks, quadtree LODs (merged 2x2 and 4x4 assets) uint8, thresholds "
+                       "2 and 4, the same 64 views"}
+    del r
     torch.cuda.empty_cache()
+    return res
+
+
+def extras(torch, sg, Renderer):
+    """Backward throughput, the batched-vs-per-block comparison on the
+    8x8x3-LOD scene and the same views over quadtree LODs."""
+    ex = {"bwd": leg_backward(torch, sg, Renderer)}
+    ex["batched"], lod_city = leg_batched(torch, sg, Renderer)
+    ex["quadtree"] = leg_quadtree(torch, sg, Renderer, lod_city=lod_city)
     return ex
 
 
