@@ -43,8 +43,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched measurements")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU leg, no extras)")
-    ap.add_argument("--leg", choices=["fwd", "bwd", "batched", "quadtree"], default="fwd",
-                    help="with --profile: the leg to run (one timed repetition of bwd / batched / quadtree)")
+    ap.add_argument("--leg", choices=["fwd", "bwd", "batched", "quadtree", "variants"], default="fwd",
+                    help="with --profile: the leg to run (one timed repetition of bwd / batched / quadtree / "
+                         "the forward's options)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a 1 GiB device copy, to scale HBM byte counters")
     return ap.parse_args()
@@ -69,7 +70,8 @@ def main():
     __graft_entry__._ensure_built()
     from paper_2312_16457_amd import Renderer, scenegen as sg
     if args.profile and args.leg != "fwd":
-        fn = {"bwd": leg_backward, "batched": lambda *a, **k: leg_batched(*a, **k)[0], "quadtree": leg_quadtree}
+        fn = {"bwd": leg_backward, "batched": lambda *a, **k: leg_batched(*a, **k)[0], "quadtree": leg_quadtree,
+              "variants": leg_variants}
         print(json.dumps({"leg": args.leg, **fn[args.leg](torch, sg, Renderer, reps=1)}), flush=True)
         return
 
@@ -149,6 +151,7 @@ def main():
         log("cpu baseline done")
     res["roofline"]["traffic"] = recorded_traffic()
     if not args.no_extras and not args.profile:
+        res["variants"] = forward_variants(torch, sg, r, view, sel, params, mlp, ms)
         del r, out
         torch.cuda.empty_cache()
         res["extras"] = extras(torch, sg, Renderer)
@@ -226,6 +229,52 @@ def log(msg, t0=[time.time()]):
     print(f"[bench {time.time() - t0[0]:7.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
+def _timed(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) * 1e3 / reps
+
+
+def forward_variants(torch, sg, r, view, sel, params, mlp, base_ms, reps=5):
+    """The bench frame with the render's options: early ray termination
+    (t_min = 1e-3, the oracle applies the same rule), one deferred MLP per
+    block before the merge (the across-block equation as written), and the
+    per-ray opacity-entropy output."""
+    from dataclasses import replace
+    res = {"base_ms": None if base_ms is None else round(base_ms, 3)}
+    p_t = replace(params, t_min=1e-3)
+    cnt = r.render([view], [sel], p_t, mlp, counts=True)
+    n_t = int(cnt["counts"][:, 0].sum().item())
+    out = r.render([view], [sel], p_t, mlp, want_aux=False)
+    ms = _timed(torch, lambda: r.render([view], [sel], p_t, mlp, out=out), reps)
+    res["early_termination_1e-3"] = {"ms": round(ms, 3), "evaluated_samples": n_t,
+                                     "Msamples_per_s": round(n_t / (ms * 1e-3) / 1e6, 1)}
+    bm = torch.tensor(np.stack([sg.xavier_mlp(100 + k) for k in range(len(r.blocks))]), device="cuda")
+    out = r.render([view], [sel], params, None, want_aux=False, block_mlp=bm)
+    ms = _timed(torch, lambda: r.render([view], [sel], params, None, out=out, block_mlp=bm), reps)
+    res["per_block_mlps"] = {"ms": round(ms, 3), "blocks": len(sel)}
+    out = r.render([view], [sel], params, mlp, want_aux=False, opacity=True)
+    ms = _timed(torch, lambda: r.render([view], [sel], params, mlp, out=out), reps)
+    res["with_opacity_entropy"] = {"ms": round(ms, 3)}
+    log("forward variants done")
+    return res
+
+
+def leg_variants(torch, sg, Renderer, reps=1):
+    """forward_variants on the bench frame, for the profiler."""
+    scene = sg.c2_scene()
+    view = sg.c2_view()
+    r = Renderer(0)
+    r.load_blocks(scene.blocks)
+    sel = r.select(view, thresholds=(1e30,), cull=True)
+    mlp = torch.tensor(sg.xavier_mlp(1), device="cuda")
+    return forward_variants(torch, sg, r, view, sel, sg.cityb_params(), mlp, None, reps=reps)
+
+
 def leg_backward(torch, sg, Renderer, reps=2):
     """Backward throughput on the fp32 4x4 scene, 8 views at 800x800."""
     log("backward: generating the fp32 4x4 scene")
@@ -260,6 +309,24 @@ def leg_backward(torch, sg, Renderer, reps=2):
     res = {"Msamples_per_s": round(n_eval / (ms * 1e-3) / 1e6, 2), "ms": round(ms, 3),
            "march_bwd_ms": round(float(np.mean(bt)), 3), "evaluated_samples": n_eval,
            "workload": "4x4 fp32 blocks 128^3 + 3x1024^2, 8 views 800x800"}
+    # the backward's options: the opacity-entropy gradient, per-block MLPs,
+    # and the sparsity regulariser at 2^14 points (forward and gradient)
+    w_op = torch.full((out["rgb"].shape[0],), 1e-3, device="cuda")
+    ms = _timed(torch, lambda: r.render_backward(views, sets, p, mlp, out["aux"], g, None, gg, gp, gm,
+                                                 opacity_weight=w_op), 1)
+    res["with_opacity_entropy_ms"] = round(ms, 3)
+    bm = torch.tensor(np.stack([sg.xavier_mlp(200 + k) for k in range(len(r.blocks))]), device="cuda")
+    gbm = torch.zeros_like(bm)
+    out_b = r.render(views, sets, p, None, block_mlp=bm)
+    ms = _timed(torch, lambda: r.render_backward(views, sets, p, None, out_b["aux"], g, None, gg, gp, None,
+                                                 block_mlp=bm, grad_block_mlp=gbm), 1)
+    res["per_block_mlps_ms"] = round(ms, 3)
+    del out_b
+    pts = torch.rand((1 << 14, 3), device="cuda") * torch.tensor([4.0, 4.0, 1.0], device="cuda")
+    refs = [(b.block_id, 0) for b in learn.blocks]
+    ms = _timed(torch, lambda: r.sparsity(refs, pts, 1.0 / 512, 1e-3, grad_grid=gg, grad_plane=gp), 5)
+    res["sparsity_2e14_points_ms"] = round(ms, 4)
+    log("backward variants done")
     del r, gg, gp, out, g
     torch.cuda.empty_cache()
     return res
