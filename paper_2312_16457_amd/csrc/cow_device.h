@@ -232,6 +232,8 @@ __device__ inline uint32_t plane_texels(const BlockU& b, int p) {
     return p == 0 ? (uint32_t)b.pd[0] * b.pd[1] : (p == 1 ? (uint32_t)b.pd[0] * b.pd[2] : (uint32_t)b.pd[1] * b.pd[2]);
 }
 
+constexpr float kLog2e = 1.44269504088896341f;
+
 template <int DT>
 __device__ inline void load_block(const DevBlock* B, BlockU& b) {
     b.R = ufl(B->R), b.Rp = ufl(B->Rp), b.O = ufl(B->O);
@@ -247,10 +249,15 @@ __device__ inline void load_block(const DevBlock* B, BlockU& b) {
     b.slot = ufp(B->brick_slot);
     b.brick = tex_rsrc(ufp(B->bricks), (uint32_t)ufl((int)B->brick_bytes));
     if (DT == 0) {
+        // raw_u8 returns log2(e) raw_0 and -log2(e) raw_c (c >= 1), the
+        // arguments of exp2 in the activations, so the factor rides in the
+        // decode scales and offsets (see act_u8); 2^24 undoes bytes_h2
         for (int t = 0; t < 4; ++t)
-            for (int c = 0; c < kNch; ++c) b.sc[t][c] = uff(B->scale[t][c]) * 16777216.0f;  // see bytes_h2
+            for (int c = 0; c < kNch; ++c)
+                b.sc[t][c] = uff(B->scale[t][c]) * (16777216.0f * (c == 0 ? kLog2e : -kLog2e));
         for (int c = 0; c < kNch; ++c)
-            b.osum[c] = uff(((B->offset[0][c] + B->offset[1][c]) + B->offset[2][c]) + B->offset[3][c]);
+            b.osum[c] = uff(((B->offset[0][c] + B->offset[1][c]) + B->offset[2][c]) + B->offset[3][c]) *
+                        (c == 0 ? kLog2e : -kLog2e);
     }
 }
 
@@ -259,7 +266,8 @@ __device__ inline int occ_cell(const BlockU& b, const float q[3]) {
     int cell[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        int k = (int)floorf(q[c] * Of);
+        // truncation equals the floor for q O >= 0, and both clamp to 0 below
+        int k = (int)(q[c] * Of);
         k = k < 0 ? 0 : k;
         cell[c] = k > b.od[c] - 1 ? b.od[c] - 1 : k;
     }
@@ -284,7 +292,7 @@ struct Lin {
 // [0, D - 1] first gives both edge cases directly: p = 0 with f = 0 below,
 // p = D - 2 with f = 1 above; inside, f = u - floor(u).
 __device__ inline Lin lin_pair(float q, int R, int D) {
-    const float u = q * (float)R - 0.5f;
+    const float u = fmaf(q, (float)R, -0.5f);  // q R is exact (R a power of two): one rounding
     const float uc = __builtin_amdgcn_fmed3f(u, 0.0f, (float)(D - 1));
     const int a = (int)uc;
     Lin t;
@@ -374,10 +382,12 @@ __device__ inline void fold_u8(const uint4 (&t)[N], const float* w, const float*
     for (int c = 0; c < kNch; ++c) raw[c] = fmaf(s[c], sc[c], raw[c]);
 }
 
-// Pre-activation features of a uint8 block at local coordinate q:
-// sum over the four textures of scale * interpolated q, plus the offsets.
-// Interpolating the bytes and decoding once equals decoding every texel
-// because the weights of each texture sum to one.
+// Pre-activation features of a uint8 block at local coordinate q, in the
+// exp2 domain of the activations: raw[0] = log2(e) x density logit, raw[c] =
+// -log2(e) x feature logit (c >= 1); each is the sum over the four textures
+// of scale * interpolated q, plus the offsets.  Interpolating the bytes and
+// decoding once equals decoding every texel because the weights of each
+// texture sum to one.
 template <bool SPARSE>
 __device__ inline void raw_u8(const BlockU& b, const float q[3], int cell, float raw[kNch]) {
     Taps T;
@@ -475,6 +485,13 @@ __device__ inline float raw0_f32(const BlockU& b, const Taps& T) {
 // activations and opacity
 // ---------------------------------------------------------------------------
 __device__ inline float sigmoidf_(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
+
+// density and activated features from raw_u8's exp2-domain values:
+// sigma = 2^(log2(e) raw_0), sigmoid(raw_c) = 1 / (1 + 2^(-log2(e) raw_c))
+__device__ inline float density_u8(const float rawx[kNch]) { return __builtin_amdgcn_exp2f(rawx[0]); }
+__device__ inline float feature_u8(const float rawx[kNch], int c) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(rawx[c]));
+}
 
 // alpha = 1 - exp(-x) for x = sigma delta >= 0 (Eq. "alpha accumulation"),
 // without the cancellation of forming 1 - exp(-x) when x is small: a
@@ -779,19 +796,24 @@ __device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ra
         const bool have = next_occupied<MODE>(b, r, sp, kb, sp.delta, k, q, cell, cur_cell, cur_occ, n_march);
         if (!__any(have)) break;
         if (have) {
-            float raw[8];
+            float raw[8], v[7], sigma;
             if (DT == 0) {
                 raw_u8<SPARSE>(b, q, cell, raw);
+                sigma = density_u8(raw);
+#pragma unroll
+                for (int c = 0; c < 7; ++c) v[c] = feature_u8(raw, 1 + c);
             } else {
                 Taps T;
                 sample_taps(b, q, T);
                 raw_f32(b, T, raw);
+                sigma = __expf(raw[0]);
+#pragma unroll
+                for (int c = 0; c < 7; ++c) v[c] = sigmoidf_(raw[1 + c]);
             }
-            const float sigma = __expf(raw[0]);
             const float alpha = alpha_of(sigma * sp.delta);
             const float w = Tk * alpha;
 #pragma unroll
-            for (int c = 0; c < 7; ++c) Ak[c] = fmaf(w, sigmoidf_(raw[1 + c]), Ak[c]);
+            for (int c = 0; c < 7; ++c) Ak[c] = fmaf(w, v[c], Ak[c]);
             Tk *= 1.0f - alpha;
             ++n_eval;
             ++k;

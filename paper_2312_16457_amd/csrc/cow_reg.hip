@@ -37,16 +37,15 @@ __global__ __launch_bounds__(256) void sparsity_kernel(SparsityArgs s) {
         const int cell = occ_cell(b, q);
         if (b.occ[cell] == 0) continue;  // the render's density is zero here
         Taps T;
-        float raw0;
+        float sigma;
         if (DT == 0) {
             float raw[kNch];
             raw_u8<false>(b, q, cell, raw);
-            raw0 = raw[0];
+            sigma = density_u8(raw);
         } else {
             sample_taps(b, q, T);
-            raw0 = raw0_f32(b, T);
+            sigma = __expf(raw0_f32(b, T));
         }
-        const float sigma = __expf(raw0);
         alpha = alpha_of(sigma * s.delta);
         if (DT == 1 && s.grad_grid) {
             // d(scale alpha)/draw_0 = scale delta sigma exp(-sigma delta),
