@@ -364,6 +364,17 @@ def leg_batched(torch, sg, Renderer, reps=2):
     n_pix = cnt["rgb"].shape[0]
     del cnt
     timings = _time_launches(torch, r, views, sets, p, mlp, reps, "batched")
+    # the 16 aerial 1080p views of the LOD city, one launch per frame
+    v16 = sg.c3_views()
+    s16 = [r.select(v, thresholds=(2.0, 4.0, 8.0), cull=True) for v in v16]
+    n16 = sum(int(r.render([v], [s], p, mlp, counts=True)["counts"][:, 0].sum().item()) for v, s in zip(v16, s16))
+    outs = [r.render([v], [s], p, mlp, want_aux=False) for v, s in zip(v16, s16)]
+
+    def frames():
+        for v, s, o in zip(v16, s16, outs):
+            r.render([v], [s], p, mlp, out=o)
+    ms16 = _timed(torch, frames, reps)
+    del outs
     tb = timings["batched_graph"]
     res = {"views": len(views), "pixels": n_pix, "evaluated_samples": n_eval,
            "blocks_per_view": [min(len(s) for s in sets), max(len(s) for s in sets)],
@@ -372,10 +383,32 @@ def leg_batched(torch, sg, Renderer, reps=2):
            "speedup_vs_per_block": round(timings["per_block_launches"] / tb, 3),
            "Msamples_per_s": round(n_eval / (tb * 1e-3) / 1e6, 1),
            "fps_1080p_equivalent": round(n_pix / (tb * 1e-3) / 2073600, 2),
-           "workload": "8x8 blocks x 3 LODs uint8, 64 views {256^2, 800^2, 1280x720, 1920x1080}"}
+           "workload": "8x8 blocks x 3 LODs uint8, 64 views {256^2, 800^2, 1280x720, 1920x1080}",
+           "aerial_16x1080p": {"ms_per_frame": round(ms16 / len(v16), 3), "fps": round(1e3 * len(v16) / ms16, 2),
+                               "evaluated_samples": n16, "Msamples_per_s": round(n16 / (ms16 * 1e-3) / 1e6, 1),
+                               "blocks_per_view": [min(len(x) for x in s16), max(len(x) for x in s16)]}}
     del r
     torch.cuda.empty_cache()
     return res, scene
+
+
+def leg_single_block(torch, sg, Renderer, reps=20):
+    """One fp32 block (32^3 grid, 128^2 planes), one 128x128 view, 128 chord
+    steps per ray."""
+    scene = sg.c1_scene()
+    view = sg.c1_view()
+    p = sg.c1_params()
+    r = Renderer(0)
+    r.load_blocks(scene.blocks)
+    sets = [[(0, 0)]]
+    mlp = torch.tensor(sg.xavier_mlp(0), device="cuda")
+    n_eval = int(r.render([view], sets, p, mlp, counts=True)["counts"][:, 0].sum().item())
+    out = r.render([view], sets, p, mlp, want_aux=False)
+    ms = _timed(torch, lambda: r.render([view], sets, p, mlp, out=out), reps)
+    res = {"ms": round(ms, 4), "evaluated_samples": n_eval, "Msamples_per_s": round(n_eval / (ms * 1e-3) / 1e6, 1),
+           "workload": "1 fp32 block 32^3 + 3x128^2, one 128x128 view, 128 chord steps"}
+    del r
+    return res
 
 
 def leg_quadtree(torch, sg, Renderer, lod_city=None, reps=2):
@@ -412,7 +445,7 @@ def leg_quadtree(torch, sg, Renderer, lod_city=None, reps=2):
 def extras(torch, sg, Renderer):
     """Backward throughput, the batched-vs-per-block comparison on the
     8x8x3-LOD scene and the same views over quadtree LODs."""
-    ex = {"bwd": leg_backward(torch, sg, Renderer)}
+    ex = {"single_block": leg_single_block(torch, sg, Renderer), "bwd": leg_backward(torch, sg, Renderer)}
     ex["batched"], lod_city = leg_batched(torch, sg, Renderer)
     ex["quadtree"] = leg_quadtree(torch, sg, Renderer, lod_city=lod_city)
     return ex
