@@ -247,7 +247,8 @@ struct QuadOrder {
         if (here.empty()) return;
         for (int e : here) {
             const cow_block_desc& d = c->entries[e].desc;
-            if (d.aabb_min[0] == x0 && d.aabb_min[1] == y0 && d.aabb_max[0] - d.aabb_min[0] == S) {
+            if (d.aabb_min[0] == x0 && d.aabb_min[1] == y0 && d.aabb_max[0] - d.aabb_min[0] == S &&
+                d.aabb_max[1] - d.aabb_min[1] == S) {
                 out.push_back(e);  // the square itself is an entry (a partition holds nothing else here)
                 return;
             }
@@ -300,9 +301,9 @@ cow_status build_tables(cow_ctx* c, const cow_view* views, int n_views, const co
         bool mixed = false;
         for (size_t a = 0; a < order.size(); ++a) {
             const cow_block_desc& da = c->entries[order[a].second].desc;
-            if (da.aabb_max[0] - da.aabb_min[0] != c->entries[order[0].second].desc.aabb_max[0] -
-                                                        c->entries[order[0].second].desc.aabb_min[0])
-                mixed = true;
+            const cow_block_desc& d0 = c->entries[order[0].second].desc;
+            for (int k = 0; k < 2; ++k)
+                if (da.aabb_max[k] - da.aabb_min[k] != d0.aabb_max[k] - d0.aabb_min[k]) mixed = true;
             for (size_t b = a + 1; b < order.size(); ++b) {
                 const cow_block_desc& db = c->entries[order[b].second].desc;
                 bool apart = false;
@@ -335,7 +336,8 @@ cow_status build_tables(cow_ctx* c, const cow_view* views, int n_views, const co
             }
             q.visit(x0, y0, S);
             if (q.out.size() != order.size())
-                return fail(c, COW_E_INVALID, std::string(who) + "entries of mixed sizes must be aligned to their own size");
+                return fail(c, COW_E_INVALID,
+                            std::string(who) + "entries of mixed sizes must be squares aligned to their own size");
             for (size_t k = 0; k < order.size(); ++k) order[k].second = q.out[k];
         }
         DevView& d = T->views[vi];
