@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched measurements")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU leg, no extras)")
-    ap.add_argument("--leg", choices=["fwd", "bwd", "batched", "quadtree", "variants"], default="fwd",
+    ap.add_argument("--leg", choices=["fwd", "bwd", "batched", "quadtree", "variants", "opaque"], default="fwd",
                     help="with --profile: the leg to run (one timed repetition of bwd / batched / quadtree / "
                          "the forward's options)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -71,7 +71,7 @@ def main():
     from paper_2312_16457_amd import Renderer, scenegen as sg
     if args.profile and args.leg != "fwd":
         fn = {"bwd": leg_backward, "batched": lambda *a, **k: leg_batched(*a, **k)[0], "quadtree": leg_quadtree,
-              "variants": leg_variants}
+              "variants": leg_variants, "opaque": leg_opaque}
         print(json.dumps({"leg": args.leg, **fn[args.leg](torch, sg, Renderer, reps=1)}), flush=True)
         return
 
@@ -264,6 +264,34 @@ def forward_variants(torch, sg, r, view, sel, params, mlp, base_ms, reps=5):
     return res
 
 
+def leg_opaque(torch, sg, Renderer, reps=3):
+    """The bench frame over the opaque variant of the city (the density
+    recipe without its shift of 5: peak density 50), with and without early
+    ray termination (t_min = 1e-3; the oracle applies the same rule)."""
+    from dataclasses import replace
+    log("opaque: generating the opaque 4x4 city")
+    scene = sg.make_scene(4, 4, ((128, 1024, 16),), sg.U8, blobs_per_block=200, blob_z=(0.0, 0.3), seed=1,
+                          shift=0.0)
+    view = sg.c2_view()
+    r = Renderer(0)
+    r.load_blocks(scene.blocks)
+    sel = r.select(view, thresholds=(1e30,), cull=True)
+    mlp = torch.tensor(sg.xavier_mlp(1), device="cuda")
+    res = {"workload": "4x4 uint8 blocks, opaque density (shift 0), one 1920x1080 view"}
+    for name, tmin in (("no_termination", 0.0), ("t_min_1e-3", 1e-3)):
+        p = replace(sg.cityb_params(), t_min=tmin)
+        cnt = r.render([view], [sel], p, mlp, counts=True)["counts"]
+        n_eval, n_march = int(cnt[:, 0].sum().item()), int(cnt[:, 1].sum().item())
+        out = r.render([view], [sel], p, mlp, want_aux=False)
+        ms = _timed(torch, lambda: r.render([view], [sel], p, mlp, out=out), reps)
+        res[name] = {"ms": round(ms, 3), "evaluated_samples": n_eval, "marched_samples": n_march,
+                     "fps": round(1e3 / ms, 1)}
+    res["speedup_from_termination"] = round(res["no_termination"]["ms"] / res["t_min_1e-3"]["ms"], 2)
+    del r
+    torch.cuda.empty_cache()
+    return res
+
+
 def leg_variants(torch, sg, Renderer, reps=1):
     """forward_variants on the bench frame, for the profiler."""
     scene = sg.c2_scene()
@@ -287,6 +315,7 @@ def leg_backward(torch, sg, Renderer, reps=2):
     mlp = torch.tensor(sg.xavier_mlp(4), device="cuda")
     out = r.render(views, sets, p, mlp, counts=True)
     n_eval = int(out["counts"][:, 0].sum().item())
+    fwd_ms = _timed(torch, lambda: r.render(views, sets, p, mlp, out=out), reps)
     g = torch.randn_like(out["rgb"]) * 1e-3
     log(f"backward: first call ({n_eval} samples)")
     gg = [torch.zeros_like(t[0]) for t in r.textures]
@@ -308,7 +337,9 @@ def leg_backward(torch, sg, Renderer, reps=2):
     log(f"backward {ms:.1f} ms")
     res = {"Msamples_per_s": round(n_eval / (ms * 1e-3) / 1e6, 2), "ms": round(ms, 3),
            "march_bwd_ms": round(float(np.mean(bt)), 3), "evaluated_samples": n_eval,
-           "workload": "4x4 fp32 blocks 128^3 + 3x1024^2, 8 views 800x800"}
+           "workload": "4x4 fp32 blocks 128^3 + 3x1024^2, 8 views 800x800",
+           "fwd_ms": round(fwd_ms, 3), "fwd_Msamples_per_s": round(n_eval / (fwd_ms * 1e-3) / 1e6, 1),
+           "fwd_gathered_GBps": round(640 * n_eval / (fwd_ms * 1e-3) / 1e9, 1)}
     # the backward's options: the opacity-entropy gradient, per-block MLPs,
     # and the sparsity regulariser at 2^14 points (forward and gradient)
     w_op = torch.full((out["rgb"].shape[0],), 1e-3, device="cuda")
@@ -328,6 +359,19 @@ def leg_backward(torch, sg, Renderer, reps=2):
     res["sparsity_2e14_points_ms"] = round(ms, 4)
     log("backward variants done")
     del r, gg, gp, out, g
+    torch.cuda.empty_cache()
+    # the fp32 forward's gather rate against the probe at the same footprint
+    from paper_2312_16457_amd import COW_F32
+    from paper_2312_16457_amd.binding import gather_probe
+    steps = max(1, int(round(n_eval / sum(v.n_pixels for v in views))))
+    nbytes = 16 * (128 ** 3 + 3 * 1024 * 1024) * 32
+    tex = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda")
+    gather_probe(views[0], tex, 4, 4, 128, 1024, COW_F32, steps, 1.0 / 512)
+    pms = min(gather_probe(views[0], tex, 4, 4, 128, 1024, COW_F32, steps, 1.0 / 512)[0] for _ in range(3))
+    probe = views[0].n_pixels * steps * 640 / (pms * 1e-3) / 1e9
+    res["fwd_gather_probe_GBps"] = round(probe, 1)
+    res["fwd_gather_frac"] = round(res["fwd_gathered_GBps"] / probe, 4)
+    del tex
     torch.cuda.empty_cache()
     return res
 
@@ -445,7 +489,8 @@ def leg_quadtree(torch, sg, Renderer, lod_city=None, reps=2):
 def extras(torch, sg, Renderer):
     """Backward throughput, the batched-vs-per-block comparison on the
     8x8x3-LOD scene and the same views over quadtree LODs."""
-    ex = {"single_block": leg_single_block(torch, sg, Renderer), "bwd": leg_backward(torch, sg, Renderer)}
+    ex = {"single_block": leg_single_block(torch, sg, Renderer), "opaque": leg_opaque(torch, sg, Renderer),
+          "bwd": leg_backward(torch, sg, Renderer)}
     ex["batched"], lod_city = leg_batched(torch, sg, Renderer)
     ex["quadtree"] = leg_quadtree(torch, sg, Renderer, lod_city=lod_city)
     return ex
