@@ -9,7 +9,6 @@
 // texture footprint; the march's own gather rate is quoted against it.
 #include <hip/hip_runtime.h>
 
-#include <string>
 
 #include "cow.h"
 #include "cow_device.h"
