@@ -151,3 +151,32 @@ def test_backward_c5_crop(torch_cuda):
     # untouched blocks receive nothing
     for k in set(range(len(learn.blocks))) - set(touched):
         assert gg[k].abs().max().item() == 0
+
+
+def test_backward_every_launch_configuration(torch_cuda):
+    """The adjoint under every launch configuration the autotuner may pick
+    (packet width, waves per workgroup, persistent or not), on a view whose
+    crop is ragged for every packet width, stays within the fp64 adjoint's
+    bar; configurations differ from each other only by the order of the fp32
+    atomic sums."""
+    torch = torch_cuda
+    from paper_2312_16457_amd import Renderer
+    scene = sg.make_scene(2, 2, ((16, 32, 4),), sg.F32, blobs_per_block=10, blob_z=(0, 0.4), seed=11, shift=2.0)
+    view = sg.pinhole(37, 23, (1.0, -1.0, 1.2), sg.look_rotation(np.array([1.0, 1.0, 0.2]) - [1.0, -1.0, 1.2]))
+    params = sg.cityb_params()
+    w = sg.random_mlp(9, 0.6)
+    r = Renderer(0).load_blocks(scene.blocks)
+    sets = [[(b.block_id, b.lod) for b in scene.blocks]]
+    mlp = torch.tensor(w, device="cuda")
+    g_rgb = np.random.default_rng(4).uniform(-1, 1, (view.n_pixels, 3))
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    grads, gm_ref = O.adjoint(ob, occs, view, list(range(ob.n)), params, w, O.pixels_of(view), g_rgb)
+    for persistent in (0, 1):
+        for tw, wv in ((8, 4), (4, 1), (16, 2), (32, 4)):
+            r.set_config(tw, wv, persistent)
+            out = r.render([view], sets, params, mlp)
+            gg, gp, gm = gpu_grads(torch, r, [view], sets, params, mlp, out["aux"],
+                                   torch.tensor(g_rgb, dtype=torch.float32, device="cuda"))
+            compare(gg, gp, gm, grads, gm_ref)
+    r.set_config(8, 4, 0)

@@ -136,3 +136,26 @@ def test_autotune_invariance(c3):
     assert torch.equal(base["rgb"], tuned["rgb"]) and torch.equal(base["aux"], tuned["aux"])
     r.set_config(8, 4, 0)
     print("autotuned config", cfg)
+
+
+def test_every_launch_configuration_bitwise(c3):
+    """Every configuration the autotuner may pick (packet width 4-32, 1-4
+    waves per workgroup, persistent or not) renders the same bits, forward
+    counts included, for a batch of views of mixed size and block counts."""
+    torch, scene, r, ob, occs, zt = c3
+    views = [v.with_crop(0, 0, min(v.W, 200), min(v.H, 120)) for v in sg.c4_views()[:5]]
+    sets = [r.select(v, thresholds=THR, cull=True) for v in views]
+    mlp = torch.tensor(sg.xavier_mlp(3), device="cuda")
+    p = sg.cityb_params()
+    r.set_config(8, 4, 0)
+    base = r.render(views, sets, p, mlp, counts=True)
+    torch.cuda.synchronize()
+    for persistent in (0, 1):
+        for tw in (4, 8, 16, 32):
+            for wv in (1, 2, 4):
+                r.set_config(tw, wv, persistent)
+                o = r.render(views, sets, p, mlp, counts=True)
+                torch.cuda.synchronize()
+                for key in ("rgb", "trans", "aux", "counts"):
+                    assert torch.equal(o[key], base[key]), (tw, wv, persistent, key)
+    r.set_config(8, 4, 0)
