@@ -672,6 +672,32 @@ __device__ inline int xcd_packet(int waves, int wave) {
     return lb * waves + wave;
 }
 
+// Persistent launches: one work counter per XCD.  XCD x owns the packets of
+// the same interleaved chunks xcd_packet gives it (chunk j of kXcdChunk
+// packets belongs to XCD j mod 8), takes them in order from its own counter,
+// and once they run out takes the other XCDs' packets through their
+// counters.  Every packet is taken exactly once; a wave gets -1 when all
+// eight counters are exhausted, so every wave reaches the exit.
+constexpr int kXcds = 8, kXcdChunk = 64;
+__device__ inline int64_t xcd_packet_of(int x, int i) {
+    return ((int64_t)(i / kXcdChunk) * kXcds + x) * kXcdChunk + (i % kXcdChunk);
+}
+// lane 0 of a wave calls this; workgroups are dispatched round-robin over the
+// XCDs, so blockIdx.x mod 8 is the workgroup's XCD
+__device__ inline int take_packet(int32_t* counters, int total) {
+    const int home = blockIdx.x & (kXcds - 1);
+    for (int s = 0; s < kXcds; ++s) {
+        const int x = (home + s) & (kXcds - 1);
+        const int i = atomicAdd(counters + x, 1);
+        // xcd_packet_of grows with i, so one index past the end exhausts x
+        if (i < total) {  // xcd_packet_of(x, i) >= i
+            const int64_t p = xcd_packet_of(x, i);
+            if (p < total) return (int)p;
+        }
+    }
+    return -1;
+}
+
 __device__ inline const DevView* find_view_by_tile(const DevView* views, int n_views, int packet) {
     int lo = 0, hi = n_views - 1;
     while (lo < hi) {

@@ -58,7 +58,7 @@ struct MarchArgs {
     float* opacity;            // [P] per-ray block-opacity entropy, or null
     const float* block_mlp;    // [entries][499] per-block deferred MLPs, or null (one MLP after the merge)
     float* rgb;                // [P][3], written by the march when block_mlp is set
-    int32_t* work_counter;     // persistent mode
+    int32_t* work_counter;     // persistent mode: one counter per XCD (8 ints)
     int32_t persistent;
     // per-block baseline: only this view and this one set position
     int32_t only_view, only_set_pos;

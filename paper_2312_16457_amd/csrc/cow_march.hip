@@ -98,9 +98,10 @@ __device__ inline void march_fwd_body(const MarchArgs& a) {
     int p = a.persistent ? 0 : ufl(xcd_packet(waves, wave));
     for (;;) {
         if (a.persistent) {
-            int q = 0;
-            if (lane == 0) q = atomicAdd(a.work_counter, 1);
+            int q = -1;
+            if (lane == 0) q = take_packet(a.work_counter, a.total_tiles);
             p = ufl(__shfl(q, 0));
+            if (p < 0) return;
         }
         if (p >= a.total_tiles) return;
         const DevView* V;
@@ -162,7 +163,7 @@ hipError_t launch_march(const MarchArgs& a, int waves, hipStream_t s) {
 }
 
 __global__ void reset_counter_kernel(int32_t* c) {
-    if (threadIdx.x == 0) c[0] = 0;
+    if (threadIdx.x < kXcds) c[threadIdx.x] = 0;  // one work counter per XCD
 }
 
 hipError_t launch_reset_counter(int32_t* counter, hipStream_t s) {

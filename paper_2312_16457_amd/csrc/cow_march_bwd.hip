@@ -281,9 +281,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
     int p = a.persistent ? 0 : ufl(xcd_packet(waves, wave));  // one call site, as in the forward
     for (;;) {
         if (a.persistent) {
-            int q = 0;
-            if (lane == 0) q = atomicAdd(a.work_counter, 1);
+            int q = -1;
+            if (lane == 0) q = take_packet(a.work_counter, a.total_tiles);
             p = ufl(__shfl(q, 0));
+            if (p < 0) return;
         }
         if (p >= a.total_tiles) return;
         const DevView* V = find_view_by_tile(a.views, a.n_views, p);
