@@ -68,6 +68,7 @@ def lib():
         vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
         L.orc_occupancy.argtypes = [C.POINTER(_Block), vp]
         L.orc_ztop.argtypes = [C.POINTER(_Block), vp]
+        L.orc_occupancy_level.argtypes = [C.POINTER(_Block), vp, C.c_int, vp]
         L.orc_ztop.restype = C.c_double
         L.orc_render.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), C.POINTER(_View),
                                  vp, C.c_int, C.POINTER(_Params), vp, vp, C.c_int, C.c_int,
@@ -180,6 +181,22 @@ def occupancy(ob, k):
     if r != 0:
         raise ValueError("bad resolutions")
     return out
+
+
+def occupancy_level(ob, k, occ, level):
+    """Level `level` of the max-pooled occupancy pyramid of entry k, shape
+    (max(Cz >> l, 1), max(Cy >> l, 1), max(Cx >> l, 1))."""
+    shape = tuple(max(n >> level, 1) for n in occ.shape)
+    out = np.zeros(shape, np.uint8)
+    r = lib().orc_occupancy_level(C.byref(ob.arr[k]), _ptr(np.ascontiguousarray(occ, np.uint8)), level, _ptr(out))
+    if r != 0:
+        raise ValueError("bad level")
+    return out
+
+
+def occupancy_levels(occ):
+    """Number of pyramid levels above the base: log2 of the largest axis."""
+    return int(max(occ.shape)).bit_length() - 1
 
 
 def ztop(ob, k, occ):

@@ -235,6 +235,29 @@ double orc_ztop(const orc_block* b, const unsigned char* occ) {
     return (double)b->lo[2] + (double)(top + 1) / (double)nz * ext;
 }
 
+/* Level `level` of the multi-level occupancy grid psi (Sec. 3, rendering
+ * stage, and Sec. 4.5 "Baking": the binary grid downsampled by max-pooling).
+ * Level 0 is the grid itself.  Cell x of level l stands for the base cells i
+ * with i_a >> l == x_a on every axis a, so the level has max(C_a >> l, 1)
+ * cells along axis a (C_a the base count), and the cell is occupied iff one of
+ * its base cells is. */
+int orc_occupancy_level(const orc_block* b, const unsigned char* occ, int level, unsigned char* out) {
+    if (level < 0 || level > 30) return -1;
+    int C[3], L[3];
+    for (int a = 0; a < 3; ++a) {
+        C[a] = dim(b, b->O, a);
+        L[a] = C[a] >> level;
+        if (L[a] < 1) L[a] = 1;
+    }
+    memset(out, 0, (size_t)L[0] * L[1] * L[2]);
+    for (int z = 0; z < C[2]; ++z)
+        for (int y = 0; y < C[1]; ++y)
+            for (int x = 0; x < C[0]; ++x)
+                if (occ[((size_t)z * C[1] + y) * C[0] + x])
+                    out[((size_t)(z >> level) * L[1] + (y >> level)) * L[0] + (x >> level)] = 1;
+    return 0;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Sample enumeration                                                      */
 /* ---------------------------------------------------------------------- */

@@ -66,6 +66,10 @@ enum {
 /* occupancy bits [O][O][O] (z,y,x) of one block by the conservative max-bound rule */
 int orc_occupancy(const orc_block* b, unsigned char* out);
 
+/* level `level` >= 0 of the max-pooled occupancy pyramid: [Lz][Ly][Lx] with
+ * L_a = max(C_a >> level, 1), C_a the base cell count along axis a */
+int orc_occupancy_level(const orc_block* b, const unsigned char* occ, int level, unsigned char* out);
+
 /* top of the highest occupied cell (world z) */
 double orc_ztop(const orc_block* b, const unsigned char* occ);
 

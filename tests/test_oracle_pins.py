@@ -956,3 +956,47 @@ def test_quadtree_order_is_per_ray_order_and_culling_exact(quad_city):
         if {scene.blocks[k].lod for k in sel} == {scene.blocks[k].lod for k in allb}:
             b = O.render(ob, occs, v, allb, p, w)
             assert np.array_equal(a["rgb"], b["rgb"])
+
+
+def np_pool(occ, level):
+    """Max-pool by numpy's reshape-and-reduce: 2^level cells per axis, or the
+    whole axis when it is shorter."""
+    s = [min(1 << level, n) for n in occ.shape]
+    z, y, x = occ.shape
+    return occ.reshape(z // s[0], s[0], y // s[1], s[1], x // s[2], s[2]).max(axis=(1, 3, 5))
+
+
+def test_occupancy_pyramid_against_numpy_pooling(quad_city):
+    """The multi-level occupancy grid (Sec. 3 rendering stage, Sec. 4.5 max-pool
+    downsampling) of cubic blocks and non-cubic merged assets: every level
+    equals numpy's reshape-max of the base grid, each level is the 2x pool of
+    the one below, the top level is one cell holding any(base), and a single
+    occupied base cell lands in exactly one coarse cell at (x, y, z) >> l."""
+    scene, ob, occs, zt = quad_city
+    rng = np.random.default_rng(12)
+    kinds = {}
+    for k, b in enumerate(scene.blocks):
+        kinds.setdefault(occs[k].shape, k)
+    assert len(kinds) >= 3  # 16^3, 32x32x16, 64x64x16 cells
+    for shape, k in kinds.items():
+        nl = O.occupancy_levels(occs[k])
+        assert 1 << nl == max(shape)
+        grids = [occs[k]] + [(rng.random(shape) < p).astype(np.uint8) for p in (0.002, 0.05, 0.5)]
+        for g in grids:
+            prev = g
+            for l in range(nl + 1):
+                lv = O.occupancy_level(ob, k, g, l)
+                assert np.array_equal(lv, np_pool(g, l)), (shape, l)
+                if l:
+                    assert np.array_equal(lv, np_pool(prev, 1)), (shape, l)
+                prev = lv
+            assert lv.shape == (1, 1, 1) and lv[0, 0, 0] == int(g.any())
+        for _ in range(12):
+            z, y, x = (int(rng.integers(n)) for n in shape)
+            g = np.zeros(shape, np.uint8)
+            g[z, y, x] = 1
+            for l in range(nl + 1):
+                lv = O.occupancy_level(ob, k, g, l)
+                assert lv.sum() == 1
+                cz, cy, cx = (min(i >> l, n - 1) for i, n in zip((z, y, x), lv.shape))
+                assert lv[cz, cy, cx] == 1
