@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched measurements")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU leg, no extras)")
-    ap.add_argument("--leg", choices=["fwd", "bwd", "batched", "quadtree", "variants", "opaque"], default="fwd",
+    ap.add_argument("--leg", choices=["fwd", "bwd", "batched", "quadtree", "variants", "opaque", "empty"],
+                    default="fwd",
                     help="with --profile: the leg to run (one timed repetition of bwd / batched / quadtree / "
                          "the forward's options)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -71,7 +72,7 @@ def main():
     from paper_2312_16457_amd import Renderer, scenegen as sg
     if args.profile and args.leg != "fwd":
         fn = {"bwd": leg_backward, "batched": lambda *a, **k: leg_batched(*a, **k)[0], "quadtree": leg_quadtree,
-              "variants": leg_variants, "opaque": leg_opaque}
+              "variants": leg_variants, "opaque": leg_opaque, "empty": leg_empty_space}
         print(json.dumps({"leg": args.leg, **fn[args.leg](torch, sg, Renderer, reps=1)}), flush=True)
         return
 
@@ -245,6 +246,7 @@ def forward_variants(torch, sg, r, view, sel, params, mlp, base_ms, reps=5):
     block before the merge (the across-block equation as written), and the
     per-ray opacity-entropy output."""
     from dataclasses import replace
+    from paper_2312_16457_amd import F_FLAT_OCC
     res = {"base_ms": None if base_ms is None else round(base_ms, 3)}
     p_t = replace(params, t_min=1e-3)
     cnt = r.render([view], [sel], p_t, mlp, counts=True)
@@ -260,7 +262,39 @@ def forward_variants(torch, sg, r, view, sel, params, mlp, base_ms, reps=5):
     out = r.render([view], [sel], params, mlp, want_aux=False, opacity=True)
     ms = _timed(torch, lambda: r.render([view], [sel], params, mlp, out=out), reps)
     res["with_opacity_entropy"] = {"ms": round(ms, 3)}
+    out = r.render([view], [sel], params, mlp, want_aux=False)
+    ms = _timed(torch, lambda: r.render([view], [sel], params, mlp, out=out, flags=F_FLAT_OCC), reps)
+    res["one_step_empty_space"] = {"ms": round(ms, 3)}
     log("forward variants done")
+    return res
+
+
+def leg_empty_space(torch, sg, Renderer, reps=3):
+    """Jumps over empty cells of the max-pooled occupancy pyramid against a
+    one-step march (COW_F_FLAT_OCC; same samples evaluated, same bits) on a
+    sparse city: the bench layout with 12 blobs per block spread over the whole
+    block height instead of 200 near the ground, one 1920x1080 view."""
+    from paper_2312_16457_amd import F_FLAT_OCC
+    log("empty space: generating the sparse 4x4 city")
+    scene = sg.make_scene(4, 4, ((128, 1024, 16),), sg.U8, blobs_per_block=12, blob_z=(0.0, 0.9),
+                          blob_s=(0.04, 0.1), seed=1)
+    view = sg.c2_view()
+    r = Renderer(0)
+    r.load_blocks(scene.blocks)
+    sel = r.select(view, thresholds=(1e30,), cull=True)
+    p = sg.cityb_params()
+    mlp = torch.tensor(sg.xavier_mlp(1), device="cuda")
+    cnt = r.render([view], [sel], p, mlp, counts=True)["counts"]
+    n_eval, n_march = int(cnt[:, 0].sum().item()), int(cnt[:, 1].sum().item())
+    res = {"workload": "4x4 uint8 blocks, 12 blobs per block over heights 0-0.9, one 1920x1080 view",
+           "evaluated_samples": n_eval, "marched_samples": n_march}
+    out = r.render([view], [sel], p, mlp, want_aux=False)
+    for name, flags in (("one_step", F_FLAT_OCC), ("pyramid_jumps", 0)):
+        ms = _timed(torch, lambda: r.render([view], [sel], p, mlp, out=out, flags=flags), reps)
+        res[name] = {"ms": round(ms, 3), "Msamples_per_s": round(n_eval / (ms * 1e-3) / 1e6, 1)}
+    res["speedup_from_jumps"] = round(res["one_step"]["ms"] / res["pyramid_jumps"]["ms"], 2)
+    del r
+    torch.cuda.empty_cache()
     return res
 
 
@@ -490,7 +524,7 @@ def extras(torch, sg, Renderer):
     """Backward throughput, the batched-vs-per-block comparison on the
     8x8x3-LOD scene and the same views over quadtree LODs."""
     ex = {"single_block": leg_single_block(torch, sg, Renderer), "opaque": leg_opaque(torch, sg, Renderer),
-          "bwd": leg_backward(torch, sg, Renderer)}
+          "empty_space": leg_empty_space(torch, sg, Renderer), "bwd": leg_backward(torch, sg, Renderer)}
     ex["batched"], lod_city = leg_batched(torch, sg, Renderer)
     ex["quadtree"] = leg_quadtree(torch, sg, Renderer, lod_city=lod_city)
     return ex

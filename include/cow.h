@@ -83,7 +83,9 @@ enum {
     COW_F_GRAPH = 1,       /* replay a cached hipGraph of the launch sequence */
     COW_F_PERSISTENT = 2,  /* persistent workgroups pulling ray packets from a counter */
     COW_F_PER_BLOCK = 4,   /* baseline: one launch per view per block, blended in order */
-    COW_F_SPARSE = 8       /* read uint8 grids from the packed brick atlas (cow_pack_bricks) */
+    COW_F_SPARSE = 8,      /* read uint8 grids from the packed brick atlas (cow_pack_bricks) */
+    COW_F_FLAT_OCC = 16    /* baseline: step through empty space one sample at a time instead of
+                              jumping over empty cells of the occupancy pyramid (same results) */
 };
 
 typedef struct cow_ctx cow_ctx;
@@ -182,6 +184,18 @@ COW_API cow_status cow_load_blocks(cow_ctx* ctx, const cow_block_desc* blocks, i
 /* Copy one loaded block's occupancy [Oz][Oy][Ox] (z, y, x; O per unit length
  * times the extent on each axis) to host memory. */
 COW_API cow_status cow_get_occupancy(cow_ctx* ctx, int block_id, int lod, uint8_t* host_out, size_t n);
+
+/* Multi-level occupancy (Sec. 3, the grids psi; Sec. 4.5 "Baking": the
+ * binary grid downsampled by max-pooling), built by cow_load_blocks.  Level 0
+ * is the grid of cow_get_occupancy; level l >= 1 holds L_a = max(O_a >> l, 1)
+ * cells along axis a, [Lz][Ly][Lx], and its cell x is occupied (1) iff a base
+ * cell i with i_a >> l == x_a on every axis is.  Levels run up to log2 of the
+ * longest axis, where one cell remains.  Grid-mode marches jump over every
+ * sample that lies in an empty cell of the coarsest empty level around it.
+ * Copies level `level` to host memory (n >= its cell count); COW_E_INVALID
+ * for a level outside that range. */
+COW_API cow_status cow_get_occupancy_level(cow_ctx* ctx, int block_id, int lod, int level, uint8_t* host_out,
+                                           size_t n);
 
 /* Per-view selection (Appendix D, "Dynamic Loading", "Depth sorting"):
  * LOD by the distance from the eye to (centre_x, centre_y, z_top of the

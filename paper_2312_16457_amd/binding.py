@@ -14,10 +14,10 @@ LIB_PATH = os.path.join(HERE, "libcow.so")
 COW_OK, COW_E_INVALID, COW_E_NOT_LOADED, COW_E_WORKSPACE, COW_E_UNSUPPORTED, COW_E_HIP, COW_E_INTERNAL = range(7)
 COW_U8, COW_F32 = 0, 1
 MODE_CHORD, MODE_GRID = 0, 1
-F_NONE, F_GRAPH, F_PERSISTENT, F_PER_BLOCK, F_SPARSE = 0, 1, 2, 4, 8
+F_NONE, F_GRAPH, F_PERSISTENT, F_PER_BLOCK, F_SPARSE, F_FLAT_OCC = 0, 1, 2, 4, 8, 16
 
 EXPORTS = ["cow_create", "cow_destroy", "cow_last_error", "cow_query_workspace", "cow_load_blocks",
-           "cow_get_occupancy", "cow_select_blocks", "cow_query_bricks", "cow_pack_bricks", "cow_render",
+           "cow_get_occupancy", "cow_get_occupancy_level", "cow_select_blocks", "cow_query_bricks", "cow_pack_bricks", "cow_render",
            "cow_render_backward", "cow_sparsity", "cow_autotune", "cow_get_config", "cow_set_config",
            "cow_set_timing", "cow_last_timing", "cow_gather_probe"]
 
@@ -80,6 +80,7 @@ def lib():
                                           P(C.c_size_t), P(C.c_size_t)]
         L.cow_load_blocks.argtypes = [vp, P(BlockDesc), C.c_int, vp, C.c_size_t, vp]
         L.cow_get_occupancy.argtypes = [vp, C.c_int, C.c_int, vp, C.c_size_t]
+        L.cow_get_occupancy_level.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, C.c_size_t]
         L.cow_select_blocks.argtypes = [vp, P(View), P(LodPolicy), P(BlockRef), C.c_int, P(C.c_int)]
         L.cow_query_bricks.argtypes = [vp, P(C.c_size_t)]
         L.cow_pack_bricks.argtypes = [vp, vp, C.c_size_t, vp]
@@ -226,6 +227,15 @@ class Renderer:
         self._check(self.L.cow_get_occupancy(self.h, block_id, lod, out.ctypes.data, out.size))
         return out.reshape(shape)
 
+    def occupancy_level(self, block_id, lod, level):
+        """Level `level` of the max-pooled occupancy pyramid, shape
+        (max(Oz >> l, 1), max(Oy >> l, 1), max(Ox >> l, 1))."""
+        k = self.blocks.index((block_id, lod))
+        shape = tuple(max(n >> max(level, 0), 1) for n in _dims(self.descs[k], self.descs[k].occ_res))
+        out = np.zeros(int(np.prod(shape)), np.uint8)
+        self._check(self.L.cow_get_occupancy_level(self.h, block_id, lod, level, out.ctypes.data, out.size))
+        return out.reshape(shape)
+
     def pack_bricks(self):
         n = C.c_size_t()
         self._check(self.L.cow_query_bricks(self.h, C.byref(n)))
@@ -319,7 +329,8 @@ class Renderer:
         return gg, gp
 
     def render_backward(self, views, sets, params, mlp, aux, grad_rgb, grad_trans=None, grad_grid=None,
-                        grad_plane=None, grad_mlp=None, opacity_weight=None, block_mlp=None, grad_block_mlp=None):
+                        grad_plane=None, grad_mlp=None, opacity_weight=None, block_mlp=None, grad_block_mlp=None,
+                        flags=0):
         """grad_grid[e] / grad_plane[e][k]: torch fp32 tensors (or None) per
         loaded entry e, accumulated in place; grad_mlp likewise.
         opacity_weight: per-pixel dL/d(opacity regulariser) or None."""
@@ -332,7 +343,7 @@ class Renderer:
         bm = self._check_block_mlp(block_mlp)
         if grad_block_mlp is not None and grad_block_mlp.numel() != 499 * len(self.blocks):
             raise ValueError("grad_block_mlp must be [loaded entries][499]")
-        p = make_params(params, opacity_weight=ow, block_mlp=bm, grad_block_mlp=grad_block_mlp)
+        p = make_params(params, flags=flags, opacity_weight=ow, block_mlp=bm, grad_block_mlp=grad_block_mlp)
         self._check(self.L.cow_render_backward(
             self.h, vs, len(views), cs, C.byref(p), None if mlp is None else mlp.data_ptr(), aux.data_ptr(),
             grad_rgb.contiguous().data_ptr(),

@@ -215,15 +215,16 @@ __device__ inline bool slab_exact(const float o[3], const float d[3], const floa
 // ---------------------------------------------------------------------------
 struct BlockU {
     __amdgpu_buffer_rsrc_t tex[4];  // grid, xy, xz, yz
+    uint64_t tp[4];                 // the same textures' addresses (uint8 path, global loads)
     __amdgpu_buffer_rsrc_t brick;   // packed grid bricks (sparse)
     const uint8_t* occ;
+    const uint8_t* skip;            // per base cell: 0 occupied, else 1 + coarsest empty level
     const int32_t* slot;
     int R, Rp, O;                   // texels (cells) per unit length
     int gd[3], pd[3], od[3];        // texels (cells) along x, y, z
     int lgx, lgy, lpx, lpy, lox, loy;  // log2 of the row lengths used in indexing
     float lo[3], hi[3];
-    float sc[4][kNch];              // uint8 decode scale per texture and channel
-    float osum[kNch];               // sum of the four textures' decode offsets
+    const float* dec;               // uint8 decode: DevBlock::dsc, then dosum (40 floats)
 };
 
 __device__ inline uint32_t grid_texels(const BlockU& b) { return (uint32_t)b.gd[0] * b.gd[1] * b.gd[2]; }
@@ -245,25 +246,20 @@ __device__ inline void load_block(const DevBlock* B, BlockU& b) {
     const uint32_t texel = DT == 0 ? 8u : 32u;
     b.tex[0] = tex_rsrc(ufp(B->grid), grid_texels(b) * texel);
     for (int p = 0; p < 3; ++p) b.tex[1 + p] = tex_rsrc(ufp(B->plane[p]), plane_texels(b, p) * texel);
+    b.tp[0] = reinterpret_cast<uint64_t>(ufp(B->grid));
+    for (int p = 0; p < 3; ++p) b.tp[1 + p] = reinterpret_cast<uint64_t>(ufp(B->plane[p]));
     b.occ = ufp(B->occ);
+    b.skip = ufp(B->skip);
     b.slot = ufp(B->brick_slot);
     b.brick = tex_rsrc(ufp(B->bricks), (uint32_t)ufl((int)B->brick_bytes));
-    if (DT == 0) {
-        // raw_u8 returns log2(e) raw_0 and -log2(e) raw_c (c >= 1), the
-        // arguments of exp2 in the activations, so the factor rides in the
-        // decode scales and offsets (see act_u8); 2^24 undoes bytes_h2
-        for (int t = 0; t < 4; ++t)
-            for (int c = 0; c < kNch; ++c)
-                b.sc[t][c] = uff(B->scale[t][c]) * (16777216.0f * (c == 0 ? kLog2e : -kLog2e));
-        for (int c = 0; c < kNch; ++c)
-            b.osum[c] = uff(((B->offset[0][c] + B->offset[1][c]) + B->offset[2][c]) + B->offset[3][c]) *
-                        (c == 0 ? kLog2e : -kLog2e);
-    }
+    // raw_u8 returns log2(e) raw_0 and -log2(e) raw_c (c >= 1), the arguments
+    // of exp2 in the activations, so the factor rides in the decode scales and
+    // offsets formed at load (DevBlock::dsc, dosum); 2^24 undoes bytes_h2
+    b.dec = ufp(&B->dsc[0][0]);
 }
 
-__device__ inline int occ_cell(const BlockU& b, const float q[3]) {
+__device__ inline int occ_cell(const BlockU& b, const float q[3], int cell[3]) {
     const float Of = (float)b.O;
-    int cell[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         // truncation equals the floor for q O >= 0, and both clamp to 0 below
@@ -272,6 +268,11 @@ __device__ inline int occ_cell(const BlockU& b, const float q[3]) {
         cell[c] = k > b.od[c] - 1 ? b.od[c] - 1 : k;
     }
     return (((cell[2] << b.loy) + cell[1]) << b.lox) + cell[0];
+}
+
+__device__ inline int occ_cell(const BlockU& b, const float q[3]) {
+    int cell[3];
+    return occ_cell(b, q, cell);
 }
 
 // ---------------------------------------------------------------------------
@@ -348,6 +349,17 @@ __device__ inline uint4 ld16u(__amdgpu_buffer_rsrc_t r, int byte_off) {
     return make_uint4(v[0], v[1], v[2], v[3]);
 }
 
+// 16 bytes at a wave-uniform base address plus a 32-bit lane offset: a
+// global load with the base in two scalar registers (a buffer resource takes
+// four).  The address is rebuilt as a global-space pointer from its integer
+// value; through a generic pointer the compiler would emit a flat load.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) u32x4_t gu32x4_t;
+__device__ inline uint4 ld16g(uint64_t base, uint32_t byte_off) {
+    const u32x4_t v = *(const gu32x4_t*)(base + byte_off);
+    return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
 // Bytes 2i and 2i + 1 of a word as two fp16 subnormals, byte * 2^-24 exactly
 // (v_perm_b32): v_fma_mix_f32 then multiplies them by fp32 weights with no
 // separate conversion.  The 2^24 comes back, exactly, in the decode scale.
@@ -369,9 +381,11 @@ __device__ inline void fold_texel(uint32_t x, uint32_t y, float w, float s[kNch]
     s[7] = fmaf(w, (float)d.y, s[7]);
 }
 
+typedef const __attribute__((address_space(4))) float cfloat;
+
 // raw[c] += scale[c] * (sum over N pairs of w q[c]) for one texture
 template <int N>
-__device__ inline void fold_u8(const uint4 (&t)[N], const float* w, const float* sc, float raw[kNch]) {
+__device__ inline void fold_u8(const uint4 (&t)[N], const float* w, const cfloat* sc, float raw[kNch]) {
     float s[kNch] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -407,20 +421,33 @@ __device__ inline void raw_u8(const BlockU& b, const float q[3], int cell, float
             g[j] = ld16u(b.brick, 8 * (base + ((zs + (j >> 1)) * s2 + ys + (j & 1)) * s2 + xs));
     } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) g[j] = ld16u(b.tex[0], 8 * T.pidx[j]);
+        for (int j = 0; j < 4; ++j) g[j] = ld16g(b.tp[0], 8u * (uint32_t)T.pidx[j]);
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        p0[j] = ld16u(b.tex[1], 8 * T.pidx[4 + j]);
-        p1[j] = ld16u(b.tex[2], 8 * T.pidx[6 + j]);
-        p2[j] = ld16u(b.tex[3], 8 * T.pidx[8 + j]);
+        p0[j] = ld16g(b.tp[1], 8u * (uint32_t)T.pidx[4 + j]);
+        p1[j] = ld16g(b.tp[2], 8u * (uint32_t)T.pidx[6 + j]);
+        p2[j] = ld16g(b.tp[3], 8u * (uint32_t)T.pidx[8 + j]);
     }
+    // The decode constants are read sample by sample with scalar loads (the
+    // block table is constant during a launch), eight at a time beside the
+    // texture that uses them: each group's pointer is an opaque copy that
+    // depends on the previous group's result, so the loads can neither leave
+    // the march loop (the 40 wave-uniform values would then hold 40 vector
+    // registers) nor gather at its top (40 scalar registers at once).
+    const float* dg = b.dec;
+    asm volatile("" : "+s"(dg));
+    const cfloat* off = (const cfloat*)dg + 4 * kNch;
 #pragma unroll
-    for (int c = 0; c < kNch; ++c) raw[c] = b.osum[c];
-    fold_u8<4>(g, T.w, b.sc[0], raw);
-    fold_u8<2>(p0, T.w + 8, b.sc[1], raw);
-    fold_u8<2>(p1, T.w + 12, b.sc[2], raw);
-    fold_u8<2>(p2, T.w + 16, b.sc[3], raw);
+    for (int c = 0; c < kNch; ++c) raw[c] = off[c];
+    asm volatile("" : "+s"(dg) : "v"(raw[0]));
+    fold_u8<4>(g, T.w, (const cfloat*)dg, raw);
+    asm volatile("" : "+s"(dg) : "v"(raw[0]));
+    fold_u8<2>(p0, T.w + 8, (const cfloat*)dg + kNch, raw);
+    asm volatile("" : "+s"(dg) : "v"(raw[0]));
+    fold_u8<2>(p1, T.w + 12, (const cfloat*)dg + 2 * kNch, raw);
+    asm volatile("" : "+s"(dg) : "v"(raw[0]));
+    fold_u8<2>(p2, T.w + 16, (const cfloat*)dg + 3 * kNch, raw);
 }
 
 // fp32 block: a texel pair is 64 contiguous bytes (channels 0-3, 4-7 of each
@@ -775,11 +802,70 @@ __device__ inline Span block_span(const MarchArgs& a, const BlockU& b, const Ray
     return s;
 }
 
+// First step index after k whose sample lies outside the level-l cell of the
+// occupancy pyramid that holds sample k (base cell indices ci), or kb if every
+// sample up to the span's end stays inside.  On each axis the base cell index
+// of a sample, trunc((fl(o + fl(t d)) - lo) O) clamped to the grid, is
+// monotone in k, so "outside the cell" is a monotone predicate and first_true
+// finds its least k exactly; the analytic crossing of the cell's exit face is
+// only the starting guess.  Every sample skipped lies in an empty pyramid
+// cell, hence in an empty base cell, so the evaluated samples are those of a
+// one-step-at-a-time march.
+__device__ inline int level_exit(const BlockU& b, const Ray& r, float delta, int k, int kb, const int ci[3], int l) {
+    const float Of = (float)b.O;
+    // An opaque zero keeps the guess's reciprocals inside the jump: hoisted
+    // out of the march loop they would hold registers across it.
+    float z = 0.0f;
+    asm volatile("" : "+v"(z));
+    float lim[3];
+    int dir[3];  // +1: leaves once u >= lim; -1: once u < lim; 0: cannot leave across this axis
+    float tx = INFINITY;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int a0 = (ci[c] >> l) << l, a1 = a0 + (1 << l);
+        dir[c] = 0;
+        lim[c] = 0.0f;
+        if (r.d[c] > 0.0f && a1 < b.od[c]) {
+            dir[c] = 1;
+            lim[c] = (float)a1;
+        } else if (r.d[c] < 0.0f && a0 > 0) {
+            dir[c] = -1;
+            lim[c] = (float)a0;
+        }
+        if (dir[c] != 0) {
+            const float face = b.lo[c] + lim[c] * __builtin_amdgcn_rcpf(Of + z);
+            tx = fminf(tx, (face - r.o[c]) * __builtin_amdgcn_rcpf(r.d[c] + z));
+        }
+    }
+    if (dir[0] == 0 && dir[1] == 0 && dir[2] == 0) return kb;  // the cell spans the rest of the block
+    auto outside = [&](int j) {
+        const float t = step_t(j, delta);
+        bool out = false;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float u = (coord(r.o[c], t, r.d[c]) - b.lo[c]) * Of;
+            out = out || (dir[c] > 0 && u >= lim[c]) || (dir[c] < 0 && u < lim[c]);
+        }
+        return out;
+    };
+    // start at the guess, clamped to (k, kb]; walk down while the sample
+    // before is already outside, then up while the sample is still inside:
+    // the result is the least outside index in (k, kb), else kb
+    int kx = guess_index(tx * __builtin_amdgcn_rcpf(delta + z) - 0.5f);
+    kx = kx > k + 1 ? (kx < kb ? kx : kb) : k + 1;
+    while (kx > k + 1 && outside(kx - 1)) --kx;
+    while (kx < kb && !outside(kx)) ++kx;
+    return kx;
+}
+
 // Advance k to the next occupied sample of the span (or to kb).  Loads the
-// occupancy byte only when the sample's cell differs from the cached one.
+// occupancy byte only when the sample's cell differs from the cached one.  In
+// grid mode an empty cell is left in one jump to the first sample outside the
+// coarsest empty pyramid cell around it (unless flat); the jumped samples count
+// as marched, as a one-step march would count them.
 template <int MODE>
-__device__ inline bool next_occupied(const BlockU& b, const Ray& r, const Span& sp, int kb, float delta, int& k,
-                                     float q[3], int& cell, int& cur_cell, bool& cur_occ, int64_t& marched) {
+__device__ inline bool next_occupied(const BlockU& b, const Ray& r, const Span& sp, int kb, float delta, bool flat,
+                                     int& k, float q[3], int& cell, int& cur_cell, bool& cur_occ, int64_t& marched) {
     while (k < kb) {
         const float t = MODE == 1 ? step_t(k, delta) : sp.tn + ((float)k + 0.5f) * sp.dr;
         bool in = true;
@@ -791,10 +877,18 @@ __device__ inline bool next_occupied(const BlockU& b, const Ray& r, const Span& 
         }
         if (in) {
             ++marched;
-            cell = occ_cell(b, q);
+            int ci[3];
+            cell = occ_cell(b, q, ci);
             if (cell != cur_cell) {
                 cur_cell = cell;
-                cur_occ = b.occ[cell] != 0;
+                const int s = b.skip[cell];
+                cur_occ = s == 0;
+                if (MODE == 1 && s != 0 && !flat) {
+                    const int kx = level_exit(b, r, delta, k, kb, ci, s - 1);
+                    marched += kx - k - 1;
+                    k = kx;
+                    continue;
+                }
             }
             if (cur_occ) return true;
         }
@@ -819,7 +913,8 @@ __device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ra
     for (;;) {
         float q[3];
         int cell = 0;
-        const bool have = next_occupied<MODE>(b, r, sp, kb, sp.delta, k, q, cell, cur_cell, cur_occ, n_march);
+        const bool have =
+            next_occupied<MODE>(b, r, sp, kb, sp.delta, a.flat_occ != 0, k, q, cell, cur_cell, cur_occ, n_march);
         if (!__any(have)) break;
         if (have) {
             float raw[8], v[7], sigma;
@@ -854,7 +949,7 @@ __device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ra
 // want == false marches nothing and gets 1.
 template <int MODE>
 __device__ inline float block_trans_f32(const BlockU& b, const Ray& r, const Span& sp, float T_before,
-                                        float t_min, bool want) {
+                                        float t_min, bool flat, bool want) {
     int k = sp.ka, kb = want ? sp.kb : sp.ka;
     int cur_cell = -1;
     bool cur_occ = false;
@@ -863,7 +958,7 @@ __device__ inline float block_trans_f32(const BlockU& b, const Ray& r, const Spa
     for (;;) {
         float q[3];
         int cell = 0;
-        const bool have = next_occupied<MODE>(b, r, sp, kb, sp.delta, k, q, cell, cur_cell, cur_occ, unused);
+        const bool have = next_occupied<MODE>(b, r, sp, kb, sp.delta, flat, k, q, cell, cur_cell, cur_occ, unused);
         if (!__any(have)) break;
         if (have) {
             Taps T;

@@ -128,6 +128,30 @@ size_t occ_cells(const cow_block_desc& d) {
     dims(d, d.occ_res, o);
     return (size_t)o[0] * o[1] * o[2];
 }
+// levels above the base of the max-pooled occupancy pyramid: log2 of the
+// longest axis, so the top level is one cell
+int occ_levels(const cow_block_desc& d) {
+    int o[3];
+    dims(d, d.occ_res, o);
+    const int m = std::max(o[0], std::max(o[1], o[2]));
+    int l = 0;
+    while ((1 << l) < m) ++l;
+    return l;
+}
+size_t occ_level_cells(const cow_block_desc& d, int l) {
+    int o[3];
+    dims(d, d.occ_res, o);
+    return (size_t)std::max(o[0] >> l, 1) * std::max(o[1] >> l, 1) * std::max(o[2] >> l, 1);
+}
+size_t occ_pyramid_cells(const cow_block_desc& d) {
+    size_t n = 0;
+    for (int l = 1; l <= occ_levels(d); ++l) n += occ_level_cells(d, l);
+    return n;
+}
+// per entry: [base][levels 1..L][skip levels], each base-sized part aligned
+size_t occ_region(const cow_block_desc& d) {
+    return align_up(occ_cells(d)) + align_up(occ_pyramid_cells(d)) + align_up(occ_cells(d));
+}
 
 cow_status validate_desc(cow_ctx* c, const cow_block_desc& d) {
     char buf[256];
@@ -169,13 +193,14 @@ cow_status validate_desc(cow_ctx* c, const cow_block_desc& d) {
     return COW_OK;
 }
 
-// load workspace layout: [DevBlock table][occupancy grids][brick slot tables]
+// load workspace layout: [DevBlock table][occupancy grids, pyramids and skip
+// levels][brick slot tables]
 size_t load_layout(const cow_block_desc* b, int n, std::vector<size_t>* occ_off,
                    std::vector<size_t>* slot_off) {
     size_t off = align_up(sizeof(DevBlock) * (size_t)n);
     for (int i = 0; i < n; ++i) {
         if (occ_off) occ_off->push_back(off);
-        off += align_up(occ_cells(b[i]));
+        off += occ_region(b[i]);
     }
     for (int i = 0; i < n; ++i) {
         if (slot_off) slot_off->push_back(off);
@@ -472,6 +497,7 @@ cow::MarchArgs march_args(cow_ctx* c, const CallTables& T, const RenderWs& w,
     a.delta = p->delta;
     for (int i = 0; i < 3; ++i) a.scene_lo[i] = c->scene_lo[i], a.scene_hi[i] = c->scene_hi[i];
     a.use_sparse = (p->flags & COW_F_SPARSE) ? 1 : 0;
+    a.flat_occ = (p->flags & COW_F_FLAT_OCC) ? 1 : 0;
     a.blocks_dtype = dtype;
     a.aux = aux;
     a.trans = trans;
@@ -832,6 +858,9 @@ cow_status cow_load_blocks(cow_ctx* c, const cow_block_desc* blocks, int n, void
         d.grid = blocks[i].grid;
         for (int k = 0; k < 3; ++k) d.plane[k] = blocks[i].plane[k];
         d.occ = c->load_ws + occ_off[i];
+        d.occ_pyr = d.occ + align_up(occ_cells(blocks[i]));
+        d.skip = d.occ_pyr + align_up(occ_pyramid_cells(blocks[i]));
+        d.n_levels = occ_levels(blocks[i]);
         d.brick_slot = nullptr;
         d.bricks = nullptr;
         for (int t = 0; t < 4; ++t)
@@ -839,13 +868,23 @@ cow_status cow_load_blocks(cow_ctx* c, const cow_block_desc* blocks, int n, void
                 d.scale[t][ch] = d.dtype == COW_U8 ? blocks[i].scale[t][ch] : 1.0f;
                 d.offset[t][ch] = d.dtype == COW_U8 ? blocks[i].offset[t][ch] : 0.0f;
             }
+        // fp32 products, rounded once each as on the device
+        const float log2e = 1.44269504088896341f;
+        for (int ch = 0; ch < 8; ++ch) {
+            const float sgn = ch == 0 ? log2e : -log2e;
+            for (int t = 0; t < 4; ++t) d.dsc[t][ch] = d.scale[t][ch] * (16777216.0f * sgn);
+            d.dosum[ch] = (((d.offset[0][ch] + d.offset[1][ch]) + d.offset[2][ch]) + d.offset[3][ch]) * sgn;
+        }
     }
     const size_t tb = sizeof(DevBlock) * (size_t)n;
     cow_status st = ensure_pinned(c, tb);
     if (st != COW_OK) return st;
     memcpy(c->pinned, c->h_blocks.data(), tb);
     HIP_TRY(c, hipMemcpyAsync(c->d_blocks, c->pinned, tb, hipMemcpyHostToDevice, stream));
-    for (int i = 0; i < n; ++i) HIP_TRY(c, cow::launch_occupancy(c->d_blocks, i, (int)occ_cells(blocks[i]), stream));
+    for (int i = 0; i < n; ++i) {
+        HIP_TRY(c, cow::launch_occupancy(c->d_blocks, i, (int)occ_cells(blocks[i]), stream));
+        HIP_TRY(c, cow::launch_occupancy_pyramid(c->d_blocks, i, c->h_blocks[i].n_levels, c->h_blocks[i].od, stream));
+    }
     // z_top of each entry from its occupancy (top of the highest occupied cell)
     size_t tot = 0;
     for (int i = 0; i < n; ++i) tot += occ_cells(blocks[i]);
@@ -884,6 +923,26 @@ cow_status cow_get_occupancy(cow_ctx* c, int block_id, int lod, uint8_t* host_ou
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipDeviceSynchronize());
     HIP_TRY(c, hipMemcpy(host_out, c->load_ws + c->entries[e].occ_off, cells, hipMemcpyDeviceToHost));
+    return COW_OK;
+}
+
+cow_status cow_get_occupancy_level(cow_ctx* c, int block_id, int lod, int level, uint8_t* host_out, size_t n) {
+    if (!c) return COW_E_INVALID;
+    if (!host_out) return fail(c, COW_E_INVALID, "null output");
+    const int e = find_entry(c, block_id, lod);
+    if (e < 0) return fail(c, COW_E_NOT_LOADED, "block not loaded");
+    const cow_block_desc& d = c->entries[e].desc;
+    if (level < 0 || level > occ_levels(d)) return fail(c, COW_E_INVALID, "no such occupancy level");
+    const size_t cells = occ_level_cells(d, level);
+    if (n < cells) return fail(c, COW_E_INVALID, "output too small");
+    size_t off = c->entries[e].occ_off;
+    if (level > 0) {
+        off += align_up(occ_cells(d));
+        for (int l = 1; l < level; ++l) off += occ_level_cells(d, l);
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());
+    HIP_TRY(c, hipMemcpy(host_out, c->load_ws + off, cells, hipMemcpyDeviceToHost));
     return COW_OK;
 }
 

@@ -21,12 +21,24 @@ struct DevBlock {
     int32_t gd[3], pd[3], od[3];  // texels (cells) along x, y, z: resolution x extent
     const void* grid;
     const void* plane[3];
-    const uint8_t* occ;        // [O][O][O]
+    const uint8_t* occ;        // [Oz][Oy][Ox] binary occupancy
+    // multi-level occupancy: levels 1..n_levels of the max-pooled pyramid,
+    // consecutive, level l [Lz][Ly][Lx] with L_a = max(od_a >> l, 1)
+    const uint8_t* occ_pyr;
+    // [Oz][Oy][Ox]: 0 for an occupied cell, else 1 + the coarsest level whose
+    // cell holding it is empty (the level the march may skip at)
+    const uint8_t* skip;
+    int32_t n_levels;
     const int32_t* brick_slot; // [O][O][O] -> brick index or -1 (sparse grids)
     const uint8_t* bricks;     // [n][(s+2)^3][8] uint8
     uint32_t brick_bytes;      // size of this block's part of the brick atlas
     float scale[4][kNch];
     float offset[4][kNch];
+    // uint8 decode in the exp2 domain of the activations, formed at load:
+    // dsc[t][c] = scale[t][c] 2^24 (+log2 e for c = 0, -log2 e otherwise),
+    // dosum[c] = (((offset[0][c] + offset[1][c]) + offset[2][c]) + offset[3][c]) (+-log2 e)
+    float dsc[4][kNch];
+    float dosum[kNch];
 };
 
 struct DevView {
@@ -51,6 +63,7 @@ struct MarchArgs {
     float t_min;               // early ray termination threshold (0: off)
     float scene_lo[3], scene_hi[3];
     int32_t use_sparse;
+    int32_t flat_occ;          // 1: step through empty cells one sample at a time (no pyramid skips)
     int32_t blocks_dtype;      // COW_U8 / COW_F32, the same for every block of the launch
     float* aux;                // [P][8] (C_d, F, T)
     float* trans;              // [P]
@@ -128,6 +141,7 @@ struct SparsityArgs {
 
 // launchers
 hipError_t launch_occupancy(const DevBlock* blocks, int entry, int n_cells, hipStream_t s);
+hipError_t launch_occupancy_pyramid(const DevBlock* blocks, int entry, int n_levels, const int od[3], hipStream_t s);
 hipError_t launch_march(const MarchArgs& a, int waves_per_group, hipStream_t s);
 hipError_t launch_reset_counter(int32_t* counter, hipStream_t s);
 hipError_t launch_clear_aux(float* aux, int64_t n_pix, hipStream_t s);

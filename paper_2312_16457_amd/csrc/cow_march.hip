@@ -2,6 +2,8 @@
 // build and sparse-brick packing for gfx950 (City-on-Web, arXiv 2312.16457).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "cow_device.h"
 
 namespace cow {
@@ -243,6 +245,75 @@ __global__ void occupancy_kernel(const DevBlock* blocks, int entry) {
 hipError_t launch_occupancy(const DevBlock* blocks, int entry, int n_cells, hipStream_t s) {
     const int n = n_cells;
     hipLaunchKernelGGL(occupancy_kernel, dim3((n + 63) / 64), dim3(64), 0, s, blocks, entry);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// multi-level occupancy (Sec. 3, the grids psi; Sec. 4.5: downsampled by
+// max-pooling)
+// ---------------------------------------------------------------------------
+__device__ inline int level_dim(int n, int l) { return max(n >> l, 1); }
+
+__device__ inline const uint8_t* pyramid_level(const DevBlock* B, int l) {
+    if (l == 0) return B->occ;
+    const uint8_t* p = B->occ_pyr;
+    for (int j = 1; j < l; ++j)
+        p += (size_t)level_dim(B->od[0], j) * level_dim(B->od[1], j) * level_dim(B->od[2], j);
+    return p;
+}
+
+// Level l from level l - 1: cell x is the OR of the cells y with y >> 1 == x,
+// at most 2 x 2 x 2 of them (fewer where the finer level is one cell wide).
+__global__ void occ_pool_kernel(const DevBlock* blocks, int entry, int l) {
+    const DevBlock* B = blocks + entry;
+    const int nx = level_dim(B->od[0], l), ny = level_dim(B->od[1], l), nz = level_dim(B->od[2], l);
+    const int fx = level_dim(B->od[0], l - 1), fy = level_dim(B->od[1], l - 1), fz = level_dim(B->od[2], l - 1);
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= nx * ny * nz) return;
+    const int x = cell % nx, y = (cell / nx) % ny, z = cell / (nx * ny);
+    const uint8_t* src = pyramid_level(B, l - 1);
+    int any = 0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const int cx = 2 * x + dx, cy = 2 * y + dy, cz = 2 * z + dz;
+                if (cx < fx && cy < fy && cz < fz) any |= src[((size_t)cz * fy + cy) * fx + cx];
+            }
+    const_cast<uint8_t*>(pyramid_level(B, l))[cell] = any ? 1 : 0;
+}
+
+// Per base cell: 0 if occupied, else 1 + the coarsest level whose cell holding
+// it is empty.  The levels are nested (an empty cell's parent may be occupied,
+// never the reverse), so the first occupied level ends the climb.
+__global__ void occ_skip_kernel(const DevBlock* blocks, int entry) {
+    const DevBlock* B = blocks + entry;
+    const int ox = B->od[0], oy = B->od[1], oz = B->od[2];
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= ox * oy * oz) return;
+    const int x = cell % ox, y = (cell / ox) % oy, z = cell / (ox * oy);
+    int s = 0;
+    if (!B->occ[cell]) {
+        s = 1;
+        for (int l = 1; l <= B->n_levels; ++l) {
+            const int nx = level_dim(ox, l), ny = level_dim(oy, l);
+            const size_t c = ((size_t)(z >> l) * ny + (y >> l)) * nx + (x >> l);
+            if (pyramid_level(B, l)[c]) break;
+            s = l + 1;
+        }
+    }
+    const_cast<uint8_t*>(B->skip)[cell] = (uint8_t)s;
+}
+
+hipError_t launch_occupancy_pyramid(const DevBlock* blocks, int entry, int n_levels, const int od[3],
+                                    hipStream_t s) {
+    for (int l = 1; l <= n_levels; ++l) {
+        const int n = std::max(od[0] >> l, 1) * std::max(od[1] >> l, 1) * std::max(od[2] >> l, 1);
+        hipLaunchKernelGGL(occ_pool_kernel, dim3((n + 63) / 64), dim3(64), 0, s, blocks, entry, l);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int n = od[0] * od[1] * od[2];
+    hipLaunchKernelGGL(occ_skip_kernel, dim3((n + 63) / 64), dim3(64), 0, s, blocks, entry);
     return hipGetLastError();
 }
 

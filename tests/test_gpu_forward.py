@@ -164,6 +164,24 @@ def test_c2_full_frame_sampled_rows(c2, torch_cuda):
     assert ref["n_eval"].sum() > 1e6
 
 
+def test_c2_full_frame_jumps_equal_flat(c2, torch_cuda):
+    """The benchmarked 1920x1080 frame with jumps over empty occupancy-pyramid
+    cells renders the same bits and sample counts as a one-step march."""
+    torch = torch_cuda
+    from paper_2312_16457_amd import F_FLAT_OCC
+    scene, r = c2
+    v = sg.c2_view()
+    sel = r.select(v, thresholds=(1e30,), cull=True)
+    mlp = torch.tensor(sg.xavier_mlp(1), device="cuda")
+    a = r.render([v], [sel], sg.cityb_params(), mlp, counts=True)
+    b = r.render([v], [sel], sg.cityb_params(), mlp, counts=True, flags=F_FLAT_OCC)
+    torch.cuda.synchronize()
+    for key in ("rgb", "trans", "aux", "counts"):
+        assert torch.equal(a[key], b[key]), key
+    c = a["counts"]
+    assert (c[:, 1] - c[:, 0]).sum().item() > 1e7  # empty steps the jumps replace
+
+
 def test_launch_variants_bitwise(c2, torch_cuda):
     """Per-block launches + blend, persistent, graph replay, packet shapes and
     waves per workgroup all give bit-identical outputs (P12)."""
