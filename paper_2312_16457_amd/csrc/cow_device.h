@@ -218,7 +218,8 @@ struct BlockU {
     uint64_t tp[4];                 // the same textures' addresses (uint8 path, global loads)
     __amdgpu_buffer_rsrc_t brick;   // packed grid bricks (sparse)
     const uint8_t* occ;
-    const uint8_t* skip;            // per base cell: 0 occupied, else 1 + coarsest empty level
+    uint64_t skip;                  // address of the per-cell skip levels (0 occupied, else 1 + the
+                                    // coarsest empty level), read with global loads
     const int32_t* slot;
     int R, Rp, O;                   // texels (cells) per unit length
     int gd[3], pd[3], od[3];        // texels (cells) along x, y, z
@@ -249,7 +250,7 @@ __device__ inline void load_block(const DevBlock* B, BlockU& b) {
     b.tp[0] = reinterpret_cast<uint64_t>(ufp(B->grid));
     for (int p = 0; p < 3; ++p) b.tp[1 + p] = reinterpret_cast<uint64_t>(ufp(B->plane[p]));
     b.occ = ufp(B->occ);
-    b.skip = ufp(B->skip);
+    b.skip = reinterpret_cast<uint64_t>(ufp(B->skip));
     b.slot = ufp(B->brick_slot);
     b.brick = tex_rsrc(ufp(B->bricks), (uint32_t)ufl((int)B->brick_bytes));
     // raw_u8 returns log2(e) raw_0 and -log2(e) raw_c (c >= 1), the arguments
@@ -353,6 +354,11 @@ __device__ inline uint4 ld16u(__amdgpu_buffer_rsrc_t r, int byte_off) {
 // global load with the base in two scalar registers (a buffer resource takes
 // four).  The address is rebuilt as a global-space pointer from its integer
 // value; through a generic pointer the compiler would emit a flat load.
+// one byte at a wave-uniform base address plus a 32-bit lane offset (global load)
+__device__ inline uint32_t ld1g(uint64_t base, uint32_t byte_off) {
+    return *(const __attribute__((address_space(1))) uint8_t*)(base + byte_off);
+}
+
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) u32x4_t gu32x4_t;
 __device__ inline uint4 ld16g(uint64_t base, uint32_t byte_off) {
@@ -881,7 +887,7 @@ __device__ inline bool next_occupied(const BlockU& b, const Ray& r, const Span& 
             cell = occ_cell(b, q, ci);
             if (cell != cur_cell) {
                 cur_cell = cell;
-                const int s = b.skip[cell];
+                const int s = ld1g(b.skip, (uint32_t)cell);
                 cur_occ = s == 0;
                 if (MODE == 1 && s != 0 && !flat) {
                     const int kx = level_exit(b, r, delta, k, kb, ci, s - 1);
