@@ -910,7 +910,10 @@ __device__ inline bool next_occupied(const BlockU& b, const Ray& r, const Span& 
 // while any lane still has an occupied sample.
 // With early termination (t_min > 0) a lane stops after the first sample at
 // which its transmittance T_before * Tk falls below t_min.
-template <int DT, int MODE, bool SPARSE>
+// JUMPS = false steps one sample at a time whatever the launch asks (the
+// adjoint: its register budget has no room for the jump code, and its
+// per-sample atomics dwarf the cost of an empty step).
+template <int DT, int MODE, bool SPARSE, bool JUMPS = true>
 __device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ray& r, const Span& sp,
                                    float T_before, float Ak[7], float& Tk, int64_t& n_eval, int64_t& n_march) {
     int k = sp.ka, kb = sp.kb;
@@ -920,7 +923,8 @@ __device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ra
         float q[3];
         int cell = 0;
         const bool have =
-            next_occupied<MODE>(b, r, sp, kb, sp.delta, a.flat_occ != 0, k, q, cell, cur_cell, cur_occ, n_march);
+            next_occupied<MODE>(b, r, sp, kb, sp.delta, !JUMPS || a.flat_occ != 0, k, q, cell, cur_cell, cur_occ,
+                                n_march);
         if (!__any(have)) break;
         if (have) {
             float raw[8], v[7], sigma;

@@ -171,7 +171,7 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
             int64_t ne = 0, nm = 0;
 #pragma unroll
             for (int c = 0; c < 7; ++c) Af[c] = 0.0f;
-            march_block<1, MODE, false>(a, b, r, sp, T_blk, Af, Tkf, ne, nm);
+            march_block<1, MODE, false, false>(a, b, r, sp, T_blk, Af, Tkf, ne, nm);
             float Ck[3];
             __amdgpu_buffer_rsrc_t gw = tex_rsrc(ba.grad_block_mlp ? ufp(ba.grad_block_mlp) + (size_t)e * kMlpParams
                                                                    : nullptr,
@@ -190,7 +190,7 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
             for (int c = 0; c < 7; ++c) Ap[c] = 0.0f;
             Tg = 1.0f;
         } else if (OPAC && __any(w_op != 0.0f)) {
-            const float Tkf = block_trans_f32<MODE>(b, r, sp, T_blk, a.t_min, a.flat_occ != 0, w_op != 0.0f);
+            const float Tkf = block_trans_f32<MODE>(b, r, sp, T_blk, a.t_min, true, w_op != 0.0f);
             g_op = w_op * opacity_dentropy(Tkf) * Tkf;
         }
         int k = sp.ka, kb = sp.kb;
@@ -207,8 +207,8 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
         for (;;) {
             float q[3];
             int cell = 0;
-            const bool have = next_occupied<MODE>(b, r, sp, kb, sp.delta, a.flat_occ != 0, k, q, cell, cur_cell,
-                                                  cur_occ, unused);
+            // one step at a time (see march_block): the same samples as the forward's jumps
+            const bool have = next_occupied<MODE>(b, r, sp, kb, sp.delta, true, k, q, cell, cur_cell, cur_occ, unused);
             if (!__any(have)) break;
             Taps T;
             float draw[8] = {0, 0, 0, 0, 0, 0, 0, 0};

@@ -4,8 +4,8 @@ Sec. 3 and Sec. 4.5) and of the grid-mode march's jumps over its empty cells.
 Bars: every pyramid level bit-exact against the oracle's pooling; evaluated
 and marched sample counts bit-exact against the oracle's one-step march, with
 rgb and transmittance within 1e-4; renders that jump bitwise equal to renders
-that step one sample at a time (COW_F_FLAT_OCC); the adjoint of both equal up
-to the order of its fp32 atomic additions."""
+that step one sample at a time (COW_F_FLAT_OCC); the adjoint (which steps one
+sample at a time) within 1e-3 of the fp64 adjoint after a jumping forward."""
 import dataclasses
 
 import numpy as np
@@ -151,40 +151,49 @@ def test_batched_views_jump_equal_flat(sparse):
                 assert torch.equal(o[key], base[key]), (flags, key)
 
 
-def test_adjoint_jump_equal_flat(have_gpu):
-    """The adjoint re-marches with the same jumps: its gradients equal the
-    one-step march's up to the order of the fp32 atomic additions."""
+def test_adjoint_after_jumping_forward(have_gpu):
+    """The adjoint steps one sample at a time and reads the aux of a forward
+    that jumped: on the sparse fp32 city its texture and MLP gradients match
+    the fp64 adjoint within 1e-3 (normwise per texture), and asking it for
+    jumps changes nothing."""
     import torch
     from paper_2312_16457_amd import F_FLAT_OCC, Renderer
     scene = sparse_scene(sg.F32, seed=23)
     r = Renderer(0).load_blocks(scene.blocks)
-    views = sparse_views()[:3]
-    sets = [r.select(v, thresholds=(1e30,), cull=True) for v in views]
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
     p = sg.cityb_params()
-    mlp = torch.tensor(sg.random_mlp(8, 0.3), device="cuda")
-    n = sum(v.n_pixels for v in views)
-    g_rgb = torch.tensor(np.random.default_rng(3).uniform(-1, 1, (n, 3)), dtype=torch.float32, device="cuda")
-    res = []
-    for flags in (0, F_FLAT_OCC):
-        out = r.render(views, sets, p, mlp, flags=flags)
-        gg = [torch.zeros_like(t[0]) for t in r.textures]
-        gp = [[torch.zeros_like(q) for q in t[1]] for t in r.textures]
-        gm = torch.zeros(499, device="cuda")
-        r.render_backward(views, sets, p, mlp, out["aux"], g_rgb, None, gg, gp, gm, flags=flags)
-        torch.cuda.synchronize()
-        res.append((gg, gp, gm))
-    (a_g, a_p, a_m), (b_g, b_p, b_m) = res
-    pairs = [(x, y) for x, y in zip(a_g, b_g)] + [(x, y) for xs, ys in zip(a_p, b_p) for x, y in zip(xs, ys)]
-    pairs.append((a_m, b_m))
-    nonzero = 0
-    for x, y in pairs:
-        den = y.abs().max().item()
-        if den == 0:
-            assert x.abs().max().item() == 0
-            continue
-        nonzero += 1
-        assert (x - y).abs().max().item() <= 1e-5 * den
-    assert nonzero > 5
+    w = sg.random_mlp(8, 0.3)
+    mlp = torch.tensor(w, device="cuda")
+    rng = np.random.default_rng(3)
+    checked = 0
+    for v in sparse_views()[:2]:
+        sel = r.select(v, thresholds=(1e30,), cull=True)
+        g_rgb = rng.uniform(-1, 1, (v.n_pixels, 3))
+        res = []
+        for flags in (0, F_FLAT_OCC):
+            out = r.render([v], [sel], p, mlp)
+            gg = [torch.zeros_like(t[0]) for t in r.textures]
+            gp = [[torch.zeros_like(q) for q in t[1]] for t in r.textures]
+            gm = torch.zeros(499, device="cuda")
+            r.render_backward([v], [sel], p, mlp, out["aux"],
+                              torch.tensor(g_rgb, dtype=torch.float32, device="cuda"), None, gg, gp, gm, flags=flags)
+            torch.cuda.synchronize()
+            res.append((gg, gp, gm))
+        (a_g, a_p, a_m), (b_g, b_p, b_m) = res
+        for x, y in list(zip(a_g, b_g)) + [(x, y) for xs, ys in zip(a_p, b_p) for x, y in zip(xs, ys)]:
+            assert (x - y).abs().max().item() <= 1e-5 * max(y.abs().max().item(), 1e-30)
+        grads, gm_ref = O.adjoint(ob, occs, v, entry_index(scene, sel), p, w.astype(np.float64), O.pixels_of(v), g_rgb)
+        for k, (g, ps) in grads.items():
+            for got, ref in [(a_g[k], g)] + [(a_p[k][i], ps[i]) for i in range(3)]:
+                den = np.abs(ref).max()
+                if den == 0:
+                    assert not got.any().item()
+                    continue
+                assert np.abs(got.cpu().numpy() - ref).max() / den <= 1e-3
+                checked += 1
+        assert np.abs(a_m.cpu().numpy() - gm_ref).max() / np.abs(gm_ref).max() <= 1e-3
+    assert checked > 8
 
 
 def test_chord_mode_unaffected(have_gpu):
