@@ -25,7 +25,6 @@ import numpy as np  # noqa: E402
 
 # MI355X published peaks
 PEAK_FP32_TFLOPS = 157.3
-PEAK_FP32_NONPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # algorithmic fp32 flops of one evaluated sample of the uint8 path:
 #   trilinear grid 8 taps x 8 ch x 2 = 128, three bilinear planes 3 x 4 x 8 x 2 = 192,
@@ -137,11 +136,7 @@ def main():
                      "kernel": "march_fwd_kernel<1,false> (uint8, grid sampling)", "kernel_ms": round(k_ms, 4),
                      "algorithmic_tflop_per_launch": round(FLOPS_PER_SAMPLE * n_eval / 1e12, 4),
                      "flops_per_sample": FLOPS_PER_SAMPLE,
-                     "gathered_GBps": round(BYTES_PER_SAMPLE_U8 * n_eval / (k_ms * 1e-3) / 1e9, 1),
-                     # ceiling without packed fp32 (not used: built with packed-fp32-ops off):
-                     # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
-                     "peak_nonpacked_fp32": PEAK_FP32_NONPACKED_TFLOPS,
-                     "frac_nonpacked": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4)},
+                     "gathered_GBps": round(BYTES_PER_SAMPLE_U8 * n_eval / (k_ms * 1e-3) / 1e9, 1)},
     }
     log(f"forward {ms:.2f} ms per frame")
     if not args.profile:
