@@ -255,7 +255,8 @@ __device__ inline void load_block(const DevBlock* B, BlockU& b) {
     b.brick = tex_rsrc(ufp(B->bricks), (uint32_t)ufl((int)B->brick_bytes));
     // raw_u8 returns log2(e) raw_0 and -log2(e) raw_c (c >= 1), the arguments
     // of exp2 in the activations, so the factor rides in the decode scales and
-    // offsets formed at load (DevBlock::dsc, dosum); 2^24 undoes bytes_h2
+    // offsets formed at load (DevBlock::dsc, dosum); 2^24 undoes the fp16-subnormal
+    // byte unpacking (bytes_even_h2, bytes_odd_h2)
     b.dec = ufp(&B->dsc[0][0]);
 }
 
@@ -366,24 +367,27 @@ __device__ inline uint4 ld16g(uint64_t base, uint32_t byte_off) {
     return make_uint4(v[0], v[1], v[2], v[3]);
 }
 
-// Bytes 2i and 2i + 1 of a word as two fp16 subnormals, byte * 2^-24 exactly
-// (v_perm_b32): v_fma_mix_f32 then multiplies them by fp32 weights with no
-// separate conversion.  The 2^24 comes back, exactly, in the decode scale.
+// Two bytes of a word as two fp16 subnormals, byte * 2^-24 exactly:
+// v_fma_mix_f32 then multiplies them by fp32 weights with no separate
+// conversion, and the 2^24 comes back, exactly, in the decode scale.  Bytes 0
+// and 2 need only a mask (a 2-cycle VOP2 instruction); bytes 1 and 3 a byte
+// permute (4 cycles).
 typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
-__device__ inline h2_t bytes_h2(uint32_t w, int i) {
-    return __builtin_bit_cast(h2_t, __builtin_amdgcn_perm(0u, w, i == 0 ? 0x0c010c00u : 0x0c030c02u));
+__device__ inline h2_t bytes_even_h2(uint32_t w) { return __builtin_bit_cast(h2_t, w & 0x00ff00ffu); }
+__device__ inline h2_t bytes_odd_h2(uint32_t w) {
+    return __builtin_bit_cast(h2_t, __builtin_amdgcn_perm(0u, w, 0x0c030c01u));
 }
 
 // s[c] += w * byte c of one uint8 texel (two words), scaled by 2^-24
 __device__ inline void fold_texel(uint32_t x, uint32_t y, float w, float s[kNch]) {
-    const h2_t a = bytes_h2(x, 0), b = bytes_h2(x, 1), c = bytes_h2(y, 0), d = bytes_h2(y, 1);
+    const h2_t a = bytes_even_h2(x), b = bytes_odd_h2(x), c = bytes_even_h2(y), d = bytes_odd_h2(y);
     s[0] = fmaf(w, (float)a.x, s[0]);
-    s[1] = fmaf(w, (float)a.y, s[1]);
-    s[2] = fmaf(w, (float)b.x, s[2]);
+    s[1] = fmaf(w, (float)b.x, s[1]);
+    s[2] = fmaf(w, (float)a.y, s[2]);
     s[3] = fmaf(w, (float)b.y, s[3]);
     s[4] = fmaf(w, (float)c.x, s[4]);
-    s[5] = fmaf(w, (float)c.y, s[5]);
-    s[6] = fmaf(w, (float)d.x, s[6]);
+    s[5] = fmaf(w, (float)d.x, s[5]);
+    s[6] = fmaf(w, (float)c.y, s[6]);
     s[7] = fmaf(w, (float)d.y, s[7]);
 }
 
