@@ -773,9 +773,32 @@ struct Ray {
     bool active;
 };
 
+// Packet index -> tile of a view's tx_n x ty_n tile grid, in blocks of 8 x 8
+// tiles (raster order inside a block, blocks in raster order; the blocks of
+// the last row and column are cut to fit).  Consecutive packets then cover a
+// compact patch of the image, and the packets one XCD runs together (chunks
+// of consecutive packets) share more texels in its L2 than a strip along one
+// tile row would.
+__device__ inline void tile_xy(int tile, int tx_n, int ty_n, int& tx, int& ty) {
+    constexpr int kB = 8;
+    const int bys = (ty_n - 1) / kB, row_tiles = kB * tx_n;  // last block row; tiles in a full block row
+    int r = tile / row_tiles;
+    r = r < bys ? r : bys;
+    int q = tile - r * row_tiles;
+    const int h = r < bys ? kB : ty_n - kB * bys;
+    const int bxs = (tx_n - 1) / kB;
+    int c = q / (h * kB);
+    c = c < bxs ? c : bxs;
+    q -= c * h * kB;
+    const int w = c < bxs ? kB : tx_n - kB * bxs;
+    ty = r * kB + q / w;
+    tx = c * kB + q % w;
+}
+
 __device__ inline void packet_ray(const MarchArgs& a, const ViewU& v, int tile, int lane, Ray& r) {
     const int tw = a.tile_w, th = a.tile_h;
-    const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
+    int tx, ty;
+    tile_xy(tile, v.tiles_x, (v.h + th - 1) / th, tx, ty);
     const int px = v.x0 + tx * tw + (lane % tw);
     const int py = v.y0 + ty * th + (lane / tw);
     r.active = px < v.x0 + v.w && py < v.y0 + v.h;
