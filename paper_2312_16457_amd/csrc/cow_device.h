@@ -839,11 +839,12 @@ __device__ inline Span block_span(const MarchArgs& a, const BlockU& b, const Ray
 // occupancy pyramid that holds sample k (base cell indices ci), or kb if every
 // sample up to the span's end stays inside.  On each axis the base cell index
 // of a sample, trunc((fl(o + fl(t d)) - lo) O) clamped to the grid, is
-// monotone in k, so "outside the cell" is a monotone predicate and first_true
-// finds its least k exactly; the analytic crossing of the cell's exit face is
-// only the starting guess.  Every sample skipped lies in an empty pyramid
-// cell, hence in an empty base cell, so the evaluated samples are those of a
-// one-step-at-a-time march.
+// monotone in k, so "outside the cell" is a monotone predicate: walking from
+// a guess (the analytic crossing of the cell's exit face) down while the
+// sample before is outside and up while the sample is inside ends at its
+// least k exactly, usually after one or two evaluations.  Every sample
+// skipped lies in an empty pyramid cell, hence in an empty base cell, so the
+// evaluated samples are those of a one-step-at-a-time march.
 __device__ inline int level_exit(const BlockU& b, const Ray& r, float delta, int k, int kb, const int ci[3], int l) {
     const float Of = (float)b.O;
     // An opaque zero keeps the guess's reciprocals inside the jump: hoisted
