@@ -53,7 +53,7 @@ class _View(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("mode", C.c_int), ("n_steps", C.c_int), ("delta", C.c_float), ("max_steps", C.c_int),
-                ("t_min", C.c_float)]
+                ("t_min", C.c_float), ("pe", C.c_int)]
 
 
 _lib = None
@@ -91,6 +91,10 @@ def lib():
                                  vp, C.c_int]
         L.orc_select_quadtree.argtypes = L.orc_select.argtypes
         L.orc_mlp.argtypes = [vp, vp, vp]
+        L.orc_mlp_pe.argtypes = [vp, C.c_int, vp, vp]
+        L.orc_mlp_params.argtypes = [C.c_int]
+        L.orc_mlp_params.restype = C.c_long
+        L.orc_posenc.argtypes = [vp, C.c_int, vp]
         L.orc_field.argtypes = [C.POINTER(_Block), C.c_int, vp, vp]
         _lib = L
     return _lib
@@ -114,7 +118,21 @@ def make_params(p):
     s = _Params()
     s.mode, s.n_steps, s.delta, s.max_steps = int(p.mode), int(p.n_steps), float(p.delta), int(p.max_steps)
     s.t_min = float(getattr(p, "t_min", 0.0))
+    s.pe = int(getattr(p, "pe_freqs", 0))
     return s
+
+
+def mlp_params(pe=0):
+    """Weights of the deferred MLP over 10 + 6 pe inputs (499 for pe = 0)."""
+    return int(lib().orc_mlp_params(int(pe)))
+
+
+def posenc(d, pe):
+    """[d, sin(2^l d), cos(2^l d) for l < pe] of one direction (3 + 6 pe values)."""
+    out = np.zeros(3 + 6 * pe, np.float64)
+    if lib().orc_posenc(_ptr(np.ascontiguousarray(d, np.float64)), int(pe), _ptr(out)) < 0:
+        raise ValueError("pe must be 0-4")
+    return out
 
 
 class OracleScene:
@@ -230,8 +248,11 @@ def render(ob, occs, view, set_idx, params, mlp, pix=None, composite=MERGED, nth
     n = pix.shape[0]
     setv = np.ascontiguousarray(set_idx, np.int32)
     w = np.ascontiguousarray(mlp, np.float64)
-    if composite == BLOCK_MLP and w.size != 499 * ob.n:
-        raise ValueError("BLOCK_MLP needs one 499-weight MLP per entry of the scene")
+    npar = mlp_params(getattr(params, "pe_freqs", 0))
+    if composite == BLOCK_MLP and w.size != npar * ob.n:
+        raise ValueError("BLOCK_MLP needs one MLP per entry of the scene")
+    if composite != BLOCK_MLP and w.size != npar:
+        raise ValueError("the MLP has %d weights" % npar)
     out = dict(rgb=np.zeros((n, 3)), trans=np.zeros(n), aux=np.zeros((n, 8)),
                n_eval=np.zeros(n, np.int64), n_march=np.zeros(n, np.int64),
                order_ok=np.zeros(n, np.int32))
@@ -310,7 +331,9 @@ def adjoint(ob, occs, view, set_idx, params, mlp, pix, grad_rgb, grad_trans=None
         gg[k] = g.ctypes.data
         for i in range(3):
             gp[3 * k + i] = ps[i].ctypes.data
-    gm = np.zeros(499, np.float64)
+    gm = np.zeros(mlp_params(getattr(params, "pe_freqs", 0)), np.float64)
+    if np.asarray(mlp).size != gm.size:
+        raise ValueError("the MLP has %d weights" % gm.size)
     gr = np.ascontiguousarray(grad_rgb, np.float64)
     gt = None if grad_trans is None else np.ascontiguousarray(grad_trans, np.float64)
     wo = None if w_opacity is None else np.ascontiguousarray(w_opacity, np.float64)
@@ -325,15 +348,17 @@ def adjoint(ob, occs, view, set_idx, params, mlp, pix, grad_rgb, grad_trans=None
 
 def adjoint_block_mlp(ob, occs, view, set_idx, params, mlps, pix, grad_rgb, grad_trans=None, w_opacity=None):
     """fp64 adjoint of the per-block deferred composite (BLOCK_MLP);
-    mlps [ob.n][499]; returns ({block: (grad_grid, [grad_planes])}, grad_mlps [ob.n][499])."""
+    mlps [ob.n][P] (P = mlp_params(params.pe_freqs)); returns ({block: (grad_grid,
+    [grad_planes])}, grad_mlps [ob.n][P])."""
     L = lib()
     pix = np.ascontiguousarray(pix, np.int32)
     setv = np.ascontiguousarray(set_idx, np.int32)
     grads, gg, gp = _grad_arrays(ob, set(int(s) for s in setv))
     w = np.ascontiguousarray(mlps, np.float64).reshape(-1)
-    if w.size != 499 * ob.n:
-        raise ValueError("one 499-weight MLP per entry of the scene")
-    gm = np.zeros(499 * ob.n, np.float64)
+    npar = mlp_params(getattr(params, "pe_freqs", 0))
+    if w.size != npar * ob.n:
+        raise ValueError("one MLP per entry of the scene")
+    gm = np.zeros(npar * ob.n, np.float64)
     gr = np.ascontiguousarray(grad_rgb, np.float64)
     gt = None if grad_trans is None else np.ascontiguousarray(grad_trans, np.float64)
     wo = None if w_opacity is None else np.ascontiguousarray(w_opacity, np.float64)
@@ -343,7 +368,7 @@ def adjoint_block_mlp(ob, occs, view, set_idx, params, mlps, pix, grad_rgb, grad
                                 gg, gp, _ptr(gm))
     if r != 0:
         raise ValueError("adjoint needs float blocks")
-    return grads, gm.reshape(ob.n, 499)
+    return grads, gm.reshape(ob.n, npar)
 
 
 def select(view, entries, ztops, thresholds=(2.0, 4.0, 8.0), cull=True, cap=4096, quadtree=False):
@@ -369,10 +394,13 @@ def select(view, entries, ztops, thresholds=(2.0, 4.0, 8.0), cull=True, cap=4096
     return out[:m]
 
 
-def mlp(w, x):
+def mlp(w, x, pe=0):
+    """sigmoid(Phi(x)) for x = [C_d, F, PE(d)] (10 + 6 pe values)."""
+    x = np.ascontiguousarray(x, np.float64)
+    if x.size != 10 + 6 * pe or np.asarray(w).size != mlp_params(pe):
+        raise ValueError("input or weight count does not match pe")
     out = np.zeros(3)
-    lib().orc_mlp(_ptr(np.ascontiguousarray(w, np.float64)), _ptr(np.ascontiguousarray(x, np.float64)),
-                  _ptr(out))
+    lib().orc_mlp_pe(_ptr(np.ascontiguousarray(w, np.float64)), int(pe), _ptr(x), _ptr(out))
     return out
 
 

@@ -391,16 +391,63 @@ static long sample_cap(const orc_params* p, int nset) {
 /* Deferred MLP (Eq. "deferred")                                            */
 /* ---------------------------------------------------------------------- */
 
+/* Input of the deferred MLP (Eq. deferred): [C_d, F, PE(d)], with PE(d) =
+ * [d, sin(2^0 d), cos(2^0 d), ..., sin(2^(L-1) d), cos(2^(L-1) d)] taken per
+ * component (L = 0: the direction alone).  10 + 6L inputs. */
+#define MLP_MAX_IN 34
+
+int orc_posenc(const double* d, int L, double* out) {
+    if (L < 0 || L > 4) return -1;
+    for (int c = 0; c < 3; ++c) out[c] = d[c];
+    for (int l = 0; l < L; ++l) {
+        const double f = ldexp(1.0, l);
+        for (int c = 0; c < 3; ++c) {
+            out[3 + 6 * l + c] = sin(f * d[c]);
+            out[6 + 6 * l + c] = cos(f * d[c]);
+        }
+    }
+    return 3 + 6 * L;
+}
+
+static int mlp_input(const double A[7], const float d[3], int L, double* x) {
+    const double dd[3] = {d[0], d[1], d[2]};
+    for (int c = 0; c < 7; ++c) x[c] = A[c];
+    return 7 + orc_posenc(dd, L, x + 7);
+}
+
+/* parameter layout: W1 [16][ni], b1 [16], W2 [16][16], b2 [16], W3 [3][16], b3 [3] */
+typedef struct mlp_shape {
+    int ni;
+    long W1, b1, W2, b2, W3, b3, n;
+} mlp_shape;
+
+static mlp_shape mlp_shape_of(int L) {
+    mlp_shape s;
+    s.ni = 10 + 6 * L;
+    s.W1 = 0;
+    s.b1 = 16L * s.ni;
+    s.W2 = s.b1 + 16;
+    s.b2 = s.W2 + 256;
+    s.W3 = s.b2 + 16;
+    s.b3 = s.W3 + 48;
+    s.n = s.b3 + 3;
+    return s;
+}
+
+long orc_mlp_params(int L) { return mlp_shape_of(L).n; }
+
 typedef struct mlp_trace {
-    double x[10], pre1[16], h1[16], pre2[16], h2[16], z[3], s[3];
+    double x[MLP_MAX_IN], pre1[16], h1[16], pre2[16], h2[16], z[3], s[3];
 } mlp_trace;
 
-static void mlp_fwd(const double* w, const double* x, mlp_trace* tr) {
-    const double *W1 = w, *b1 = w + 160, *W2 = w + 176, *b2 = w + 432, *W3 = w + 448, *b3 = w + 496;
-    memcpy(tr->x, x, sizeof(double) * 10);
+static void mlp_fwd(const double* w, const mlp_shape* sh, const double* x, mlp_trace* tr) {
+    const int ni = sh->ni;
+    const double *W1 = w + sh->W1, *b1 = w + sh->b1, *W2 = w + sh->W2, *b2 = w + sh->b2, *W3 = w + sh->W3,
+                 *b3 = w + sh->b3;
+    memcpy(tr->x, x, sizeof(double) * ni);
     for (int o = 0; o < 16; ++o) {
         double a = b1[o];
-        for (int i = 0; i < 10; ++i) a += W1[o * 10 + i] * x[i];
+        for (int i = 0; i < ni; ++i) a += W1[o * ni + i] * x[i];
         tr->pre1[o] = a;
         tr->h1[o] = a > 0.0 ? a : 0.0;
     }
@@ -427,9 +474,16 @@ void orc_field(const orc_block* b, int n, const float* pts, double* raw) {
 }
 
 void orc_mlp(const double* mlp, const double* x, double* out) {
+    orc_mlp_pe(mlp, 0, x, out);
+}
+
+int orc_mlp_pe(const double* mlp, int L, const double* x, double* out) {
+    if (L < 0 || L > 4) return -1;
+    const mlp_shape sh = mlp_shape_of(L);
     mlp_trace tr;
-    mlp_fwd(mlp, x, &tr);
+    mlp_fwd(mlp, &sh, x, &tr);
     for (int c = 0; c < 3; ++c) out[c] = tr.s[c];
+    return 0;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -521,11 +575,11 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
                 }
             }
             if (composite == ORC_BLOCK_MLP) {
-                double x[10];
-                for (int c = 0; c < 7; ++c) x[c] = Ak[c];
-                for (int c = 0; c < 3; ++c) x[7 + c] = d[c];
+                const mlp_shape sh = mlp_shape_of(p->pe);
+                double x[MLP_MAX_IN];
+                mlp_input(Ak, d, p->pe, x);
                 mlp_trace tr;
-                mlp_fwd(mlp + 499 * (long)set[run], x, &tr);
+                mlp_fwd(mlp + sh.n * (long)set[run], &sh, x, &tr);
                 for (int c = 0; c < 3; ++c) Cb[c] += T * (Ak[c] + tr.s[c]);
             }
             for (int c = 0; c < 7; ++c) A[c] += T * Ak[c];
@@ -594,11 +648,11 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
         free(Ak);
     }
     free(run_pos);
-    double x[10];
-    for (int c = 0; c < 7; ++c) x[c] = A[c];
-    for (int c = 0; c < 3; ++c) x[7 + c] = d[c];
+    const mlp_shape sh = mlp_shape_of(p->pe);
+    double x[MLP_MAX_IN];
+    mlp_input(A, d, p->pe, x);
     mlp_trace tr;
-    mlp_fwd(mlp, x, &tr);
+    mlp_fwd(mlp, &sh, x, &tr);
     for (int c = 0; c < 3; ++c) rgb[c] = A[c] + tr.s[c];
     *trans = T;
     for (int c = 0; c < 7; ++c) aux[c] = A[c];
@@ -613,6 +667,7 @@ int orc_render(const orc_block* blocks, int nblocks, const unsigned char* const*
                const double* mlp, const int* pix, int npix, int composite,
                double* rgb, double* trans, double* aux, long long* n_eval,
                long long* n_march, int* order_ok, int nthreads) {
+    if (p->pe < 0 || p->pe > 4) return -1;
     long cap = sample_cap(p, nset);
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
@@ -689,6 +744,7 @@ int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const
                 double* const* grad_plane, double* grad_mlp) {
     for (int s = 0; s < nset; ++s)
         if (blocks[set[s]].dtype != ORC_F64) return -1;
+    if (p->pe < 0 || p->pe > 4) return -1;
     long cap = sample_cap(p, nset);
     sample* buf = (sample*)malloc(sizeof(sample) * cap);
     pt_val* pv = (pt_val*)malloc(sizeof(pt_val) * cap);
@@ -697,7 +753,8 @@ int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const
     double* Tb = (double*)malloc(sizeof(double) * (cap + 1));
     double* suf = (double*)malloc(sizeof(double) * 7 * (cap + 1));
     long* ev = (long*)malloc(sizeof(long) * cap);
-    const double *W1 = mlp, *W2 = mlp + 176, *W3 = mlp + 448;
+    const mlp_shape sh = mlp_shape_of(p->pe);
+    const double *W1 = mlp + sh.W1, *W2 = mlp + sh.W2, *W3 = mlp + sh.W3;
     for (int q = 0; q < npix; ++q) {
         float d[3];
         long n = enumerate(blocks, nblocks, occ, v, set, nset, p, pix[2 * q], pix[2 * q + 1], buf,
@@ -745,13 +802,12 @@ int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const
         for (long s = m - 2; s >= 0; --s)
             for (int c = 0; c < 7; ++c) suf[7 * s + c] = suf[7 * (s + 1) + c] + wts[s + 1] * pv[s + 1].v[c];
         /* MLP backward */
-        double x[10];
-        for (int c = 0; c < 7; ++c) x[c] = A[c];
-        for (int c = 0; c < 3; ++c) x[7 + c] = d[c];
+        double x[MLP_MAX_IN];
+        mlp_input(A, d, p->pe, x);
         mlp_trace tr;
-        mlp_fwd(mlp, x, &tr);
+        mlp_fwd(mlp, &sh, x, &tr);
         const double* g = grad_rgb + 3 * q;
-        double dz[3], dh2[16], dh1[16], dx[10];
+        double dz[3], dh2[16], dh1[16], dx[7];
         for (int o = 0; o < 3; ++o) dz[o] = g[o] * tr.s[o] * (1.0 - tr.s[o]);
         for (int i = 0; i < 16; ++i) {
             double a = 0.0;
@@ -763,21 +819,21 @@ int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const
             for (int o = 0; o < 16; ++o) a += W2[o * 16 + i] * dh2[o];
             dh1[i] = tr.pre1[i] > 0.0 ? a : 0.0;
         }
-        for (int i = 0; i < 10; ++i) {
+        for (int i = 0; i < 7; ++i) { /* the direction inputs are constants */
             double a = 0.0;
-            for (int o = 0; o < 16; ++o) a += W1[o * 10 + i] * dh1[o];
+            for (int o = 0; o < 16; ++o) a += W1[o * sh.ni + i] * dh1[o];
             dx[i] = a;
         }
         if (grad_mlp) {
             for (int o = 0; o < 16; ++o) {
-                for (int i = 0; i < 10; ++i) grad_mlp[o * 10 + i] += dh1[o] * tr.x[i];
-                grad_mlp[160 + o] += dh1[o];
-                for (int i = 0; i < 16; ++i) grad_mlp[176 + o * 16 + i] += dh2[o] * tr.h1[i];
-                grad_mlp[432 + o] += dh2[o];
+                for (int i = 0; i < sh.ni; ++i) grad_mlp[sh.W1 + o * sh.ni + i] += dh1[o] * tr.x[i];
+                grad_mlp[sh.b1 + o] += dh1[o];
+                for (int i = 0; i < 16; ++i) grad_mlp[sh.W2 + o * 16 + i] += dh2[o] * tr.h1[i];
+                grad_mlp[sh.b2 + o] += dh2[o];
             }
             for (int o = 0; o < 3; ++o) {
-                for (int i = 0; i < 16; ++i) grad_mlp[448 + o * 16 + i] += dz[o] * tr.h2[i];
-                grad_mlp[496 + o] += dz[o];
+                for (int i = 0; i < 16; ++i) grad_mlp[sh.W3 + o * 16 + i] += dz[o] * tr.h2[i];
+                grad_mlp[sh.b3 + o] += dz[o];
             }
         }
         double u[7];
@@ -834,6 +890,8 @@ int orc_adjoint_block_mlp(const orc_block* blocks, int nblocks, const unsigned c
                           double* const* grad_plane, double* grad_mlp) {
     for (int s = 0; s < nset; ++s)
         if (blocks[set[s]].dtype != ORC_F64) return -1;
+    if (p->pe < 0 || p->pe > 4) return -1;
+    const mlp_shape sh = mlp_shape_of(p->pe);
     long cap = sample_cap(p, nset);
     sample* buf = (sample*)malloc(sizeof(sample) * cap);
     pt_val* pv = (pt_val*)malloc(sizeof(pt_val) * cap);
@@ -880,10 +938,9 @@ int orc_adjoint_block_mlp(const orc_block* blocks, int nblocks, const unsigned c
             for (int c = 0; c < 7; ++c) Ak[7 * nr + c] = A[c];
             Tk[nr] = T;
             Pk[nr] = P;
-            double x[10];
-            for (int c = 0; c < 7; ++c) x[c] = A[c];
-            for (int c = 0; c < 3; ++c) x[7 + c] = d[c];
-            mlp_fwd(mlp + 499 * (long)set[run], x, &tr[nr]);
+            double x[MLP_MAX_IN];
+            mlp_input(A, d, p->pe, x);
+            mlp_fwd(mlp + sh.n * (long)set[run], &sh, x, &tr[nr]);
             for (int c = 0; c < 3; ++c) Ck[3 * nr + c] = A[c] + tr[nr].s[c];
             P *= T;
             ++nr;
@@ -894,9 +951,9 @@ int orc_adjoint_block_mlp(const orc_block* blocks, int nblocks, const unsigned c
         const double gT = grad_trans ? grad_trans[q] : 0.0;
         double R[3] = {0, 0, 0}; /* sum over later blocks of P_k' C^k' */
         for (int k = nr - 1; k >= 0; --k) {
-            const double* W1 = mlp + 499 * (long)set[rpos[k]];
-            const double *W2 = W1 + 176, *W3 = W1 + 448;
-            double dz[3], dh2[16], dh1[16], dx[10];
+            const double* Wk = mlp + sh.n * (long)set[rpos[k]];
+            const double *W1 = Wk + sh.W1, *W2 = Wk + sh.W2, *W3 = Wk + sh.W3;
+            double dz[3], dh2[16], dh1[16], dx[7];
             for (int o = 0; o < 3; ++o) dz[o] = Pk[k] * g[o] * tr[k].s[o] * (1.0 - tr[k].s[o]);
             for (int i = 0; i < 16; ++i) {
                 double a = 0.0;
@@ -908,22 +965,22 @@ int orc_adjoint_block_mlp(const orc_block* blocks, int nblocks, const unsigned c
                 for (int o = 0; o < 16; ++o) a += W2[o * 16 + i] * dh2[o];
                 dh1[i] = tr[k].pre1[i] > 0.0 ? a : 0.0;
             }
-            for (int i = 0; i < 10; ++i) {
+            for (int i = 0; i < 7; ++i) { /* the direction inputs are constants */
                 double a = 0.0;
-                for (int o = 0; o < 16; ++o) a += W1[o * 10 + i] * dh1[o];
+                for (int o = 0; o < 16; ++o) a += W1[o * sh.ni + i] * dh1[o];
                 dx[i] = a;
             }
             if (grad_mlp) {
-                double* gm = grad_mlp + 499 * (long)set[rpos[k]];
+                double* gm = grad_mlp + sh.n * (long)set[rpos[k]];
                 for (int o = 0; o < 16; ++o) {
-                    for (int i = 0; i < 10; ++i) gm[o * 10 + i] += dh1[o] * tr[k].x[i];
-                    gm[160 + o] += dh1[o];
-                    for (int i = 0; i < 16; ++i) gm[176 + o * 16 + i] += dh2[o] * tr[k].h1[i];
-                    gm[432 + o] += dh2[o];
+                    for (int i = 0; i < sh.ni; ++i) gm[sh.W1 + o * sh.ni + i] += dh1[o] * tr[k].x[i];
+                    gm[sh.b1 + o] += dh1[o];
+                    for (int i = 0; i < 16; ++i) gm[sh.W2 + o * 16 + i] += dh2[o] * tr[k].h1[i];
+                    gm[sh.b2 + o] += dh2[o];
                 }
                 for (int o = 0; o < 3; ++o) {
-                    for (int i = 0; i < 16; ++i) gm[448 + o * 16 + i] += dz[o] * tr[k].h2[i];
-                    gm[496 + o] += dz[o];
+                    for (int i = 0; i < 16; ++i) gm[sh.W3 + o * 16 + i] += dz[o] * tr[k].h2[i];
+                    gm[sh.b3 + o] += dz[o];
                 }
             }
             double u[7];

@@ -48,6 +48,7 @@ typedef struct orc_params {
     float delta;             /* mode 1 step length */
     int max_steps;           /* mode 1 cap counted from scene entry */
     float t_min;             /* stop a ray after the first evaluated sample with T < t_min (0: off) */
+    int pe;                  /* deferred MLP input: [C_d, F, PE(d)] with L = pe frequencies (0-4) */
 } orc_params;
 
 enum {
@@ -62,6 +63,14 @@ enum {
                                 over the blocks the ray marches at least one sample in;
                                 aux = (C, 0, 0, 0, 0, T) */
 };
+
+/* positional encoding of a direction (Eq. deferred): [d, sin(2^l d), cos(2^l d) for
+ * l < L], per component; writes and returns 3 + 6L values (-1 for L outside 0-4) */
+int orc_posenc(const double* d, int L, double* out);
+
+/* parameter count of the deferred MLP over 10 + 6L inputs: W1 [16][10+6L], b1 [16],
+ * W2 [16][16], b2 [16], W3 [3][16], b3 [3] (499 for L = 0) */
+long orc_mlp_params(int L);
 
 /* occupancy bits [O][O][O] (z,y,x) of one block by the conservative max-bound rule */
 int orc_occupancy(const orc_block* b, unsigned char* out);
@@ -149,6 +158,8 @@ void orc_field(const orc_block* b, int n, const float* pts, double* raw);
 
 /* the MLP alone: x[10] -> out[3] = sigmoid(z) (before adding C_d) */
 void orc_mlp(const double* mlp, const double* x, double* out);
+/* the same with 10 + 6L inputs x = [C_d, F, PE(d)]; -1 for L outside 0-4 */
+int orc_mlp_pe(const double* mlp, int L, const double* x, double* out);
 
 #ifdef __cplusplus
 }

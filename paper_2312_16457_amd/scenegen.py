@@ -130,6 +130,7 @@ class RenderParams:
     delta: float = 1.0 / 512.0  # mode B step
     max_steps: int = 2048  # mode B cap, counted from scene entry
     t_min: float = 0.0  # early ray termination threshold on the transmittance (0: off)
+    pe_freqs: int = 0  # deferred MLP input [C_d, F, PE(d)] with this many frequencies (0-4)
 
 
 # --------------------------------------------------------------------------
@@ -325,24 +326,33 @@ def homogeneous_block(R=8, Rp=8, O=4, sigma=2.0, color=(0.2, 0.5, 0.8), feat=(0.
                     np.ones((4, NCH), np.float32), np.zeros((4, NCH), np.float32))
 
 
-def xavier_mlp(seed):
+def mlp_sizes(pe=0):
+    """(out, in) of the three layers over 10 + 6 pe inputs."""
+    return ((16, 10 + 6 * pe), (16, 16), (3, 16))
+
+
+def mlp_nparam(pe=0):
+    return sum(o * i + o for o, i in mlp_sizes(pe))
+
+
+def xavier_mlp(seed, pe=0):
     """Xavier-uniform weights a = sqrt(6/(fan_in+fan_out)), zero biases."""
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(3)[1])
     parts = []
-    for o, i in MLP_SIZES:
+    for o, i in mlp_sizes(pe):
         a = math.sqrt(6.0 / (i + o))
         parts.append(rng.uniform(-a, a, size=(o, i)).reshape(-1))
         parts.append(np.zeros(o))
     w = np.concatenate(parts).astype(np.float32)
-    assert w.size == MLP_NPARAM
+    assert w.size == mlp_nparam(pe)
     return w
 
 
-def random_mlp(seed, scale=1.0):
+def random_mlp(seed, scale=1.0, pe=0):
     """Weights and biases all drawn from U(-scale, scale) (for tests that need
     non-zero biases)."""
     rng = np.random.default_rng(seed)
-    return rng.uniform(-scale, scale, MLP_NPARAM).astype(np.float32)
+    return rng.uniform(-scale, scale, mlp_nparam(pe)).astype(np.float32)
 
 
 # --------------------------------------------------------------------------

@@ -1000,3 +1000,143 @@ def test_occupancy_pyramid_against_numpy_pooling(quad_city):
                 assert lv.sum() == 1
                 cz, cy, cx = (min(i >> l, n - 1) for i, n in zip((z, y, x), lv.shape))
                 assert lv[cz, cy, cx] == 1
+
+
+# ---------------------------------------------------------------------------
+# P21: positional encoding of the view direction in the deferred MLP
+# (Eq. deferred): [d, sin(2^l d), cos(2^l d) for l < L]
+# ---------------------------------------------------------------------------
+def test_posenc_identities_and_values():
+    """The identity part is d; every (sin, cos) pair lies on the unit circle;
+    each frequency doubles the previous one (double-angle identities, which a
+    wrong scale, a swapped sin/cos or a misplaced block breaks); the first
+    frequency is 1 (closed-form values at pi/6, pi/2, 0)."""
+    rng = np.random.default_rng(21)
+    for pe in range(5):
+        assert O.mlp_params(pe) == 499 + 96 * pe
+        for _ in range(20):
+            d = rng.standard_normal(3)
+            d /= np.linalg.norm(d)
+            g = O.posenc(d, pe)
+            assert g.size == 3 + 6 * pe
+            np.testing.assert_array_equal(g[:3], d)
+            for l in range(pe):
+                s, c = g[3 + 6 * l:6 + 6 * l], g[6 + 6 * l:9 + 6 * l]
+                np.testing.assert_allclose(s * s + c * c, 1.0, atol=1e-15)
+                if l + 1 < pe:
+                    s2, c2 = g[9 + 6 * l:12 + 6 * l], g[12 + 6 * l:15 + 6 * l]
+                    np.testing.assert_allclose(s2, 2 * s * c, atol=1e-14)
+                    np.testing.assert_allclose(c2, c * c - s * s, atol=1e-14)
+    g = O.posenc(np.array([np.pi / 6, np.pi / 2, 0.0]), 2)
+    np.testing.assert_allclose(g[3:6], [0.5, 1.0, 0.0], atol=1e-15)
+    np.testing.assert_allclose(g[6:9], [np.sqrt(3) / 2, 0.0, 1.0], atol=1e-15)
+    np.testing.assert_allclose(g[9:12], [np.sqrt(3) / 2, 0.0, 0.0], atol=1e-15)
+    with pytest.raises(ValueError):
+        O.posenc(np.zeros(3), 5)
+
+
+def test_mlp_with_posenc_against_torch():
+    import torch
+    pe = 4
+    ni = 10 + 6 * pe
+    w = sg.random_mlp(8, scale=0.5, pe=pe).astype(np.float64)
+    o1 = 16 * ni
+    net = torch.nn.Sequential(torch.nn.Linear(ni, 16), torch.nn.ReLU(), torch.nn.Linear(16, 16),
+                              torch.nn.ReLU(), torch.nn.Linear(16, 3), torch.nn.Sigmoid()).double()
+    with torch.no_grad():
+        net[0].weight.copy_(torch.tensor(w[0:o1].reshape(16, ni)))
+        net[0].bias.copy_(torch.tensor(w[o1:o1 + 16]))
+        net[2].weight.copy_(torch.tensor(w[o1 + 16:o1 + 272].reshape(16, 16)))
+        net[2].bias.copy_(torch.tensor(w[o1 + 272:o1 + 288]))
+        net[4].weight.copy_(torch.tensor(w[o1 + 288:o1 + 336].reshape(3, 16)))
+        net[4].bias.copy_(torch.tensor(w[o1 + 336:o1 + 339]))
+    rng = np.random.default_rng(1)
+    for _ in range(30):
+        x = rng.uniform(-1, 1, ni)
+        ref = net(torch.tensor(x)[None]).detach().numpy()[0]
+        np.testing.assert_allclose(O.mlp(w, x, pe), ref, atol=1e-14)
+
+
+def widened(w0, pe):
+    """The 10-input MLP w0 as an MLP over 10 + 6 pe inputs whose extra
+    first-layer columns are zero."""
+    ni = 10 + 6 * pe
+    W1 = np.zeros((16, ni))
+    W1[:, :10] = w0[:160].reshape(16, 10)
+    return np.concatenate([W1.ravel(), w0[160:]])
+
+
+@pytest.mark.parametrize("composite", [O.MERGED, O.BLOCK_MLP])
+def test_posenc_render_reduces_to_plain_direction(composite):
+    """With the encoding's first-layer columns zero, a render with PE(d)
+    equals the render with the plain direction (both composites)."""
+    scene = tiny_city(nb=2, lods=((8, 16, 4),), shift=2.0, blobs=8, seed=31)
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    v = tiny_view(10, 8)
+    p0 = sg.RenderParams(mode=1, delta=1.0 / 128, max_steps=4096)
+    p4 = sg.RenderParams(mode=1, delta=1.0 / 128, max_steps=4096, pe_freqs=4)
+    if composite == O.MERGED:
+        w0 = sg.random_mlp(3, 0.6).astype(np.float64)
+        w4 = widened(w0, 4)
+    else:
+        w0 = np.stack([sg.random_mlp(40 + k, 0.6) for k in range(ob.n)]).astype(np.float64)
+        w4 = np.stack([widened(x, 4) for x in w0])
+    a = O.render(ob, occs, v, list(range(ob.n)), p0, w0, composite=composite)
+    b = O.render(ob, occs, v, list(range(ob.n)), p4, w4, composite=composite)
+    assert np.abs(a["rgb"]).max() > 0.1
+    np.testing.assert_allclose(b["rgb"], a["rgb"], atol=1e-15)
+    w4x = w4.copy()
+    w4x.reshape(-1, w4.shape[-1])[:, 10] += 0.5  # a first sin column: the colour changes
+    c = O.render(ob, occs, v, list(range(ob.n)), p4, w4x, composite=composite)
+    assert np.abs(c["rgb"] - a["rgb"]).max() > 1e-4
+
+
+def test_adjoint_with_posenc_matches_finite_differences():
+    pe = 4
+    ni = 10 + 6 * pe
+    scene = tiny_city(nb=2, lods=((8, 16, 4),), shift=1.5, blobs=8, seed=13)
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    v = tiny_view(12, 10, eye=(1.0, -0.8, 1.1), target=(1.0, 1.0, 0.15))
+    p = sg.RenderParams(mode=1, delta=1.0 / 128, max_steps=4096, pe_freqs=pe)
+    rng = np.random.default_rng(3)
+    # kink-free: |W1 x| <= 34 * 0.1 < b1 = 4 for inputs in [-1, 1]
+    w = np.concatenate([rng.uniform(-0.1, 0.1, 16 * ni), np.full(16, 4.0), rng.uniform(-0.05, 0.05, 256),
+                        np.full(16, 7.0), rng.uniform(-0.02, 0.02, 48), rng.uniform(-0.5, 0.5, 3)])
+    setv = list(range(ob.n))
+    pix = O.pixels_of(v)
+    target = np.random.default_rng(4).uniform(0, 1, (len(pix), 3))
+
+    def loss():
+        return np.mean((O.render(ob, occs, v, setv, p, w, pix=pix)["rgb"] - target) ** 2)
+
+    r0 = O.render(ob, occs, v, setv, p, w, pix=pix)
+    g_rgb = 2 * (r0["rgb"] - target) / target.size
+    grads, gm = O.adjoint(ob, occs, v, setv, p, w, pix, g_rgb)
+    assert gm.size == O.mlp_params(pe)
+    h = 1e-3
+    # row 0 of W1 at encoding columns, then anywhere
+    picks = [int(c) for c in rng.choice(np.arange(10, ni), 8, replace=False)]
+    picks += [int(i) for i in rng.choice(gm.size, 10, replace=False)]
+    for i in picks:
+        old = w[i]
+        w[i] = old + h
+        Lp = loss()
+        w[i] = old - h
+        Lm = loss()
+        w[i] = old
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(gm[i] - fd) <= 1e-4 * abs(fd) + 1e-8, (i, gm[i], fd)
+    k = next(iter(grads))
+    g = grads[k][1][0]
+    idx = tuple(np.argwhere(np.abs(g) > 1e-3 * np.abs(g).max())[0])
+    arr = ob.f64[k][1][0]
+    old = arr[idx]
+    arr[idx] = old + h
+    Lp = loss()
+    arr[idx] = old - h
+    Lm = loss()
+    arr[idx] = old
+    fd = (Lp - Lm) / (2 * h)
+    assert abs(g[idx] - fd) <= 1e-4 * abs(fd) + 1e-9
