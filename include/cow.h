@@ -29,7 +29,8 @@
  *   (right, down, forward).  Pixel (i, j) has direction
  *   normalize(R [(i + 1/2 - cx)/fx, (j + 1/2 - cy)/fy, 1]).
  *   MLP weights: float[499] = W1[16][10], b1[16], W2[16][16], b2[16],
- *   W3[3][16], b3[3] (row-major, out x in); input x = [C_d(3), F(4), d(3)].
+ *   W3[3][16], b3[3] (row-major, out x in); input x = [C_d(3), F(4), d(3)],
+ *   or with params->pe_freqs = 4 float[883] over x = [C_d(3), F(4), PE(d)(27)].
  *
  * Memory ownership.  Every device buffer is owned by the caller.  The library
  * keeps non-owning pointers to the textures passed to cow_load_blocks until
@@ -154,6 +155,14 @@ typedef struct cow_render_params {
      * holds (C, 0, 0, 0, 0, T). */
     const float* block_mlp;
     float* grad_block_mlp;          /* cow_render_backward: device [entries][499], accumulated, or NULL */
+    /* Positional encoding of the direction input of the deferred MLPs (Eq.
+     * deferred: Phi(C_d, F, PE(d))): PE(d) = [d, sin(2^l d), cos(2^l d) for
+     * l < pe_freqs], per component, so the MLP takes 10 + 6 pe_freqs inputs and
+     * holds 499 + 96 pe_freqs weights (W1 [16][10 + 6 pe_freqs], then b1, W2,
+     * b2, W3, b3 as above); every "499" of this header then reads 883.  0 (the
+     * direction alone) or 4; 1-3 give COW_E_UNSUPPORTED, other values
+     * COW_E_INVALID. */
+    int32_t pe_freqs;
 } cow_render_params;
 
 /* Create a context bound to HIP device `device` (host state only). */

@@ -58,7 +58,8 @@ class LodPolicy(C.Structure):
 class Params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_steps", C.c_int32), ("delta", C.c_float), ("max_steps", C.c_int32),
                 ("t_min", C.c_float), ("flags", C.c_int32), ("counts", C.c_void_p), ("opacity", C.c_void_p),
-                ("opacity_weight", C.c_void_p), ("block_mlp", C.c_void_p), ("grad_block_mlp", C.c_void_p)]
+                ("opacity_weight", C.c_void_p), ("block_mlp", C.c_void_p), ("grad_block_mlp", C.c_void_p),
+                ("pe_freqs", C.c_int32)]
 
 
 _lib = None
@@ -123,7 +124,13 @@ def make_params(p, flags=0, counts=None, opacity=None, opacity_weight=None, bloc
     s.opacity_weight = None if opacity_weight is None else opacity_weight.data_ptr()
     s.block_mlp = None if block_mlp is None else block_mlp.data_ptr()
     s.grad_block_mlp = None if grad_block_mlp is None else grad_block_mlp.data_ptr()
+    s.pe_freqs = int(getattr(p, "pe_freqs", 0))
     return s
+
+
+def mlp_params(pe=0):
+    """Weights of the deferred MLP over 10 + 6 pe inputs (499 for pe = 0)."""
+    return 499 + 96 * int(pe)
 
 
 def _dims(d, res):
@@ -280,19 +287,22 @@ class Renderer:
             setattr(self, attr, cur)
         return cur
 
-    def _check_block_mlp(self, block_mlp):
+    def _check_block_mlp(self, block_mlp, pe=0):
         torch = self.torch
         if block_mlp is None:
             return None
+        n = mlp_params(pe)
         if (block_mlp.dtype != torch.float32 or block_mlp.device != self.device
-                or block_mlp.numel() != 499 * len(self.blocks)):
-            raise ValueError("block_mlp must be [loaded entries][499] float32 on the device")
+                or block_mlp.numel() != n * len(self.blocks)):
+            raise ValueError(f"block_mlp must be [loaded entries][{n}] float32 on the device")
         return block_mlp.contiguous()
 
     def render(self, views, sets, params, mlp, want_aux=True, counts=False, flags=0, out=None, opacity=False,
                block_mlp=None):
-        """block_mlp: [loaded entries][499] per-block deferred MLPs (shading
-        before the merge); mlp is then unused and may be None."""
+        """block_mlp: [loaded entries][P] per-block deferred MLPs (shading
+        before the merge); mlp is then unused and may be None.  P =
+        mlp_params(params.pe_freqs): 499, or 883 with four encoding
+        frequencies of the direction."""
         torch = self.torch
         vs = (View * len(views))(*[make_view(v) for v in views])
         cs, keep = self._sets(sets)
@@ -304,11 +314,12 @@ class Renderer:
                        counts=torch.zeros((n_pix, 2), dtype=torch.int64, device=self.device) if counts else None,
                        opacity=torch.zeros(n_pix, dtype=torch.float32, device=self.device) if opacity else None)
         ws = self._ws("render_ws", len(views), n_pix)
-        bm = self._check_block_mlp(block_mlp)
+        pe = int(getattr(params, "pe_freqs", 0))
+        bm = self._check_block_mlp(block_mlp, pe)
         p = make_params(params, flags, out.get("counts"), out.get("opacity"), block_mlp=bm)
         if bm is None and (mlp is None or mlp.dtype != torch.float32 or mlp.device != self.device
-                           or mlp.numel() != 499):
-            raise ValueError("mlp must be 499 float32 values on the device")
+                           or mlp.numel() != mlp_params(pe)):
+            raise ValueError(f"mlp must be {mlp_params(pe)} float32 values on the device")
         aux = out.get("aux")
         self._check(self.L.cow_render(self.h, vs, len(views), cs, C.byref(p), None if mlp is None else mlp.data_ptr(),
                                       out["rgb"].data_ptr(), out["trans"].data_ptr(),
@@ -340,9 +351,15 @@ class Renderer:
         ws = self._ws("bwd_ws", len(views), n_pix, backward=True)
         gg, gp = self._grad_tables(grad_grid, grad_plane)
         ow = None if opacity_weight is None else opacity_weight.contiguous()
-        bm = self._check_block_mlp(block_mlp)
-        if grad_block_mlp is not None and grad_block_mlp.numel() != 499 * len(self.blocks):
-            raise ValueError("grad_block_mlp must be [loaded entries][499]")
+        pe = int(getattr(params, "pe_freqs", 0))
+        n = mlp_params(pe)
+        bm = self._check_block_mlp(block_mlp, pe)
+        if grad_block_mlp is not None and grad_block_mlp.numel() != n * len(self.blocks):
+            raise ValueError(f"grad_block_mlp must be [loaded entries][{n}]")
+        if bm is None and mlp is not None and mlp.numel() != n:
+            raise ValueError(f"mlp must hold {n} weights")
+        if grad_mlp is not None and grad_mlp.numel() != n:
+            raise ValueError(f"grad_mlp must hold {n} values")
         p = make_params(params, flags=flags, opacity_weight=ow, block_mlp=bm, grad_block_mlp=grad_block_mlp)
         self._check(self.L.cow_render_backward(
             self.h, vs, len(views), cs, C.byref(p), None if mlp is None else mlp.data_ptr(), aux.data_ptr(),
@@ -424,8 +441,8 @@ def make_render_fn(with_opacity=False, per_block_mlp=False):
     Differentiable inputs: the MLP weights and every fp32 texture of the
     loaded blocks (grid, xy, xz, yz per entry, in load order).  Outputs rgb
     and trans, plus the per-ray opacity regulariser with with_opacity.  With
-    per_block_mlp the MLP input is [loaded entries][499], one deferred MLP
-    per block applied before the merge."""
+    per_block_mlp the MLP input is [loaded entries][P], one deferred MLP
+    per block applied before the merge (P = mlp_params(params.pe_freqs))."""
     import torch
 
     class RenderFn(torch.autograd.Function):

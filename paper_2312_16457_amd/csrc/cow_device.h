@@ -542,35 +542,53 @@ __device__ inline float alpha_of(float x) {
     return x < 0.0625f ? series : 1.0f - __expf(-x);
 }
 
-// One block's deferred shading for one lane (Eq. "deferred" per block):
-// C = C_d + sigmoid(Phi(C_d, F, d)), Phi 10 -> 16 -> 16 -> 3 with ReLU, the
-// 499 weights laid out W1[16][10], b1, W2[16][16], b2, W3[3][16], b3 and read
-// through a wave-uniform pointer (scalar loads).
-__device__ inline void block_shade(const float* w, const float A[7], const float d[3], float C[3]) {
-    float x[10], h1[16], h2[16];
+// Input of the deferred MLP (Eq. "deferred"): [C_d, F, PE(d)] with PE(d) =
+// [d, sin(2^l d), cos(2^l d) for l < L], per component; the scaled arguments
+// are exact (powers of two), sinf/cosf the accurate library versions.
+template <int L>
+__device__ inline void mlp_input(const float A[7], const float d[3], float* x) {
 #pragma unroll
     for (int c = 0; c < 7; ++c) x[c] = A[c];
 #pragma unroll
     for (int c = 0; c < 3; ++c) x[7 + c] = d[c];
 #pragma unroll
-    for (int o = 0; o < 16; ++o) {
-        float a = w[160 + o];
+    for (int l = 0; l < L; ++l)
 #pragma unroll
-        for (int i = 0; i < 10; ++i) a = fmaf(w[o * 10 + i], x[i], a);
+        for (int c = 0; c < 3; ++c) {
+            const float t = (float)(1 << l) * d[c];
+            x[10 + 6 * l + c] = sinf(t);
+            x[13 + 6 * l + c] = cosf(t);
+        }
+}
+
+// One block's deferred shading for one lane (Eq. "deferred" per block):
+// C = C_d + sigmoid(Phi(C_d, F, PE(d))), Phi NI -> 16 -> 16 -> 3 with ReLU,
+// the weights laid out as in MlpShape<L> and read through a wave-uniform
+// pointer (scalar loads).
+template <int L>
+__device__ inline void block_shade(const float* w, const float A[7], const float d[3], float C[3]) {
+    using S = MlpShape<L>;
+    float x[S::NI], h1[16], h2[16];
+    mlp_input<L>(A, d, x);
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+        float a = w[S::B1 + o];
+#pragma unroll
+        for (int i = 0; i < S::NI; ++i) a = fmaf(w[o * S::NI + i], x[i], a);
         h1[o] = fmaxf(a, 0.0f);
     }
 #pragma unroll
     for (int o = 0; o < 16; ++o) {
-        float a = w[432 + o];
+        float a = w[S::B2 + o];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) a = fmaf(w[176 + o * 16 + i], h1[i], a);
+        for (int i = 0; i < 16; ++i) a = fmaf(w[S::W2 + o * 16 + i], h1[i], a);
         h2[o] = fmaxf(a, 0.0f);
     }
 #pragma unroll
     for (int o = 0; o < 3; ++o) {
-        float a = w[496 + o];
+        float a = w[S::B3 + o];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) a = fmaf(w[448 + o * 16 + i], h2[i], a);
+        for (int i = 0; i < 16; ++i) a = fmaf(w[S::W3 + o * 16 + i], h2[i], a);
         C[o] = A[o] + sigmoidf_(a);
     }
 }
@@ -581,38 +599,38 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
-// Adjoint of block_shade for one lane: C = A + sigmoid(Phi(A, d)) weighted
-// by P in the merge, g = dL/dC of the ray.  Returns C and u = dL/dA (with
-// P folded in).  With want_gw, the gradient of the 499 weights is summed over
-// the wave and added once to gw (wave-collective: every lane calls it, an
-// inactive lane with zero weight).
-__device__ __attribute__((noinline)) void block_shade_adjoint(const float* w, const float A[7], const float d[3], float P,
-                                           const float g[3], bool active, float C[3], float u[7], bool want_gw,
-                                           __amdgpu_buffer_rsrc_t gw, int lane) {
-    float x[10], h1[16], h2[16], s[3];
-#pragma unroll
-    for (int c = 0; c < 7; ++c) x[c] = A[c];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) x[7 + c] = d[c];
+// Adjoint of block_shade for one lane: C = A + sigmoid(Phi(A, PE(d)))
+// weighted by P in the merge, g = dL/dC of the ray.  Returns C and u = dL/dA
+// (with P folded in; the direction inputs are constants).  With want_gw, the
+// gradient of the weights is summed over the wave and added once to gw
+// (wave-collective: every lane calls it, an inactive lane with zero weight).
+template <int L>
+__device__ __attribute__((noinline)) void block_shade_adjoint(const float* w, const float A[7], const float d[3],
+                                                              float P, const float g[3], bool active, float C[3],
+                                                              float u[7], bool want_gw, __amdgpu_buffer_rsrc_t gw,
+                                                              int lane) {
+    using S = MlpShape<L>;
+    float x[S::NI], h1[16], h2[16], s[3];
+    mlp_input<L>(A, d, x);
 #pragma unroll
     for (int o = 0; o < 16; ++o) {
-        float a = w[160 + o];
+        float a = w[S::B1 + o];
 #pragma unroll
-        for (int i = 0; i < 10; ++i) a = fmaf(w[o * 10 + i], x[i], a);
+        for (int i = 0; i < S::NI; ++i) a = fmaf(w[o * S::NI + i], x[i], a);
         h1[o] = fmaxf(a, 0.0f);
     }
 #pragma unroll
     for (int o = 0; o < 16; ++o) {
-        float a = w[432 + o];
+        float a = w[S::B2 + o];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) a = fmaf(w[176 + o * 16 + i], h1[i], a);
+        for (int i = 0; i < 16; ++i) a = fmaf(w[S::W2 + o * 16 + i], h1[i], a);
         h2[o] = fmaxf(a, 0.0f);
     }
 #pragma unroll
     for (int o = 0; o < 3; ++o) {
-        float a = w[496 + o];
+        float a = w[S::B3 + o];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) a = fmaf(w[448 + o * 16 + i], h2[i], a);
+        for (int i = 0; i < 16; ++i) a = fmaf(w[S::W3 + o * 16 + i], h2[i], a);
         s[o] = sigmoidf_(a);
         C[o] = A[o] + s[o];
     }
@@ -624,27 +642,30 @@ __device__ __attribute__((noinline)) void block_shade_adjoint(const float* w, co
     for (int i = 0; i < 16; ++i) {
         float a = 0.0f;
 #pragma unroll
-        for (int o = 0; o < 3; ++o) a = fmaf(w[448 + o * 16 + i], dz[o], a);
+        for (int o = 0; o < 3; ++o) a = fmaf(w[S::W3 + o * 16 + i], dz[o], a);
         dh2[i] = h2[i] > 0.0f ? a : 0.0f;
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         float a = 0.0f;
 #pragma unroll
-        for (int o = 0; o < 16; ++o) a = fmaf(w[176 + o * 16 + i], dh2[o], a);
+        for (int o = 0; o < 16; ++o) a = fmaf(w[S::W2 + o * 16 + i], dh2[o], a);
         dh1[i] = h1[i] > 0.0f ? a : 0.0f;
     }
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
         float a = c < 3 ? wP * g[c] : 0.0f;
 #pragma unroll
-        for (int o = 0; o < 16; ++o) a = fmaf(w[o * 10 + c], dh1[o], a);
+        for (int o = 0; o < 16; ++o) a = fmaf(w[o * S::NI + c], dh1[o], a);
         u[c] = a;
     }
     if (!want_gw) return;
     // weight gradient, in the weights' own layout: lane (i % 64) keeps the
     // wave sum of entry i in acc[i / 64]
-    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    constexpr int NQ = (S::N + 63) / 64;
+    float acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0f;
 #define COW_RED(idx, val)                                   \
     {                                                       \
         const float t_ = wave_sum(val);                     \
@@ -653,25 +674,25 @@ __device__ __attribute__((noinline)) void block_shade_adjoint(const float* w, co
 #pragma unroll
     for (int o = 0; o < 16; ++o) {
 #pragma unroll
-        for (int i = 0; i < 10; ++i) COW_RED(o * 10 + i, dh1[o] * x[i]);
-        COW_RED(160 + o, dh1[o]);
+        for (int i = 0; i < S::NI; ++i) COW_RED(o * S::NI + i, dh1[o] * x[i]);
+        COW_RED(S::B1 + o, dh1[o]);
     }
 #pragma unroll
     for (int o = 0; o < 16; ++o) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) COW_RED(176 + o * 16 + i, dh2[o] * h1[i]);
-        COW_RED(432 + o, dh2[o]);
+        for (int i = 0; i < 16; ++i) COW_RED(S::W2 + o * 16 + i, dh2[o] * h1[i]);
+        COW_RED(S::B2 + o, dh2[o]);
     }
 #pragma unroll
     for (int o = 0; o < 3; ++o) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) COW_RED(448 + o * 16 + i, dz[o] * h2[i]);
-        COW_RED(496 + o, dz[o]);
+        for (int i = 0; i < 16; ++i) COW_RED(S::W3 + o * 16 + i, dz[o] * h2[i]);
+        COW_RED(S::B3 + o, dz[o]);
     }
 #undef COW_RED
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-        if (q * 64 + lane < kMlpParams) __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(acc[q], gw, 4 * (q * 64 + lane), 0, 0);
+    for (int q = 0; q < NQ; ++q)
+        if (q * 64 + lane < S::N) __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(acc[q], gw, 4 * (q * 64 + lane), 0, 0);
 }
 
 // Binary entropy of a block's opacity a = 1 - Tk (Eq. "opacity loss"), with

@@ -432,7 +432,7 @@ size_t render_ws_layout(int64_t n_views, int64_t n_refs, int64_t n_pix, bool nee
         // gradient pointers (4 per entry), then shadow pointers (4 per entry)
         r.grad_ptrs = (float**)take(sizeof(float*) * 8 * (size_t)std::max<int64_t>(n_entries, 1));
         r.u = (float*)take(32 * (size_t)n_pix);
-        r.grad_mlp_scratch = (float*)take(4 * cow::kMlpParams);
+        r.grad_mlp_scratch = (float*)take(4 * cow::kMlpParamsMax);
         r.jobs = (cow::FoldJob*)take(sizeof(cow::FoldJob) * 4 * (size_t)std::max<int64_t>(n_entries, 1));
         r.shadow = (unsigned char*)take(shadow);
     }
@@ -453,6 +453,9 @@ cow_status validate_params(cow_ctx* c, const cow_render_params* p) {
         return fail(c, COW_E_INVALID, "unknown mode");
     }
     if (!(p->t_min >= 0.0f && p->t_min < 1.0f)) return fail(c, COW_E_INVALID, "t_min must be in [0, 1)");
+    if (p->pe_freqs < 0 || p->pe_freqs > 4) return fail(c, COW_E_INVALID, "pe_freqs must be in [0, 4]");
+    if (p->pe_freqs != 0 && p->pe_freqs != 4)
+        return fail(c, COW_E_UNSUPPORTED, "the deferred MLP kernels are built for 0 or 4 encoding frequencies");
     return COW_OK;
 }
 
@@ -504,6 +507,7 @@ cow::MarchArgs march_args(cow_ctx* c, const CallTables& T, const RenderWs& w,
     a.counts = p->counts;
     a.opacity = p->opacity;
     a.block_mlp = p->block_mlp;
+    a.pe = p->pe_freqs;
     a.rgb = nullptr;
     a.work_counter = w.counter;
     a.persistent = c->cfg.persistent;
@@ -1096,6 +1100,7 @@ static cow_status render_impl(cow_ctx* c, const cow_view* views, int n_views, co
     m.aux = aux_out;
     m.rgb = rgb;
     m.trans = trans;
+    m.pe = p->pe_freqs;
     const bool per_block = (p->flags & COW_F_PER_BLOCK) != 0;
     if (!per_block) a.persistent = c->cfg.persistent || (p->flags & COW_F_PERSISTENT) ? 1 : 0;
     c->have_fwd = c->timing && !(p->flags & COW_F_GRAPH) && !per_block;
@@ -1195,6 +1200,7 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     mb.grad_rgb = grad_rgb;
     mb.u = w.u;
     mb.grad_mlp = grad_mlp ? grad_mlp : w.grad_mlp_scratch;
+    mb.pe = p->pe_freqs;
     if (!p->block_mlp) HIP_TRY(c, cow::launch_mlp_bwd(mb, s));  // per-block MLPs: adjoint inside the march
     cow::BwdArgs ba{};
     ba.m = march_args(c, T, w, p, COW_F32, const_cast<float*>(aux), nullptr);

@@ -10,7 +10,17 @@
 namespace cow {
 
 constexpr int kNch = 8;
-constexpr int kMlpParams = 499;
+constexpr int kMlpParams = 499;  // deferred MLP over 10 inputs
+// Deferred MLP over [C_d, F, PE(d)] with L frequencies of positional encoding
+// (L = 0: the direction alone): 10 + 6L inputs, weights W1 [16][NI], b1 [16],
+// W2 [16][16], b2 [16], W3 [3][16], b3 [3].
+template <int L>
+struct MlpShape {
+    static constexpr int NI = 10 + 6 * L, W1 = 0, B1 = 16 * NI, W2 = B1 + 16, B2 = W2 + 256, W3 = B2 + 16,
+                         B3 = W3 + 48, N = B3 + 3;
+};
+constexpr int kMlpParamsMax = MlpShape<4>::N;  // 883
+inline constexpr int mlp_params(int L) { return 499 + 96 * L; }
 // largest camera-anchored step index; t_k = (k + 1/2) delta is exact in fp32
 // below 2^23
 constexpr int32_t kMaxStep = (1 << 23) - 2;
@@ -69,7 +79,8 @@ struct MarchArgs {
     float* trans;              // [P]
     int64_t* counts;           // [P][2] or null
     float* opacity;            // [P] per-ray block-opacity entropy, or null
-    const float* block_mlp;    // [entries][499] per-block deferred MLPs, or null (one MLP after the merge)
+    const float* block_mlp;    // [entries][mlp_params(pe)] per-block deferred MLPs, or null (one MLP after the merge)
+    int32_t pe;                // positional-encoding frequencies of the deferred MLPs' direction input (0 or 4)
     float* rgb;                // [P][3], written by the march when block_mlp is set
     int32_t* work_counter;     // persistent mode: one counter per XCD (8 ints)
     int32_t persistent;
@@ -81,10 +92,11 @@ struct MlpArgs {
     const DevView* views;
     int32_t n_views;
     int64_t n_pix;
-    const float* mlp;
+    const float* mlp;          // [mlp_params(pe)]
     const float* aux;
     float* rgb;
     float* trans;
+    int32_t pe;                // positional-encoding frequencies (0 or 4)
 };
 
 struct MlpBwdArgs {
@@ -95,7 +107,8 @@ struct MlpBwdArgs {
     const float* aux;
     const float* grad_rgb;
     float* u;                  // [P][8]: dL/d(C_d, F) in 0..6
-    float* grad_mlp;           // [499], accumulated
+    float* grad_mlp;           // [mlp_params(pe)], accumulated
+    int32_t pe;                // positional-encoding frequencies (0 or 4)
 };
 
 struct BwdArgs {
@@ -104,7 +117,7 @@ struct BwdArgs {
     const float* grad_trans;   // [P] or null
     const float* w_opacity;    // [P] dL/d(per-ray opacity entropy), or null
     const float* grad_rgb;     // [P][3], read directly with per-block MLPs (m.block_mlp)
-    float* grad_block_mlp;     // [entries][499], accumulated, or null
+    float* grad_block_mlp;     // [entries][mlp_params(pe)], accumulated, or null
     float* const* grad_grid;   // device array of per-entry pointers
     float* const* grad_plane;  // device array, 3 per entry
     // Odd-pair gradients: a texel pair (p, p + 1) with p odd straddles two

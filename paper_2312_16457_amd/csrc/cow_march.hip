@@ -8,7 +8,9 @@
 
 namespace cow {
 
-template <int MODE, int DT, bool SPARSE>
+// PE: positional-encoding frequencies of the per-block MLPs' direction input
+// (a kernel of its own, so the plain kernels carry none of its code)
+template <int MODE, int DT, bool SPARSE, int PE = 0>
 __device__ __attribute__((always_inline)) inline void march_packet(const MarchArgs& a, const DevView* V, int tile,
                                                                    int lane) {
     ViewU v;
@@ -56,7 +58,7 @@ __device__ __attribute__((always_inline)) inline void march_packet(const MarchAr
             // ray marches adds its colour C^k under the prefix transmittance
             if (n_march > marched_before) {
                 float Ck[3];
-                block_shade(ufp(a.block_mlp) + (size_t)e * kMlpParams, Ak, r.d, Ck);
+                block_shade<PE>(ufp(a.block_mlp) + (size_t)e * MlpShape<PE>::N, Ak, r.d, Ck);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) A[c] = fmaf(T, Ck[c], A[c]);
             }
@@ -89,7 +91,7 @@ __device__ __attribute__((always_inline)) inline void march_packet(const MarchAr
 // All blocks of one launch share a texture dtype (checked on the host).  The
 // uint8 kernel runs four waves per SIMD; the fp32 one keeps its 40 texel
 // loads (160 registers) in flight with two.
-template <int MODE, int DT, bool SPARSE>
+template <int MODE, int DT, bool SPARSE, int PE = 0>
 __device__ inline void march_fwd_body(const MarchArgs& a) {
     const int lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
@@ -115,7 +117,7 @@ __device__ inline void march_fwd_body(const MarchArgs& a) {
             V = find_view_by_tile(a.views, a.n_views, p);
             tile = p - ufl(V->tile_begin);
         }
-        march_packet<MODE, DT, SPARSE>(a, V, tile, lane);
+        march_packet<MODE, DT, SPARSE, PE>(a, V, tile, lane);
         if (!a.persistent) return;
     }
 }
@@ -128,6 +130,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void m
 template <int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void march_fwd_f32_kernel(MarchArgs a) {
     march_fwd_body<MODE, 1, false>(a);
+}
+
+// per-block deferred MLPs over [C_d, F, PE(d)] with four frequencies
+template <int MODE, int DT, bool SPARSE>
+__global__ __launch_bounds__(256) void march_fwd_pe_kernel(MarchArgs a) {
+    march_fwd_body<MODE, DT, SPARSE, 4>(a);
 }
 
 hipError_t launch_march(const MarchArgs& a, int waves, hipStream_t s) {
@@ -143,6 +151,27 @@ hipError_t launch_march(const MarchArgs& a, int waves, hipStream_t s) {
         grid = dim3((a.total_tiles + waves - 1) / waves);
     }
     const int dt = a.blocks_dtype;
+    if (a.block_mlp && a.pe == 4) {
+#define COW_LAUNCH_PE(M, D, S) hipLaunchKernelGGL((march_fwd_pe_kernel<M, D, S>), grid, block, 0, s, a)
+        if (dt == 1) {
+            if (a.mode == 1)
+                COW_LAUNCH_PE(1, 1, false);
+            else
+                COW_LAUNCH_PE(0, 1, false);
+        } else if (a.mode == 1) {
+            if (a.use_sparse)
+                COW_LAUNCH_PE(1, 0, true);
+            else
+                COW_LAUNCH_PE(1, 0, false);
+        } else {
+            if (a.use_sparse)
+                COW_LAUNCH_PE(0, 0, true);
+            else
+                COW_LAUNCH_PE(0, 0, false);
+        }
+#undef COW_LAUNCH_PE
+        return hipGetLastError();
+    }
 #define COW_LAUNCH(M, S) hipLaunchKernelGGL((march_fwd_kernel<M, S>), grid, block, 0, s, a)
     if (dt == 1) {
         if (a.mode == 1)

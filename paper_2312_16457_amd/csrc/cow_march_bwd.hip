@@ -173,11 +173,16 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
             for (int c = 0; c < 7; ++c) Af[c] = 0.0f;
             march_block<1, MODE, false, false>(a, b, r, sp, T_blk, Af, Tkf, ne, nm);
             float Ck[3];
-            __amdgpu_buffer_rsrc_t gw = tex_rsrc(ba.grad_block_mlp ? ufp(ba.grad_block_mlp) + (size_t)e * kMlpParams
+            const int np = mlp_params(a.pe);  // weights per block: 499, or 883 with four PE frequencies
+            __amdgpu_buffer_rsrc_t gw = tex_rsrc(ba.grad_block_mlp ? ufp(ba.grad_block_mlp) + (size_t)e * np
                                                                    : nullptr,
-                                                 4u * kMlpParams);
-            block_shade_adjoint(ufp(a.block_mlp) + (size_t)e * kMlpParams, Af, r.d, T_blk, g, nm > 0, Ck, u,
-                                ba.grad_block_mlp != nullptr, gw, lane);
+                                                 4u * (uint32_t)np);
+            if (a.pe == 4)
+                block_shade_adjoint<4>(ufp(a.block_mlp) + (size_t)e * np, Af, r.d, T_blk, g, nm > 0, Ck, u,
+                                       ba.grad_block_mlp != nullptr, gw, lane);
+            else
+                block_shade_adjoint<0>(ufp(a.block_mlp) + (size_t)e * np, Af, r.d, T_blk, g, nm > 0, Ck, u,
+                                       ba.grad_block_mlp != nullptr, gw, lane);
             float R = gT * TN;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {

@@ -8,7 +8,7 @@
 namespace cow {
 
 // ---------------------------------------------------------------------------
-// deferred MLP on MFMA: x = [C_d, F, d] -> 16 -> 16 -> 3, C = C_d + sigmoid(z)
+// deferred MLP on MFMA: x = [C_d, F, PE(d)] -> 16 -> 16 -> 3, C = C_d + sigmoid(z)
 // ---------------------------------------------------------------------------
 //
 // v_mfma_f32_16x16x4f32 computes D[16][16] += A[16][4] B[4][16]; lane l
@@ -17,33 +17,40 @@ namespace cow {
 // columns; for layers 2 and 3 the K index of (step s, lane group g) is 4g+s,
 // so the B operand is exactly the lane's own previous-layer output.
 
+template <int L>
 __global__ __launch_bounds__(256) void mlp_fwd_kernel(MlpArgs a) {
-    __shared__ float W[kMlpParams + 1];
-    __shared__ float X[4][64][11];
-    for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) W[i] = a.mlp[i];
+    using S = MlpShape<L>;
+    constexpr int NI = S::NI, KS = (NI + 3) / 4;  // first-layer inputs, MFMA steps over them
+    __shared__ float W[S::N + 1];
+    __shared__ float X[4][64][NI + 1];
+    for (int i = threadIdx.x; i < S::N; i += blockDim.x) W[i] = a.mlp[i];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64;
     const int64_t pix = base + lane;
-    float x[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    float x[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) x[k] = 0.0f;
     if (pix < a.n_pix) {
         const float4 lo = reinterpret_cast<const float4*>(a.aux)[2 * pix];
         const float4 hi = reinterpret_cast<const float4*>(a.aux)[2 * pix + 1];
-        x[0] = lo.x, x[1] = lo.y, x[2] = lo.z, x[3] = lo.w, x[4] = hi.x, x[5] = hi.y, x[6] = hi.z;
-        pixel_direction(a.views, a.n_views, pix, x + 7);
+        const float A[7] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z};
+        float d[3];
+        pixel_direction(a.views, a.n_views, pix, d);
+        mlp_input<L>(A, d, x);
     }
 #pragma unroll
-    for (int k = 0; k < 10; ++k) X[wave][lane][k] = x[k];
+    for (int k = 0; k < NI; ++k) X[wave][lane][k] = x[k];
     __syncthreads();
-    const float *W1 = W, *b1 = W + 160, *W2 = W + 176, *b2 = W + 432, *W3 = W + 448, *b3 = W + 496;
+    const float *W1 = W, *b1 = W + S::B1, *W2 = W + S::W2, *b2 = W + S::B2, *W3 = W + S::W3, *b3 = W + S::B3;
     const int j = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         floatx4 h = {b1[4 * g + 0], b1[4 * g + 1], b1[4 * g + 2], b1[4 * g + 3]};
 #pragma unroll
-        for (int s = 0; s < 3; ++s) {
+        for (int s = 0; s < KS; ++s) {
             const int k = g + 4 * s;
-            const float av = k < 10 ? W1[j * 10 + k] : 0.0f;
-            const float bv = k < 10 ? X[wave][16 * t + j][k] : 0.0f;
+            const float av = k < NI ? W1[j * NI + k] : 0.0f;
+            const float bv = k < NI ? X[wave][16 * t + j][k] : 0.0f;
             h = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, h, 0, 0, 0);
         }
         floatx4 h2 = {b2[4 * g + 0], b2[4 * g + 1], b2[4 * g + 2], b2[4 * g + 3]};
@@ -70,7 +77,10 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(MlpArgs a) {
 hipError_t launch_mlp(const MlpArgs& a, hipStream_t s) {
     if (a.n_pix <= 0) return hipSuccess;
     const int64_t blocks = (a.n_pix + 255) / 256;
-    hipLaunchKernelGGL(mlp_fwd_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    if (a.pe == 4)
+        hipLaunchKernelGGL(mlp_fwd_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(mlp_fwd_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -86,32 +96,42 @@ hipError_t launch_mlp(const MlpArgs& a, hipStream_t s) {
 // K = 4 pixels per instruction and keeps the accumulators across its
 // grid-stride loop; one set of atomics per workgroup at the end.
 
+template <int L>
 __global__ __launch_bounds__(256) void mlp_bwd_kernel(MlpBwdArgs a) {
-    __shared__ float W[kMlpParams + 1];
+    using S = MlpShape<L>;
+    constexpr int NI = S::NI;
+    constexpr int XT = (NI + 1 + 15) / 16, XW = 16 * XT;  // column tiles of [x, 1] for dW1 and db1
+    __shared__ float W[S::N + 1];
     __shared__ float S_dh1[4][64][17];
-    __shared__ float S_x[4][64][17];
+    __shared__ float S_x[4][64][XW + 1];
     __shared__ float S_dh2[4][64][17];
     __shared__ float S_h1[4][64][17];
     __shared__ float S_dz[4][64][4];
     __shared__ float S_h2[4][64][17];
-    __shared__ float S_red[4][kMlpParams + 1];
-    for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) W[i] = a.mlp[i];
+    __shared__ float S_red[4][S::N + 1];
+    for (int i = threadIdx.x; i < S::N; i += blockDim.x) W[i] = a.mlp[i];
     __syncthreads();
-    const float *W1 = W, *b1 = W + 160, *W2 = W + 176, *b2 = W + 432, *W3 = W + 448, *b3 = W + 496;
+    const float *W1 = W, *b1 = W + S::B1, *W2 = W + S::W2, *b2 = W + S::B2, *W3 = W + S::W3, *b3 = W + S::B3;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j = lane & 15, g = lane >> 4;
-    floatx4 acc1 = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0}, acc3 = {0, 0, 0, 0};
+    floatx4 acc1[XT], acc2 = {0, 0, 0, 0}, acc3 = {0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < XT; ++t) acc1[t] = floatx4{0, 0, 0, 0};
     float bias_acc = 0.0f;  // lanes 0..15: db2[lane]; lanes 16..18: db3[lane-16]
     const int64_t n_chunks = (a.n_pix + 63) / 64;
     for (int64_t chunk = (int64_t)blockIdx.x * 4 + wave; chunk < n_chunks; chunk += (int64_t)gridDim.x * 4) {
         const int64_t pix = chunk * 64 + lane;
         const bool act = pix < a.n_pix;
-        float x[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0}, gr[3] = {0, 0, 0};
+        float x[NI], gr[3] = {0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < NI; ++k) x[k] = 0.0f;
         if (act) {
             const float4 lo = reinterpret_cast<const float4*>(a.aux)[2 * pix];
             const float4 hi = reinterpret_cast<const float4*>(a.aux)[2 * pix + 1];
-            x[0] = lo.x, x[1] = lo.y, x[2] = lo.z, x[3] = lo.w, x[4] = hi.x, x[5] = hi.y, x[6] = hi.z;
-            pixel_direction(a.views, a.n_views, pix, x + 7);
+            const float A[7] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z};
+            float d[3];
+            pixel_direction(a.views, a.n_views, pix, d);
+            mlp_input<L>(A, d, x);
             gr[0] = a.grad_rgb[3 * pix], gr[1] = a.grad_rgb[3 * pix + 1], gr[2] = a.grad_rgb[3 * pix + 2];
         }
         float pre1[16], h1[16], pre2[16], h2[16], dz[3], dh2[16], dh1[16];
@@ -119,7 +139,7 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(MlpBwdArgs a) {
         for (int o = 0; o < 16; ++o) {
             float s = b1[o];
 #pragma unroll
-            for (int i = 0; i < 10; ++i) s = fmaf(W1[o * 10 + i], x[i], s);
+            for (int i = 0; i < NI; ++i) s = fmaf(W1[o * NI + i], x[i], s);
             pre1[o] = s;
             h1[o] = fmaxf(s, 0.0f);
         }
@@ -156,10 +176,10 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(MlpBwdArgs a) {
         if (act) {
             float u[8];
 #pragma unroll
-            for (int i = 0; i < 7; ++i) {
+            for (int i = 0; i < 7; ++i) {  // the direction inputs are constants
                 float s = 0.0f;
                 #pragma unroll
-                for (int o = 0; o < 16; ++o) s = fmaf(W1[o * 10 + i], dh1[o], s);
+                for (int o = 0; o < 16; ++o) s = fmaf(W1[o * NI + i], dh1[o], s);
                 u[i] = s + (i < 3 ? gr[i] : 0.0f);
             }
             u[7] = 0.0f;
@@ -174,8 +194,9 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(MlpBwdArgs a) {
             S_dh2[wave][lane][i] = dh2[i];
             S_h1[wave][lane][i] = h1[i];
             S_h2[wave][lane][i] = h2[i];
-            S_x[wave][lane][i] = i < 10 ? x[i] : (i == 10 && act ? 1.0f : 0.0f);
         }
+#pragma unroll
+        for (int i = 0; i < XW; ++i) S_x[wave][lane][i] = i < NI ? x[i] : (i == NI && act ? 1.0f : 0.0f);
 #pragma unroll
         for (int i = 0; i < 3; ++i) S_dz[wave][lane][i] = dz[i];
         S_dz[wave][lane][3] = 0.0f;
@@ -183,7 +204,10 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(MlpBwdArgs a) {
         __builtin_amdgcn_wave_barrier();
         for (int s = 0; s < 16; ++s) {
             const int p = 4 * s + g;  // pixel of this lane's K slot
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(S_dh1[wave][p][j], S_x[wave][p][j], acc1, 0, 0, 0);
+            const float dh1p = S_dh1[wave][p][j];
+#pragma unroll
+            for (int t = 0; t < XT; ++t)
+                acc1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(dh1p, S_x[wave][p][16 * t + j], acc1[t], 0, 0, 0);
             acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(S_dh2[wave][p][j], S_h1[wave][p][j], acc2, 0, 0, 0);
             const float a3 = j < 3 ? S_dz[wave][p][j] : 0.0f;
             acc3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, S_h2[wave][p][j], acc3, 0, 0, 0);
@@ -204,15 +228,19 @@ __global__ __launch_bounds__(256) void mlp_bwd_kernel(MlpBwdArgs a) {
     float* red = S_red[wave];
     for (int r = 0; r < 4; ++r) {
         const int i = 4 * g + r;
-        if (j < 10) red[i * 10 + j] = acc1[r];
-        if (j == 10) red[160 + i] = acc1[r];
-        red[176 + i * 16 + j] = acc2[r];
-        if (i < 3) red[448 + i * 16 + j] = acc3[r];
+#pragma unroll
+        for (int t = 0; t < XT; ++t) {
+            const int col = 16 * t + j;
+            if (col < NI) red[i * NI + col] = acc1[t][r];
+            if (col == NI) red[S::B1 + i] = acc1[t][r];
+        }
+        red[S::W2 + i * 16 + j] = acc2[r];
+        if (i < 3) red[S::W3 + i * 16 + j] = acc3[r];
     }
-    if (lane < 16) red[432 + lane] = bias_acc;
-    if (lane >= 16 && lane < 19) red[496 + lane - 16] = bias_acc;
+    if (lane < 16) red[S::B2 + lane] = bias_acc;
+    if (lane >= 16 && lane < 19) red[S::B3 + lane - 16] = bias_acc;
     __syncthreads();
-    for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) {
+    for (int i = threadIdx.x; i < S::N; i += blockDim.x) {
         const float s = ((S_red[0][i] + S_red[1][i]) + S_red[2][i]) + S_red[3][i];
         atomicAdd(a.grad_mlp + i, s);
     }
@@ -223,7 +251,10 @@ hipError_t launch_mlp_bwd(const MlpBwdArgs& a, hipStream_t s) {
     const int64_t chunks = (a.n_pix + 63) / 64;
     int64_t groups = (chunks + 3) / 4;
     if (groups > 1024) groups = 1024;
-    hipLaunchKernelGGL(mlp_bwd_kernel, dim3((unsigned)groups), dim3(256), 0, s, a);
+    if (a.pe == 4)
+        hipLaunchKernelGGL(mlp_bwd_kernel<4>, dim3((unsigned)groups), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(mlp_bwd_kernel<0>, dim3((unsigned)groups), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
