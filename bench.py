@@ -260,6 +260,16 @@ def forward_variants(torch, sg, r, view, sel, params, mlp, base_ms, reps=5):
     out = r.render([view], [sel], params, mlp, want_aux=False)
     ms = _timed(torch, lambda: r.render([view], [sel], params, mlp, out=out, flags=F_FLAT_OCC), reps)
     res["one_step_empty_space"] = {"ms": round(ms, 3)}
+    # the deferred MLPs over the positional encoding of the direction (Eq. deferred, 4 frequencies)
+    p_pe = replace(params, pe_freqs=4)
+    mlp_pe = torch.tensor(sg.xavier_mlp(1, pe=4), device="cuda")
+    out = r.render([view], [sel], p_pe, mlp_pe, want_aux=False)
+    ms = _timed(torch, lambda: r.render([view], [sel], p_pe, mlp_pe, out=out), reps)
+    res["mlp_with_posenc"] = {"ms": round(ms, 3)}
+    bm_pe = torch.tensor(np.stack([sg.xavier_mlp(100 + k, pe=4) for k in range(len(r.blocks))]), device="cuda")
+    out = r.render([view], [sel], p_pe, None, want_aux=False, block_mlp=bm_pe)
+    ms = _timed(torch, lambda: r.render([view], [sel], p_pe, None, out=out, block_mlp=bm_pe), reps)
+    res["per_block_mlps_with_posenc"] = {"ms": round(ms, 3)}
     log("forward variants done")
     return res
 
