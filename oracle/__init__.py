@@ -40,6 +40,7 @@ class _Block(C.Structure):
         ("g8", C.c_void_p), ("p8", C.c_void_p * 3),
         ("gf", C.c_void_p), ("pf", C.c_void_p * 3),
         ("scale", (C.c_float * 8) * 4), ("offset", (C.c_float * 8) * 4),
+        ("contracted", C.c_int),
     ]
 
 
@@ -53,7 +54,7 @@ class _View(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("mode", C.c_int), ("n_steps", C.c_int), ("delta", C.c_float), ("max_steps", C.c_int),
-                ("t_min", C.c_float), ("pe", C.c_int)]
+                ("t_min", C.c_float), ("pe", C.c_int), ("ext_delta", C.c_float), ("ext_max_steps", C.c_int)]
 
 
 _lib = None
@@ -95,6 +96,10 @@ def lib():
         L.orc_mlp_params.argtypes = [C.c_int]
         L.orc_mlp_params.restype = C.c_long
         L.orc_posenc.argtypes = [vp, C.c_int, vp]
+        L.orc_contract.argtypes = [vp, vp]
+        L.orc_contract.restype = None
+        L.orc_local_q.argtypes = [C.POINTER(_Block), vp, vp]
+        L.orc_local_q.restype = C.c_float
         L.orc_field.argtypes = [C.POINTER(_Block), C.c_int, vp, vp]
         _lib = L
     return _lib
@@ -119,12 +124,30 @@ def make_params(p):
     s.mode, s.n_steps, s.delta, s.max_steps = int(p.mode), int(p.n_steps), float(p.delta), int(p.max_steps)
     s.t_min = float(getattr(p, "t_min", 0.0))
     s.pe = int(getattr(p, "pe_freqs", 0))
+    s.ext_delta = float(getattr(p, "ext_delta", 0.0))
+    s.ext_max_steps = int(getattr(p, "ext_max_steps", 0))
     return s
 
 
 def mlp_params(pe=0):
     """Weights of the deferred MLP over 10 + 6 pe inputs (499 for pe = 0)."""
     return int(lib().orc_mlp_params(int(pe)))
+
+
+def contract(x):
+    """MERF's contraction (max norm) of one point, fp64: identity inside the
+    unit cube, everything else into the cube of radius 2."""
+    y = np.zeros(3, np.float64)
+    lib().orc_contract(_ptr(np.ascontiguousarray(x, np.float64)), _ptr(y))
+    return y
+
+
+def local_q(ob, k, p):
+    """fp32 texture-space coordinate of world point p in block k (the
+    decision sequence) and the max norm of its box-normalised coordinate."""
+    q = np.zeros(3, np.float32)
+    m = lib().orc_local_q(C.byref(ob.arr[k]), _ptr(np.ascontiguousarray(p, np.float32)), _ptr(q))
+    return q, float(m)
 
 
 def posenc(d, pe):
@@ -155,6 +178,7 @@ class OracleScene:
             s.lo[:] = [float(x) for x in b.aabb_min]
             s.hi[:] = [float(x) for x in b.aabb_max]
             s.R, s.Rp, s.O = int(b.grid_res), int(b.plane_res), int(b.occ_res)
+            s.contracted = int(bool(getattr(b, "contracted", False)))
             for t in range(4):
                 s.scale[t][:] = [float(x) for x in b.scale[t]]
                 s.offset[t][:] = [float(x) for x in b.offset[t]]

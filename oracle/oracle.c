@@ -76,11 +76,60 @@ static int slab32(const float o[3], const float d[3], const float lo[3], const f
  * times the block's extent on that axis (a whole power of two). */
 static int dim(const orc_block* b, int res, int c) { return res * (int)(b->hi[c] - b->lo[c]); }
 
+/* Contraction of the implementation details (MERF's, in the max norm):
+ * identity inside the unit cube; outside it a coordinate below the norm is
+ * divided by the norm and the one(s) attaining it become (2 - 1/|x_j|)
+ * sign(x_j), so all of space lands in the cube of radius 2.  The condition
+ * "x_j equals the norm" is read on |x_j| (the sign factor shows negative
+ * coordinates are meant too). */
+void orc_contract(const double* x, double* y) {
+    double m = 0.0;
+    for (int c = 0; c < 3; ++c) m = fabs(x[c]) > m ? fabs(x[c]) : m;
+    for (int c = 0; c < 3; ++c) {
+        if (m <= 1.0)
+            y[c] = x[c];
+        else if (fabs(x[c]) == m)
+            y[c] = (2.0 - 1.0 / fabs(x[c])) * (x[c] / fabs(x[c]));
+        else
+            y[c] = x[c] / m;
+    }
+}
+
+/* fp32 decision sequence of the contraction for the box [lo, hi): the
+ * box-normalised coordinate x = (p - centre) (2 / extent) is contracted and
+ * mapped to texture space, q = (contract(x) + 2) (extent / 4), so the block's
+ * texels cover the contracted cube and the box itself its middle half per
+ * axis.  Returns max_c |x_c|. */
+static float contract32(const float lo[3], const float hi[3], const float p[3], float q[3]) {
+    float x[3], m = 0.0f;
+    for (int c = 0; c < 3; ++c) {
+        float ext = hi[c] - lo[c];
+        float ctr = lo[c] + 0.5f * ext;
+        x[c] = (p[c] - ctr) * (2.0f / ext);
+        float a = fabsf(x[c]);
+        if (a > m) m = a;
+    }
+    for (int c = 0; c < 3; ++c) {
+        float y = x[c];
+        if (m > 1.0f) y = fabsf(x[c]) == m ? copysignf(2.0f - 1.0f / m, x[c]) : x[c] / m;
+        q[c] = (y + 2.0f) * (0.25f * (hi[c] - lo[c]));
+    }
+    return m;
+}
+
+/* local (texture-space) coordinate of a sample in block b: p - lo, or the
+ * contracted coordinate for a contracted block */
+float orc_local_q(const orc_block* b, const float* p, float* q) {
+    if (b->contracted) return contract32(b->lo, b->hi, p, q);
+    for (int c = 0; c < 3; ++c) q[c] = p[c] - b->lo[c];
+    return 0.0f;
+}
+
 /* occupancy cell of a sample in block b (fp32 local coordinate) */
 static int occ_cell(const orc_block* b, const float p[3], float q[3]) {
     int cell[3];
+    orc_local_q(b, p, q);
     for (int c = 0; c < 3; ++c) {
-        q[c] = p[c] - b->lo[c];
         float s = q[c] * (float)b->O;
         int k = (int)floorf(s);
         if (k < 0) k = 0;
@@ -278,6 +327,85 @@ static int cmp_tin(const void* a, const void* b) {
     return x[1] < y[1] ? -1 : (x[1] > y[1]);
 }
 
+/* The ray's interval inside the footprint's column (x and y only; the
+ * slab32 sequence on two axes, t clamped at 0). */
+static int slab_xy(const float o[3], const float d[3], const float lo[3], const float hi[3], float* tn,
+                   float* tf) {
+    float t0 = 0.0f, t1 = INFINITY;
+    for (int c = 0; c < 2; ++c) {
+        if (d[c] == 0.0f) {
+            if (o[c] < lo[c] || o[c] > hi[c]) return 0;
+            continue;
+        }
+        float inv = 1.0f / d[c];
+        float a = (lo[c] - o[c]) * inv;
+        float b = (hi[c] - o[c]) * inv;
+        float mn = a < b ? a : b, mx = a < b ? b : a;
+        if (mn > t0) t0 = mn;
+        if (mx < t1) t1 = mx;
+    }
+    *tn = t0;
+    *tf = t1;
+    return t0 < t1;
+}
+
+/* One exterior segment of a ray, [t_start, t_end), outside the footprint
+ * [X0, X1) x [Y0, Y1) of the scene.  A point there belongs to the block
+ * column nearest in the max norm (Eq. "blocks"); where several tie, to the
+ * one the clamped unit cell names: (clamp(floor(x - X0)), clamp(floor(y - Y0))).
+ * Steps are uniform in contracted space to first order: from t the next
+ * sample lies ext_delta m^2 further, m = max(1, |x|_inf) of the point's
+ * coordinate normalised to its owner cell (unit in x and y, the scene's
+ * height in z), whose contraction has radial derivative 1/m^2.  The first
+ * sample sits half a base step in; a sample is taken (listed) when its point
+ * lies outside the footprint, its owner is a contracted block of the view's
+ * set and m <= 1 / ext_delta; the post-exit segment (post = 1) ends at the
+ * first point beyond that far limit, and every segment after ext_max_steps
+ * steps. */
+static long ext_phase(const orc_block* blocks, const unsigned char* const* occ, const int* set, int nset,
+                      const orc_params* p, const float o[3], const float d[3], const float slo[3],
+                      const float shi[3], float t_start, float t_end, int post, sample* out, long n, long cap) {
+    const float nxm = (shi[0] - slo[0]) - 1.0f, nym = (shi[1] - slo[1]) - 1.0f;
+    const float far = 1.0f / p->ext_delta;
+    float t = t_start + 0.5f * p->ext_delta;
+    for (int st = 0; st < p->ext_max_steps; ++st) {
+        if (!post && !(t < t_end)) break;
+        float pt[3];
+        position(o, d, t, pt);
+        float fx = floorf(pt[0] - slo[0]), fy = floorf(pt[1] - slo[1]);
+        fx = fx < 0.0f ? 0.0f : (fx > nxm ? nxm : fx);
+        fy = fy < 0.0f ? 0.0f : (fy > nym ? nym : fy);
+        const float clo[3] = {slo[0] + fx, slo[1] + fy, slo[2]};
+        const float chi[3] = {clo[0] + 1.0f, clo[1] + 1.0f, shi[2]};
+        float q[3];
+        float m = contract32(clo, chi, pt, q);
+        if (m < 1.0f) m = 1.0f;
+        const float w = (p->ext_delta * m) * m;
+        if (m > far) {
+            if (post) break;
+        } else if (!(slo[0] <= pt[0] && pt[0] < shi[0] && slo[1] <= pt[1] && pt[1] < shi[1])) {
+            int s_hit = -1;
+            for (int s = 0; s < nset; ++s) {
+                const orc_block* b = &blocks[set[s]];
+                if (b->contracted && b->lo[0] == clo[0] && b->lo[1] == clo[1]) {
+                    s_hit = s;
+                    break;
+                }
+            }
+            if (s_hit >= 0 && n < cap) {
+                sample* sm = &out[n++];
+                sm->set_pos = s_hit;
+                sm->k = -1;
+                sm->delta = w;
+                int cell = occ_cell(&blocks[set[s_hit]], pt, sm->q);
+                sm->occupied = occ[set[s_hit]][cell] != 0;
+            }
+        }
+        t = t + w;
+    }
+    return n;
+}
+
 /* Enumerate the samples of one ray in compositing order (front to back).
  * Returns the number written (<= cap).  Empty samples (no block in the set,
  * or outside every block) are not listed; unoccupied ones are, with
@@ -335,56 +463,72 @@ static long enumerate(const orc_block* blocks, int nblocks, const unsigned char*
             if (blocks[b].lo[c] < slo[c]) slo[c] = blocks[b].lo[c];
             if (blocks[b].hi[c] > shi[c]) shi[c] = blocks[b].hi[c];
         }
-    /* scan bound from an fp64 slab test of the box grown by 1e-3 */
-    double tfar = INFINITY, tnear = 0.0;
-    for (int c = 0; c < 3; ++c) {
-        double lo = (double)slo[c] - 1e-3, hi = (double)shi[c] + 1e-3, oc = o[c], dc = d[c];
-        if (dc == 0.0) {
-            if (oc < lo || oc > hi) return 0;
-            continue;
-        }
-        double a = (lo - oc) / dc, bb = (hi - oc) / dc;
-        double mn = a < bb ? a : bb, mx = a < bb ? bb : a;
-        if (mn > tnear) tnear = mn;
-        if (mx < tfar) tfar = mx;
+    /* exterior of the footprint (contracted boundary blocks): the part of the
+     * ray before it enters the footprint's column, then, after the blocks,
+     * the part after it leaves it */
+    int ext = 0;
+    if (p->ext_delta > 0.0f && p->ext_max_steps > 0)
+        for (int s = 0; s < nset; ++s) ext |= blocks[set[s]].contracted;
+    float fin = INFINITY, fout = INFINITY;
+    if (ext) {
+        if (!slab_xy(o, d, slo, shi, &fin, &fout)) fin = fout = INFINITY;
+        n = ext_phase(blocks, occ, set, nset, p, o, d, slo, shi, 0.0f, fin, 0, out, n, cap);
     }
-    if (!(tnear <= tfar)) return 0;
-    long kmax = (long)ceil(tfar / (double)p->delta) + 8;
-    long k0 = -1;
-    for (long k = 0; k <= kmax; ++k) {
-        float t = ((float)k + 0.5f) * p->delta;
-        float pt[3];
-        position(o, d, t, pt);
-        if (inside(pt, slo, shi)) {
-            k0 = k;
-            break;
+    do {
+        /* scan bound from an fp64 slab test of the box grown by 1e-3 */
+        double tfar = INFINITY, tnear = 0.0;
+        int miss = 0;
+        for (int c = 0; c < 3; ++c) {
+            double lo = (double)slo[c] - 1e-3, hi = (double)shi[c] + 1e-3, oc = o[c], dc = d[c];
+            if (dc == 0.0) {
+                if (oc < lo || oc > hi) miss = 1;
+                continue;
+            }
+            double a = (lo - oc) / dc, bb = (hi - oc) / dc;
+            double mn = a < bb ? a : bb, mx = a < bb ? bb : a;
+            if (mn > tnear) tnear = mn;
+            if (mx < tfar) tfar = mx;
         }
-    }
-    if (k0 < 0) return 0;
-    for (long k = k0; k < k0 + p->max_steps; ++k) {
-        float t = ((float)k + 0.5f) * p->delta;
-        float pt[3];
-        position(o, d, t, pt);
-        int s_hit = -1;
-        for (int s = 0; s < nset; ++s)
-            if (inside(pt, blocks[set[s]].lo, blocks[set[s]].hi)) {
-                s_hit = s;
+        if (miss || !(tnear <= tfar)) break;
+        long kmax = (long)ceil(tfar / (double)p->delta) + 8;
+        long k0 = -1;
+        for (long k = 0; k <= kmax; ++k) {
+            float t = ((float)k + 0.5f) * p->delta;
+            float pt[3];
+            position(o, d, t, pt);
+            if (inside(pt, slo, shi)) {
+                k0 = k;
                 break;
             }
-        if (s_hit < 0) continue;
-        if (n >= cap) break;
-        sample* sm = &out[n++];
-        sm->set_pos = s_hit;
-        sm->k = k;
-        sm->delta = p->delta;
-        int cell = occ_cell(&blocks[set[s_hit]], pt, sm->q);
-        sm->occupied = occ[set[s_hit]][cell] != 0;
-    }
+        }
+        if (k0 < 0) break;
+        for (long k = k0; k < k0 + p->max_steps; ++k) {
+            float t = ((float)k + 0.5f) * p->delta;
+            float pt[3];
+            position(o, d, t, pt);
+            int s_hit = -1;
+            for (int s = 0; s < nset; ++s)
+                if (inside(pt, blocks[set[s]].lo, blocks[set[s]].hi)) {
+                    s_hit = s;
+                    break;
+                }
+            if (s_hit < 0) continue;
+            if (n >= cap) break;
+            sample* sm = &out[n++];
+            sm->set_pos = s_hit;
+            sm->k = k;
+            sm->delta = p->delta;
+            int cell = occ_cell(&blocks[set[s_hit]], pt, sm->q);
+            sm->occupied = occ[set[s_hit]][cell] != 0;
+        }
+    } while (0);
+    if (ext && fout < INFINITY) n = ext_phase(blocks, occ, set, nset, p, o, d, slo, shi, fout, INFINITY, 1, out, n, cap);
     return n;
 }
 
 static long sample_cap(const orc_params* p, int nset) {
-    return p->mode == 0 ? (long)p->n_steps * (nset > 0 ? nset : 1) : (long)p->max_steps;
+    if (p->mode == 0) return (long)p->n_steps * (nset > 0 ? nset : 1);
+    return (long)p->max_steps + (p->ext_delta > 0.0f && p->ext_max_steps > 0 ? 2L * p->ext_max_steps : 0L);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -662,12 +806,31 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
     *ook = ordered;
 }
 
+/* Contracted blocks are boundary columns: one unit in x and y, the scene's
+ * full height in z (the exterior's owner cells have that shape). */
+static int contracted_ok(const orc_block* blocks, int nblocks, const orc_params* p) {
+    if (!(p->ext_delta >= 0.0f && p->ext_delta < INFINITY) || p->ext_max_steps < 0) return 0;
+    float zlo = INFINITY, zhi = -INFINITY;
+    for (int b = 0; b < nblocks; ++b) {
+        if (blocks[b].lo[2] < zlo) zlo = blocks[b].lo[2];
+        if (blocks[b].hi[2] > zhi) zhi = blocks[b].hi[2];
+    }
+    for (int b = 0; b < nblocks; ++b) {
+        const orc_block* k = &blocks[b];
+        if (k->contracted && (k->hi[0] - k->lo[0] != 1.0f || k->hi[1] - k->lo[1] != 1.0f || k->lo[2] != zlo ||
+                              k->hi[2] != zhi))
+            return 0;
+    }
+    return 1;
+}
+
 int orc_render(const orc_block* blocks, int nblocks, const unsigned char* const* occ,
                const orc_view* v, const int* set, int nset, const orc_params* p,
                const double* mlp, const int* pix, int npix, int composite,
                double* rgb, double* trans, double* aux, long long* n_eval,
                long long* n_march, int* order_ok, int nthreads) {
     if (p->pe < 0 || p->pe > 4) return -1;
+    if (!contracted_ok(blocks, nblocks, p)) return -1;
     long cap = sample_cap(p, nset);
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();

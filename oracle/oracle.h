@@ -33,6 +33,8 @@ typedef struct orc_block {
     const double* pf[3];
     float scale[4][8];       /* uint8 decode q*scale+offset (tex 0 grid, 1 xy, 2 xz, 3 yz) */
     float offset[4][8];
+    int contracted;          /* boundary block whose representation covers the contracted cube
+                                [-2,2]^3 of its box-normalised coordinate (MERF contraction) */
 } orc_block;
 
 typedef struct orc_view {
@@ -49,6 +51,8 @@ typedef struct orc_params {
     int max_steps;           /* mode 1 cap counted from scene entry */
     float t_min;             /* stop a ray after the first evaluated sample with T < t_min (0: off) */
     int pe;                  /* deferred MLP input: [C_d, F, PE(d)] with L = pe frequencies (0-4) */
+    float ext_delta;         /* mode 1, contracted blocks: exterior step scale (0: no exterior) */
+    int ext_max_steps;       /* exterior steps per ray segment outside the footprint */
 } orc_params;
 
 enum {
@@ -71,6 +75,12 @@ int orc_posenc(const double* d, int L, double* out);
 /* parameter count of the deferred MLP over 10 + 6L inputs: W1 [16][10+6L], b1 [16],
  * W2 [16][16], b2 [16], W3 [3][16], b3 [3] (499 for L = 0) */
 long orc_mlp_params(int L);
+/* contraction of the implementation details (MERF): x -> contract(x), fp64 */
+void orc_contract(const double* x, double* y);
+/* fp32 texture-space coordinate of world point p in block b (decision
+ * sequence; contracted blocks map through the contraction); returns the max
+ * norm of the box-normalised coordinate (0 for plain blocks) */
+float orc_local_q(const orc_block* b, const float* p, float* q);
 
 /* occupancy bits [O][O][O] (z,y,x) of one block by the conservative max-bound rule */
 int orc_occupancy(const orc_block* b, unsigned char* out);

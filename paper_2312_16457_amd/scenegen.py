@@ -64,6 +64,7 @@ class BlockLod:
     planes: list  # 3 x [Rp][Rp][8]
     scale: np.ndarray  # float32[4][8]
     offset: np.ndarray  # float32[4][8]
+    contracted: bool = False  # boundary block whose textures cover the contracted cube
 
     def decoded(self):
         """Float32 texture values (grid, [xy, xz, yz]) after the uint8 decode."""
@@ -131,6 +132,8 @@ class RenderParams:
     max_steps: int = 2048  # mode B cap, counted from scene entry
     t_min: float = 0.0  # early ray termination threshold on the transmittance (0: off)
     pe_freqs: int = 0  # deferred MLP input [C_d, F, PE(d)] with this many frequencies (0-4)
+    ext_delta: float = 0.0  # exterior step scale of contracted boundary blocks (0: no exterior)
+    ext_max_steps: int = 0  # exterior steps per segment
 
 
 # --------------------------------------------------------------------------
@@ -532,3 +535,21 @@ def c5_views(seed=4, n=8, W=800, H=800, center=(2.0, 2.0)):
         yaw = math.atan2(center[1] + dy - eye[1], center[0] + dx - eye[0])
         views.append(pinhole(W, H, eye, look_rotation(yaw_pitch_forward(yaw, pd))))
     return views
+
+
+def contract_boundary(blocks):
+    """The same entries with every unit block on the footprint's edge marked
+    contracted (the implementation details' boundary blocks): their textures
+    are then read as covering the contracted cube [-2, 2]^3 of the box, so
+    the outer part of each texture holds the exterior (synthetic content,
+    as for every block here)."""
+    import dataclasses
+    lo = np.min([b.aabb_min for b in blocks], axis=0)
+    hi = np.max([b.aabb_max for b in blocks], axis=0)
+    out = []
+    for b in blocks:
+        ext = np.asarray(b.aabb_max) - np.asarray(b.aabb_min)
+        edge = (b.aabb_min[0] == lo[0] or b.aabb_max[0] == hi[0] or b.aabb_min[1] == lo[1] or b.aabb_max[1] == hi[1])
+        unit = ext[0] == 1 and ext[1] == 1 and b.aabb_min[2] == lo[2] and b.aabb_max[2] == hi[2]
+        out.append(dataclasses.replace(b, contracted=bool(edge and unit)))
+    return out

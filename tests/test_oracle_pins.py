@@ -11,6 +11,7 @@ Parity unpinned: only the absolute appearance of the synthetic scenes (their
 recipe is a reading of the workload description, not a value the paper
 prints).
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -1140,3 +1141,105 @@ def test_adjoint_with_posenc_matches_finite_differences():
     arr[idx] = old
     fd = (Lp - Lm) / (2 * h)
     assert abs(g[idx] - fd) <= 1e-4 * abs(fd) + 1e-9
+
+
+# ---------------------------------------------------------------------------
+# P22: contraction of boundary blocks (implementation details, the MERF
+# contraction equation) and the exterior they own
+# ---------------------------------------------------------------------------
+def test_contraction_closed_forms():
+    """Values the contraction equation fixes: identity inside the unit cube;
+    outside, the coordinate(s) attaining the max norm m go to (2 - 1/m) with
+    their sign and the others are divided by m; odd symmetry; all of space
+    lands strictly inside the cube of radius 2; continuous across |x| = 1."""
+    assert np.allclose(O.contract([0.5, -1.0, 0.2]), [0.5, -1.0, 0.2], atol=0, rtol=0)
+    assert np.allclose(O.contract([3.0, 0.0, 0.0]), [5.0 / 3.0, 0.0, 0.0], rtol=1e-15)
+    assert np.allclose(O.contract([3.0, 1.5, -0.5]), [5.0 / 3.0, 0.5, -1.0 / 6.0], rtol=1e-15)
+    assert np.allclose(O.contract([-4.0, 4.0, 1.0]), [-1.75, 1.75, 0.25], rtol=1e-15)
+    rng = np.random.default_rng(22)
+    for _ in range(200):
+        x = rng.normal(size=3) * np.exp(rng.uniform(-2, 6))
+        y = O.contract(x)
+        m = np.abs(x).max()
+        assert np.allclose(O.contract(-x), -y, rtol=0, atol=0)
+        assert np.abs(y).max() < 2.0
+        if m > 1:
+            # a ray from the origin: the contracted radius is 2 - 1/m, the direction kept
+            assert np.isclose(np.abs(y).max(), 2.0 - 1.0 / m, rtol=1e-14)
+            j = np.argmax(np.abs(x))
+            k = [c for c in range(3) if c != j]
+            assert np.allclose(y[k] / y[j], x[k] / x[j] * (1.0 / m) / (2.0 - 1.0 / m) * m, rtol=1e-12)
+    u = np.array([1.0, 0.3, -0.7])
+    for eps in (1e-6, 1e-9):
+        assert np.allclose(O.contract(u * (1 + eps)), u, atol=3 * eps)
+
+
+def test_contracted_local_coordinate_is_the_definition_in_fp32():
+    """The fp32 decision sequence of a contracted block's texture coordinate
+    agrees with q = (contract((p - centre) 2/extent) + 2) extent/4 in fp64 to
+    a few fp32 ulps; a plain block's is p - lo exactly."""
+    b = sg.homogeneous_block(origin=(2, -1, 0))
+    cb = sg.contract_boundary([b])[0]
+    assert cb.contracted
+    ob = O.OracleScene([b, dataclasses.replace(cb, block_id=1)])
+    rng = np.random.default_rng(23)
+    ctr = np.array([2.5, -0.5, 0.5])
+    for _ in range(300):
+        p = (ctr + rng.normal(size=3) * np.exp(rng.uniform(-3, 4))).astype(np.float32)
+        q0, m0 = O.local_q(ob, 0, p)
+        assert np.array_equal(q0, (p - np.float32([2, -1, 0])).astype(np.float32)) and m0 == 0.0
+        q1, m1 = O.local_q(ob, 1, p)
+        x = (p.astype(np.float64) - ctr) * 2.0
+        assert np.isclose(m1, np.abs(x).max(), rtol=1e-6)
+        assert np.allclose(q1, (O.contract(x) + 2.0) / 4.0, atol=4e-7)
+
+
+def _shell_block(sig_shell, sig_box, col_shell, col_box, R=8):
+    """A contracted unit block whose texels in the outer shell (contracted
+    |y|_inf > 1) hold one constant field and those of the box another."""
+    b = sg.contract_boundary([sg.homogeneous_block(R=R, Rp=8, O=4)])[0]
+    y = (np.arange(R) + 0.5) / R * 4.0 - 2.0
+    shell = np.maximum(np.maximum(np.abs(y)[:, None, None], np.abs(y)[None, :, None]), np.abs(y)[None, None, :]) > 1
+    g = b.grid.copy()
+    logit = lambda v: math.log(v / (1.0 - v))
+    for mask, s, col in ((shell, sig_shell, col_shell), (~shell, sig_box, col_box)):
+        g[mask, 0] = math.log(s)
+        for i, c in enumerate(col):
+            g[mask, 1 + i] = logit(c)
+    return dataclasses.replace(b, grid=g)
+
+
+def test_exterior_is_composited_before_and_after_the_city():
+    """Camera outside the footprint looking at the block: an opaque shell in
+    front hides the box, so the accumulated colour is the shell's own colour
+    (one sample with alpha = 1).  Looking away, the ray never enters the
+    footprint and sees only the exterior: for a homogeneous medium the
+    accumulated colour is (1 - T) times the medium's colour (the telescoping
+    sum of T_i alpha_i), with 0 < T < 1."""
+    shell_col, box_col = (0.9, 0.2, 0.1), (0.1, 0.7, 0.3)
+    blk = _shell_block(1e4, 5.0, shell_col, box_col)
+    ob = O.OracleScene([blk])
+    occs = [O.occupancy(ob, 0)]
+    w = sg.random_mlp(3, 0.5)
+    p = sg.RenderParams(mode=1, ext_delta=1.0 / 64, ext_max_steps=4096)
+    inward = sg.pinhole(3, 3, (2.5, 0.5, 0.5), sg.look_rotation([-1.0, 0.0, 0.0]), 20.0)
+    ref = O.render(ob, occs, inward, [0], p, w, pix=np.array([[1, 1]], np.int32))
+    assert ref["trans"][0] < 1e-12
+    assert np.allclose(ref["aux"][0, :3], shell_col, atol=1e-9)
+    assert ref["n_march"][0] >= 1
+    # no exterior sampling: the box's colour shows instead
+    p0 = sg.RenderParams(mode=1)
+    ref0 = O.render(ob, occs, inward, [0], p0, w, pix=np.array([[1, 1]], np.int32))
+    assert not np.allclose(ref0["aux"][0, :3], shell_col, atol=1e-2)
+    thin = _shell_block(0.05, 5.0, shell_col, box_col)
+    ob2 = O.OracleScene([thin])
+    outward = sg.pinhole(3, 3, (2.5, 0.5, 0.5), sg.look_rotation([1.0, 0.0, 0.0]), 20.0)
+    ref2 = O.render(ob2, [O.occupancy(ob2, 0)], outward, [0], p, w, pix=np.array([[1, 1]], np.int32))
+    T = ref2["trans"][0]
+    assert 0.0 < T < 1.0
+    assert np.allclose(ref2["aux"][0, :3], (1.0 - T) * np.array(shell_col), rtol=1e-9)
+    # a plain (uncontracted) block owns no exterior: nothing is sampled
+    plain = dataclasses.replace(thin, contracted=False)
+    ob3 = O.OracleScene([plain])
+    ref3 = O.render(ob3, [O.occupancy(ob3, 0)], outward, [0], p, w, pix=np.array([[1, 1]], np.int32))
+    assert ref3["trans"][0] == 1.0 and ref3["n_march"][0] == 0
