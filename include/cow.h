@@ -104,7 +104,19 @@ typedef struct cow_block_desc {
     const void* plane[3];           /* device, xy: [P_y][P_x][8], xz: [P_z][P_x][8], yz: [P_z][P_y][8] */
     float scale[4][8];              /* uint8 decode; ignored for COW_F32 */
     float offset[4][8];
+    /* COW_BLOCK_CONTRACTED: a boundary block with an unbounded representation
+     * (implementation details, the contraction equation, after MERF).  Its
+     * textures and occupancy cover the contracted cube [-2, 2]^3 of the
+     * box-normalised coordinate x = (p - centre) (2 / extent), mapped to the
+     * block's texture space by q = (contract(x) + 2) (extent / 4): the box
+     * fills the middle half of every axis, the rest of space the outer
+     * shell.  Such a block must be one unit wide in x and y and span the full
+     * height of the loaded scene (it owns the space beyond its outer faces,
+     * see cow_render_params.ext_delta).  0 for a plain block. */
+    int32_t flags;
 } cow_block_desc;
+
+enum { COW_BLOCK_CONTRACTED = 1 };
 
 typedef struct cow_view {
     int32_t W, H;                   /* image size */
@@ -163,6 +175,26 @@ typedef struct cow_render_params {
      * direction alone) or 4; 1-3 give COW_E_UNSUPPORTED, other values
      * COW_E_INVALID. */
     int32_t pe_freqs;
+    /* Exterior of contracted boundary blocks (grid mode).  Outside the
+     * footprint of the loaded scene (the union of the blocks' x-y extents) a
+     * point belongs to the block column nearest in the max norm (Eq. "blocks"),
+     * ties going to the one named by clamping the point's unit cell into the
+     * footprint; when that block is contracted and in the view's set, the
+     * ray samples it there.  Two segments per ray: from the camera to the
+     * footprint's column, and from the column's exit on.  Steps start half of
+     * ext_delta in and grow as ext_delta m^2, m = max(1, |x|_inf) of the
+     * point's coordinate normalised to its owner cell, which keeps them about
+     * uniform in contracted space; a point with m > 1 / ext_delta is beyond
+     * the far limit (the segment after the column ends there); each segment
+     * takes at most ext_max_steps steps.  Exterior samples composite in ray
+     * order with the blocks (before them, then after them) and count in
+     * counts like any sample.  ext_delta = 0 (or ext_max_steps = 0): no
+     * exterior sampling.  A call whose sets hold a contracted block must use
+     * grid mode, one MLP after the merge, no opacity output and no per-block
+     * launches (else COW_E_UNSUPPORTED); cow_render_backward and
+     * cow_sparsity reject contracted blocks with COW_E_UNSUPPORTED. */
+    float ext_delta;
+    int32_t ext_max_steps;
 } cow_render_params;
 
 /* Create a context bound to HIP device `device` (host state only). */

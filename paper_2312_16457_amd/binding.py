@@ -15,6 +15,7 @@ COW_OK, COW_E_INVALID, COW_E_NOT_LOADED, COW_E_WORKSPACE, COW_E_UNSUPPORTED, COW
 COW_U8, COW_F32 = 0, 1
 MODE_CHORD, MODE_GRID = 0, 1
 F_NONE, F_GRAPH, F_PERSISTENT, F_PER_BLOCK, F_SPARSE, F_FLAT_OCC = 0, 1, 2, 4, 8, 16
+BLOCK_CONTRACTED = 1  # cow_block_desc.flags: boundary block over the contracted cube
 
 EXPORTS = ["cow_create", "cow_destroy", "cow_last_error", "cow_query_workspace", "cow_load_blocks",
            "cow_get_occupancy", "cow_get_occupancy_level", "cow_select_blocks", "cow_query_bricks", "cow_pack_bricks", "cow_render",
@@ -33,7 +34,7 @@ class BlockDesc(C.Structure):
                 ("aabb_min", C.c_float * 3), ("aabb_max", C.c_float * 3),
                 ("grid_res", C.c_int32), ("plane_res", C.c_int32), ("occ_res", C.c_int32),
                 ("dtype", C.c_int32), ("grid", C.c_void_p), ("plane", C.c_void_p * 3),
-                ("scale", (C.c_float * 8) * 4), ("offset", (C.c_float * 8) * 4)]
+                ("scale", (C.c_float * 8) * 4), ("offset", (C.c_float * 8) * 4), ("flags", C.c_int32)]
 
 
 class View(C.Structure):
@@ -59,7 +60,7 @@ class Params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_steps", C.c_int32), ("delta", C.c_float), ("max_steps", C.c_int32),
                 ("t_min", C.c_float), ("flags", C.c_int32), ("counts", C.c_void_p), ("opacity", C.c_void_p),
                 ("opacity_weight", C.c_void_p), ("block_mlp", C.c_void_p), ("grad_block_mlp", C.c_void_p),
-                ("pe_freqs", C.c_int32)]
+                ("pe_freqs", C.c_int32), ("ext_delta", C.c_float), ("ext_max_steps", C.c_int32)]
 
 
 _lib = None
@@ -125,6 +126,8 @@ def make_params(p, flags=0, counts=None, opacity=None, opacity_weight=None, bloc
     s.block_mlp = None if block_mlp is None else block_mlp.data_ptr()
     s.grad_block_mlp = None if grad_block_mlp is None else grad_block_mlp.data_ptr()
     s.pe_freqs = int(getattr(p, "pe_freqs", 0))
+    s.ext_delta = float(getattr(p, "ext_delta", 0.0))
+    s.ext_max_steps = int(getattr(p, "ext_max_steps", 0))
     return s
 
 
@@ -194,6 +197,8 @@ class Renderer:
             d.aabb_max[:] = [float(x) for x in get("aabb_max")]
             d.grid_res, d.plane_res, d.occ_res = int(get("grid_res")), int(get("plane_res")), int(get("occ_res"))
             d.dtype = int(get("dtype"))
+            contracted = b.get("contracted", False) if isinstance(b, dict) else getattr(b, "contracted", False)
+            d.flags = BLOCK_CONTRACTED if contracted else 0
             g = get("grid")
             ps = list(get("planes"))
             if not torch.is_tensor(g):

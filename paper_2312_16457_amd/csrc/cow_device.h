@@ -226,6 +226,7 @@ struct BlockU {
     int lgx, lgy, lpx, lpy, lox, loy;  // log2 of the row lengths used in indexing
     float lo[3], hi[3];
     const float* dec;               // uint8 decode: DevBlock::dsc, then dosum (40 floats)
+    int contracted;                 // texture space is the contracted cube of the box
 };
 
 __device__ inline uint32_t grid_texels(const BlockU& b) { return (uint32_t)b.gd[0] * b.gd[1] * b.gd[2]; }
@@ -258,6 +259,30 @@ __device__ inline void load_block(const DevBlock* B, BlockU& b) {
     // offsets formed at load (DevBlock::dsc, dosum); 2^24 undoes the fp16-subnormal
     // byte unpacking (bytes_even_h2, bytes_odd_h2)
     b.dec = ufp(&B->dsc[0][0]);
+    b.contracted = ufl(B->contracted);
+}
+
+// Contraction (implementation details, after MERF) of the box [lo, hi) in
+// fp32, the decision sequence: x = (p - centre) (2 / extent); inside the unit
+// cube x itself, else x_c / m for a coordinate below m = |x|_inf and
+// (2 - 1/m) sign(x_c) for one attaining it; texture space q = (y + 2) (extent / 4).
+// Returns m.
+__device__ inline float contract_q(const float lo[3], const float hi[3], const float p[3], float q[3]) {
+    float x[3], m = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float ext = hi[c] - lo[c];
+        const float ctr = lo[c] + 0.5f * ext;
+        x[c] = (p[c] - ctr) * (2.0f / ext);
+        m = fmaxf(m, fabsf(x[c]));
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float y = x[c];
+        if (m > 1.0f) y = fabsf(x[c]) == m ? copysignf(2.0f - 1.0f / m, x[c]) : x[c] / m;
+        q[c] = (y + 2.0f) * (0.25f * (hi[c] - lo[c]));
+    }
+    return m;
 }
 
 __device__ inline int occ_cell(const BlockU& b, const float q[3], int cell[3]) {
@@ -918,18 +943,24 @@ __device__ inline int level_exit(const BlockU& b, const Ray& r, float delta, int
 // grid mode an empty cell is left in one jump to the first sample outside the
 // coarsest empty pyramid cell around it (unless flat); the jumped samples count
 // as marched, as a one-step march would count them.
-template <int MODE>
+// CT: the launch may hold contracted blocks, whose samples map to texture
+// space through the contraction and step one at a time.
+template <int MODE, bool CT = false>
 __device__ inline bool next_occupied(const BlockU& b, const Ray& r, const Span& sp, int kb, float delta, bool flat,
                                      int& k, float q[3], int& cell, int& cur_cell, bool& cur_occ, int64_t& marched) {
+    if (CT && b.contracted) flat = true;
     while (k < kb) {
         const float t = MODE == 1 ? step_t(k, delta) : sp.tn + ((float)k + 0.5f) * sp.dr;
         bool in = true;
+        float pw[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float p = coord(r.o[c], t, r.d[c]);
             if (MODE == 0) in = in && (b.lo[c] <= p && p < b.hi[c]);
             q[c] = p - b.lo[c];
+            pw[c] = p;
         }
+        if (CT && b.contracted) contract_q(b.lo, b.hi, pw, q);
         if (in) {
             ++marched;
             int ci[3];
@@ -962,7 +993,7 @@ __device__ inline bool next_occupied(const BlockU& b, const Ray& r, const Span& 
 // JUMPS = false steps one sample at a time whatever the launch asks (the
 // adjoint: its register budget has no room for the jump code, and its
 // per-sample atomics dwarf the cost of an empty step).
-template <int DT, int MODE, bool SPARSE, bool JUMPS = true>
+template <int DT, int MODE, bool SPARSE, bool JUMPS = true, bool CT = false>
 __device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ray& r, const Span& sp,
                                    float T_before, float Ak[7], float& Tk, int64_t& n_eval, int64_t& n_march) {
     int k = sp.ka, kb = sp.kb;
@@ -972,8 +1003,8 @@ __device__ inline void march_block(const MarchArgs& a, const BlockU& b, const Ra
         float q[3];
         int cell = 0;
         const bool have =
-            next_occupied<MODE>(b, r, sp, kb, sp.delta, !JUMPS || a.flat_occ != 0, k, q, cell, cur_cell, cur_occ,
-                                n_march);
+            next_occupied<MODE, CT>(b, r, sp, kb, sp.delta, !JUMPS || a.flat_occ != 0, k, q, cell, cur_cell, cur_occ,
+                                    n_march);
         if (!__any(have)) break;
         if (have) {
             float raw[8], v[7], sigma;

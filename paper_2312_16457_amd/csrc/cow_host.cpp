@@ -182,6 +182,9 @@ cow_status validate_desc(cow_ctx* c, const cow_block_desc& d) {
     if (grid_texels(d) * tex >= (1ull << 31) || plane_texels(d, 0) * tex >= (1ull << 31) ||
         plane_texels(d, 1) * tex >= (1ull << 31) || plane_texels(d, 2) * tex >= (1ull << 31))
         return fail(c, COW_E_INVALID, who + "texture larger than 2 GiB");
+    if (d.flags & ~COW_BLOCK_CONTRACTED) return fail(c, COW_E_INVALID, who + "unknown block flags");
+    if ((d.flags & COW_BLOCK_CONTRACTED) && (d.aabb_max[0] - d.aabb_min[0] != 1.0f || d.aabb_max[1] - d.aabb_min[1] != 1.0f))
+        return fail(c, COW_E_INVALID, who + "a contracted block must be one unit wide in x and y");
     if (!d.grid || !d.plane[0] || !d.plane[1] || !d.plane[2])
         return fail(c, COW_E_INVALID, who + "null texture pointer");
     if (d.dtype == COW_U8)
@@ -456,7 +459,16 @@ cow_status validate_params(cow_ctx* c, const cow_render_params* p) {
     if (p->pe_freqs < 0 || p->pe_freqs > 4) return fail(c, COW_E_INVALID, "pe_freqs must be in [0, 4]");
     if (p->pe_freqs != 0 && p->pe_freqs != 4)
         return fail(c, COW_E_UNSUPPORTED, "the deferred MLP kernels are built for 0 or 4 encoding frequencies");
+    if (!(p->ext_delta >= 0.0f && p->ext_delta <= 1.0f)) return fail(c, COW_E_INVALID, "ext_delta must be in [0, 1]");
+    if (p->ext_max_steps < 0 || p->ext_max_steps > (1 << 16)) return fail(c, COW_E_INVALID, "ext_max_steps out of range");
     return COW_OK;
+}
+
+// whether a call's sets hold a contracted block
+bool any_contracted(const cow_ctx* c, const std::vector<int32_t>& refs) {
+    for (int32_t e : refs)
+        if (c->entries[e].desc.flags & COW_BLOCK_CONTRACTED) return true;
+    return false;
 }
 
 cow_status check_dtypes(cow_ctx* c, const CallTables& T, int* dtype) {
@@ -513,6 +525,9 @@ cow::MarchArgs march_args(cow_ctx* c, const CallTables& T, const RenderWs& w,
     a.persistent = c->cfg.persistent;
     a.only_view = -1;
     a.only_set_pos = -1;
+    a.contract = any_contracted(c, T.refs) ? 1 : 0;
+    a.ext_delta = a.contract && p->ext_max_steps > 0 ? p->ext_delta : 0.0f;
+    a.ext_max_steps = a.ext_delta > 0.0f ? p->ext_max_steps : 0;
     return a;
 }
 
@@ -823,6 +838,13 @@ cow_status cow_load_blocks(cow_ctx* c, const cow_block_desc* blocks, int n, void
                 if (overlap) return fail(c, COW_E_INVALID, "blocks overlap");
             }
         }
+    {  // contracted blocks span the scene's full height
+        float zlo = INFINITY, zhi = -INFINITY;
+        for (int i = 0; i < n; ++i) zlo = std::min(zlo, blocks[i].aabb_min[2]), zhi = std::max(zhi, blocks[i].aabb_max[2]);
+        for (int i = 0; i < n; ++i)
+            if ((blocks[i].flags & COW_BLOCK_CONTRACTED) && (blocks[i].aabb_min[2] != zlo || blocks[i].aabb_max[2] != zhi))
+                return fail(c, COW_E_INVALID, "a contracted block must span the scene's full height");
+    }
     std::vector<size_t> occ_off, slot_off;
     const size_t need = load_layout(blocks, n, &occ_off, &slot_off);
     if (!load_ws || load_bytes < need) return fail(c, COW_E_WORKSPACE, "load workspace too small");
@@ -858,6 +880,7 @@ cow_status cow_load_blocks(cow_ctx* c, const cow_block_desc* blocks, int n, void
         dims(blocks[i], d.Rp, d.pd);
         dims(blocks[i], d.O, d.od);
         d.dtype = blocks[i].dtype;
+        d.contracted = (blocks[i].flags & COW_BLOCK_CONTRACTED) ? 1 : 0;
         if (d.dtype != c->dtype) c->mixed_dtype = true;
         d.grid = blocks[i].grid;
         for (int k = 0; k < 3; ++k) d.plane[k] = blocks[i].plane[k];
@@ -1081,6 +1104,9 @@ static cow_status render_impl(cow_ctx* c, const cow_view* views, int n_views, co
     st = check_dtypes(c, T, &dtype);
     if (st != COW_OK) return st;
     if ((p->flags & COW_F_SPARSE) && dtype != COW_U8) return fail(c, COW_E_UNSUPPORTED, "sparse bricks hold uint8 grids only");
+    if (any_contracted(c, T.refs) && (p->mode != COW_MODE_GRID || p->block_mlp || p->opacity || (p->flags & COW_F_PER_BLOCK)))
+        return fail(c, COW_E_UNSUPPORTED, "contracted blocks render in grid mode with one MLP after the merge, "
+                                          "without opacity output or per-block launches");
     RenderWs w;
     const size_t need = render_ws_layout(n_views, (int64_t)T.refs.size(), T.n_pix, aux == nullptr, false,
                                          (int64_t)c->entries.size(), 0, (unsigned char*)ws, &w);
@@ -1136,6 +1162,7 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     for (int32_t e : T.refs)
         if (c->entries[e].desc.dtype != COW_F32)
             return fail(c, COW_E_UNSUPPORTED, "backward needs float32 textures");
+    if (any_contracted(c, T.refs)) return fail(c, COW_E_UNSUPPORTED, "the adjoint does not march contracted blocks");
     RenderWs w;
     std::vector<cow_block_desc> descs;
     for (const Entry& en : c->entries) descs.push_back(en.desc);
@@ -1244,6 +1271,8 @@ cow_status cow_sparsity(cow_ctx* c, const cow_block_set* set, const float* pts, 
         const int e = find_entry(c, set->refs[r].block_id, set->refs[r].lod);
         if (e < 0) return fail(c, COW_E_INVALID, "set names a (block, lod) that is not loaded");
         idx[r] = e;
+        if (c->entries[e].desc.flags & COW_BLOCK_CONTRACTED)
+            return fail(c, COW_E_UNSUPPORTED, "sparsity points are not mapped through the contraction");
         const int d = c->entries[e].desc.dtype;
         if (dtype >= 0 && d != dtype) return fail(c, COW_E_UNSUPPORTED, "one call must use blocks of a single dtype");
         dtype = d;

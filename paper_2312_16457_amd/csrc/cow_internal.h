@@ -49,6 +49,7 @@ struct DevBlock {
     // dosum[c] = (((offset[0][c] + offset[1][c]) + offset[2][c]) + offset[3][c]) (+-log2 e)
     float dsc[4][kNch];
     float dosum[kNch];
+    int32_t contracted;        // texture space is the contracted cube (boundary block)
 };
 
 struct DevView {
@@ -86,6 +87,10 @@ struct MarchArgs {
     int32_t persistent;
     // per-block baseline: only this view and this one set position
     int32_t only_view, only_set_pos;
+    // exterior of contracted boundary blocks: step scale (0: none), steps per segment
+    float ext_delta;
+    int32_t ext_max_steps;
+    int32_t contract;          // some block of the call is contracted: the contraction kernel
 };
 
 struct MlpArgs {

@@ -8,9 +8,148 @@
 
 namespace cow {
 
+// The ray's interval inside the footprint's column: the exact slab test on
+// x and y only, t clamped at 0.
+__device__ inline bool slab_xy(const float o[3], const float d[3], const float lo[3], const float hi[3], float* tn,
+                               float* tf) {
+    float t0 = 0.0f, t1 = INFINITY;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        if (d[c] == 0.0f) {
+            if (o[c] < lo[c] || o[c] > hi[c]) return false;
+            continue;
+        }
+        const float inv = 1.0f / d[c];
+        const float a = (lo[c] - o[c]) * inv;
+        const float b = (hi[c] - o[c]) * inv;
+        const float mn = a < b ? a : b, mx = a < b ? b : a;
+        if (mn > t0) t0 = mn;
+        if (mx < t1) t1 = mx;
+    }
+    *tn = t0;
+    *tf = t1;
+    return t0 < t1;
+}
+
+// One exterior segment [t_start, t_end) of a lane's ray outside the scene's
+// footprint, sampled in the contracted representation of the boundary block
+// that owns each point (implementation details; Eq. "blocks" in the max
+// norm, ties to the clamped unit cell).  From t the next point lies
+// ext_delta m^2 further, m = max(1, |x|_inf) in the owner cell's normalised
+// coordinate: about uniform steps in contracted space.  A point is sampled
+// when it lies outside the footprint, within the far limit m <= 1/ext_delta,
+// and its owner is a contracted block of the view's set; the segment after
+// the column (post) ends at the far limit.  The segment's samples composite
+// into (Ae, Te), merged into (A, T) at the end (Eq. "volume rendering across
+// blocks").  Lanes of a wave may sample different owners: each round
+// evaluates one owner for all lanes that need it, the textures addressed
+// through that block's wave-uniform descriptors.
+template <int DT, bool SPARSE>
+__device__ inline void march_exterior(const MarchArgs& a, const ViewU& v, const Ray& r, float t_start, float t_end,
+                                      bool post, bool want, float A[7], float& T, int64_t& n_eval, int64_t& n_march) {
+    const float slo[3] = {a.scene_lo[0], a.scene_lo[1], a.scene_lo[2]};
+    const float shi[3] = {a.scene_hi[0], a.scene_hi[1], a.scene_hi[2]};
+    const float nxm = (shi[0] - slo[0]) - 1.0f, nym = (shi[1] - slo[1]) - 1.0f;
+    const float far = 1.0f / a.ext_delta;
+    float t = t_start + 0.5f * a.ext_delta;
+    int st = 0;
+    bool live = want;
+    float cur_fx = -1.0f, cur_fy = -1.0f;
+    int cur_e = -1;
+    float Ae[7] = {0, 0, 0, 0, 0, 0, 0}, Te = 1.0f;
+    for (;;) {
+        bool have = false;
+        float q[3] = {0.0f, 0.0f, 0.0f}, w = 0.0f;
+        while (live && st < a.ext_max_steps) {
+            if (!post && !(t < t_end)) {
+                live = false;
+                break;
+            }
+            float p[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) p[c] = coord(r.o[c], t, r.d[c]);
+            float fx = floorf(p[0] - slo[0]), fy = floorf(p[1] - slo[1]);
+            fx = fx < 0.0f ? 0.0f : (fx > nxm ? nxm : fx);
+            fy = fy < 0.0f ? 0.0f : (fy > nym ? nym : fy);
+            const float clo[3] = {slo[0] + fx, slo[1] + fy, slo[2]};
+            const float chi[3] = {clo[0] + 1.0f, clo[1] + 1.0f, shi[2]};
+            float m = contract_q(clo, chi, p, q);
+            if (m < 1.0f) m = 1.0f;
+            w = (a.ext_delta * m) * m;
+            ++st;
+            t = t + w;
+            if (m > far) {
+                if (post) live = false;
+                continue;
+            }
+            if (slo[0] <= p[0] && p[0] < shi[0] && slo[1] <= p[1] && p[1] < shi[1]) continue;
+            if (fx != cur_fx || fy != cur_fy) {  // owner of the cell: a contracted block of the set
+                cur_fx = fx, cur_fy = fy, cur_e = -1;
+                for (int j = 0; j < v.set_n; ++j) {
+                    const int e = ufl(a.refs[v.set_begin + j]);
+                    const DevBlock* B = a.blocks + e;
+                    if (ufl(B->contracted) && uff(B->lo[0]) == clo[0] && uff(B->lo[1]) == clo[1]) {
+                        cur_e = e;
+                        break;
+                    }
+                }
+            }
+            if (cur_e < 0) continue;
+            ++n_march;
+            have = true;
+            break;
+        }
+        if (!__any(have)) break;
+        bool pending = have;
+        bool occupied = false;
+        float sigma = 0.0f, val[7] = {0, 0, 0, 0, 0, 0, 0};
+        while (__any(pending)) {
+            const uint64_t mask = __ballot(pending);
+            const int first = __ffsll((unsigned long long)mask) - 1;
+            const int eu = ufl(__shfl(cur_e, first));
+            BlockU b;
+            load_block<DT>(a.blocks + eu, b);
+            if (pending && cur_e == eu) {
+                pending = false;
+                const int cell = occ_cell(b, q);
+                occupied = ld1g(b.skip, (uint32_t)cell) == 0;
+                if (occupied) {
+                    float raw[8];
+                    if (DT == 0) {
+                        raw_u8<SPARSE>(b, q, cell, raw);
+                        sigma = density_u8(raw);
+#pragma unroll
+                        for (int c = 0; c < 7; ++c) val[c] = feature_u8(raw, 1 + c);
+                    } else {
+                        Taps Tp;
+                        sample_taps(b, q, Tp);
+                        raw_f32(b, Tp, raw);
+                        sigma = __expf(raw[0]);
+#pragma unroll
+                        for (int c = 0; c < 7; ++c) val[c] = sigmoidf_(raw[1 + c]);
+                    }
+                }
+            }
+        }
+        if (have && occupied) {
+            const float alpha = alpha_of(sigma * w);
+            const float wt = Te * alpha;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) Ae[c] = fmaf(wt, val[c], Ae[c]);
+            Te *= 1.0f - alpha;
+            ++n_eval;
+            if (T * Te < a.t_min) live = false;  // early ray termination
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 7; ++c) A[c] = fmaf(T, Ae[c], A[c]);
+    T *= Te;
+}
+
 // PE: positional-encoding frequencies of the per-block MLPs' direction input
 // (a kernel of its own, so the plain kernels carry none of its code)
-template <int MODE, int DT, bool SPARSE, int PE = 0>
+// CT: the launch holds contracted blocks (the contraction kernel)
+template <int MODE, int DT, bool SPARSE, int PE = 0, bool CT = false>
 __device__ __attribute__((always_inline)) inline void march_packet(const MarchArgs& a, const DevView* V, int tile,
                                                                    int lane) {
     ViewU v;
@@ -40,6 +179,13 @@ __device__ __attribute__((always_inline)) inline void march_packet(const MarchAr
         if (a.counts) n_eval = a.counts[2 * r.pix], n_march = a.counts[2 * r.pix + 1];
         if (a.opacity) H = a.opacity[r.pix];
     }
+    float fin = INFINITY, fout = INFINITY;  // the ray's interval in the footprint's column
+    if (CT && a.ext_delta > 0.0f) {
+        const float slo[3] = {a.scene_lo[0], a.scene_lo[1], a.scene_lo[2]};
+        const float shi[3] = {a.scene_hi[0], a.scene_hi[1], a.scene_hi[2]};
+        if (!slab_xy(r.o, r.d, slo, shi, &fin, &fout)) fin = fout = INFINITY;
+        march_exterior<DT, SPARSE>(a, v, r, 0.0f, fin, false, r.active, A, T, n_eval, n_march);
+    }
     for (int j = r0; j < r1; ++j) {
         const int e = ufl(a.refs[v.set_begin + j]);
         BlockU b;
@@ -49,7 +195,7 @@ __device__ __attribute__((always_inline)) inline void march_packet(const MarchAr
         if (!__any(sp.ka < sp.kb)) continue;
         float Ak[7] = {0, 0, 0, 0, 0, 0, 0}, Tk = 1.0f;
         const int64_t marched_before = n_march;
-        march_block<DT, MODE, SPARSE>(a, b, r, sp, T, Ak, Tk, n_eval, n_march);
+        march_block<DT, MODE, SPARSE, true, CT>(a, b, r, sp, T, Ak, Tk, n_eval, n_march);
         // opacity regulariser: entropy of the block's opacity 1 - Tk, for
         // every block the ray marches (Eq. "opacity loss")
         if (a.opacity && n_march > marched_before) H += opacity_entropy(Tk);
@@ -70,6 +216,9 @@ __device__ __attribute__((always_inline)) inline void march_packet(const MarchAr
         }
         T *= Tk;
     }
+    if (CT && a.ext_delta > 0.0f)
+        march_exterior<DT, SPARSE>(a, v, r, fout, INFINITY, true, r.active && fout < INFINITY && !(T < a.t_min), A, T,
+                                   n_eval, n_march);
     if (r.active) {
         float4* aux4 = reinterpret_cast<float4*>(a.aux);
         aux4[2 * r.pix] = make_float4(A[0], A[1], A[2], A[3]);
@@ -91,7 +240,7 @@ __device__ __attribute__((always_inline)) inline void march_packet(const MarchAr
 // All blocks of one launch share a texture dtype (checked on the host).  The
 // uint8 kernel runs four waves per SIMD; the fp32 one keeps its 40 texel
 // loads (160 registers) in flight with two.
-template <int MODE, int DT, bool SPARSE, int PE = 0>
+template <int MODE, int DT, bool SPARSE, int PE = 0, bool CT = false>
 __device__ inline void march_fwd_body(const MarchArgs& a) {
     const int lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
@@ -117,7 +266,7 @@ __device__ inline void march_fwd_body(const MarchArgs& a) {
             V = find_view_by_tile(a.views, a.n_views, p);
             tile = p - ufl(V->tile_begin);
         }
-        march_packet<MODE, DT, SPARSE, PE>(a, V, tile, lane);
+        march_packet<MODE, DT, SPARSE, PE, CT>(a, V, tile, lane);
         if (!a.persistent) return;
     }
 }
@@ -138,6 +287,12 @@ __global__ __launch_bounds__(256) void march_fwd_pe_kernel(MarchArgs a) {
     march_fwd_body<MODE, DT, SPARSE, 4>(a);
 }
 
+// grid mode with contracted boundary blocks and their exterior
+template <int DT, bool SPARSE>
+__global__ __launch_bounds__(256) void march_fwd_ct_kernel(MarchArgs a) {
+    march_fwd_body<1, DT, SPARSE, 0, true>(a);
+}
+
 hipError_t launch_march(const MarchArgs& a, int waves, hipStream_t s) {
     if (a.total_tiles <= 0) return hipSuccess;
     dim3 block(64 * waves);
@@ -151,6 +306,15 @@ hipError_t launch_march(const MarchArgs& a, int waves, hipStream_t s) {
         grid = dim3((a.total_tiles + waves - 1) / waves);
     }
     const int dt = a.blocks_dtype;
+    if (a.contract) {  // grid mode, one MLP after the merge (checked on the host)
+        if (dt == 1)
+            hipLaunchKernelGGL((march_fwd_ct_kernel<1, false>), grid, block, 0, s, a);
+        else if (a.use_sparse)
+            hipLaunchKernelGGL((march_fwd_ct_kernel<0, true>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((march_fwd_ct_kernel<0, false>), grid, block, 0, s, a);
+        return hipGetLastError();
+    }
     if (a.block_mlp && a.pe == 4) {
 #define COW_LAUNCH_PE(M, D, S) hipLaunchKernelGGL((march_fwd_pe_kernel<M, D, S>), grid, block, 0, s, a)
         if (dt == 1) {

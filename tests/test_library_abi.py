@@ -59,14 +59,15 @@ def test_struct_layouts_match_c():
     #include <stddef.h>
     #include "cow.h"
     int main(void) {
-      printf("%zu %zu %zu %zu\n", sizeof(cow_block_desc), offsetof(cow_block_desc, grid),
-             offsetof(cow_block_desc, scale), offsetof(cow_block_desc, offset));
+      printf("%zu %zu %zu %zu %zu\n", sizeof(cow_block_desc), offsetof(cow_block_desc, grid),
+             offsetof(cow_block_desc, scale), offsetof(cow_block_desc, offset), offsetof(cow_block_desc, flags));
       printf("%zu %zu %zu\n", sizeof(cow_view), offsetof(cow_view, eye), offsetof(cow_view, fx));
       printf("%zu %zu\n", sizeof(cow_block_ref), sizeof(cow_block_set));
       printf("%zu %zu\n", sizeof(cow_lod_policy), offsetof(cow_lod_policy, cull));
-      printf("%zu %zu %zu %zu %zu\n", sizeof(cow_render_params), offsetof(cow_render_params, flags),
+      printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(cow_render_params), offsetof(cow_render_params, flags),
              offsetof(cow_render_params, counts), offsetof(cow_render_params, opacity),
-             offsetof(cow_render_params, opacity_weight));
+             offsetof(cow_render_params, opacity_weight), offsetof(cow_render_params, ext_delta),
+             offsetof(cow_render_params, ext_max_steps));
       return 0;
     }
     """
@@ -78,12 +79,12 @@ def test_struct_layouts_match_c():
                                "-I", "/opt/rocm/include", src, "-o", exe])
         vals = [list(map(int, l.split())) for l in subprocess.check_output([exe], text=True).splitlines()]
     assert vals[0] == [C.sizeof(B.BlockDesc), B.BlockDesc.grid.offset, B.BlockDesc.scale.offset,
-                       B.BlockDesc.offset.offset]
+                       B.BlockDesc.offset.offset, B.BlockDesc.flags.offset]
     assert vals[1] == [C.sizeof(B.View), B.View.eye.offset, B.View.fx.offset]
     assert vals[2] == [C.sizeof(B.BlockRef), C.sizeof(B.BlockSet)]
     assert vals[3] == [C.sizeof(B.LodPolicy), B.LodPolicy.cull.offset]
     assert vals[4] == [C.sizeof(B.Params), B.Params.flags.offset, B.Params.counts.offset, B.Params.opacity.offset,
-                       B.Params.opacity_weight.offset]
+                       B.Params.opacity_weight.offset, B.Params.ext_delta.offset, B.Params.ext_max_steps.offset]
 
 
 def test_null_context_and_no_device(libcow):
