@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched measurements")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU leg, no extras)")
-    ap.add_argument("--leg", choices=["fwd", "bwd", "batched", "quadtree", "variants", "opaque", "empty"],
+    ap.add_argument("--leg", choices=["fwd", "bwd", "batched", "quadtree", "variants", "opaque", "empty", "contract"],
                     default="fwd",
                     help="with --profile: the leg to run (one timed repetition of bwd / batched / quadtree / "
                          "the forward's options)")
@@ -71,7 +71,8 @@ def main():
     from paper_2312_16457_amd import Renderer, scenegen as sg
     if args.profile and args.leg != "fwd":
         fn = {"bwd": leg_backward, "batched": lambda *a, **k: leg_batched(*a, **k)[0], "quadtree": leg_quadtree,
-              "variants": leg_variants, "opaque": leg_opaque, "empty": leg_empty_space}
+              "variants": leg_variants, "opaque": leg_opaque, "empty": leg_empty_space,
+              "contract": leg_contracted}
         print(json.dumps({"leg": args.leg, **fn[args.leg](torch, sg, Renderer, reps=1)}), flush=True)
         return
 
@@ -303,6 +304,39 @@ def leg_empty_space(torch, sg, Renderer, reps=3):
     return res
 
 
+def leg_contracted(torch, sg, Renderer, reps=3):
+    """Contracted boundary blocks (the 12 edge blocks of the bench city) with
+    their exterior sampled (ext_delta 1/64, at most 512 steps per segment),
+    against the same city with plain blocks, from the bench camera and from
+    one outside the footprint looking across it (1920x1080 each)."""
+    import numpy as np
+    from dataclasses import replace
+    log("contracted: generating the 4x4 city")
+    scene = sg.c2_scene()
+    cams = {"bench_view": sg.c2_view(),
+            "outside_view": sg.pinhole(1920, 1080, (2.0, -2.5, 1.6),
+                                       sg.look_rotation(np.asarray((0.0, 1.0, -0.45))))}
+    res = {"workload": "4x4 uint8 blocks (128^3 + 3 x 1024^2), 12 edge blocks contracted, 1920x1080 views",
+           "ext_delta": 1.0 / 64, "ext_max_steps": 512}
+    for label, blocks, p in (("plain", scene.blocks, sg.cityb_params()),
+                             ("contracted", sg.contract_boundary(scene.blocks),
+                              replace(sg.cityb_params(), ext_delta=1.0 / 64, ext_max_steps=512))):
+        r = Renderer(0)
+        r.load_blocks(blocks)
+        mlp = torch.tensor(sg.xavier_mlp(1), device="cuda")
+        for cam, view in cams.items():
+            sel = r.select(view, thresholds=(1e30,), cull=False)
+            cnt = r.render([view], [sel], p, mlp, counts=True)["counts"]
+            n_eval, n_march = int(cnt[:, 0].sum().item()), int(cnt[:, 1].sum().item())
+            out = r.render([view], [sel], p, mlp, want_aux=False)
+            ms = _timed(torch, lambda: r.render([view], [sel], p, mlp, out=out), reps)
+            res[f"{label}_{cam}"] = {"ms": round(ms, 3), "evaluated_samples": n_eval, "marched_samples": n_march,
+                                     "Msamples_per_s": round(n_eval / (ms * 1e-3) / 1e6, 1)}
+        del r
+        torch.cuda.empty_cache()
+    return res
+
+
 def leg_opaque(torch, sg, Renderer, reps=3):
     """The bench frame over the opaque variant of the city (the density
     recipe without its shift of 5: peak density 50), with and without early
@@ -529,7 +563,8 @@ def extras(torch, sg, Renderer):
     """Backward throughput, the batched-vs-per-block comparison on the
     8x8x3-LOD scene and the same views over quadtree LODs."""
     ex = {"single_block": leg_single_block(torch, sg, Renderer), "opaque": leg_opaque(torch, sg, Renderer),
-          "empty_space": leg_empty_space(torch, sg, Renderer), "bwd": leg_backward(torch, sg, Renderer)}
+          "empty_space": leg_empty_space(torch, sg, Renderer), "contracted": leg_contracted(torch, sg, Renderer),
+          "bwd": leg_backward(torch, sg, Renderer)}
     ex["batched"], lod_city = leg_batched(torch, sg, Renderer)
     ex["quadtree"] = leg_quadtree(torch, sg, Renderer, lod_city=lod_city)
     return ex
