@@ -111,3 +111,66 @@ def test_contracted_blocks_reject_unsupported_calls(torch_cuda):
     with pytest.raises(CowError) as ei:
         Renderer(0).load_blocks([low, top])
     assert ei.value.status == 1
+
+
+def test_contracted_two_views_graph_and_termination(torch_cuda):
+    """Two views in one call, replayed from a captured graph, on the opaque
+    variant with early termination (t_min = 1e-5): the same outputs as the
+    oracle per view; a sample count may differ by one where fp32 and fp64
+    transmittances meet t_min within rounding."""
+    from paper_2312_16457_amd import F_GRAPH, Renderer
+    scene = sg.make_scene(3, 3, ((16, 64, 8),), sg.U8, blobs_per_block=10, blob_z=(0, 0.3), seed=5, shift=0.0)
+    sc = types.SimpleNamespace(blocks=sg.contract_boundary(scene.blocks))
+    views = [sg.pinhole(29, 23, e, sg.look_rotation(np.asarray(f))) for e, f in
+             (VIEWS["outside_looking_in"], VIEWS["above_looking_out"])]
+    p = sg.RenderParams(mode=1, t_min=1e-5, ext_delta=1.0 / 64, ext_max_steps=512)
+    r = Renderer(0).load_blocks(sc.blocks)
+    refs = [(b.block_id, b.lod) for b in sc.blocks]
+    w = sg.random_mlp(6, 0.7)
+    mlp = torch_cuda.tensor(w, device="cuda")
+    eager = r.render(views, [refs, refs], p, mlp, counts=True)
+    for _ in range(3):  # graph replays, with eager work and synchronisation between them
+        out = r.render(views, [refs, refs], p, mlp, counts=True, flags=F_GRAPH)
+        torch_cuda.cuda.synchronize()
+        for k in ("rgb", "trans", "aux", "counts"):
+            assert torch_cuda.equal(out[k], eager[k]), k
+    ob = O.OracleScene(sc.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    off = 0
+    for v in views:
+        n = v.crop[2] * v.crop[3]
+        ref = O.render(ob, occs, v, list(range(ob.n)), p, w)
+        cnt = eager["counts"][off:off + n].cpu().numpy()
+        d = np.abs(cnt[:, 0] - ref["n_eval"])
+        assert (d != 0).mean() <= 1e-2 and d.max() <= 1
+        for k in ("rgb", "trans"):
+            assert np.abs(eager[k][off:off + n].cpu().numpy() - ref[k]).max() <= TOL, k
+        off += n
+
+
+@pytest.mark.parametrize("cam", ["bench", "outside"])
+def test_contracted_bench_city_full_frame_sampled_rows(torch_cuda, cam):
+    """The contraction leg's workload at full size (4x4 uint8 blocks of 128^3
+    + 3 x 1024^2, 12 edge blocks contracted, 1920x1080, the launch the bench
+    times): every pixel rendered on the GPU, eight spread rows checked
+    against the oracle, sample counts bit-exact."""
+    from paper_2312_16457_amd import Renderer
+    sc = types.SimpleNamespace(blocks=sg.contract_boundary(sg.c2_scene().blocks))
+    view = sg.c2_view() if cam == "bench" else sg.pinhole(1920, 1080, (2.0, -2.5, 1.6),
+                                                          sg.look_rotation(np.asarray((0.0, 1.0, -0.45))))
+    p = sg.RenderParams(mode=1, ext_delta=1.0 / 64, ext_max_steps=512)
+    r = Renderer(0).load_blocks(sc.blocks)
+    refs = [(b.block_id, b.lod) for b in sc.blocks]
+    w = sg.xavier_mlp(1)
+    out = r.render([view], [refs], p, torch_cuda.tensor(w, device="cuda"), counts=True)
+    torch_cuda.cuda.synchronize()
+    ob = O.OracleScene(sc.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    rows = [0, 137, 301, 480, 611, 777, 950, 1079]
+    pix = O.pixels_of(view, rows=rows)
+    ref = O.render(ob, occs, view, list(range(ob.n)), p, w, pix=pix)
+    lin = pix[:, 1] * 1920 + pix[:, 0]
+    cnt = out["counts"].cpu().numpy()[lin]
+    assert np.array_equal(cnt[:, 1], ref["n_march"]) and np.array_equal(cnt[:, 0], ref["n_eval"])
+    for k in ("rgb", "trans", "aux"):
+        assert np.abs(out[k].cpu().numpy()[lin] - ref[k]).max() <= TOL, k
