@@ -100,6 +100,9 @@ def lib():
         L.orc_contract.restype = None
         L.orc_local_q.argtypes = [C.POINTER(_Block), vp, vp]
         L.orc_local_q.restype = C.c_float
+        L.orc_ext_samples.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), vp, C.c_int,
+                                      C.POINTER(_Params), vp, vp, C.c_float, C.c_float, C.c_int, vp, vp, C.c_long]
+        L.orc_ext_samples.restype = C.c_long
         L.orc_field.argtypes = [C.POINTER(_Block), C.c_int, vp, vp]
         _lib = L
     return _lib
@@ -148,6 +151,19 @@ def local_q(ob, k, p):
     q = np.zeros(3, np.float32)
     m = lib().orc_local_q(C.byref(ob.arr[k]), _ptr(np.ascontiguousarray(p, np.float32)), _ptr(q))
     return q, float(m)
+
+
+def ext_samples(ob, occs, set_idx, params, o, d, t_start, t_end, post, cap=4096):
+    """Texture coordinates and step lengths of the samples of one exterior
+    segment of the ray (o, d)."""
+    q = np.zeros((cap, 3), np.float32)
+    dl = np.zeros(cap, np.float64)
+    s = np.ascontiguousarray(set_idx, np.int32)
+    pr = make_params(params)
+    n = lib().orc_ext_samples(ob.arr, ob.n, _occ_ptrs(ob, occs), _ptr(s), len(s), C.byref(pr),
+                              _ptr(np.ascontiguousarray(o, np.float32)), _ptr(np.ascontiguousarray(d, np.float32)),
+                              float(t_start), float(t_end), int(post), _ptr(q), _ptr(dl), cap)
+    return q[:n], dl[:n]
 
 
 def posenc(d, pe):

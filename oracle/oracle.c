@@ -406,6 +406,27 @@ static long ext_phase(const orc_block* blocks, const unsigned char* const* occ, 
     return n;
 }
 
+/* Samples of one exterior segment of a ray, for tests: texture-space
+ * coordinates (3 per sample) and step lengths, at most cap. */
+long orc_ext_samples(const orc_block* blocks, int nblocks, const unsigned char* const* occ, const int* set,
+                     int nset, const orc_params* p, const float* o, const float* d, float t_start, float t_end,
+                     int post, float* q_out, double* delta_out, long cap) {
+    float slo[3] = {INFINITY, INFINITY, INFINITY}, shi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = 0; b < nblocks; ++b)
+        for (int c = 0; c < 3; ++c) {
+            if (blocks[b].lo[c] < slo[c]) slo[c] = blocks[b].lo[c];
+            if (blocks[b].hi[c] > shi[c]) shi[c] = blocks[b].hi[c];
+        }
+    sample* buf = (sample*)malloc(sizeof(sample) * (cap > 0 ? cap : 1));
+    long n = ext_phase(blocks, occ, set, nset, p, o, d, slo, shi, t_start, t_end, post, buf, 0, cap);
+    for (long i = 0; i < n; ++i) {
+        for (int c = 0; c < 3; ++c) q_out[3 * i + c] = buf[i].q[c];
+        delta_out[i] = buf[i].delta;
+    }
+    free(buf);
+    return n;
+}
+
 /* Enumerate the samples of one ray in compositing order (front to back).
  * Returns the number written (<= cap).  Empty samples (no block in the set,
  * or outside every block) are not listed; unoccupied ones are, with

@@ -81,6 +81,11 @@ void orc_contract(const double* x, double* y);
  * sequence; contracted blocks map through the contraction); returns the max
  * norm of the box-normalised coordinate (0 for plain blocks) */
 float orc_local_q(const orc_block* b, const float* p, float* q);
+/* the samples of one exterior segment [t_start, t_end) of the ray (o, d):
+ * texture-space coordinates and step lengths; returns their number (<= cap) */
+long orc_ext_samples(const orc_block* blocks, int nblocks, const unsigned char* const* occ, const int* set,
+                     int nset, const orc_params* p, const float* o, const float* d, float t_start, float t_end,
+                     int post, float* q_out, double* delta_out, long cap);
 
 /* occupancy bits [O][O][O] (z,y,x) of one block by the conservative max-bound rule */
 int orc_occupancy(const orc_block* b, unsigned char* out);

@@ -1243,3 +1243,33 @@ def test_exterior_is_composited_before_and_after_the_city():
     ob3 = O.OracleScene([plain])
     ref3 = O.render(ob3, [O.occupancy(ob3, 0)], outward, [0], p, w, pix=np.array([[1, 1]], np.int32))
     assert ref3["trans"][0] == 1.0 and ref3["n_march"][0] == 0
+
+
+def test_exterior_steps_are_about_uniform_in_contracted_space():
+    """Along a ray leaving a contracted unit block's centre through its +x
+    face, the exterior samples' contracted x-coordinate y = 4 q - 2 grows by
+    2 delta / (1 + 2 delta m) per step, so by a step within [2 delta / 3,
+    2 delta] while m runs from 1 to the far limit 1/delta (a step rule in m
+    instead of m^2, or a wrong factor, leaves that band); the samples cover the
+    shell up to within 2 delta of its outer face, and the y and z coordinates
+    stay at the centre.  A ray leaving along a face diagonal keeps equal x and
+    y contracted coordinates."""
+    blk = sg.contract_boundary([sg.homogeneous_block()])[0]
+    ob = O.OracleScene([blk])
+    occs = [O.occupancy(ob, 0)]
+    for delta in (1.0 / 32, 1.0 / 64):
+        p = sg.RenderParams(mode=1, ext_delta=delta, ext_max_steps=100000)
+        q, dl = O.ext_samples(ob, occs, [0], p, (0.5, 0.5, 0.5), (1.0, 0.0, 0.0), 0.5, np.inf, 1)
+        y = 4.0 * q[:, 0].astype(np.float64) - 2.0
+        assert len(y) > 10
+        dy = np.diff(y)
+        assert (dy > 2 * delta / 3 * (1 - 1e-4)).all() and (dy < 2 * delta * (1 + 1e-4)).all()
+        assert y[0] > 1.0 and y[-1] > 2.0 - 2 * delta
+        assert np.allclose(q[:, 1:], 0.5, atol=1e-6)
+        # the step lengths are the world distances between consecutive samples
+        m = 1.0 / (2.0 - y)
+        assert np.allclose(dl, delta * m * m, rtol=1e-5)
+    u = np.array([1.0, 1.0, 0.0]) / np.sqrt(2.0)
+    q, _ = O.ext_samples(ob, occs, [0], sg.RenderParams(mode=1, ext_delta=1 / 64, ext_max_steps=100000),
+                         (0.5, 0.5, 0.5), u, 0.5 * np.sqrt(2.0), np.inf, 1)
+    assert len(q) > 10 and np.allclose(q[:, 0], q[:, 1], atol=1e-6)
