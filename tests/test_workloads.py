@@ -39,3 +39,18 @@ def test_c3_views_and_lod_mix(c3_small):
         for k in O.select(v, scene.blocks, zt, thresholds=(2, 4, 8), cull=True):
             lods[scene.blocks[k].lod] += 1
     assert (lods > 0).all(), lods  # every LOD is exercised
+
+
+def test_contract_boundary_marks_the_edge_columns():
+    """The contraction workload: of a 4x4 city's 16 unit blocks the 12 on the
+    footprint's edge are contracted, the 4 inner ones stay plain, and the
+    textures are untouched; merged (2x2) assets are never contracted."""
+    from paper_2312_16457_amd import scenegen as sg
+    scene = sg.make_scene(4, 4, ((8, 16, 4),), sg.U8, blobs_per_block=2, seed=3)
+    out = sg.contract_boundary(scene.blocks)
+    edge = [b.aabb_min[0] in (0, 3) or b.aabb_min[1] in (0, 3) for b in scene.blocks]
+    assert [b.contracted for b in out] == edge and sum(edge) == 12
+    assert all(a.grid is b.grid for a, b in zip(scene.blocks, out))
+    merged = sg.merged_lods(scene.blocks, 4, 4, 2)
+    big = [b for b in sg.contract_boundary(merged) if b.aabb_max[0] - b.aabb_min[0] > 1]
+    assert big and not any(b.contracted for b in big)
