@@ -275,7 +275,12 @@ int orc_occupancy(const orc_block* b, unsigned char* out) {
     return 0;
 }
 
+/* Height of a block's content (Appendix D, the z of the rectangle the viewer
+ * tests): the top face of its highest occupied cell, the floor when empty.  A
+ * contracted block's texture z is the contracted coordinate, not world z, and
+ * the block owns space above its box: its box top. */
 double orc_ztop(const orc_block* b, const unsigned char* occ) {
+    if (b->contracted) return (double)b->hi[2];
     int nz = dim(b, b->O, 2), nxy = dim(b, b->O, 0) * dim(b, b->O, 1), top = -1;
     for (int z = 0; z < nz; ++z)
         for (int i = 0; i < nxy; ++i)

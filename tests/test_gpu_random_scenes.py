@@ -4,9 +4,13 @@ height, with or without merged 2x2 LOD assets (quadtree selection), seen
 from random cameras (a fifth of them along a coordinate axis) with or
 without early termination.
 
-Bars: per-pixel evaluated and marched sample counts bit-exact and rgb within
-1e-4 of the oracle; the render with occupancy-pyramid jumps bitwise equal to
-the one-step march (COW_F_FLAT_OCC)."""
+Bars: rgb and transmittance within 1e-4 of the oracle; the render with
+occupancy-pyramid jumps bitwise equal to the one-step march (COW_F_FLAT_OCC).
+Sample counts: bit-exact without early termination.  With t_min > 0 the
+kernel compares its fp32 transmittance with t_min and the oracle its fp64
+one, so where the two straddle t_min a ray may stop one evaluated sample
+earlier or later: at most max(1, 1e-3 of the rays) differ, each by one
+evaluated sample, and every other ray has both counts equal."""
 import dataclasses
 
 import numpy as np
@@ -45,6 +49,17 @@ def random_view(rng, nb):
     return sg.pinhole(int(rng.integers(8, 40)), int(rng.integers(8, 40)), eye, sg.look_rotation(fwd))
 
 
+def check_counts(cnt, ref, t_min):
+    if t_min == 0.0:
+        assert np.array_equal(cnt[:, 0], ref["n_eval"])
+        assert np.array_equal(cnt[:, 1], ref["n_march"])
+        return
+    diff = cnt[:, 0] != ref["n_eval"]
+    assert diff.sum() <= max(1, int(1e-3 * len(diff))), int(diff.sum())
+    assert np.abs(cnt[:, 0] - ref["n_eval"]).max() <= 1
+    assert np.array_equal(cnt[~diff, 1], ref["n_march"][~diff])
+
+
 @pytest.mark.parametrize("seed", [11, 12])
 def test_random_scenes_and_cameras(have_gpu, seed):
     import torch
@@ -75,8 +90,7 @@ def test_random_scenes_and_cameras(have_gpu, seed):
                 assert torch.equal(out[key], flat[key]), key
             ref = O.render(ob, occs, v, [look[tuple(x)] for x in sel], p, w)
             cnt = out["counts"].cpu().numpy()
-            assert np.array_equal(cnt[:, 0], ref["n_eval"])
-            assert np.array_equal(cnt[:, 1], ref["n_march"])
+            check_counts(cnt, ref, p.t_min)
             assert np.abs(out["rgb"].cpu().numpy() - ref["rgb"]).max() <= TOL
             assert np.abs(out["trans"].cpu().numpy() - ref["trans"]).max() <= TOL
             cases += 1

@@ -430,6 +430,141 @@ def test_occupancy_skip_changes_little():
 
 
 # ---------------------------------------------------------------------------
+# P8 (exact rule): the occupancy bit is the max-bound of the density over the
+# cell's interpolation support (Sec. 4.5 "Baking", read as a conservative
+# bound), recomputed here in numpy from the definition alone
+# ---------------------------------------------------------------------------
+THRESH32 = np.float32(math.log(0.01))
+
+
+def np_occupancy(b):
+    """Per axis a cell c reads the texel indices [c s - 1, (c + 1) s] (clamped
+    to the texture), s = texels per cell; bound = ((max G + max XY) + max XZ) +
+    max YZ over the density channel in fp32, each uint8 texel decoded as
+    fl(fl(q s) + o); the cell is occupied iff bound > fl32(ln 0.01)."""
+    ext = [int(round(float(b.aabb_max[a] - b.aabb_min[a]))) for a in range(3)]
+
+    def ch0(arr, t):
+        v = arr[..., 0]
+        if b.dtype == sg.U8:
+            return v.astype(np.float32) * np.float32(b.scale[t, 0]) + np.float32(b.offset[t, 0])
+        return v.astype(np.float32)
+
+    g = ch0(b.grid, 0)
+    pl = [ch0(p, 1 + i) for i, p in enumerate(b.planes)]
+    C = [b.occ_res * e for e in ext]  # cells along x, y, z
+    s, sp = b.grid_res // b.occ_res, b.plane_res // b.occ_res
+
+    def rng(c, step, n):
+        return max(c * step - 1, 0), min((c + 1) * step, n - 1) + 1
+
+    out = np.zeros((C[2], C[1], C[0]), np.uint8)
+    for cz in range(C[2]):
+        for cy in range(C[1]):
+            for cx in range(C[0]):
+                c = (cx, cy, cz)
+                gr = [rng(c[a], s, g.shape[2 - a]) for a in range(3)]
+                mg = g[gr[2][0]:gr[2][1], gr[1][0]:gr[1][1], gr[0][0]:gr[0][1]].max()
+                # planes indexed [v][u]: xy (u=x, v=y), xz (u=x, v=z), yz (u=y, v=z)
+                m = []
+                for p, (au, av) in zip(pl, ((0, 1), (0, 2), (1, 2))):
+                    u0, u1 = rng(c[au], sp, p.shape[1])
+                    v0, v1 = rng(c[av], sp, p.shape[0])
+                    m.append(p[v0:v1, u0:u1].max())
+                bound = np.float32(np.float32(np.float32(mg + m[0]) + m[1]) + m[2])
+                out[cz, cy, cx] = 1 if bound > THRESH32 else 0
+    return out
+
+
+@pytest.mark.parametrize("kind", ["f32", "u8", "merged_u8", "merged_f32"])
+def test_occupancy_exact_rule_against_numpy(kind):
+    if kind.startswith("merged"):
+        dt = sg.U8 if kind.endswith("u8") else sg.F32
+        fine = sg.make_scene(2, 2, ((32, 64, 8),), dt, blobs_per_block=3, blob_z=(0.0, 0.3), blob_s=(0.03, 0.08),
+                             seed=5).blocks
+        blocks = sg.merged_lods(fine, 2, 2, 2, dtype=dt)
+        b = [x for x in blocks if x.lod == 1][0]
+    else:
+        dt = sg.F32 if kind == "f32" else sg.U8
+        b = sg.make_scene(1, 1, ((32, 64, 8),), dt, blobs_per_block=6, blob_z=(0.0, 0.5), seed=13).blocks[0]
+    ob = O.OracleScene([b])
+    occ = O.occupancy(ob, 0)
+    ref = np_occupancy(b)
+    assert 0.05 < ref.mean() < 0.95  # both states present, so the comparison has teeth
+    assert np.array_equal(occ, ref)
+
+
+def test_occupancy_support_range_and_strict_threshold():
+    """Impulses place the texel range exactly: grid texel i along x (s = 4
+    texels per cell) is read by the cells c with 4c - 1 <= i <= 4c + 4, so
+    texel 5 by cell 1 alone and texels 3, 4, 7, 8 by two cells; a range
+    grown or shrunk by one texel fails.  A bound equal to fl32(ln 0.01) is
+    empty and the next float up is occupied (strict >)."""
+    R, Rp, Oc = 32, 32, 8
+    lo = np.zeros(3, np.float32)
+
+    def block(grid0, plane0=0.0):
+        grid = np.zeros((R, R, R, 8), np.float32)
+        grid[..., 0] = grid0
+        planes = [np.zeros((Rp, Rp, 8), np.float32) for _ in range(3)]
+        for p in planes:
+            p[..., 0] = plane0
+        return sg.BlockLod(0, 0, lo, lo + 1, R, Rp, Oc, sg.F32, grid, planes,
+                           np.ones((4, 8), np.float32), np.zeros((4, 8), np.float32))
+
+    expect = {3: {0, 1}, 4: {0, 1}, 5: {1}, 7: {1, 2}, 8: {1, 2}, 0: {0}, 31: {7}}
+    for i, cells in expect.items():
+        g = np.full((R, R, R), -20.0, np.float32)
+        g[12, 17, i] = 5.0  # z = 12 (cells 2 and 3), y = 17 (cell 4 alone), x = i
+        occ = O.occupancy(O.OracleScene([block(g)]), 0)
+        hit = set(np.nonzero(occ.any(axis=(0, 1)))[0].tolist())
+        assert hit == cells, (i, hit)
+        assert set(np.nonzero(occ.any(axis=(0, 2)))[0].tolist()) == {4}
+        assert set(np.nonzero(occ.any(axis=(1, 2)))[0].tolist()) == {2, 3}
+    # strict threshold
+    edge = O.occupancy(O.OracleScene([block(THRESH32)]), 0)
+    assert not edge.any()
+    g = np.full((R, R, R), THRESH32, np.float32)
+    g[0, 0, 0] = np.nextafter(THRESH32, np.float32(1))
+    up = O.occupancy(O.OracleScene([block(g)]), 0)
+    assert up.sum() == 1 and up[0, 0, 0] == 1
+    # the four textures add: a plane value lifts every cell over the threshold
+    assert O.occupancy(O.OracleScene([block(np.full((R, R, R), THRESH32, np.float32), 1e-3)]), 0).all()
+
+
+# ---------------------------------------------------------------------------
+# z_top (Appendix D: the height of a block's content, which sets its LOD
+# distance and its culling box): the top face of the highest occupied cell
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ext_z,O_res", [(1, 8), (1, 16), (2, 2)])
+def test_ztop_closed_form(ext_z, O_res):
+    rng = np.random.default_rng(ext_z * 31 + O_res)
+    lo = np.array([3.0, -2.0, 0.0], np.float32)
+    hi = lo + np.array([1.0, 1.0, float(ext_z)], np.float32)
+    R = 2 * O_res
+    b = sg.BlockLod(0, 0, lo, hi, R, R, O_res, sg.F32, np.zeros((R * ext_z, R, R, 8), np.float32),
+                    [np.zeros((R, R, 8), np.float32), np.zeros((R * ext_z, R, 8), np.float32),
+                     np.zeros((R * ext_z, R, 8), np.float32)],
+                    np.ones((4, 8), np.float32), np.zeros((4, 8), np.float32))
+    ob = O.OracleScene([b])
+    nz = O_res * ext_z
+    shape = (nz, O_res, O_res)
+    assert O.ztop(ob, 0, np.zeros(shape, np.uint8)) == float(lo[2])  # empty: the floor
+    for _ in range(6):
+        occ = np.zeros(shape, np.uint8)
+        k = int(rng.integers(nz))
+        occ[k, rng.integers(O_res), rng.integers(O_res)] = 1
+        below = int(rng.integers(k + 1))  # cells below the top change nothing
+        occ[below, rng.integers(O_res), rng.integers(O_res)] = 1
+        assert O.ztop(ob, 0, occ) == float(lo[2]) + (k + 1) / nz * ext_z
+    # a contracted block's texture z is not world z: its top is its box's top
+    bc = dataclasses.replace(b, contracted=True)
+    occ = np.zeros(shape, np.uint8)
+    occ[0, 0, 0] = 1
+    assert O.ztop(O.OracleScene([bc]), 0, occ) == float(hi[2])
+
+
+# ---------------------------------------------------------------------------
 # P10/P11: selection -- culling is conservative, per-view order == per-ray order
 # ---------------------------------------------------------------------------
 def test_culling_conservative_and_order_on_lod_scene():
