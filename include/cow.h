@@ -251,6 +251,12 @@ COW_API cow_status cow_get_occupancy_level(cow_ctx* ctx, int block_id, int lod, 
  * when given, drops far coarsest entries; order: coarsest entries by xy
  * distance, inside an entry its children by quadrant (the eye's, the two
  * beside it, the opposite; ties: lower id).  n_thresholds must be >= L.
+ * Contracted boundary blocks (COW_BLOCK_CONTRACTED) also own the unbounded
+ * space beyond their outer faces: z_top of such a block is its box top; a
+ * block whose LOD-0 entry is contracted is never culled and, beyond the far
+ * cut, takes LOD n_thresholds - 1 instead of being dropped; in quadtree mode
+ * an entry whose footprint holds a contracted LOD-0 entry is never culled,
+ * never dropped and never drawn merged (its children are examined).
  * All decisions in fp64.  Writes up to cap refs; *n_out = count. */
 COW_API cow_status cow_select_blocks(cow_ctx* ctx, const cow_view* view, const cow_lod_policy* policy,
                              cow_block_ref* out, int cap, int* n_out);

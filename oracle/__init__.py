@@ -88,7 +88,7 @@ def lib():
                                    C.c_int, C.c_double, C.c_double, vp, C.POINTER(C.c_void_p),
                                    C.POINTER(C.c_void_p)]
         L.orc_sparsity.restype = C.c_double
-        L.orc_select.argtypes = [C.POINTER(_View), C.c_int, vp, vp, vp, vp, vp, vp, C.c_int, C.c_int,
+        L.orc_select.argtypes = [C.POINTER(_View), C.c_int, vp, vp, vp, vp, vp, vp, vp, C.c_int, C.c_int,
                                  vp, C.c_int]
         L.orc_select_quadtree.argtypes = L.orc_select.argtypes
         L.orc_mlp.argtypes = [vp, vp, vp]
@@ -412,8 +412,9 @@ def adjoint_block_mlp(ob, occs, view, set_idx, params, mlps, pix, grad_rgb, grad
 
 
 def select(view, entries, ztops, thresholds=(2.0, 4.0, 8.0), cull=True, cap=4096, quadtree=False):
-    """entries: list of BlockLod (or objects with block_id, lod, aabb_min, aabb_max);
-    ztops: per entry.  Returns chosen entry indices in front-to-back order.
+    """entries: list of BlockLod (or objects with block_id, lod, aabb_min, aabb_max
+    and optionally contracted); ztops: per entry.  Returns chosen entry indices
+    in front-to-back order.
     quadtree: entries of LOD l are merged assets over 2^l x 2^l blocks."""
     n = len(entries)
     ids = np.array([e.block_id for e in entries], np.int32)
@@ -421,11 +422,12 @@ def select(view, entries, ztops, thresholds=(2.0, 4.0, 8.0), cull=True, cap=4096
     lo = np.array([e.aabb_min for e in entries], np.float32).reshape(-1)
     hi = np.array([e.aabb_max for e in entries], np.float32).reshape(-1)
     zt = np.ascontiguousarray(ztops, np.float64)
+    ct = np.array([int(bool(getattr(e, "contracted", False))) for e in entries], np.int32)
     thr = np.ascontiguousarray(thresholds, np.float64)
     out = np.zeros(cap, np.int32)
     vs = make_view(view)
     fn = lib().orc_select_quadtree if quadtree else lib().orc_select
-    m = fn(C.byref(vs), n, _ptr(ids), _ptr(lods), _ptr(lo), _ptr(hi), _ptr(zt), _ptr(thr),
+    m = fn(C.byref(vs), n, _ptr(ids), _ptr(lods), _ptr(lo), _ptr(hi), _ptr(zt), _ptr(ct), _ptr(thr),
            len(thr), int(cull), _ptr(out), cap)
     if m == -3:
         raise ValueError("quadtree selection needs a threshold for every LOD below the coarsest")

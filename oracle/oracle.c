@@ -373,6 +373,7 @@ static long ext_phase(const orc_block* blocks, const unsigned char* const* occ, 
     const float nxm = (shi[0] - slo[0]) - 1.0f, nym = (shi[1] - slo[1]) - 1.0f;
     const float far = 1.0f / p->ext_delta;
     float t = t_start + 0.5f * p->ext_delta;
+    float m_prev = INFINITY;
     for (int st = 0; st < p->ext_max_steps; ++st) {
         if (!post && !(t < t_end)) break;
         float pt[3];
@@ -386,8 +387,13 @@ static long ext_phase(const orc_block* blocks, const unsigned char* const* occ, 
         float m = contract32(clo, chi, pt, q);
         if (m < 1.0f) m = 1.0f;
         const float w = (p->ext_delta * m) * m;
+        /* beyond the far limit: the segment after the column ends there; the
+         * one before it ends once m grows past it (m is convex along a ray
+         * outside the column, so it never comes back) */
+        const int rising = m > m_prev;
+        m_prev = m;
         if (m > far) {
-            if (post) break;
+            if (post || rising) break;
         } else if (!(slo[0] <= pt[0] && pt[0] < shi[0] && slo[1] <= pt[1] && pt[1] < shi[1])) {
             int s_hit = -1;
             for (int s = 0; s < nset; ++s) {
@@ -500,6 +506,7 @@ static long enumerate(const orc_block* blocks, int nblocks, const unsigned char*
         if (!slab_xy(o, d, slo, shi, &fin, &fout)) fin = fout = INFINITY;
         n = ext_phase(blocks, occ, set, nset, p, o, d, slo, shi, 0.0f, fin, 0, out, n, cap);
     }
+    long k_end = -1; /* end of the window of max_steps steps, when the ray enters the box */
     do {
         /* scan bound from an fp64 slab test of the box grown by 1e-3 */
         double tfar = INFINITY, tnear = 0.0;
@@ -528,6 +535,7 @@ static long enumerate(const orc_block* blocks, int nblocks, const unsigned char*
             }
         }
         if (k0 < 0) break;
+        k_end = k0 + p->max_steps;
         for (long k = k0; k < k0 + p->max_steps; ++k) {
             float t = ((float)k + 0.5f) * p->delta;
             float pt[3];
@@ -548,7 +556,12 @@ static long enumerate(const orc_block* blocks, int nblocks, const unsigned char*
             sm->occupied = occ[set[s_hit]][cell] != 0;
         }
     } while (0);
-    if (ext && fout < INFINITY) n = ext_phase(blocks, occ, set, nset, p, o, d, slo, shi, fout, INFINITY, 1, out, n, cap);
+    /* the cap truncates the ray: when the window ends before the ray leaves
+     * the column, nothing behind it (the exterior beyond the column included)
+     * is sampled */
+    const int capped = k_end >= 0 && ((float)k_end + 0.5f) * p->delta < fout;
+    if (ext && fout < INFINITY && !capped)
+        n = ext_phase(blocks, occ, set, nset, p, o, d, slo, shi, fout, INFINITY, 1, out, n, cap);
     return n;
 }
 
@@ -1331,8 +1344,8 @@ static int culled(const orc_view* v, const double lo[3], const double hi[3]) {
 }
 
 int orc_select(const orc_view* v, int nent, const int* ids, const int* lods, const float* lo,
-               const float* hi, const double* ztop, const double* thresholds, int n_thr,
-               int cull, int* out, int cap) {
+               const float* hi, const double* ztop, const int* contracted, const double* thresholds,
+               int n_thr, int cull, int* out, int cap) {
     int n = 0;
     double* key = (double*)malloc(sizeof(double) * (nent + 1));
     for (int e = 0; e < nent; ++e) {
@@ -1347,6 +1360,9 @@ int orc_select(const orc_view* v, int nent, const int* ids, const int* lods, con
                 lod = l;
                 break;
             }
+        /* a contracted block also owns the space beyond its outer faces, out to
+         * infinity: the far cut and the frustum test of its box do not apply */
+        if (lod < 0 && contracted[e]) lod = n_thr - 1;
         if (lod < 0) continue; /* beyond the far cut */
         int chosen = -1;
         for (int f = 0; f < nent; ++f)
@@ -1355,7 +1371,7 @@ int orc_select(const orc_view* v, int nent, const int* ids, const int* lods, con
             free(key);
             return -2;
         }
-        if (cull) {
+        if (cull && !contracted[e]) {
             double blo[3] = {lo[3 * chosen], lo[3 * chosen + 1], lo[3 * chosen + 2]};
             double bhi[3] = {hi[3 * chosen], hi[3 * chosen + 1], ztop[chosen]};
             if (culled(v, blo, bhi)) continue;
@@ -1400,8 +1416,12 @@ typedef struct qt_state {
     const int *ids, *lods;
     const float *lo, *hi;
     const double *ztop, *thr;
+    const int* contracted;
     int n_thr, cull, *out, cap, n;
 } qt_state;
+
+/* the entry's footprint holds a contracted finest-level entry */
+static int qt_pinned(const qt_state* q, int e);
 
 static int xy_inside(const qt_state* q, int f, int e) {
     return q->lo[3 * f] >= q->lo[3 * e] && q->hi[3 * f] <= q->hi[3 * e] && q->lo[3 * f + 1] >= q->lo[3 * e + 1] &&
@@ -1418,8 +1438,14 @@ static double qt_dist(const qt_state* q, int e) {
     return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
+static int qt_pinned(const qt_state* q, int e) {
+    for (int f = 0; f < q->nent; ++f)
+        if (q->lods[f] == 0 && q->contracted[f] && xy_inside(q, f, e)) return 1;
+    return 0;
+}
+
 static int qt_visible(const qt_state* q, int e) {
-    if (!q->cull) return 1;
+    if (!q->cull || qt_pinned(q, e)) return 1;
     double blo[3] = {q->lo[3 * e], q->lo[3 * e + 1], q->lo[3 * e + 2]};
     double bhi[3] = {q->hi[3 * e], q->hi[3 * e + 1], q->ztop[e]};
     return !culled(q->v, blo, bhi);
@@ -1448,7 +1474,7 @@ static void qt_visit(qt_state* q, int e) {
         rank[nk] = ((fx >= cx) != ex) + ((fy >= cy) != ey);
         kid[nk++] = f;
     }
-    if (all_far) {
+    if (all_far && !qt_pinned(q, e)) {
         qt_emit(q, e);
         return;
     }
@@ -1467,19 +1493,19 @@ static void qt_visit(qt_state* q, int e) {
 }
 
 int orc_select_quadtree(const orc_view* v, int nent, const int* ids, const int* lods, const float* lo,
-                        const float* hi, const double* ztop, const double* thresholds, int n_thr, int cull,
-                        int* out, int cap) {
+                        const float* hi, const double* ztop, const int* contracted, const double* thresholds,
+                        int n_thr, int cull, int* out, int cap) {
     int L = 0;
     for (int e = 0; e < nent; ++e)
         if (lods[e] > L) L = lods[e];
     if (n_thr < L) return -3;
-    qt_state q = {v, nent, ids, lods, lo, hi, ztop, thresholds, n_thr, cull, out, cap, 0};
+    qt_state q = {v, nent, ids, lods, lo, hi, ztop, thresholds, contracted, n_thr, cull, out, cap, 0};
     int* roots = (int*)malloc(sizeof(int) * (nent + 1));
     double* key = (double*)malloc(sizeof(double) * (nent + 1));
     int nr = 0;
     for (int e = 0; e < nent; ++e) {
         if (lods[e] != L || !qt_visible(&q, e)) continue;
-        if (n_thr > L && qt_dist(&q, e) >= thresholds[L]) continue;
+        if (n_thr > L && qt_dist(&q, e) >= thresholds[L] && !qt_pinned(&q, e)) continue;
         double cx = 0.5 * ((double)lo[3 * e] + (double)hi[3 * e]), cy = 0.5 * ((double)lo[3 * e + 1] + (double)hi[3 * e + 1]);
         double dx = (double)v->eye[0] - cx, dy = (double)v->eye[1] - cy;
         roots[nr] = e;

@@ -151,21 +151,26 @@ double orc_sparsity(const orc_block* blocks, int nblocks, const unsigned char* c
 
 /* Per-view block selection: LOD by eye-to-centre distance, frustum culling,
  * front-to-back order by xy distance.  Inputs per distinct block entry k:
- * ids[k], lods[k], lo/hi[3k..], ztop[k].  Writes chosen entry indices in order.
+ * ids[k], lods[k], lo/hi[3k..], ztop[k], contracted[k].  A block whose finest
+ * entry is contracted (it owns the unbounded space beyond its outer faces) is
+ * never culled, and beyond the far cut takes LOD n_thr - 1 instead of being
+ * dropped.  Writes chosen entry indices in order.
  * Returns the count, or -2 if a chosen (block, LOD) is not among the entries. */
 int orc_select(const orc_view* v, int nent, const int* ids, const int* lods, const float* lo,
-               const float* hi, const double* ztop, const double* thresholds, int n_thr,
-               int cull, int* out, int cap);
+               const float* hi, const double* ztop, const int* contracted, const double* thresholds,
+               int n_thr, int cull, int* out, int cap);
 
 /* Quadtree selection over merged LOD entries (an entry of LOD l covers
  * 2^l x 2^l blocks): coarse to fine, an entry of LOD l > 0 is drawn when
  * every visible LOD l-1 entry inside it is at distance >= thresholds[l-1];
  * front-to-back order by recursive quadrants.  n_thr >= the coarsest LOD
- * (-3 otherwise); thresholds[L], when given, drops far coarsest entries.
+ * (-3 otherwise); thresholds[L], when given, drops far coarsest entries.  An
+ * entry whose footprint holds a contracted finest-level entry is never
+ * culled, never dropped and never drawn merged (its children are examined).
  * Returns the count of chosen entry indices written to out. */
 int orc_select_quadtree(const orc_view* v, int nent, const int* ids, const int* lods, const float* lo,
-                        const float* hi, const double* ztop, const double* thresholds, int n_thr, int cull,
-                        int* out, int cap);
+                        const float* hi, const double* ztop, const int* contracted, const double* thresholds,
+                        int n_thr, int cull, int* out, int cap);
 
 /* pre-activation features at n world points of block b (points outside the
  * block are evaluated by the same clamped rule): raw[8n] */

@@ -655,6 +655,7 @@ struct QuadSelect {
     const cow_lod_policy* pol;
     std::vector<std::vector<int>> kids;
     std::vector<double> zfine;
+    std::vector<char> pinned;  // holds a contracted finest-level block: always opened, never culled
     std::vector<int> out;
 
     static bool inside_xy(const cow_block_desc& a, const cow_block_desc& b) {
@@ -671,7 +672,7 @@ struct QuadSelect {
         return std::sqrt(dx * dx + dy * dy + dz * dz);
     }
     bool visible(int e) const {
-        if (!pol->cull) return true;
+        if (!pol->cull || pinned[e]) return true;
         const cow_block_desc& d = c->entries[e].desc;
         const double lo[3] = {d.aabb_min[0], d.aabb_min[1], d.aabb_min[2]};
         const double hi[3] = {d.aabb_max[0], d.aabb_max[1], c->entries[e].ztop};
@@ -692,7 +693,7 @@ struct QuadSelect {
             const int rank = ((centre(f, 0) >= centre(e, 0)) != ex) + ((centre(f, 1) >= centre(e, 1)) != ey);
             seen.push_back({rank, f});
         }
-        if (far) {
+        if (far && !pinned[e]) {
             out.push_back(e);
             return;
         }
@@ -710,20 +711,22 @@ cow_status select_quadtree(cow_ctx* c, const cow_view* v, const cow_lod_policy* 
     int L = 0;
     for (auto& e : c->entries) L = std::max(L, e.desc.lod);
     if (pol->n_thresholds < L) return fail(c, COW_E_INVALID, "quadtree selection needs a threshold per finer LOD");
-    QuadSelect q{c, v, pol, std::vector<std::vector<int>>(ne), std::vector<double>(ne, -INFINITY), {}};
+    QuadSelect q{c, v, pol, std::vector<std::vector<int>>(ne), std::vector<double>(ne, -INFINITY),
+                 std::vector<char>(ne, 0), {}};
     for (int e = 0; e < ne; ++e) {
         const cow_block_desc& d = c->entries[e].desc;
         for (int f = 0; f < ne; ++f) {
             const cow_block_desc& g = c->entries[f].desc;
             if (!QuadSelect::inside_xy(g, d)) continue;
             if (g.lod == 0) q.zfine[e] = std::max(q.zfine[e], c->entries[f].ztop);
+            if (g.lod == 0 && (g.flags & COW_BLOCK_CONTRACTED)) q.pinned[e] = 1;
             if (d.lod > 0 && g.lod == d.lod - 1) q.kids[e].push_back(f);
         }
     }
     std::vector<std::pair<double, int>> roots;
     for (int e = 0; e < ne; ++e) {
         if (c->entries[e].desc.lod != L || !q.visible(e)) continue;
-        if (pol->n_thresholds > L && q.dist(e) >= pol->thresholds[L]) continue;
+        if (pol->n_thresholds > L && q.dist(e) >= pol->thresholds[L] && !q.pinned[e]) continue;
         const double dx = (double)v->eye[0] - q.centre(e, 0), dy = (double)v->eye[1] - q.centre(e, 1);
         roots.push_back({std::sqrt(dx * dx + dy * dy), e});
     }
@@ -934,6 +937,9 @@ cow_status cow_load_blocks(cow_ctx* c, const cow_block_desc* blocks, int n, void
                 if (occ[off + (size_t)z * layer + k]) top = z;
         const double ext = (double)blocks[i].aabb_max[2] - (double)blocks[i].aabb_min[2];
         c->entries[i].ztop = (double)blocks[i].aabb_min[2] + (double)(top + 1) / o[2] * ext;
+        // a contracted block's texture z is the contracted coordinate, not
+        // world z, and it owns the space above its box: its box top
+        if (blocks[i].flags & COW_BLOCK_CONTRACTED) c->entries[i].ztop = (double)blocks[i].aabb_max[2];
         off += occ_cells(blocks[i]);
     }
     c->loaded = true;
@@ -1000,10 +1006,15 @@ cow_status cow_select_blocks(cow_ctx* c, const cow_view* v, const cow_lod_policy
                 lod = l;
                 break;
             }
+        // a contracted boundary block also owns the unbounded space beyond
+        // its outer faces: never dropped by the far cut (its coarsest level
+        // the policy names instead) and never culled
+        const bool contracted = (d.flags & COW_BLOCK_CONTRACTED) != 0;
+        if (lod < 0 && contracted) lod = pol->n_thresholds - 1;
         if (lod < 0) continue;  // beyond the far cut
         const int chosen = find_entry(c, d.block_id, lod);
         if (chosen < 0) return fail(c, COW_E_NOT_LOADED, "selected LOD is not loaded");
-        if (pol->cull) {
+        if (pol->cull && !contracted) {
             const cow_block_desc& cd = c->entries[chosen].desc;
             const double lo[3] = {cd.aabb_min[0], cd.aabb_min[1], cd.aabb_min[2]};
             const double hi[3] = {cd.aabb_max[0], cd.aabb_max[1], c->entries[chosen].ztop};

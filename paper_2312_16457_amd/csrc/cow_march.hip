@@ -54,7 +54,7 @@ __device__ inline void march_exterior(const MarchArgs& a, const ViewU& v, const 
     float t = t_start + 0.5f * a.ext_delta;
     int st = 0;
     bool live = want;
-    float cur_fx = -1.0f, cur_fy = -1.0f;
+    float cur_fx = -1.0f, cur_fy = -1.0f, m_prev = INFINITY;
     int cur_e = -1;
     float Ae[7] = {0, 0, 0, 0, 0, 0, 0}, Te = 1.0f;
     for (;;) {
@@ -78,8 +78,13 @@ __device__ inline void march_exterior(const MarchArgs& a, const ViewU& v, const 
             w = (a.ext_delta * m) * m;
             ++st;
             t = t + w;
+            // beyond the far limit: the segment after the column ends there,
+            // the one before it once m grows past it (m is convex along a ray
+            // outside the column: it never comes back)
+            const bool rising = m > m_prev;
+            m_prev = m;
             if (m > far) {
-                if (post) live = false;
+                if (post || rising) live = false;
                 continue;
             }
             if (slo[0] <= p[0] && p[0] < shi[0] && slo[1] <= p[1] && p[1] < shi[1]) continue;
@@ -216,9 +221,13 @@ __device__ __attribute__((always_inline)) inline void march_packet(const MarchAr
         }
         T *= Tk;
     }
-    if (CT && a.ext_delta > 0.0f)
-        march_exterior<DT, SPARSE>(a, v, r, fout, INFINITY, true, r.active && fout < INFINITY && !(T < a.t_min), A, T,
-                                   n_eval, n_march);
+    if (CT && a.ext_delta > 0.0f) {
+        // the cap truncates the ray: a window that ends before the ray leaves
+        // the column leaves the exterior behind it unsampled
+        const bool capped = MODE == 1 && hit && step_t(w1, a.delta) < fout;
+        march_exterior<DT, SPARSE>(a, v, r, fout, INFINITY, true,
+                                   r.active && fout < INFINITY && !capped && !(T < a.t_min), A, T, n_eval, n_march);
+    }
     if (r.active) {
         float4* aux4 = reinterpret_cast<float4*>(a.aux);
         aux4[2 * r.pix] = make_float4(A[0], A[1], A[2], A[3]);

@@ -1408,3 +1408,132 @@ def test_exterior_steps_are_about_uniform_in_contracted_space():
     q, _ = O.ext_samples(ob, occs, [0], sg.RenderParams(mode=1, ext_delta=1 / 64, ext_max_steps=100000),
                          (0.5, 0.5, 0.5), u, 0.5 * np.sqrt(2.0), np.inf, 1)
     assert len(q) > 10 and np.allclose(q[:, 0], q[:, 1], atol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Selection with contracted boundary blocks: such a block also owns the space
+# beyond its outer faces (Eq. "blocks" in the max norm), so neither the
+# frustum test of its box nor the far cut may drop it (Appendix D culling,
+# read conservatively)
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def contraction_city():
+    scene = sg.make_scene(4, 4, ((8, 16, 4),), sg.U8, blobs_per_block=4, blob_z=(0.0, 0.3), seed=31)
+    blocks = sg.contract_boundary(scene.blocks)
+    ob = O.OracleScene(blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    zt = [O.ztop(ob, k, occs[k]) for k in range(ob.n)]
+    return blocks, ob, occs, zt
+
+
+CONTRACTION_VIEWS = {
+    # inside the city, looking out over the +x edge
+    "looking_out": ((2.2, 2.0, 0.6), (1.0, 0.15, 0.05)),
+    # low inside the city, looking up past the -y edge: the content (and the
+    # boxes up to its top) lie below the frustum, the exterior does not
+    "looking_up": ((2.0, 1.0, 0.35), (0.0, -0.35, 1.0)),
+    # ten widths beyond the far edge's opposite side, looking at the city
+    "far": ((-6.0, 2.0, 1.5), (1.0, 0.0, -0.12)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CONTRACTION_VIEWS))
+def test_selection_keeps_contracted_blocks(contraction_city, name):
+    blocks, ob, occs, zt = contraction_city
+    eye, fwd = CONTRACTION_VIEWS[name]
+    v = sg.pinhole(40, 24, eye, sg.look_rotation(np.asarray(fwd)))
+    thr = (8.0,)
+    p = sg.RenderParams(mode=1, ext_delta=1.0 / 32, ext_max_steps=256)
+    w = sg.random_mlp(5, 0.6)
+    contracted = {k for k, b in enumerate(blocks) if b.contracted}
+    sel = list(O.select(v, blocks, zt, thresholds=thr, cull=True))
+    unculled = list(O.select(v, blocks, zt, thresholds=thr, cull=False))
+    assert contracted <= set(sel)  # never culled, never beyond the far cut
+    # culling stays exact with the exterior: the culled set renders bitwise
+    # like every block within the far cut
+    a = O.render(ob, occs, v, sel, p, w)
+    b = O.render(ob, occs, v, unculled, p, w)
+    assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["trans"], b["trans"])
+    assert (a["n_march"] > 0).mean() > 0.3
+    if name == "far":
+        # the plain inner blocks are all nearer than the far edge, yet the far
+        # edge's contracted blocks (more than 8 widths away) are drawn
+        far = [k for k in contracted
+               if np.hypot(eye[0] - blocks[k].aabb_min[0] - 0.5, eye[1] - blocks[k].aabb_min[1] - 0.5) > 8.5]
+        assert far and set(far) <= set(sel)
+        c = O.render(ob, occs, v, [k for k in sel if k not in far], p, w)
+        assert np.abs(c["trans"] - a["trans"]).max() > 1e-3  # and they matter: they own the exterior there
+    else:
+        assert len(unculled) > len(sel)  # some plain block was culled
+    if name == "looking_up":
+        # the old rule (contracted blocks culled by their box, z_top read from
+        # texture z) drops blocks whose exterior this view sees
+        plain = [dataclasses.replace(x, contracted=False) for x in blocks]
+        obp = O.OracleScene(plain)
+        old = set(O.select(v, plain, [O.ztop(obp, j, occs[j]) for j in range(len(plain))], thresholds=(1e30,),
+                           cull=True))
+        boxes_out = [k for k in contracted if k not in old]
+        assert boxes_out
+        c = O.render(ob, occs, v, [k for k in sel if k not in boxes_out], p, w)
+        assert np.abs(c["trans"] - a["trans"]).max() > 1e-3
+
+
+def test_quadtree_selection_opens_assets_holding_contracted_blocks():
+    """Quadtree LOD over an 8x8 city with contracted edge columns: a merged
+    asset whose footprint holds a contracted block is always opened down to
+    that block (the merged asset owns no exterior), inner assets still merge,
+    and the chosen footprints tile the city exactly once."""
+    scene = sg.make_scene(8, 8, ((8, 16, 4),), sg.U8, blobs_per_block=2, blob_z=(0.0, 0.3), seed=33)
+    fine = sg.contract_boundary(scene.blocks)
+    blocks = fine + sg.merged_lods(scene.blocks, 8, 8, 3)
+    ob = O.OracleScene(blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    zt = [O.ztop(ob, k, occs[k]) for k in range(ob.n)]
+    contracted = {k for k, b in enumerate(blocks) if b.contracted}
+    assert len(contracted) == 28
+    p = sg.RenderParams(mode=1, ext_delta=1.0 / 32, ext_max_steps=256)
+    w = sg.random_mlp(6, 0.6)
+    merged_seen = 0
+    for eye, fwd in (((4.0, -9.0, 6.0), (0.0, 1.0, -0.55)), ((4.2, 3.9, 7.0), (0.1, 0.05, -1.0))):
+        v = sg.pinhole(32, 24, eye, sg.look_rotation(np.asarray(fwd)))
+        sel = list(O.select(v, blocks, zt, thresholds=(1.0, 2.0), cull=True, quadtree=True))
+        assert contracted <= set(sel)
+        cover = np.zeros((8, 8), int)
+        for k in sel:
+            b = blocks[k]
+            x0, y0 = int(b.aabb_min[0]), int(b.aabb_min[1])
+            x1, y1 = int(b.aabb_max[0]), int(b.aabb_max[1])
+            cover[y0:y1, x0:x1] += 1
+            merged_seen += b.lod > 0
+            if b.lod > 0:
+                assert not any(blocks[c].aabb_min[0] >= x0 and blocks[c].aabb_max[0] <= x1 and
+                               blocks[c].aabb_min[1] >= y0 and blocks[c].aabb_max[1] <= y1 for c in contracted)
+        assert cover.max() <= 1
+        unculled = list(O.select(v, blocks, zt, thresholds=(1.0, 2.0), cull=False, quadtree=True))
+        a = O.render(ob, occs, v, sel, p, w)
+        b = O.render(ob, occs, v, unculled, p, w)
+        assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["trans"], b["trans"])
+        assert a["order_ok"].all()
+    assert merged_seen > 0
+
+
+def test_step_cap_truncates_the_exterior_behind_it(contraction_city):
+    """The cap of max_steps steps from scene entry truncates a ray: when it
+    ends before the ray leaves the footprint's column, the exterior beyond
+    the column is not sampled either (no hole followed by more samples).  An
+    axis ray at y = 0.5, z = 0.2 from x = -0.5 crosses the 4-wide city from
+    t = 0.5 to t = 4.5 (2048 steps of 1/512 in the box): with a cap of 1024
+    its samples are the exterior before the column plus 1024 box steps; with
+    a cap of 4096 they add the 2048 box steps and the exterior after it."""
+    blocks, ob, occs, zt = contraction_city
+    v = axis_view((-0.5, 0.5, 0.2), (1.0, 0.0, 0.0))
+    allb = list(range(len(blocks)))
+    o, d = (-0.5, 0.5, 0.2), (1.0, 0.0, 0.0)
+    base = dict(mode=1, ext_delta=1.0 / 32, ext_max_steps=256)
+    pre, _ = O.ext_samples(ob, occs, allb, sg.RenderParams(**base), o, d, 0.0, 0.5, 0)
+    post, _ = O.ext_samples(ob, occs, allb, sg.RenderParams(**base), o, d, 4.5, np.inf, 1)
+    assert len(pre) > 0 and len(post) > 0
+    capped = O.render(ob, occs, v, allb, sg.RenderParams(max_steps=1024, **base), zero_mlp())
+    full = O.render(ob, occs, v, allb, sg.RenderParams(max_steps=4096, **base), zero_mlp())
+    assert capped["n_march"][0] == len(pre) + 1024
+    assert full["n_march"][0] == len(pre) + 2048 + len(post)
