@@ -105,11 +105,18 @@ def main():
         march_ms.append(r.last_timing()[0])
     r.set_timing(False)
     torch.cuda.synchronize()
+    # one step = the whole per-frame path: the view's block set (selection on
+    # the host: culling and depth order), then the render
     t_start = time.perf_counter()
     for _ in range(steps):
-        r.render([view], [sel], params, mlp, out=out)
+        sel_t = r.select(view, thresholds=(1e30,), cull=True)
+        r.render([view], [sel_t], params, mlp, out=out)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t_start) * 1e3 / steps
+    t_sel = time.perf_counter()
+    for _ in range(100):
+        r.select(view, thresholds=(1e30,), cull=True)
+    select_ms = (time.perf_counter() - t_sel) * 1e3 / 100
     msamples = n_eval / (ms * 1e-3) / 1e6
     fps = 1000.0 / ms
     k_ms = float(np.mean(march_ms))
@@ -132,6 +139,7 @@ def main():
                    "pixels": view.n_pixels, "evaluated_samples": n_eval, "marched_samples": n_march,
                    "blocks": len(sel)},
         "fps_1080p": round(fps, 2),
+        "select_ms": round(select_ms, 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
                      "kernel": "march_fwd_kernel<1,false> (uint8, grid sampling)", "kernel_ms": round(k_ms, 4),

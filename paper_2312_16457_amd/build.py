@@ -1,6 +1,7 @@
 """Build the HIP library (libcow.so) for gfx950 with hipcc, in-tree."""
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 
@@ -21,10 +22,27 @@ HIP_FLAGS = [
 ]
 
 
+SOURCES = ("cow_march.hip", "cow_march_bwd.hip", "cow_mlp.hip", "cow_reg.hip", "cow_gather.hip", "cow_host.cpp")
+
+
+def source_digest():
+    """First 16 hex digits of the SHA-256 of the library's sources and headers
+    (part of the autotuner's cache key)."""
+    h = hashlib.sha256()
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp", ".h")))
+    for f in names:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    with open(os.path.join(ROOT, "include", "cow.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build_library(verbose=False):
-    srcs = [os.path.join(CSRC, f) for f in ("cow_march.hip", "cow_march_bwd.hip", "cow_mlp.hip", "cow_reg.hip", "cow_gather.hip", "cow_host.cpp")]
+    srcs = [os.path.join(CSRC, f) for f in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = ["hipcc"] + HIP_FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + srcs
+    cmd = ["hipcc"] + HIP_FLAGS + [f'-DCOW_SOURCE_DIGEST="{source_digest()}"', "-I", os.path.join(ROOT, "include"),
+                                   "-o", tmp] + srcs
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd, stderr=None if verbose else subprocess.DEVNULL)

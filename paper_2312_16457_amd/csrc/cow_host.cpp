@@ -14,6 +14,11 @@
 #include "cow.h"
 #include "cow_internal.h"
 
+// digest of the library's sources, set by the build (tune-cache key)
+#ifndef COW_SOURCE_DIGEST
+#define COW_SOURCE_DIGEST "unversioned"
+#endif
+
 using cow::DevBlock;
 using cow::DevView;
 
@@ -37,6 +42,17 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
 };
+
+// one pinned host buffer for table uploads and the event that marks the end
+// of the copy that last read it
+struct Staging {
+    unsigned char* buf = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+constexpr int kStagingSlots = 4;
+constexpr size_t kStagingInitial = 1 << 18;  // per slot, allocated by cow_create
 
 // default launch: 8x8 ray packets, four waves per workgroup, XCD-chunked
 // packet order (measured fastest on the 4x4-block 1080p frame; the
@@ -63,11 +79,11 @@ struct cow_ctx {
     // sparse bricks
     bool bricks_packed = false;
     size_t brick_bytes = 0;
-    // pinned staging for table uploads
-    unsigned char* pinned = nullptr;
-    size_t pinned_bytes = 0;
-    hipEvent_t staging_done = nullptr;
-    bool staging_pending = false;
+    // pinned staging for table uploads: a ring of slots, each reused only
+    // once the copy that last read it has finished, so the host can run
+    // several calls ahead of the device
+    Staging staging[kStagingSlots];
+    int staging_next = 0;
     // graphs are captured on this stream (the caller's may be the null
     // stream, which cannot capture) and launched on the caller's
     hipStream_t capture_stream = nullptr;
@@ -212,18 +228,32 @@ size_t load_layout(const cow_block_desc* b, int n, std::vector<size_t>* occ_off,
     return off;
 }
 
-cow_status ensure_pinned(cow_ctx* c, size_t bytes) {
-    if (c->staging_pending) {
-        HIP_TRY(c, hipEventSynchronize(c->staging_done));
-        c->staging_pending = false;
+// The next staging slot, at least `bytes` long: waits only for the copy
+// that last read this slot (kStagingSlots calls back), and grows the slot
+// when it is too small (the only allocation on the render path).
+cow_status take_staging(cow_ctx* c, size_t bytes, Staging** out) {
+    Staging& st = c->staging[c->staging_next];
+    c->staging_next = (c->staging_next + 1) % kStagingSlots;
+    if (st.pending) {
+        HIP_TRY(c, hipEventSynchronize(st.done));
+        st.pending = false;
     }
-    if (bytes <= c->pinned_bytes) return COW_OK;
-    if (c->pinned) HIP_TRY(c, hipHostFree(c->pinned));
-    c->pinned = nullptr;
-    c->pinned_bytes = 0;
-    size_t want = std::max<size_t>(bytes, 1 << 16);
-    HIP_TRY(c, hipHostMalloc((void**)&c->pinned, want, hipHostMallocDefault));
-    c->pinned_bytes = want;
+    if (bytes > st.bytes) {
+        if (st.buf) HIP_TRY(c, hipHostFree(st.buf));
+        st.buf = nullptr;
+        st.bytes = 0;
+        const size_t want = std::max(bytes, kStagingInitial);
+        HIP_TRY(c, hipHostMalloc((void**)&st.buf, want, hipHostMallocDefault));
+        st.bytes = want;
+    }
+    *out = &st;
+    return COW_OK;
+}
+
+// mark a slot busy until the work enqueued on s so far (its copy) is done
+cow_status release_staging(cow_ctx* c, Staging* st, hipStream_t s) {
+    HIP_TRY(c, hipEventRecord(st->done, s));
+    st->pending = true;
     return COW_OK;
 }
 
@@ -484,15 +514,14 @@ cow_status check_dtypes(cow_ctx* c, const CallTables& T, int* dtype) {
 
 cow_status upload_tables(cow_ctx* c, const CallTables& T, const RenderWs& w, hipStream_t s) {
     const size_t vb = sizeof(DevView) * T.views.size(), rb = 4 * T.refs.size();
-    cow_status st = ensure_pinned(c, vb + rb + 64);
+    Staging* sl = nullptr;
+    cow_status st = take_staging(c, align_up(vb) + rb + 64, &sl);
     if (st != COW_OK) return st;
-    memcpy(c->pinned, T.views.data(), vb);
-    memcpy(c->pinned + align_up(vb), T.refs.data(), rb);
-    if (vb) HIP_TRY(c, hipMemcpyAsync(w.views, c->pinned, vb, hipMemcpyHostToDevice, s));
-    if (rb) HIP_TRY(c, hipMemcpyAsync(w.refs, c->pinned + align_up(vb), rb, hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipEventRecord(c->staging_done, s));
-    c->staging_pending = true;
-    return COW_OK;
+    memcpy(sl->buf, T.views.data(), vb);
+    memcpy(sl->buf + align_up(vb), T.refs.data(), rb);
+    if (vb) HIP_TRY(c, hipMemcpyAsync(w.views, sl->buf, vb, hipMemcpyHostToDevice, s));
+    if (rb) HIP_TRY(c, hipMemcpyAsync(w.refs, sl->buf + align_up(vb), rb, hipMemcpyHostToDevice, s));
+    return release_staging(c, sl, s);
 }
 
 cow::MarchArgs march_args(cow_ctx* c, const CallTables& T, const RenderWs& w,
@@ -769,9 +798,13 @@ cow_status cow_create(cow_ctx** out, int device) {
     }
     c->n_cus = prop.multiProcessorCount;
     c->arch = prop.gcnArchName;
-    if (hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming) != hipSuccess) {
-        delete c;
-        return COW_E_HIP;
+    for (auto& st : c->staging) {
+        if (hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void**)&st.buf, kStagingInitial, hipHostMallocDefault) != hipSuccess) {
+            cow_destroy(c);
+            return COW_E_HIP;
+        }
+        st.bytes = kStagingInitial;
     }
     *out = c;
     return COW_OK;
@@ -780,10 +813,13 @@ cow_status cow_create(cow_ctx** out, int device) {
 cow_status cow_destroy(cow_ctx* c) {
     if (!c) return COW_E_INVALID;
     (void)hipSetDevice(c->device);
-    if (c->staging_pending) (void)hipEventSynchronize(c->staging_done);
+    for (auto& st : c->staging)
+        if (st.pending) (void)hipEventSynchronize(st.done);
     drop_graphs(c);
-    if (c->pinned) (void)hipHostFree(c->pinned);
-    if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+    for (auto& st : c->staging) {
+        if (st.buf) (void)hipHostFree(st.buf);
+        if (st.done) (void)hipEventDestroy(st.done);
+    }
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -907,10 +943,13 @@ cow_status cow_load_blocks(cow_ctx* c, const cow_block_desc* blocks, int n, void
         }
     }
     const size_t tb = sizeof(DevBlock) * (size_t)n;
-    cow_status st = ensure_pinned(c, tb);
+    Staging* sl = nullptr;
+    cow_status st = take_staging(c, tb, &sl);
     if (st != COW_OK) return st;
-    memcpy(c->pinned, c->h_blocks.data(), tb);
-    HIP_TRY(c, hipMemcpyAsync(c->d_blocks, c->pinned, tb, hipMemcpyHostToDevice, stream));
+    memcpy(sl->buf, c->h_blocks.data(), tb);
+    HIP_TRY(c, hipMemcpyAsync(c->d_blocks, sl->buf, tb, hipMemcpyHostToDevice, stream));
+    st = release_staging(c, sl, stream);
+    if (st != COW_OK) return st;
     for (int i = 0; i < n; ++i) {
         HIP_TRY(c, cow::launch_occupancy(c->d_blocks, i, (int)occ_cells(blocks[i]), stream));
         HIP_TRY(c, cow::launch_occupancy_pyramid(c->d_blocks, i, c->h_blocks[i].n_levels, c->h_blocks[i].od, stream));
@@ -1216,18 +1255,19 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     const size_t vb = sizeof(DevView) * T.views.size(), rb = 4 * T.refs.size(), pb = sizeof(float*) * ptrs.size();
     const size_t jb = sizeof(cow::FoldJob) * jobs.size();
     const size_t o_ref = align_up(vb), o_ptr = o_ref + align_up(rb), o_job = o_ptr + align_up(pb);
-    st = ensure_pinned(c, o_job + jb);
+    Staging* sl = nullptr;
+    st = take_staging(c, o_job + jb, &sl);
     if (st != COW_OK) return st;
-    memcpy(c->pinned, T.views.data(), vb);
-    memcpy(c->pinned + o_ref, T.refs.data(), rb);
-    memcpy(c->pinned + o_ptr, ptrs.data(), pb);
-    if (jb) memcpy(c->pinned + o_job, jobs.data(), jb);
-    HIP_TRY(c, hipMemcpyAsync(w.views, c->pinned, vb, hipMemcpyHostToDevice, s));
-    if (rb) HIP_TRY(c, hipMemcpyAsync(w.refs, c->pinned + o_ref, rb, hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipMemcpyAsync(w.grad_ptrs, c->pinned + o_ptr, pb, hipMemcpyHostToDevice, s));
-    if (jb) HIP_TRY(c, hipMemcpyAsync(w.jobs, c->pinned + o_job, jb, hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipEventRecord(c->staging_done, s));
-    c->staging_pending = true;
+    memcpy(sl->buf, T.views.data(), vb);
+    memcpy(sl->buf + o_ref, T.refs.data(), rb);
+    memcpy(sl->buf + o_ptr, ptrs.data(), pb);
+    if (jb) memcpy(sl->buf + o_job, jobs.data(), jb);
+    HIP_TRY(c, hipMemcpyAsync(w.views, sl->buf, vb, hipMemcpyHostToDevice, s));
+    if (rb) HIP_TRY(c, hipMemcpyAsync(w.refs, sl->buf + o_ref, rb, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(w.grad_ptrs, sl->buf + o_ptr, pb, hipMemcpyHostToDevice, s));
+    if (jb) HIP_TRY(c, hipMemcpyAsync(w.jobs, sl->buf + o_job, jb, hipMemcpyHostToDevice, s));
+    st = release_staging(c, sl, s);
+    if (st != COW_OK) return st;
     HIP_TRY(c, cow::launch_shadow_zero(w.jobs, (int)jobs.size(), max_texels, s));
     cow::MlpBwdArgs mb{};
     mb.views = w.views;
@@ -1303,14 +1343,15 @@ cow_status cow_sparsity(cow_ctx* c, const cow_block_set* set, const float* pts, 
             ptrs[e] = grad_grid[e];
             for (int k = 0; k < 3; ++k) ptrs[ne + 3 * e + k] = grad_plane[3 * e + k];
         }
-    cow_status st = ensure_pinned(c, ib + pb);
+    Staging* sl = nullptr;
+    cow_status st = take_staging(c, ib + pb, &sl);
     if (st != COW_OK) return st;
-    memcpy(c->pinned, idx.data(), 4 * idx.size());
-    memcpy(c->pinned + ib, ptrs.data(), pb);
+    memcpy(sl->buf, idx.data(), 4 * idx.size());
+    memcpy(sl->buf + ib, ptrs.data(), pb);
     unsigned char* d = (unsigned char*)ws;
-    HIP_TRY(c, hipMemcpyAsync(d, c->pinned, ib + pb, hipMemcpyHostToDevice, s));
-    HIP_TRY(c, hipEventRecord(c->staging_done, s));
-    c->staging_pending = true;
+    HIP_TRY(c, hipMemcpyAsync(d, sl->buf, ib + pb, hipMemcpyHostToDevice, s));
+    st = release_staging(c, sl, s);
+    if (st != COW_OK) return st;
     cow::SparsityArgs a{};
     a.blocks = c->d_blocks;
     a.set = (const int32_t*)d;
@@ -1393,10 +1434,12 @@ cow_status cow_autotune(cow_ctx* c, const cow_view* views, int n_views, const co
         n_pix += (int64_t)views[v].crop_w * views[v].crop_h;
         n_refs += sets[v].n;
     }
-    // cache key: device, workload shape, library layout
+    // cache key: device, workload shape, and the digest of the library's
+    // sources (a rebuilt kernel may prefer another configuration)
     char key[256];
-    snprintf(key, sizeof key, "%s|cu%d|v%d|p%lld|r%lld|m%d|s%d|f%d|dt%d", c->arch.c_str(), c->n_cus, n_views,
-             (long long)n_pix, (long long)n_refs, p->mode, p->max_steps, p->flags & COW_F_SPARSE, c->dtype);
+    snprintf(key, sizeof key, "%s|cu%d|v%d|p%lld|r%lld|m%d|s%d|f%d|dt%d|src%s", c->arch.c_str(), c->n_cus, n_views,
+             (long long)n_pix, (long long)n_refs, p->mode, p->max_steps, p->flags & COW_F_SPARSE, c->dtype,
+             COW_SOURCE_DIGEST);
     // cache: one JSON object per line
     if (cache_path) {
         FILE* f = fopen(cache_path, "r");
@@ -1424,12 +1467,40 @@ cow_status cow_autotune(cow_ctx* c, const cow_view* views, int n_views, const co
     float* trans = rgb + 3 * n_pix;
     const TuneCfg saved = c->cfg;
     const bool saved_timing = c->timing;
-    hipEvent_t e0, e1;
-    HIP_TRY(c, hipEventCreate(&e0));
-    HIP_TRY(c, hipEventCreate(&e1));
+    // events and the context's configuration are restored on every exit
+    struct Guard {
+        cow_ctx* c;
+        TuneCfg cfg;
+        bool timing;
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Guard() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+            c->timing = timing;
+        }
+    } guard{c, saved, saved_timing};
+    HIP_TRY(c, hipEventCreate(&guard.e[0]));
+    HIP_TRY(c, hipEventCreate(&guard.e[1]));
     cow_render_params q = *p;
     q.flags &= COW_F_SPARSE;
     q.counts = nullptr;
+    // one warm-up render and three timed ones in configuration t; any failure
+    // ends the sweep with that status and the previous configuration restored
+    auto trial = [&](const TuneCfg& t, float* ms) -> cow_status {
+        c->cfg = t;
+        c->timing = false;
+        cow_status r = render_impl(c, views, n_views, sets, &q, mlp, rgb, trans, nullptr, ws, ws_bytes, s);
+        if (r != COW_OK) return r;
+        HIP_TRY(c, hipEventRecord(guard.e[0], s));
+        for (int it = 0; it < 3; ++it) {
+            r = render_impl(c, views, n_views, sets, &q, mlp, rgb, trans, nullptr, ws, ws_bytes, s);
+            if (r != COW_OK) return r;
+        }
+        HIP_TRY(c, hipEventRecord(guard.e[1], s));
+        HIP_TRY(c, hipEventSynchronize(guard.e[1]));
+        HIP_TRY(c, hipEventElapsedTime(ms, guard.e[0], guard.e[1]));
+        return COW_OK;
+    };
     float best = INFINITY;
     TuneCfg best_cfg = saved;
     const int tws[] = {8, 16, 4, 32};
@@ -1437,31 +1508,19 @@ cow_status cow_autotune(cow_ctx* c, const cow_view* views, int n_views, const co
     for (int persistent = 0; persistent < 2; ++persistent)
         for (int tw : tws)
             for (int wv : wvs) {
-                c->cfg = TuneCfg{tw, wv, persistent};
-                c->timing = false;
-                st = render_impl(c, views, n_views, sets, &q, mlp, rgb, trans, nullptr, ws, ws_bytes, s);
-                if (st != COW_OK) break;
-                HIP_TRY(c, hipEventRecord(e0, s));
-                for (int it = 0; it < 3; ++it) {
-                    st = render_impl(c, views, n_views, sets, &q, mlp, rgb, trans, nullptr, ws, ws_bytes, s);
-                    if (st != COW_OK) break;
+                const TuneCfg t{tw, wv, persistent};
+                float ms = 0.0f;
+                st = trial(t, &ms);
+                if (st != COW_OK) {
+                    c->cfg = saved;
+                    drop_graphs(c);
+                    return st;
                 }
-                HIP_TRY(c, hipEventRecord(e1, s));
-                HIP_TRY(c, hipEventSynchronize(e1));
-                float ms = 0;
-                HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
                 if (ms < best) {
                     best = ms;
-                    best_cfg = c->cfg;
+                    best_cfg = t;
                 }
             }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    c->timing = saved_timing;
-    if (st != COW_OK) {
-        c->cfg = saved;
-        return st;
-    }
     c->cfg = best_cfg;
     drop_graphs(c);
     if (cache_path) {
