@@ -31,6 +31,11 @@ PEAK_HBM_GBS = 8000.0
 #   interpolation weights 30, decode q*s+o 4 x 8 x 2 = 64, texture sum 3 x 8 = 24,
 #   activations (exp + 7 sigmoid) 22, alpha / weight / composite of 7 values / T 20
 FLOPS_PER_SAMPLE = 128 + 192 + 30 + 64 + 24 + 22 + 20  # 480
+# the same sample counted as vector-ALU operations (an FMA is one), the
+# measure of the work a sample needs quoted beside the flop count: about 200
+# FMA (interpolation, weights, decode, composite), 160 byte conversions,
+# 9 exp + 7 rcp, rounded to 450
+VALU_OPS_PER_SAMPLE = 450
 BYTES_PER_SAMPLE_U8 = 160  # 20 texels x 8 uint8 channels gathered per evaluated sample
 
 
@@ -70,7 +75,8 @@ def main():
     __graft_entry__._ensure_built()
     from paper_2312_16457_amd import Renderer, scenegen as sg
     if args.profile and args.leg != "fwd":
-        fn = {"bwd": leg_backward, "batched": lambda *a, **k: leg_batched(*a, **k)[0], "quadtree": leg_quadtree,
+        fn = {"bwd": lambda *a, **k: leg_backward(*a, **k)[0], "batched": lambda *a, **k: leg_batched(*a, **k)[0],
+              "quadtree": leg_quadtree,
               "variants": leg_variants, "opaque": leg_opaque, "empty": leg_empty_space,
               "contract": leg_contracted}
         print(json.dumps({"leg": args.leg, **fn[args.leg](torch, sg, Renderer, reps=1)}), flush=True)
@@ -145,6 +151,10 @@ def main():
                      "kernel": "march_fwd_kernel<1,false> (uint8, grid sampling)", "kernel_ms": round(k_ms, 4),
                      "algorithmic_tflop_per_launch": round(FLOPS_PER_SAMPLE * n_eval / 1e12, 4),
                      "flops_per_sample": FLOPS_PER_SAMPLE,
+                     "frac_basis": "480 algorithmic fp32 flops per evaluated sample (an FMA counts 2)",
+                     "valu_ops_per_sample": VALU_OPS_PER_SAMPLE,
+                     "frac_at_valu_ops": round(VALU_OPS_PER_SAMPLE * n_eval / (k_ms * 1e-3) / 1e12 /
+                                               PEAK_FP32_TFLOPS, 4),
                      "gathered_GBps": round(BYTES_PER_SAMPLE_U8 * n_eval / (k_ms * 1e-3) / 1e9, 1)},
     }
     log(f"forward {ms:.2f} ms per frame")
@@ -155,11 +165,16 @@ def main():
         res["cpu_baseline"] = cpu_baseline(scene, view, sel, params, w)
         log("cpu baseline done")
     res["roofline"]["traffic"] = recorded_traffic()
+    comp = compulsory_bytes()
+    if comp:
+        res["roofline"]["hbm_compulsory_bytes"] = comp
+        if res["roofline"]["traffic"]:
+            res["roofline"]["traffic_over_compulsory"] = round(res["roofline"]["traffic"] / comp, 2)
     if not args.no_extras and not args.profile:
         res["variants"] = forward_variants(torch, sg, r, view, sel, params, mlp, ms)
         del r, out
         torch.cuda.empty_cache()
-        res["extras"] = extras(torch, sg, Renderer)
+        res["extras"] = extras(torch, sg, Renderer, cpu=res.get("cpu_baseline"))
     print(json.dumps(res), flush=True)
 
 
@@ -183,6 +198,17 @@ def recorded_traffic():
     if rec.get("source_digest") != source_digest():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def compulsory_bytes():
+    """The march's compulsory HBM bytes per launch on the bench frame: the
+    unique 128-byte texture lines its evaluated samples read, the occupancy
+    bytes and its outputs, as counted by the oracle's committed script
+    (oracle/compulsory_bytes.py; the record names its command)."""
+    path = os.path.join(ROOT, "profiles", "compulsory_bytes_4x4_1080p.json")
+    if not os.path.exists(path):
+        return None
+    return json.load(open(path)).get("compulsory_bytes_march")
 
 
 def gather_ceiling(torch, view, n_eval, march_GBps):
@@ -211,23 +237,132 @@ def gather_ceiling(torch, view, n_eval, march_GBps):
     return out
 
 
+def _threads():
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+
+
+def host_cpu():
+    """CPU model, cores and SMT of the host, from lscpu."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+    except Exception:
+        pass
+    return {"model": info.get("Model name"), "sockets": info.get("Socket(s)"),
+            "cores_per_socket": info.get("Core(s) per socket"), "threads_per_core": info.get("Thread(s) per core"),
+            "logical_cpus": info.get("CPU(s)"), "threads_used": _threads()}
+
+
+def _oracle_rate(O, ob, occs, view, set_idx, params, w, pix, fp32=False, threads=None):
+    t = time.perf_counter()
+    ref = O.render(ob, occs, view, set_idx, params, w, pix=pix, nthreads=threads or _threads(), fp32=fp32)
+    dt = time.perf_counter() - t
+    n = int(ref["n_eval"].sum())
+    return {"Msamples_per_s": round(n / dt / 1e6, 3), "seconds": round(dt, 2), "evaluated_samples": n,
+            "rays": int(len(pix))}
+
+
 def cpu_baseline(scene, view, sel, params, w):
     """The CPU oracle, as it stands, on every second row of the same frame
-    (about 10 s of work on 16 host threads)."""
+    (about 10 s of work on 16 host threads), in fp64 (the oracle) and in its
+    single-precision build (the same decisions, continuous per-sample math in
+    float); plus the single-block frame in full."""
     import oracle as O
     ob = O.OracleScene(scene.blocks)
     occs = [O.occupancy(ob, k) for k in range(ob.n)]
     set_idx = [next(k for k, b in enumerate(scene.blocks) if (b.block_id, b.lod) == s) for s in sel]
     rows = np.arange(0, view.H, 2)
     pix = O.pixels_of(view, rows=rows)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    threads = _threads()
+    f64 = _oracle_rate(O, ob, occs, view, set_idx, params, w, pix)
+    f32 = _oracle_rate(O, ob, occs, view, set_idx, params, w, pix, fp32=True)
+    res = {"value": f64["Msamples_per_s"], "unit": "Msamples/s", "cores": threads,
+           "kind": "oracle", "sample": f"every second row of the 1920x1080 frame ({len(rows)} rows, "
+                                       f"{len(pix)} rays, {f64['evaluated_samples']} evaluated samples), "
+                                       f"fp64, {f64['seconds']:.1f}s",
+           "host": host_cpu(), "fp32": f32,
+           "note": "the oracle is a plain per-ray reference, not a tuned CPU renderer; Msamples/s counts "
+                   "evaluated samples"}
+    del ob, occs
+    from paper_2312_16457_amd import scenegen as sg
+    c1 = sg.c1_scene()
+    ob1 = O.OracleScene(c1.blocks)
+    occ1 = [O.occupancy(ob1, 0)]
+    v1 = sg.c1_view()
+    pix1 = O.pixels_of(v1)
+    w1 = sg.xavier_mlp(0)
+    res["legs"] = {"single_block_128x128_full_frame": {
+        "fp64": _oracle_rate(O, ob1, occ1, v1, [0], sg.c1_params(), w1, pix1),
+        "fp32": _oracle_rate(O, ob1, occ1, v1, [0], sg.c1_params(), w1, pix1, fp32=True)}}
+    return res
+
+
+def cpu_baseline_lod(scene, sg):
+    """The oracle on the 8x8x3-LOD city: the 16 aerial 1080p views (two of
+    them, every 16th row) and the 64-view batch (every 512th row of every
+    view), fp64 and fp32; rates are evaluated samples per second on that
+    sample, which equal the whole workload's by construction of the unit
+    (extrapolated, labelled)."""
+    import oracle as O
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    zt = [O.ztop(ob, k, occs[k]) for k in range(ob.n)]
+    p = sg.cityb_params()
+    w = sg.xavier_mlp(3)
+    out = {}
+    for name, views, every in (("lod_city_aerial_16x1080p", sg.c3_views()[:2], 16),
+                               ("batched_64_views", sg.c4_views(), 512)):
+        legs = {}
+        for fp32 in (False, True):
+            t = time.perf_counter()
+            n = rays = 0
+            for v in views:
+                sel = O.select(v, scene.blocks, zt, thresholds=(2.0, 4.0, 8.0), cull=True)
+                pix = O.pixels_of(v, rows=np.arange(0, v.H, every))
+                r = O.render(ob, occs, v, sel, p, w, pix=pix, nthreads=_threads(), fp32=fp32)
+                n += int(r["n_eval"].sum())
+                rays += len(pix)
+            dt = time.perf_counter() - t
+            legs["fp32" if fp32 else "fp64"] = {"Msamples_per_s": round(n / dt / 1e6, 3), "seconds": round(dt, 2),
+                                                "evaluated_samples": n, "rays": rays}
+        legs["sample"] = (f"{len(views)} views, every {every}th row (extrapolated: the rate over this sample "
+                          "stands for the whole workload)")
+        out[name] = legs
+    return out
+
+
+def cpu_baseline_adjoint(learn, sg):
+    """The fp64 adjoint (one thread: the oracle's adjoint is serial) on the
+    64x64 crop of the differentiable workload's view 0 with the most evaluated
+    samples among 16 seeded windows (counted by the oracle)."""
+    import oracle as O
+    ob = O.OracleScene(learn.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    setv = list(range(ob.n))
+    v0 = sg.c5_views()[0]
+    p = sg.cityb_params()
+    w = sg.xavier_mlp(4)
+    rng = np.random.default_rng(0)
+    cands = [(int(rng.integers(0, 800 - 64)), int(rng.integers(0, 800 - 64))) for _ in range(16)]
+
+    def score(c):
+        pix = np.array([[c[0] + i, c[1] + j] for j in range(0, 64, 8) for i in range(0, 64, 8)], np.int32)
+        return int(O.render(ob, occs, v0, setv, p, w, pix=pix)["n_eval"].sum())
+    x0, y0 = max(cands, key=score)
+    crop = v0.with_crop(x0, y0, 64, 64)
+    pix = O.pixels_of(crop)
+    r = O.render(ob, occs, crop, setv, p, w, pix=pix)
+    n = int(r["n_eval"].sum())
+    g = np.random.default_rng(1).uniform(-1e-3, 1e-3, (len(pix), 3))
     t = time.perf_counter()
-    ref = O.render(ob, occs, view, set_idx, params, w, pix=pix, nthreads=threads)
+    O.adjoint(ob, occs, crop, setv, p, w, pix, g)
     dt = time.perf_counter() - t
-    return {"value": round(ref["n_eval"].sum() / dt / 1e6, 3), "unit": "Msamples/s", "cores": threads,
-            "kind": "oracle", "sample": f"every second row of the 1920x1080 frame ({len(rows)} rows, "
-                                        f"{len(pix)} rays, {int(ref['n_eval'].sum())} evaluated samples), "
-                                        f"fp64, {dt:.1f}s"}
+    return {"Msamples_per_s": round(n / dt / 1e6, 3), "seconds": round(dt, 2), "evaluated_samples": n,
+            "cores": 1, "sample": f"64x64 crop at ({x0}, {y0}) of view 0, fp64 adjoint"}
 
 
 def log(msg, t0=[time.time()]):
@@ -454,10 +589,13 @@ def leg_backward(torch, sg, Renderer, reps=2):
     res["fwd_gather_frac"] = round(res["fwd_gathered_GBps"] / probe, 4)
     del tex
     torch.cuda.empty_cache()
-    return res
+    return res, learn
 
 
 def _time_launches(torch, r, views, sets, p, mlp, reps, tag):
+    """The batch three ways: one graph-replayed launch over every view, one
+    fused launch (march + MLP) per view, and one launch per view per block
+    (the paper's one-shader-per-block design)."""
     from paper_2312_16457_amd import F_GRAPH, F_PER_BLOCK
     out = r.render(views, sets, p, mlp, want_aux=False)
     timings = {}
@@ -470,6 +608,15 @@ def _time_launches(torch, r, views, sets, p, mlp, reps, tag):
             r.render(views, sets, p, mlp, out=out, flags=flags)
         torch.cuda.synchronize()
         timings[name] = (time.perf_counter() - t) * 1e3 / reps
+    del out
+    log(f"{tag}: timing per_view_launches")
+    outs = [r.render([v], [s], p, mlp, want_aux=False) for v, s in zip(views, sets)]
+
+    def per_view():
+        for v, s, o in zip(views, sets, outs):
+            r.render([v], [s], p, mlp, out=o)
+    timings["per_view_launches"] = _timed(torch, per_view, reps)
+    del outs
     return timings
 
 
@@ -501,20 +648,52 @@ def leg_batched(torch, sg, Renderer, reps=2):
     ms16 = _timed(torch, frames, reps)
     del outs
     tb = timings["batched_graph"]
+    del r
+    torch.cuda.empty_cache()
+    # gather rate of the batch and of the 16 aerial frames against the probe
+    # at the LOD city's footprint class (HBM-resident: 8 x 8 blocks of 128^3
+    # + 3 x 1024^2, 2.5 GiB, at the batch's mean evaluated samples per ray)
+    gat = lod_city_gather(torch, sg, n_eval / n_pix, {"batched_64_views": (n_eval, tb), "aerial_16x1080p": (n16, ms16)})
     res = {"views": len(views), "pixels": n_pix, "evaluated_samples": n_eval,
            "blocks_per_view": [min(len(s) for s in sets), max(len(s) for s in sets)],
            "launches_per_block_mode": sum(max(len(s), 1) for s in sets) + 1,
            "ms_batched": round(tb, 2), "ms_per_block": round(timings["per_block_launches"], 2),
+           "ms_per_view": round(timings["per_view_launches"], 2),
            "speedup_vs_per_block": round(timings["per_block_launches"] / tb, 3),
+           "speedup_vs_per_view": round(timings["per_view_launches"] / tb, 3),
            "Msamples_per_s": round(n_eval / (tb * 1e-3) / 1e6, 1),
            "fps_1080p_equivalent": round(n_pix / (tb * 1e-3) / 2073600, 2),
            "workload": "8x8 blocks x 3 LODs uint8, 64 views {256^2, 800^2, 1280x720, 1920x1080}",
            "aerial_16x1080p": {"ms_per_frame": round(ms16 / len(v16), 3), "fps": round(1e3 * len(v16) / ms16, 2),
                                "evaluated_samples": n16, "Msamples_per_s": round(n16 / (ms16 * 1e-3) / 1e6, 1),
-                               "blocks_per_view": [min(len(x) for x in s16), max(len(x) for x in s16)]}}
-    del r
-    torch.cuda.empty_cache()
+                               "blocks_per_view": [min(len(x) for x in s16), max(len(x) for x in s16)]},
+           "gather": gat}
     return res, scene
+
+
+def lod_city_gather(torch, sg, steps_per_ray, legs):
+    """The texel-gather probe on a 1920x1080 view over an 8 x 8 field of
+    uint8 blocks of 128^3 + 3 x 1024^2 (2.5 GiB, the footprint class of the
+    8x8x3-LOD city's 3.1 GiB), at the given mean evaluated samples per ray;
+    each leg's gathered bytes per second (160 B per evaluated sample) as a
+    fraction of it."""
+    from paper_2312_16457_amd import COW_U8
+    from paper_2312_16457_amd.binding import gather_probe
+    view = sg.c2_view()
+    steps = max(1, int(round(steps_per_ray)))
+    nbytes = 64 * (128 ** 3 + 3 * 1024 * 1024) * 8
+    tex = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda")
+    gather_probe(view, tex, 8, 8, 128, 1024, COW_U8, steps, 1.0 / 512)
+    best = min(gather_probe(view, tex, 8, 8, 128, 1024, COW_U8, steps, 1.0 / 512)[0] for _ in range(3))
+    probe = view.n_pixels * steps * BYTES_PER_SAMPLE_U8 / (best * 1e-3) / 1e9
+    del tex
+    torch.cuda.empty_cache()
+    out = {"probe_footprint_GiB": round(nbytes / 2 ** 30, 2), "probe_steps_per_ray": steps,
+           "probe_GBps": round(probe, 1)}
+    for name, (n, ms) in legs.items():
+        gb = BYTES_PER_SAMPLE_U8 * n / (ms * 1e-3) / 1e9
+        out[name] = {"gathered_GBps": round(gb, 1), "frac_of_probe": round(gb / probe, 4)}
+    return out
 
 
 def leg_single_block(torch, sg, Renderer, reps=20):
@@ -557,7 +736,9 @@ def leg_quadtree(torch, sg, Renderer, lod_city=None, reps=2):
            "entries_per_view": [min(len(s) for s in sets), max(len(s) for s in sets)],
            "entries_by_lod": [sum(1 for s in sets for _, l in s if l == k) for k in range(3)],
            "ms_batched": round(tb, 2), "ms_per_block": round(timings["per_block_launches"], 2),
+           "ms_per_view": round(timings["per_view_launches"], 2),
            "speedup_vs_per_block": round(timings["per_block_launches"] / tb, 3),
+           "speedup_vs_per_view": round(timings["per_view_launches"] / tb, 3),
            "Msamples_per_s": round(n_eval / (tb * 1e-3) / 1e6, 1),
            "fps_1080p_equivalent": round(n_pix / (tb * 1e-3) / 2073600, 2),
            "workload": "8x8 blocks, quadtree LODs (merged 2x2 and 4x4 assets) uint8, thresholds "
@@ -567,13 +748,21 @@ def leg_quadtree(torch, sg, Renderer, lod_city=None, reps=2):
     return res
 
 
-def extras(torch, sg, Renderer):
+def extras(torch, sg, Renderer, cpu=None):
     """Backward throughput, the batched-vs-per-block comparison on the
-    8x8x3-LOD scene and the same views over quadtree LODs."""
+    8x8x3-LOD scene and the same views over quadtree LODs.  cpu: the CPU
+    baseline's dict, whose legs on these workloads' scenes are added here."""
     ex = {"single_block": leg_single_block(torch, sg, Renderer), "opaque": leg_opaque(torch, sg, Renderer),
-          "empty_space": leg_empty_space(torch, sg, Renderer), "contracted": leg_contracted(torch, sg, Renderer),
-          "bwd": leg_backward(torch, sg, Renderer)}
+          "empty_space": leg_empty_space(torch, sg, Renderer), "contracted": leg_contracted(torch, sg, Renderer)}
+    ex["bwd"], learn = leg_backward(torch, sg, Renderer)
+    if cpu is not None:
+        cpu.setdefault("legs", {})["fp64_adjoint_c5_crop"] = cpu_baseline_adjoint(learn, sg)
+        log("cpu baseline: adjoint leg done")
+    del learn
     ex["batched"], lod_city = leg_batched(torch, sg, Renderer)
+    if cpu is not None:
+        cpu.setdefault("legs", {}).update(cpu_baseline_lod(lod_city, sg))
+        log("cpu baseline: LOD city legs done")
     ex["quadtree"] = leg_quadtree(torch, sg, Renderer, lod_city=lod_city)
     return ex
 

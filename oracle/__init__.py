@@ -20,15 +20,20 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
+# the same source with single-precision continuous arithmetic, for timing only
+LIB32 = os.path.join(HERE, "liboracle_f32.so")
 
 MERGED, MONOLITHIC, REVERSED, BY_ID, ALPHA_NORM, BLOCK_MLP = range(6)
 
 
 def build():
-    """Compile oracle.c with gcc: fp32 decisions must not be contracted."""
-    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-o", LIB, os.path.join(HERE, "oracle.c"), "-lm"]
-    subprocess.check_call(cmd)
+    """Compile oracle.c with gcc: fp32 decisions must not be contracted.  Also
+    the single-precision build (continuous per-sample arithmetic in float,
+    the same decisions), which only the benchmark's CPU baseline times."""
+    base = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+    src = os.path.join(HERE, "oracle.c")
+    subprocess.check_call(base + ["-o", LIB, src, "-lm"])
+    subprocess.check_call(base + ["-DORC_REAL=float", "-o", LIB32, src, "-lm"])
 
 
 class _Block(C.Structure):
@@ -57,15 +62,16 @@ class _Params(C.Structure):
                 ("t_min", C.c_float), ("pe", C.c_int), ("ext_delta", C.c_float), ("ext_max_steps", C.c_int)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB):
+def lib(fp32=False):
+    """The oracle library; fp32=True: its single-precision build (timing only)."""
+    path = LIB32 if fp32 else LIB
+    if path not in _libs:
+        if not os.path.exists(path):
             build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(path)
         vp, ip, dp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double)
         L.orc_occupancy.argtypes = [C.POINTER(_Block), vp]
         L.orc_ztop.argtypes = [C.POINTER(_Block), vp]
@@ -91,6 +97,8 @@ def lib():
         L.orc_select.argtypes = [C.POINTER(_View), C.c_int, vp, vp, vp, vp, vp, vp, vp, C.c_int, C.c_int,
                                  vp, C.c_int]
         L.orc_select_quadtree.argtypes = L.orc_select.argtypes
+        L.orc_touched_texels.argtypes = [C.POINTER(_Block), C.c_int, C.POINTER(C.c_void_p), C.POINTER(_View), vp,
+                                         C.c_int, C.POINTER(_Params), vp, C.c_long, C.POINTER(C.c_void_p), C.c_int]
         L.orc_mlp.argtypes = [vp, vp, vp]
         L.orc_mlp_pe.argtypes = [vp, C.c_int, vp, vp]
         L.orc_mlp_params.argtypes = [C.c_int]
@@ -104,8 +112,8 @@ def lib():
                                       C.POINTER(_Params), vp, vp, C.c_float, C.c_float, C.c_int, vp, vp, C.c_long]
         L.orc_ext_samples.restype = C.c_long
         L.orc_field.argtypes = [C.POINTER(_Block), C.c_int, vp, vp]
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 def _ptr(a):
@@ -280,8 +288,9 @@ def pixels_of(view, rows=None, stride=1):
     return np.stack([ii.reshape(-1), jj.reshape(-1)], axis=1).astype(np.int32)
 
 
-def render(ob, occs, view, set_idx, params, mlp, pix=None, composite=MERGED, nthreads=0):
-    L = lib()
+def render(ob, occs, view, set_idx, params, mlp, pix=None, composite=MERGED, nthreads=0, fp32=False):
+    """fp32=True runs the single-precision build (for timing; not the oracle)."""
+    L = lib(fp32)
     if pix is None:
         pix = pixels_of(view)
     pix = np.ascontiguousarray(pix, np.int32)
@@ -302,6 +311,30 @@ def render(ob, occs, view, set_idx, params, mlp, pix=None, composite=MERGED, nth
                  _ptr(out["aux"]), _ptr(out["n_eval"]), _ptr(out["n_march"]),
                  _ptr(out["order_ok"]), int(nthreads))
     return out
+
+
+def touched_texels(ob, occs, view, set_idx, params, pix=None, nthreads=0):
+    """Per entry of set_idx: four uint8 masks (grid [z][y][x], then the xy,
+    xz, yz planes [v][u]) with 1 at every texel the evaluated samples of the
+    given pixels read (t_min = 0, plain blocks)."""
+    if pix is None:
+        pix = pixels_of(view)
+    pix = np.ascontiguousarray(pix, np.int32)
+    setv = np.ascontiguousarray(set_idx, np.int32)
+    masks = {}
+    arr = (C.c_void_p * (4 * ob.n))()
+    for k in setv:
+        b = ob.blocks[int(k)]
+        ms = [np.zeros(b.grid.shape[:3], np.uint8)] + [np.zeros(p.shape[:2], np.uint8) for p in b.planes]
+        masks[int(k)] = ms
+        for t in range(4):
+            arr[4 * int(k) + t] = ms[t].ctypes.data
+    vs, ps = make_view(view), make_params(params)
+    r = lib().orc_touched_texels(ob.arr, ob.n, _occ_ptrs(ob, occs), C.byref(vs), _ptr(setv), len(setv), C.byref(ps),
+                                 _ptr(pix), pix.shape[0], arr, int(nthreads))
+    if r != 0:
+        raise ValueError("touched texels need t_min = 0 and plain blocks")
+    return masks
 
 
 def ray_blocks(ob, view, set_idx, params, i, j, cap=128):

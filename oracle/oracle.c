@@ -10,14 +10,24 @@
  */
 #include "oracle.h"
 
-#include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <tgmath.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
 
 #define NCH 8
+
+/* Type of the continuous per-sample arithmetic (interpolation, decode,
+ * activations, compositing).  double for the oracle.  A build with
+ * -DORC_REAL=float exists only to time the same code in single precision
+ * (the benchmark's CPU baseline); its decisions are the same fp32 ones.  The
+ * MLP, the adjoint's sums and everything at the interface stay double. */
+#ifndef ORC_REAL
+#define ORC_REAL double
+#endif
+typedef ORC_REAL real;
 
 /* ---------------------------------------------------------------------- */
 /* Discrete decisions in exact fp32                                         */
@@ -143,13 +153,13 @@ static int occ_cell(const orc_block* b, const float p[3], float q[3]) {
 /* Texture access                                                           */
 /* ---------------------------------------------------------------------- */
 
-static double texel(const orc_block* b, int tex, long idx, int ch) {
+static real texel(const orc_block* b, int tex, long idx, int ch) {
     if (b->dtype == ORC_U8) {
         const unsigned char* src = tex == 0 ? b->g8 : b->p8[tex - 1];
-        return (double)src[idx * NCH + ch] * (double)b->scale[tex][ch] + (double)b->offset[tex][ch];
+        return (real)src[idx * NCH + ch] * (real)b->scale[tex][ch] + (real)b->offset[tex][ch];
     }
     const double* src = tex == 0 ? b->gf : b->pf[tex - 1];
-    return src[idx * NCH + ch];
+    return (real)src[idx * NCH + ch];
 }
 
 /* texel value as the fp32 decision sees it: fl(fl(q*s)+o), or the stored value */
@@ -167,14 +177,14 @@ static int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a
 
 /* cell-centred linear interpolation taps with clamp-to-edge: u = q*R - 1/2
  * for R texels per unit length, D texels along the axis */
-static void lin_taps(double q, int R, int D, int idx[2], double w[2]) {
-    double u = q * (double)R - 0.5;
-    double f0 = floor(u);
-    double f = u - f0;
+static void lin_taps(real q, int R, int D, int idx[2], real w[2]) {
+    real u = q * (real)R - (real)0.5;
+    real f0 = floor(u);
+    real f = u - f0;
     int a = (int)f0;
     idx[0] = clampi(a, 0, D - 1);
     idx[1] = clampi(a + 1, 0, D - 1);
-    w[0] = 1.0 - f;
+    w[0] = (real)1 - f;
     w[1] = f;
 }
 
@@ -187,15 +197,15 @@ typedef struct tap {
 /* raw features = grid trilinear + three bilinear planes, summed ((G+XY)+XZ)+YZ.
  * taps (20 entries) receive the texel index and interpolation weight of each
  * texture sample, for the adjoint. */
-static void eval_raw(const orc_block* b, const float q32[3], double raw[NCH], tap* taps) {
-    double q[3] = {q32[0], q32[1], q32[2]};
+static void eval_raw(const orc_block* b, const float q32[3], real raw[NCH], tap* taps) {
+    real q[3] = {q32[0], q32[1], q32[2]};
     int gi[3][2], pi[3][2];
-    double gw[3][2], pw[3][2];
+    real gw[3][2], pw[3][2];
     for (int c = 0; c < 3; ++c) {
         lin_taps(q[c], b->R, dim(b, b->R, c), gi[c], gw[c]);
         lin_taps(q[c], b->Rp, dim(b, b->Rp, c), pi[c], pw[c]);
     }
-    double part[4][NCH];
+    real part[4][NCH];
     memset(part, 0, sizeof(part));
     int nt = 0;
     /* grid [z][y][x] */
@@ -203,7 +213,7 @@ static void eval_raw(const orc_block* b, const float q32[3], double raw[NCH], ta
         for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx) {
                 long idx = ((long)gi[2][dz] * dim(b, b->R, 1) + gi[1][dy]) * dim(b, b->R, 0) + gi[0][dx];
-                double w = gw[2][dz] * gw[1][dy] * gw[0][dx];
+                real w = gw[2][dz] * gw[1][dy] * gw[0][dx];
                 for (int ch = 0; ch < NCH; ++ch) part[0][ch] += w * texel(b, 0, idx, ch);
                 if (taps) taps[nt++] = (tap){0, idx, w};
             }
@@ -214,7 +224,7 @@ static void eval_raw(const orc_block* b, const float q32[3], double raw[NCH], ta
         for (int dv = 0; dv < 2; ++dv)
             for (int du = 0; du < 2; ++du) {
                 long idx = (long)pi[av][dv] * dim(b, b->Rp, au) + pi[au][du];
-                double w = pw[av][dv] * pw[au][du];
+                real w = pw[av][dv] * pw[au][du];
                 for (int ch = 0; ch < NCH; ++ch) part[1 + pl][ch] += w * texel(b, 1 + pl, idx, ch);
                 if (taps) taps[nt++] = (tap){1 + pl, idx, w};
             }
@@ -222,7 +232,7 @@ static void eval_raw(const orc_block* b, const float q32[3], double raw[NCH], ta
     for (int ch = 0; ch < NCH; ++ch) raw[ch] = ((part[0][ch] + part[1][ch]) + part[2][ch]) + part[3][ch];
 }
 
-static double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
+static real sigm(real x) { return (real)1 / ((real)1 + exp(-x)); }
 
 /* ---------------------------------------------------------------------- */
 /* Occupancy: conservative max-bound of the interpolated density           */
@@ -239,6 +249,10 @@ int orc_occupancy(const orc_block* b, unsigned char* out) {
         P[a] = dim(b, Rp, a);
         C[a] = dim(b, O, a);
     }
+    /* cells are independent: split the z layers over threads */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
     for (int cz = 0; cz < C[2]; ++cz)
         for (int cy = 0; cy < C[1]; ++cy)
             for (int cx = 0; cx < C[0]; ++cx) {
@@ -652,7 +666,9 @@ void orc_field(const orc_block* b, int n, const float* pts, double* raw) {
     for (int k = 0; k < n; ++k) {
         float q[3];
         for (int c = 0; c < 3; ++c) q[c] = pts[3 * k + c] - b->lo[c];
-        eval_raw(b, q, raw + NCH * k, NULL);
+        real r8[NCH];
+        eval_raw(b, q, r8, NULL);
+        for (int ch = 0; ch < NCH; ++ch) raw[NCH * k + ch] = r8[ch];
     }
 }
 
@@ -674,10 +690,10 @@ int orc_mlp_pe(const double* mlp, int L, const double* x, double* out) {
 /* ---------------------------------------------------------------------- */
 
 typedef struct pt_val {
-    double sigma, v[7];
+    real sigma, v[7];
 } pt_val;
 
-static void shade(const orc_block* b, const float q[3], pt_val* pv, double raw[NCH], tap* taps) {
+static void shade(const orc_block* b, const float q[3], pt_val* pv, real raw[NCH], tap* taps) {
     eval_raw(b, q, raw, taps);
     pv->sigma = exp(raw[0]);
     for (int c = 0; c < 7; ++c) pv->v[c] = sigm(raw[1 + c]);
@@ -708,17 +724,17 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
      * to the monolithic and the merged composite alike) */
     const double t_min = p->t_min;
     long n_used = n; /* samples up to and including the terminating one */
-    double A[7] = {0}, T = 1.0;
+    real A[7] = {0}, T = 1;
     if (composite == ORC_MONOLITHIC) {
         eval = 0;
         for (long s = 0; s < n; ++s) {
             if (!buf[s].occupied) continue;
             pt_val pv;
-            double raw[NCH];
+            real raw[NCH];
             shade(&blocks[set[buf[s].set_pos]], buf[s].q, &pv, raw, NULL);
-            double sd = pv.sigma * buf[s].delta;
-            double alpha = -expm1(-sd);
-            double w = T * alpha;
+            real sd = pv.sigma * (real)buf[s].delta;
+            real alpha = -expm1(-sd);
+            real w = T * alpha;
             for (int c = 0; c < 7; ++c) A[c] += w * pv.v[c];
             T *= exp(-sd);
             ++eval;
@@ -739,15 +755,15 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
         double Cb[3] = {0, 0, 0};
         while (s < n && !stop) {
             const int run = buf[s].set_pos;
-            double Ak[7] = {0}, Tk = 1.0;
+            real Ak[7] = {0}, Tk = 1;
             for (; s < n && buf[s].set_pos == run; ++s) {
                 if (!buf[s].occupied) continue;
                 pt_val pv;
-                double raw[NCH];
+                real raw[NCH];
                 shade(&blocks[set[run]], buf[s].q, &pv, raw, NULL);
-                double sd = pv.sigma * buf[s].delta;
-                double alpha = -expm1(-sd);
-                double w = Tk * alpha;
+                real sd = pv.sigma * (real)buf[s].delta;
+                real alpha = -expm1(-sd);
+                real w = Tk * alpha;
                 for (int c = 0; c < 7; ++c) Ak[c] += w * pv.v[c];
                 Tk *= exp(-sd);
                 ++eval;
@@ -759,8 +775,9 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
             }
             if (composite == ORC_BLOCK_MLP) {
                 const mlp_shape sh = mlp_shape_of(p->pe);
-                double x[MLP_MAX_IN];
-                mlp_input(Ak, d, p->pe, x);
+                double x[MLP_MAX_IN], Ak64[7];
+                for (int c = 0; c < 7; ++c) Ak64[c] = Ak[c];
+                mlp_input(Ak64, d, p->pe, x);
                 mlp_trace tr;
                 mlp_fwd(mlp + sh.n * (long)set[run], &sh, x, &tr);
                 for (int c = 0; c < 3; ++c) Cb[c] += T * (Ak[c] + tr.s[c]);
@@ -791,7 +808,7 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
             }
             if (!buf[s].occupied) continue;
             pt_val pv;
-            double raw[NCH];
+            real raw[NCH];
             shade(&blocks[set[buf[s].set_pos]], buf[s].q, &pv, raw, NULL);
             double sd = pv.sigma * buf[s].delta;
             double alpha = -expm1(-sd);
@@ -832,8 +849,9 @@ static void render_one(const orc_block* blocks, int nblocks, const unsigned char
     }
     free(run_pos);
     const mlp_shape sh = mlp_shape_of(p->pe);
-    double x[MLP_MAX_IN];
-    mlp_input(A, d, p->pe, x);
+    double x[MLP_MAX_IN], A64[7];
+    for (int c = 0; c < 7; ++c) A64[c] = A[c];
+    mlp_input(A64, d, p->pe, x);
     mlp_trace tr;
     mlp_fwd(mlp, &sh, x, &tr);
     for (int c = 0; c < 3; ++c) rgb[c] = A[c] + tr.s[c];
@@ -892,6 +910,77 @@ int orc_render(const orc_block* blocks, int nblocks, const unsigned char* const*
             if (n_eval) n_eval[q] = ne;
             if (n_march) n_march[q] = nm;
             if (order_ok) order_ok[q] = ok;
+        }
+        free(buf);
+    }
+    (void)nthreads;
+    return 0;
+}
+
+/* Texels the evaluated samples of the given pixels read (the compulsory
+ * texture bytes of a frame, Sec. 4.5 "Baking": the textures a renderer must
+ * fetch at least once): for every sample in an occupied cell, the eight grid
+ * taps and four taps per plane of the interpolation (clamped indices, as in
+ * eval_raw), marked with 1 in marks[4 e + t] (e the entry in `blocks`, t =
+ * 0 grid, 1-3 the xy, xz, yz planes; byte arrays of the textures' texel
+ * counts, NULL to skip).  Without early termination only (t_min = 0): the
+ * samples a terminated ray skips depend on its shading.  Returns 0, or -1
+ * for t_min > 0 or contracted blocks. */
+static void mark_taps(const orc_block* b, const float q32[3], unsigned char* const* mk) {
+    int gi[3][2], pi[3][2];
+    real gw[3][2], pw[3][2];
+    for (int c = 0; c < 3; ++c) {
+        lin_taps((real)q32[c], b->R, dim(b, b->R, c), gi[c], gw[c]);
+        lin_taps((real)q32[c], b->Rp, dim(b, b->Rp, c), pi[c], pw[c]);
+    }
+    if (mk[0])
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    long idx = ((long)gi[2][dz] * dim(b, b->R, 1) + gi[1][dy]) * dim(b, b->R, 0) + gi[0][dx];
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+                    mk[0][idx] = 1;
+                }
+    static const int axes[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int pl = 0; pl < 3; ++pl) {
+        if (!mk[1 + pl]) continue;
+        int au = axes[pl][0], av = axes[pl][1];
+        for (int dv = 0; dv < 2; ++dv)
+            for (int du = 0; du < 2; ++du) {
+                long idx = (long)pi[av][dv] * dim(b, b->Rp, au) + pi[au][du];
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+                mk[1 + pl][idx] = 1;
+            }
+    }
+}
+
+int orc_touched_texels(const orc_block* blocks, int nblocks, const unsigned char* const* occ, const orc_view* v,
+                       const int* set, int nset, const orc_params* p, const int* pix, long npix,
+                       unsigned char* const* marks, int nthreads) {
+    if (p->t_min > 0.0f) return -1;
+    for (int s = 0; s < nset; ++s)
+        if (blocks[set[s]].contracted) return -1;
+    long cap = sample_cap(p, nset);
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+        sample* buf = (sample*)malloc(sizeof(sample) * cap);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+        for (long q = 0; q < npix; ++q) {
+            long n = enumerate(blocks, nblocks, occ, v, set, nset, p, pix[2 * q], pix[2 * q + 1], buf, cap, NULL);
+            for (long k = 0; k < n; ++k) {
+                if (!buf[k].occupied) continue;
+                int e = set[buf[k].set_pos];
+                mark_taps(&blocks[e], buf[k].q, marks + 4 * e);
+            }
         }
         free(buf);
     }
@@ -966,7 +1055,7 @@ int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const
         double T = 1.0, A[7] = {0};
         for (long s = 0; s < n; ++s) {
             if (!buf[s].occupied) continue;
-            double raw[NCH];
+            real raw[NCH];
             shade(&blocks[set[buf[s].set_pos]], buf[s].q, &pv[m], raw, &taps[20 * m]);
             double sd = pv[m].sigma * buf[s].delta;
             double alpha = -expm1(-sd);
@@ -1124,7 +1213,7 @@ int orc_adjoint_block_mlp(const orc_block* blocks, int nblocks, const unsigned c
             double A[7] = {0}, T = 1.0;
             for (; s < n && buf[s].set_pos == run; ++s) {
                 if (!buf[s].occupied) continue;
-                double raw[NCH];
+                real raw[NCH];
                 shade(&blocks[set[run]], buf[s].q, &pv[m], raw, &taps[20 * m]);
                 double sd = pv[m].sigma * buf[s].delta;
                 double alpha = -expm1(-sd);
@@ -1257,7 +1346,7 @@ int orc_opacity(const orc_block* blocks, int nblocks, const unsigned char* const
             for (; s < n && buf[s].set_pos == run; ++s) {
                 if (!buf[s].occupied) continue;
                 pt_val pv;
-                double raw[NCH];
+                real raw[NCH];
                 shade(&blocks[set[run]], buf[s].q, &pv, raw, NULL);
                 Tk *= exp(-pv.sigma * buf[s].delta);
                 if (p->t_min > 0.0f && T * Tk < (double)p->t_min) {
@@ -1293,7 +1382,7 @@ double orc_sparsity(const orc_block* blocks, int nblocks, const unsigned char* c
         float q[3];
         int cell = occ_cell(b, pt, q);
         if (!occ[set[s_hit]][cell]) continue; /* density is zero in unoccupied cells */
-        double raw[NCH];
+        real raw[NCH];
         eval_raw(b, q, raw, taps);
         double sigma = exp(raw[0]);
         double alpha = -expm1(-sigma * delta);

@@ -172,6 +172,15 @@ int orc_select_quadtree(const orc_view* v, int nent, const int* ids, const int* 
                         const float* hi, const double* ztop, const int* contracted, const double* thresholds,
                         int n_thr, int cull, int* out, int cap);
 
+/* Texels read by the evaluated samples of pixels pix[npix][2] (the compulsory
+ * texture bytes of a frame): marks[4 e + t] (t = 0 grid, 1-3 the xy, xz, yz
+ * planes; NULL to skip) receive 1 at every texel index the interpolation of
+ * an occupied sample of entry e taps (clamped, as the render's field).
+ * t_min = 0 and plain blocks only (-1 otherwise); 0 on success. */
+int orc_touched_texels(const orc_block* blocks, int nblocks, const unsigned char* const* occ, const orc_view* v,
+                       const int* set, int nset, const orc_params* p, const int* pix, long npix,
+                       unsigned char* const* marks, int nthreads);
+
 /* pre-activation features at n world points of block b (points outside the
  * block are evaluated by the same clamped rule): raw[8n] */
 void orc_field(const orc_block* b, int n, const float* pts, double* raw);

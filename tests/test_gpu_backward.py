@@ -122,23 +122,26 @@ def test_backward_c5_crop(torch_cuda):
     r = Renderer(0).load_blocks(learn.blocks)
     sets = [[(b.block_id, 0) for b in learn.blocks]]
     # crop: the 64x64 window of view 0 with the most evaluated samples among
-    # 16 seeded candidates
+    # 16 seeded candidates, counted by the oracle on every 8th pixel of each
     rng = np.random.default_rng(0)
     v0 = views[0]
     cands = [(int(rng.integers(0, 800 - 64)), int(rng.integers(0, 800 - 64))) for _ in range(16)]
-    mlp = torch.tensor(w_learn, device="cuda")
-    full = r.render([v0], sets, params, mlp, counts=True)
-    cnt = full["counts"][:, 0].reshape(800, 800).cpu().numpy()
-    x0, y0 = max(cands, key=lambda c: cnt[c[1]:c[1] + 64, c[0]:c[0] + 64].sum())
+    ob = O.OracleScene(learn.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+
+    def score(c):
+        pix = np.array([[c[0] + i, c[1] + j] for j in range(0, 64, 8) for i in range(0, 64, 8)], np.int32)
+        return int(O.render(ob, occs, v0, list(range(ob.n)), params, w_learn, pix=pix)["n_eval"].sum())
+    x0, y0 = max(cands, key=score)
     crop = v0.with_crop(x0, y0, 64, 64)
+    mlp = torch.tensor(w_learn, device="cuda")
     out = r.render([crop], sets, params, mlp)
     # target image of the crop: the second scene rendered by the oracle
     ob_t = O.OracleScene(target.blocks)
     occ_t = [O.occupancy(ob_t, k) for k in range(ob_t.n)]
     pix = O.pixels_of(crop)
     tgt = O.render(ob_t, occ_t, crop, list(range(ob_t.n)), params, w_tgt, pix=pix)["rgb"]
-    ob = O.OracleScene(learn.blocks)
-    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    del ob_t, occ_t
     ref = O.render(ob, occs, crop, list(range(ob.n)), params, w_learn, pix=pix)
     assert np.abs(out["rgb"].cpu().numpy() - ref["rgb"]).max() <= 1e-4
     g_rgb = 2 * (ref["rgb"] - tgt) / tgt.size  # dL/dC of the MSE over pixels x channels

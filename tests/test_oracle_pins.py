@@ -1537,3 +1537,146 @@ def test_step_cap_truncates_the_exterior_behind_it(contraction_city):
     full = O.render(ob, occs, v, allb, sg.RenderParams(max_steps=4096, **base), zero_mlp())
     assert capped["n_march"][0] == len(pre) + 1024
     assert full["n_march"][0] == len(pre) + 2048 + len(post)
+
+
+def test_touched_texels_closed_form():
+    """The texels a frame's evaluated samples read (its compulsory texture
+    bytes): an axis ray along +x at y = z = 0.5 through a homogeneous block
+    (8 texels per axis, every cell occupied) samples x over the whole chord,
+    so the grid taps are x = 0..7 at y, z in {3, 4} (u = 0.5 R - 1/2 = 3.5),
+    the xy plane u = 0..7 at v = y in {3, 4}, the xz plane u = 0..7 at v = z in
+    {3, 4}, the yz plane the 2 x 2 texels (3..4, 3..4); a ray that misses the
+    block reads nothing."""
+    b = sg.homogeneous_block(R=8, Rp=8, O=4, sigma=2.0)
+    ob = O.OracleScene([b])
+    occs = [O.occupancy(ob, 0)]
+    assert occs[0].all()
+    v = axis_view((-0.25, 0.5, 0.5), (1.0, 0.0, 0.0))
+    m = O.touched_texels(ob, occs, v, [0], sg.RenderParams(mode=1))[0]
+    g = np.zeros((8, 8, 8), np.uint8)
+    g[3:5, 3:5, :] = 1
+    xy = np.zeros((8, 8), np.uint8)
+    xy[3:5, :] = 1
+    yz = np.zeros((8, 8), np.uint8)
+    yz[3:5, 3:5] = 1
+    assert np.array_equal(m[0], g) and np.array_equal(m[1], xy) and np.array_equal(m[2], xy)
+    assert np.array_equal(m[3], yz)
+    miss = axis_view((-0.25, 1.5, 0.5), (1.0, 0.0, 0.0))
+    assert all(not x.any() for x in O.touched_texels(ob, occs, miss, [0], sg.RenderParams(mode=1))[0])
+    # empty cells read nothing: the same ray through a block whose cells are all empty
+    assert all(not x.any() for x in O.touched_texels(ob, [np.zeros_like(occs[0])], v, [0],
+                                                     sg.RenderParams(mode=1))[0])
+
+
+# ---------------------------------------------------------------------------
+# P13 at the differentiable workload's size: central differences on the
+# 64 x 64 crop (Sec. 4.2, consistent training through the block merge)
+# ---------------------------------------------------------------------------
+def _pixel_dirs(view, pix):
+    """Unit world directions of the given pixels (fp64 of the camera model)."""
+    R = np.asarray(view.R, np.float64).reshape(3, 3)
+    x = (pix[:, 0] + 0.5 - float(view.cx)) / float(view.fx)
+    y = (pix[:, 1] + 0.5 - float(view.cy)) / float(view.fy)
+    u = np.stack([x, y, np.ones_like(x)], 1) @ R.T
+    return u / np.linalg.norm(u, axis=1, keepdims=True)
+
+
+def _kink_risk(w, X, i, h):
+    """Whether moving MLP weight i by +-h may carry some pixel's ReLU
+    pre-activation across zero (layout W1 [16][10], b1, W2 [16][16], b2,
+    W3 [3][16], b3; inputs X [n][10])."""
+    W1, b1 = w[:160].reshape(16, 10), w[160:176]
+    W2, b2 = w[176:432].reshape(16, 16), w[432:448]
+    pre1 = X @ W1.T + b1
+    h1 = np.maximum(pre1, 0.0)
+    pre2 = h1 @ W2.T + b2
+    if i < 176:  # W1[o][j] or b1[o]
+        o = (i // 10) if i < 160 else i - 160
+        dx = np.abs(X[:, i % 10]) if i < 160 else np.ones(len(X))
+        if (np.abs(pre1[:, o]) <= 2 * h * dx).any():
+            return True
+        return bool((np.abs(pre2) <= 2 * h * dx[:, None] * np.abs(W2[:, o])[None, :]).any())
+    if i < 448:  # W2[j][o] or b2[j]
+        j = ((i - 176) // 16) if i < 432 else i - 432
+        dx = h1[:, (i - 176) % 16] if i < 432 else np.ones(len(X))
+        return bool((np.abs(pre2[:, j]) <= 2 * h * dx).any())
+    return False  # W3, b3: after the last ReLU
+
+
+@pytest.mark.slow
+def test_c5_crop_adjoint_against_finite_differences():
+    """The differentiable workload (4x4 fp32 blocks of 128^3 + 3 x 1024^2,
+    view 0 of its eight 800x800 views): on the 64 x 64 window with the most
+    evaluated samples among 16 seeded candidates (counted by the oracle), the
+    fp64 adjoint of the MSE against the target scene's image matches central
+    differences (h = 1e-3, fp64) on 64 seeded parameters the crop touches:
+    24 grid texel-channels, 8 texel-channels per plane, 16 MLP weights (a
+    weight whose perturbation could carry a ReLU pre-activation of some
+    pixel across zero is redrawn)."""
+    learn, target = sg.c5_scenes()
+    v0 = sg.c5_views()[0]
+    p = sg.cityb_params()
+    w = sg.xavier_mlp(4).astype(np.float64)
+    ob = O.OracleScene(learn.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    setv = list(range(ob.n))
+    rng = np.random.default_rng(0)
+    cands = [(int(rng.integers(0, 800 - 64)), int(rng.integers(0, 800 - 64))) for _ in range(16)]
+
+    def score(c):
+        pix = np.array([[c[0] + i, c[1] + j] for j in range(0, 64, 8) for i in range(0, 64, 8)], np.int32)
+        return int(O.render(ob, occs, v0, setv, p, w, pix=pix)["n_eval"].sum())
+    x0, y0 = max(cands, key=score)
+    crop = v0.with_crop(x0, y0, 64, 64)
+    pix = O.pixels_of(crop)
+    ob_t = O.OracleScene(target.blocks)
+    tgt = O.render(ob_t, [O.occupancy(ob_t, k) for k in range(ob_t.n)], crop, list(range(ob_t.n)), p,
+                   sg.xavier_mlp(5), pix=pix)["rgb"]
+    del ob_t, target
+
+    def loss():
+        r = O.render(ob, occs, crop, setv, p, w, pix=pix)
+        return np.mean((r["rgb"] - tgt) ** 2), r
+    L0, r0 = loss()
+    assert r0["n_eval"].sum() > 1_000_000
+    g_rgb = 2 * (r0["rgb"] - tgt) / tgt.size
+    grads, gm = O.adjoint(ob, occs, crop, setv, p, w, pix, g_rgb)
+    gmax = max(max(np.abs(g).max(), max(np.abs(q).max() for q in ps)) for g, ps in grads.values())
+    assert gmax > 0
+    h = 1e-3
+    picks = []
+    for arr_i, n_pick in ((0, 24), (1, 8), (2, 8), (3, 8)):
+        cand = [(k, tuple(i)) for k, (g, ps) in grads.items()
+                for i in np.argwhere(np.abs(g if arr_i == 0 else ps[arr_i - 1]) > 1e-3 * gmax)]
+        for c in rng.choice(len(cand), n_pick, replace=False):
+            picks.append((cand[c][0], arr_i, cand[c][1]))
+    for k, arr_i, idx in picks:
+        fg, fps = ob.f64[k]
+        arr = fg if arr_i == 0 else fps[arr_i - 1]
+        ga = (grads[k][0] if arr_i == 0 else grads[k][1][arr_i - 1])[idx]
+        old = arr[idx]
+        arr[idx] = old + h
+        Lp, _ = loss()
+        arr[idx] = old - h
+        Lm, _ = loss()
+        arr[idx] = old
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(ga - fd) <= 1e-4 * abs(fd) + 1e-6 * gmax, (k, arr_i, idx, ga, fd)
+    X = np.concatenate([r0["aux"][:, :7], _pixel_dirs(crop, pix)], 1)
+    mlp_picks = []
+    while len(mlp_picks) < 16:
+        i = int(rng.integers(499))
+        if i not in mlp_picks and not _kink_risk(w, X, i, h):
+            mlp_picks.append(i)
+    assert any(i < 448 for i in mlp_picks)  # hidden layers are exercised, not only the output layer
+    gmm = np.abs(gm).max()
+    for i in mlp_picks:
+        old = w[i]
+        w[i] = old + h
+        Lp, _ = loss()
+        w[i] = old - h
+        Lm, _ = loss()
+        w[i] = old
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(gm[i] - fd) <= 1e-4 * abs(fd) + 1e-6 * gmm, (i, gm[i], fd)
+    assert len(picks) + len(mlp_picks) == 64
