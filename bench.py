@@ -709,7 +709,10 @@ def leg_single_block(torch, sg, Renderer, reps=20):
     n_eval = int(r.render([view], sets, p, mlp, counts=True)["counts"][:, 0].sum().item())
     out = r.render([view], sets, p, mlp, want_aux=False)
     ms = _timed(torch, lambda: r.render([view], sets, p, mlp, out=out), reps)
+    from paper_2312_16457_amd import F_GRAPH
+    ms_g = _timed(torch, lambda: r.render([view], sets, p, mlp, out=out, flags=F_GRAPH), reps)
     res = {"ms": round(ms, 4), "evaluated_samples": n_eval, "Msamples_per_s": round(n_eval / (ms * 1e-3) / 1e6, 1),
+           "ms_graph": round(ms_g, 4), "Msamples_per_s_graph": round(n_eval / (ms_g * 1e-3) / 1e6, 1),
            "workload": "1 fp32 block 32^3 + 3x128^2, one 128x128 view, 128 chord steps"}
     del r
     return res
