@@ -278,6 +278,24 @@ COW_API cow_status cow_render(cow_ctx* ctx, const cow_view* views, int n_views, 
                       const cow_render_params* params, const float* mlp, float* rgb, float* trans,
                       float* aux, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* cow_render for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results as cow_render, with no workspace argument.  The
+ * per-call view and block-set tables and the persistent launch's counters
+ * live in a fixed scratch array inside the library, one per GPU (about 128
+ * KiB of device memory each, held until the process ends; its address is
+ * taken when the first context is created on that GPU).  The call makes no
+ * device or pinned-host allocation.  Limits: at most 256 views and 16384
+ * set entries per call (COW_E_INVALID beyond), aux must be given (it is the
+ * only per-pixel scratch cow_render would otherwise take from its
+ * workspace; COW_E_INVALID if NULL), and COW_F_GRAPH is refused
+ * (COW_E_UNSUPPORTED: instantiating a graph allocates).  Every call on one
+ * GPU shares that GPU's scratch: calls on different streams of one GPU that
+ * overlap in time race on it and must be ordered by the caller. */
+COW_API cow_status cow_render_noalloc(cow_ctx* ctx, const cow_view* views, int n_views, const cow_block_set* sets,
+                                      const cow_render_params* params, const float* mlp, float* rgb, float* trans,
+                                      float* aux, hipStream_t stream);
+
 /* Adjoint of cow_render for COW_F32 blocks.  grad_rgb [P][3] and grad_trans
  * [P] (nullable) are dL/d outputs, as is params->opacity_weight (nullable);
  * aux is the forward's aux.  Gradients are

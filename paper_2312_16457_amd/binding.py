@@ -18,7 +18,7 @@ F_NONE, F_GRAPH, F_PERSISTENT, F_PER_BLOCK, F_SPARSE, F_FLAT_OCC = 0, 1, 2, 4, 8
 BLOCK_CONTRACTED = 1  # cow_block_desc.flags: boundary block over the contracted cube
 
 EXPORTS = ["cow_create", "cow_destroy", "cow_last_error", "cow_query_workspace", "cow_load_blocks",
-           "cow_get_occupancy", "cow_get_occupancy_level", "cow_select_blocks", "cow_query_bricks", "cow_pack_bricks", "cow_render",
+           "cow_get_occupancy", "cow_get_occupancy_level", "cow_select_blocks", "cow_query_bricks", "cow_pack_bricks", "cow_render", "cow_render_noalloc",
            "cow_render_backward", "cow_sparsity", "cow_autotune", "cow_get_config", "cow_set_config",
            "cow_set_timing", "cow_last_timing", "cow_gather_probe"]
 
@@ -87,6 +87,7 @@ def lib():
         L.cow_query_bricks.argtypes = [vp, P(C.c_size_t)]
         L.cow_pack_bricks.argtypes = [vp, vp, C.c_size_t, vp]
         L.cow_render.argtypes = [vp, P(View), C.c_int, P(BlockSet), P(Params), vp, vp, vp, vp, vp, C.c_size_t, vp]
+        L.cow_render_noalloc.argtypes = [vp, P(View), C.c_int, P(BlockSet), P(Params), vp, vp, vp, vp, vp]
         L.cow_render_backward.argtypes = [vp, P(View), C.c_int, P(BlockSet), P(Params), vp, vp, vp, vp,
                                           P(vp), P(vp), vp, vp, C.c_size_t, vp]
         L.cow_sparsity.argtypes = [vp, P(BlockSet), vp, C.c_int64, C.c_float, C.c_float, vp, vp, vp, vp, vp,
@@ -329,6 +330,18 @@ class Renderer:
         self._check(self.L.cow_render(self.h, vs, len(views), cs, C.byref(p), None if mlp is None else mlp.data_ptr(),
                                       out["rgb"].data_ptr(), out["trans"].data_ptr(),
                                       None if aux is None else aux.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
+        return out
+
+    def render_noalloc(self, views, sets, params, mlp, out, flags=0):
+        """cow_render_noalloc into caller-given outputs `out` (rgb, trans, aux
+        and optionally counts, as returned by render): no workspace."""
+        vs = (View * len(views))(*[make_view(v) for v in views])
+        cs, keep = self._sets(sets)
+        p = make_params(params, flags, out.get("counts"), out.get("opacity"))
+        aux = out.get("aux")
+        self._check(self.L.cow_render_noalloc(self.h, vs, len(views), cs, C.byref(p), mlp.data_ptr(),
+                                              out["rgb"].data_ptr(), out["trans"].data_ptr(),
+                                              None if aux is None else aux.data_ptr(), _stream()))
         return out
 
     def _grad_tables(self, grad_grid, grad_plane):

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,6 +24,34 @@ using cow::DevBlock;
 using cow::DevView;
 
 namespace {
+
+// Scratch of cow_render_noalloc: the per-call view and block-set tables and
+// the persistent launch's counters, for callers that cannot allocate device
+// memory.  One copy per GPU, held until the process ends; its device address
+// is looked up once per device (hipGetSymbolAddress) when a context is
+// created there.  In host code the name is only a stand-in, never an address.
+constexpr size_t kScratchBytes = 128 * 1024;
+constexpr int kNoAllocMaxViews = 256;
+constexpr int kNoAllocMaxRefs = 16384;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// the device address of `scratch` on `device`, which must be current
+hipError_t scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch[device] = ptr;
+    }
+    *out = g_scratch[device];
+    return hipSuccess;
+}
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxViews = 1 << 16;
@@ -94,6 +123,8 @@ struct cow_ctx {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool have_fwd = false, have_bwd = false;
     std::vector<GraphEntry> graphs;
+    // this device's copy of the cow_render_noalloc scratch
+    unsigned char* scratch = nullptr;
     std::string err;
 };
 
@@ -231,7 +262,7 @@ size_t load_layout(const cow_block_desc* b, int n, std::vector<size_t>* occ_off,
 // The next staging slot, at least `bytes` long: waits only for the copy
 // that last read this slot (kStagingSlots calls back), and grows the slot
 // when it is too small (the only allocation on the render path).
-cow_status take_staging(cow_ctx* c, size_t bytes, Staging** out) {
+cow_status take_staging(cow_ctx* c, size_t bytes, Staging** out, bool may_grow = true) {
     Staging& st = c->staging[c->staging_next];
     c->staging_next = (c->staging_next + 1) % kStagingSlots;
     if (st.pending) {
@@ -239,6 +270,7 @@ cow_status take_staging(cow_ctx* c, size_t bytes, Staging** out) {
         st.pending = false;
     }
     if (bytes > st.bytes) {
+        if (!may_grow) return fail(c, COW_E_INTERNAL, "staging slot too small for a call that may not allocate");
         if (st.buf) HIP_TRY(c, hipHostFree(st.buf));
         st.buf = nullptr;
         st.bytes = 0;
@@ -512,10 +544,10 @@ cow_status check_dtypes(cow_ctx* c, const CallTables& T, int* dtype) {
     return COW_OK;
 }
 
-cow_status upload_tables(cow_ctx* c, const CallTables& T, const RenderWs& w, hipStream_t s) {
+cow_status upload_tables(cow_ctx* c, const CallTables& T, const RenderWs& w, hipStream_t s, bool may_grow = true) {
     const size_t vb = sizeof(DevView) * T.views.size(), rb = 4 * T.refs.size();
     Staging* sl = nullptr;
-    cow_status st = take_staging(c, align_up(vb) + rb + 64, &sl);
+    cow_status st = take_staging(c, align_up(vb) + rb + 64, &sl, may_grow);
     if (st != COW_OK) return st;
     memcpy(sl->buf, T.views.data(), vb);
     memcpy(sl->buf + align_up(vb), T.refs.data(), rb);
@@ -787,7 +819,7 @@ cow_status cow_create(cow_ctx** out, int device) {
     *out = nullptr;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return COW_E_HIP;
-    if (device < 0 || device >= n) return COW_E_INVALID;
+    if (device < 0 || device >= n || device >= kMaxDevices) return COW_E_INVALID;
     cow_ctx* c = new (std::nothrow) cow_ctx();
     if (!c) return COW_E_INTERNAL;
     c->device = device;
@@ -806,6 +838,12 @@ cow_status cow_create(cow_ctx** out, int device) {
         }
         st.bytes = kStagingInitial;
     }
+    void* sp = nullptr;
+    if (scratch_address(device, &sp) != hipSuccess) {
+        cow_destroy(c);
+        return COW_E_HIP;
+    }
+    c->scratch = (unsigned char*)sp;
     *out = c;
     return COW_OK;
 }
@@ -1137,15 +1175,32 @@ cow_status cow_pack_bricks(cow_ctx* c, void* brick_ws, size_t brick_bytes, hipSt
     return COW_OK;
 }
 
+// noalloc: the tables live in this device's scratch array instead of ws
+// (cow_render_noalloc), which bounds the views and set entries of a call,
+// needs the caller's aux and rules out graph replay (instantiating a graph
+// allocates)
 static cow_status render_impl(cow_ctx* c, const cow_view* views, int n_views, const cow_block_set* sets,
                               const cow_render_params* p, const float* mlp, float* rgb, float* trans,
-                              float* aux, void* ws, size_t ws_bytes, hipStream_t s) {
+                              float* aux, void* ws, size_t ws_bytes, hipStream_t s, bool noalloc = false) {
     if (!c) return COW_E_INVALID;
     if (!c->loaded) return fail(c, COW_E_NOT_LOADED, "no blocks loaded");
     if (!views || !sets || n_views < 1 || n_views > kMaxViews) return fail(c, COW_E_INVALID, "bad views");
     cow_status st = validate_params(c, p);
     if (st != COW_OK) return st;
     if ((!mlp && !p->block_mlp) || !rgb || !trans) return fail(c, COW_E_INVALID, "null mlp or output");
+    if (noalloc) {
+        if (!aux) return fail(c, COW_E_INVALID, "cow_render_noalloc needs the aux output");
+        if (n_views > kNoAllocMaxViews)
+            return fail(c, COW_E_INVALID, "cow_render_noalloc: more than 256 views in one call");
+        int64_t refs = 0;
+        for (int v = 0; v < n_views; ++v) refs += sets[v].n > 0 ? sets[v].n : 0;
+        if (refs > kNoAllocMaxRefs)
+            return fail(c, COW_E_INVALID, "cow_render_noalloc: more than 16384 set entries in one call");
+        if (p->flags & COW_F_GRAPH)
+            return fail(c, COW_E_UNSUPPORTED, "cow_render_noalloc does not replay graphs (instantiation allocates)");
+        ws = c->scratch;
+        ws_bytes = kScratchBytes;
+    }
     if ((p->flags & COW_F_SPARSE) && !c->bricks_packed) return fail(c, COW_E_INVALID, "bricks not packed");
     CallTables T;
     st = build_tables(c, views, n_views, sets, c->cfg.tile_w, &T);
@@ -1163,7 +1218,7 @@ static cow_status render_impl(cow_ctx* c, const cow_view* views, int n_views, co
     if (!ws || ws_bytes < need) return fail(c, COW_E_WORKSPACE, "render workspace too small");
     if (T.n_pix == 0) return COW_OK;
     HIP_TRY(c, hipSetDevice(c->device));
-    st = upload_tables(c, T, w, s);
+    st = upload_tables(c, T, w, s, !noalloc);
     if (st != COW_OK) return st;
     float* aux_out = aux ? aux : w.aux;
     cow::MarchArgs a = march_args(c, T, w, p, dtype, aux_out, trans);
@@ -1189,6 +1244,16 @@ cow_status cow_render(cow_ctx* c, const cow_view* views, int n_views, const cow_
                       void* ws, size_t ws_bytes, hipStream_t s) {
     try {
         return render_impl(c, views, n_views, sets, p, mlp, rgb, trans, aux, ws, ws_bytes, s);
+    } catch (...) {
+        return fail(c, COW_E_INTERNAL, "internal error");
+    }
+}
+
+cow_status cow_render_noalloc(cow_ctx* c, const cow_view* views, int n_views, const cow_block_set* sets,
+                              const cow_render_params* p, const float* mlp, float* rgb, float* trans, float* aux,
+                              hipStream_t s) {
+    try {
+        return render_impl(c, views, n_views, sets, p, mlp, rgb, trans, aux, nullptr, 0, s, true);
     } catch (...) {
         return fail(c, COW_E_INTERNAL, "internal error");
     }
