@@ -1,11 +1,10 @@
 // Vector-ALU issue rates on gfx950: a measurement aid, not part of the
 // render path.  Each lane runs eight independent chains of one instruction
 // kind (inline assembly, so the loop holds exactly that instruction, 32 of
-// them per loop trip), 2048 workgroups of 256 lanes (eight waves per SIMD,
-// all resident at once).  Two figures per kind: cycles per wave64
-// instruction per SIMD from the shader clock (s_memtime, read by each wave
-// around its loop: the mean span over eight waves' instructions), and the
-// same from the kernel time of HIP events at the given clock.  It also checks the
+// them per loop trip), 2048 workgroups of 256 lanes (eight waves per SIMD);
+// the kernel time from HIP events gives cycles per wave64 instruction per
+// SIMD at the given clock (the nominal 2.4 GHz unless another is passed; at a
+// lower real clock the true cycle counts are proportionally smaller).  It also checks the
 // semantic the byte-select (SDWA) form of v_mul_f32 is used for: with fp32
 // denormal inputs preserved, src1_sel:BYTE_k reads byte k of a word as the
 // fp32 denormal b 2^-149, so w 2^125 times it is w b 2^-24, rounded once.
@@ -38,14 +37,12 @@ constexpr int kBlocks = 2048;
 #define OP2(asmstr) asm volatile(asmstr : "+v"(a[c]) : "v"(b))
 
 template <int K>
-__global__ void __launch_bounds__(kThreads) issue_kernel(float* out, unsigned long long* span, int iters,
-                                                         float seed) {
+__global__ void __launch_bounds__(kThreads) issue_kernel(float* out, int iters, float seed) {
     float a[kChains];
     const unsigned bw = 0x3f7f1f40u ^ (threadIdx.x * 2654435761u);
     const float b = __uint_as_float((bw & 0x007fffffu) | 0x3f000000u);  // in [0.5, 1)
 #pragma unroll
     for (int c = 0; c < kChains; ++c) a[c] = seed + 1e-3f * (float)(threadIdx.x + c);
-    const unsigned long long t0 = __builtin_amdgcn_s_memtime();
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
@@ -73,8 +70,6 @@ __global__ void __launch_bounds__(kThreads) issue_kernel(float* out, unsigned lo
             if (K == 19) OP2("v_xor_b32 %0, %0, %1");
         }
     }
-    const unsigned long long t1 = __builtin_amdgcn_s_memtime();
-    if ((threadIdx.x & 63) == 0) span[blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)] = t1 - t0;
     float s = 0.0f;
 #pragma unroll
     for (int c = 0; c < kChains; ++c) s += a[c];
@@ -102,13 +97,13 @@ __global__ void sdwa_check_kernel(const unsigned* words, const float* w, float* 
 }
 
 template <int K>
-float time_kind(float* out, unsigned long long* span, int iters) {
+float time_kind(float* out, int iters) {
     hipEvent_t e0, e1;
     CHECK(hipEventCreate(&e0));
     CHECK(hipEventCreate(&e1));
-    hipLaunchKernelGGL(issue_kernel<K>, dim3(kBlocks), dim3(kThreads), 0, 0, out, span, iters, 1.0f);
+    hipLaunchKernelGGL(issue_kernel<K>, dim3(kBlocks), dim3(kThreads), 0, 0, out, iters, 1.0f);
     CHECK(hipEventRecord(e0, 0));
-    hipLaunchKernelGGL(issue_kernel<K>, dim3(kBlocks), dim3(kThreads), 0, 0, out, span, iters, 1.0f);
+    hipLaunchKernelGGL(issue_kernel<K>, dim3(kBlocks), dim3(kThreads), 0, 0, out, iters, 1.0f);
     CHECK(hipEventRecord(e1, 0));
     CHECK(hipEventSynchronize(e1));
     float ms = 0.0f;
@@ -119,18 +114,11 @@ float time_kind(float* out, unsigned long long* span, int iters) {
 }
 
 template <int K>
-void report(const char* name, float* out, unsigned long long* span, int iters, double ghz, int simds) {
-    const float ms = time_kind<K>(out, span, iters);
-    const int nw = kBlocks * kThreads / 64;
-    unsigned long long* hs = (unsigned long long*)malloc(sizeof(unsigned long long) * nw);
-    CHECK(hipMemcpy(hs, span, sizeof(unsigned long long) * nw, hipMemcpyDeviceToHost));
-    double mean = 0.0;
-    for (int i = 0; i < nw; ++i) mean += (double)hs[i] / nw;
-    free(hs);
-    const double per_wave = (double)iters * 4 * kChains;  // instructions of one wave
-    const double waves_per_simd = (double)nw / simds;
-    const double instr_per_simd = per_wave * waves_per_simd;
-    printf("| `%s` | %.2f | %.2f |\n", name, mean / (per_wave * waves_per_simd), ms * 1e-3 * ghz * 1e9 / instr_per_simd);
+void report(const char* name, float* out, int iters, double ghz, int simds) {
+    const float ms = time_kind<K>(out, iters);
+    const double waves = (double)kBlocks * kThreads / 64.0;
+    const double instr_per_simd = waves * iters * 4 * kChains / simds;
+    printf("| `%s` | %.2f |\n", name, ms * 1e-3 * ghz * 1e9 / instr_per_simd);
 }
 
 int main(int argc, char** argv) {
@@ -170,34 +158,30 @@ int main(int argc, char** argv) {
     printf("byte-select check: %ld of %d products differ from w b 2^-24 rounded once\n", bad, 4 * n);
     // issue rates
     float* out;
-    unsigned long long* span;
     CHECK(hipMalloc(&out, (size_t)kBlocks * kThreads * 4));
-    CHECK(hipMalloc(&span, sizeof(unsigned long long) * kBlocks * (kThreads / 64)));
     const int iters = 1024;
-    printf("| Instruction | Cycles per wave64 instruction per SIMD, shader clock | same, from the kernel time at %.2f GHz |\n"
-           "|---|---|---|\n", ghz);
-    report<0>("v_mul_f32 (VOP2)", out, span, iters, ghz, simds);
-    report<1>("v_fmac_f32 (VOP2)", out, span, iters, ghz, simds);
-    report<2>("v_fma_f32 (VOP3)", out, span, iters, ghz, simds);
-    report<3>("v_fma_mix_f32 (VOP3P)", out, span, iters, ghz, simds);
-    report<4>("v_mov_b32_sdwa, byte select (VOP1 + SDWA)", out, span, iters, ghz, simds);
-    report<5>("v_mul_f32_sdwa, byte select (VOP2 + SDWA)", out, span, iters, ghz, simds);
-    report<6>("v_perm_b32 (VOP3)", out, span, iters, ghz, simds);
-    report<7>("v_and_b32 (VOP2, literal)", out, span, iters, ghz, simds);
-    report<8>("v_cvt_i32_f32 (VOP1)", out, span, iters, ghz, simds);
-    report<9>("v_floor_f32 (VOP1)", out, span, iters, ghz, simds);
-    report<10>("v_fract_f32 (VOP1)", out, span, iters, ghz, simds);
-    report<11>("v_med3_f32 (VOP3)", out, span, iters, ghz, simds);
-    report<12>("v_add_lshl_u32 (VOP3)", out, span, iters, ghz, simds);
-    report<13>("v_add_u32 (VOP2)", out, span, iters, ghz, simds);
-    report<14>("v_exp_f32", out, span, iters, ghz, simds);
-    report<15>("v_rcp_f32", out, span, iters, ghz, simds);
-    report<16>("v_fmaak_f32 (VOP2, literal)", out, span, iters, ghz, simds);
-    report<17>("v_sub_f32 (VOP2)", out, span, iters, ghz, simds);
-    report<18>("v_cvt_f32_ubyte1 (VOP1)", out, span, iters, ghz, simds);
-    report<19>("v_xor_b32 (VOP2)", out, span, iters, ghz, simds);
+    printf("| Instruction | Cycles per wave64 instruction per SIMD (kernel time at %.2f GHz) |\n|---|---|\n", ghz);
+    report<0>("v_mul_f32 (VOP2)", out, iters, ghz, simds);
+    report<1>("v_fmac_f32 (VOP2)", out, iters, ghz, simds);
+    report<2>("v_fma_f32 (VOP3)", out, iters, ghz, simds);
+    report<3>("v_fma_mix_f32 (VOP3P)", out, iters, ghz, simds);
+    report<4>("v_mov_b32_sdwa, byte select (VOP1 + SDWA)", out, iters, ghz, simds);
+    report<5>("v_mul_f32_sdwa, byte select (VOP2 + SDWA)", out, iters, ghz, simds);
+    report<6>("v_perm_b32 (VOP3)", out, iters, ghz, simds);
+    report<7>("v_and_b32 (VOP2, literal)", out, iters, ghz, simds);
+    report<8>("v_cvt_i32_f32 (VOP1)", out, iters, ghz, simds);
+    report<9>("v_floor_f32 (VOP1)", out, iters, ghz, simds);
+    report<10>("v_fract_f32 (VOP1)", out, iters, ghz, simds);
+    report<11>("v_med3_f32 (VOP3)", out, iters, ghz, simds);
+    report<12>("v_add_lshl_u32 (VOP3)", out, iters, ghz, simds);
+    report<13>("v_add_u32 (VOP2)", out, iters, ghz, simds);
+    report<14>("v_exp_f32", out, iters, ghz, simds);
+    report<15>("v_rcp_f32", out, iters, ghz, simds);
+    report<16>("v_fmaak_f32 (VOP2, literal)", out, iters, ghz, simds);
+    report<17>("v_sub_f32 (VOP2)", out, iters, ghz, simds);
+    report<18>("v_cvt_f32_ubyte1 (VOP1)", out, iters, ghz, simds);
+    report<19>("v_xor_b32 (VOP2)", out, iters, ghz, simds);
     CHECK(hipFree(out));
-    CHECK(hipFree(span));
     CHECK(hipFree(dw));
     CHECK(hipFree(dwt));
     CHECK(hipFree(dout));
