@@ -587,6 +587,15 @@ def leg_backward(torch, sg, Renderer, reps=2):
     probe = views[0].n_pixels * steps * 640 / (pms * 1e-3) / 1e9
     res["fwd_gather_probe_GBps"] = round(probe, 1)
     res["fwd_gather_frac"] = round(res["fwd_gathered_GBps"] / probe, 4)
+    # the fp32 forward's HBM reads per launch from its committed rocprofv3
+    # FETCH_SIZE pass (null when the kernel's sources changed since)
+    path = os.path.join(ROOT, "profiles", "traffic_march_fwd_f32_8x800.json")
+    if os.path.exists(path):
+        rec = json.load(open(path))
+        if rec.get("source_digest") == source_digest():
+            hbm = rec["hbm_read_bytes_per_launch"] / (fwd_ms * 1e-3) / 1e9
+            res["fwd_hbm_read_GBps"] = round(hbm, 1)
+            res["fwd_hbm_frac_of_peak"] = round(hbm / PEAK_HBM_GBS, 4)
     del tex
     torch.cuda.empty_cache()
     return res, learn
