@@ -269,11 +269,17 @@ COW_API cow_status cow_select_blocks(cow_ctx* ctx, const cow_view* view, const c
 COW_API cow_status cow_query_bricks(cow_ctx* ctx, size_t* brick_bytes);
 COW_API cow_status cow_pack_bricks(cow_ctx* ctx, void* brick_ws, size_t brick_bytes, hipStream_t stream);
 
-/* Render n_views views.  Pixels are the views' crops concatenated in view
- * order, row-major within each crop (P in total).  sets[v] lists the
- * (block, LOD) entries view v renders; the library orders them front to back
- * by xy distance.  mlp: device float[499].  Outputs (device): rgb [P][3],
- * trans [P], aux [P][8] = (C_d, F, T) or NULL (required before a backward). */
+/* Render n_views views: per pixel ray, the samples of each block composited
+ * front to back (Sec. 3, Eqs. "alpha accumulation" and "combined
+ * accumulation"; Appendix A, Eq. "volume rendering inside blocks"), the
+ * blocks merged in depth order (Sec. 4.2, Eq. "volume rendering across
+ * blocks", with T^k carried as prod(1 - alpha_i) by Appendix A) and the
+ * result shaded by the deferred MLP (Sec. 3, Eq. "deferred").  Pixels are
+ * the views' crops concatenated in view order, row-major within each crop (P
+ * in total).  sets[v] lists the (block, LOD) entries view v renders; the
+ * library orders them front to back by xy distance (Appendix D, "Depth
+ * sorting").  mlp: device float[499].  Outputs (device): rgb [P][3], trans
+ * [P], aux [P][8] = (C_d, F, T) or NULL (required before a backward). */
 COW_API cow_status cow_render(cow_ctx* ctx, const cow_view* views, int n_views, const cow_block_set* sets,
                       const cow_render_params* params, const float* mlp, float* rgb, float* trans,
                       float* aux, void* ws, size_t ws_bytes, hipStream_t stream);
@@ -296,7 +302,11 @@ COW_API cow_status cow_render_noalloc(cow_ctx* ctx, const cow_view* views, int n
                                       const cow_render_params* params, const float* mlp, float* rgb, float* trans,
                                       float* aux, hipStream_t stream);
 
-/* Adjoint of cow_render for COW_F32 blocks.  grad_rgb [P][3] and grad_trans
+/* Adjoint of cow_render for COW_F32 blocks: the gradients that training
+ * through the block-merged render needs (Sec. 4.2, the block-based rendering
+ * used in training for consistency between training and rendering), by the
+ * chain rule through the deferred MLP, the merge across blocks and the
+ * per-block composite, with each ray's samples recomputed.  grad_rgb [P][3] and grad_trans
  * [P] (nullable) are dL/d outputs, as is params->opacity_weight (nullable);
  * aux is the forward's aux.  Gradients are
  * ACCUMULATED into grad_grid[e] / grad_plane[3e + k] for loaded entry e (in
