@@ -350,7 +350,11 @@ COW_API cow_status cow_autotune(cow_ctx* ctx, const cow_view* views, int n_views
                         size_t ws_bytes, const char* cache_path, hipStream_t stream);
 
 /* Current launch configuration (packet width in pixels, waves per
- * workgroup, persistent flag) and an explicit override. */
+ * workgroup, persistent flag) and an explicit override.  persistent: 1 =
+ * waves take packets from per-XCD work counters until they run out, 0 = one
+ * wave per packet, -1 (the default) = by texture type: 1 for COW_F32 launches
+ * (forward and adjoint), 0 for COW_U8.  The configuration never changes
+ * results. */
 COW_API cow_status cow_get_config(cow_ctx* ctx, int* tile_w, int* waves, int* persistent);
 COW_API cow_status cow_set_config(cow_ctx* ctx, int tile_w, int waves, int persistent);
 

@@ -755,13 +755,14 @@ __device__ inline int xcd_packet(int waves, int wave) {
     return lb * waves + wave;
 }
 
-// Persistent launches: one work counter per XCD.  XCD x owns the packets of
-// the same interleaved chunks xcd_packet gives it (chunk j of kXcdChunk
-// packets belongs to XCD j mod 8), takes them in order from its own counter,
+// Persistent launches: one work counter per XCD.  XCD x owns interleaved
+// chunks of kXcdChunk consecutive packets (chunk j belongs to XCD j mod 8;
+// 256 packets are four blocks of 8 x 8 tiles, so the packets an XCD runs
+// together cover a compact patch of one view), takes them in order from its own counter,
 // and once they run out takes the other XCDs' packets through their
 // counters.  Every packet is taken exactly once; a wave gets -1 when all
 // eight counters are exhausted, so every wave reaches the exit.
-constexpr int kXcds = 8, kXcdChunk = 64;
+constexpr int kXcds = 8, kXcdChunk = 256;
 __device__ inline int64_t xcd_packet_of(int x, int i) {
     return ((int64_t)(i / kXcdChunk) * kXcds + x) * kXcdChunk + (i % kXcdChunk);
 }

@@ -84,11 +84,15 @@ constexpr int kStagingSlots = 4;
 constexpr size_t kStagingInitial = 1 << 18;  // per slot, allocated by cow_create
 
 // default launch: 8x8 ray packets, four waves per workgroup, XCD-chunked
-// packet order (measured fastest on the 4x4-block 1080p frame; the
-// autotuner may change it)
+// packet order; persistent -1 picks by texture type: fp32 launches (forward
+// and adjoint) take packets from the per-XCD work counters, uint8 launches
+// are one wave per packet (each measured fastest on its 4x4-block workload;
+// the autotuner may change any of it)
 struct TuneCfg {
-    int tile_w = 8, waves = 4, persistent = 0;
+    int tile_w = 8, waves = 4, persistent = -1;
 };
+
+int persistent_for(const TuneCfg& t, int dtype) { return t.persistent < 0 ? (dtype == COW_F32 ? 1 : 0) : t.persistent; }
 
 }  // namespace
 
@@ -583,7 +587,7 @@ cow::MarchArgs march_args(cow_ctx* c, const CallTables& T, const RenderWs& w,
     a.pe = p->pe_freqs;
     a.rgb = nullptr;
     a.work_counter = w.counter;
-    a.persistent = c->cfg.persistent;
+    a.persistent = persistent_for(c->cfg, dtype);
     a.only_view = -1;
     a.only_set_pos = -1;
     a.contract = any_contracted(c, T.refs) ? 1 : 0;
@@ -1233,7 +1237,7 @@ static cow_status render_impl(cow_ctx* c, const cow_view* views, int n_views, co
     m.trans = trans;
     m.pe = p->pe_freqs;
     const bool per_block = (p->flags & COW_F_PER_BLOCK) != 0;
-    if (!per_block) a.persistent = c->cfg.persistent || (p->flags & COW_F_PERSISTENT) ? 1 : 0;
+    if (!per_block) a.persistent = a.persistent || (p->flags & COW_F_PERSISTENT) ? 1 : 0;
     c->have_fwd = c->timing && !(p->flags & COW_F_GRAPH) && !per_block;
     if (p->flags & COW_F_GRAPH) return run_graph(c, T, a, m, per_block, s);
     return enqueue_forward(c, T, a, m, per_block, s);
@@ -1347,7 +1351,6 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     if (!p->block_mlp) HIP_TRY(c, cow::launch_mlp_bwd(mb, s));  // per-block MLPs: adjoint inside the march
     cow::BwdArgs ba{};
     ba.m = march_args(c, T, w, p, COW_F32, const_cast<float*>(aux), nullptr);
-    ba.m.persistent = c->cfg.persistent;
     ba.m.counts = nullptr;
     ba.m.opacity = nullptr;
     ba.u = w.u;
@@ -1451,7 +1454,7 @@ cow_status cow_set_config(cow_ctx* c, int tile_w, int waves, int persistent) {
     if (!(waves == 1 || waves == 2 || waves == 4)) return fail(c, COW_E_INVALID, "waves per workgroup: 1, 2 or 4");
     c->cfg.tile_w = tile_w;
     c->cfg.waves = waves;
-    c->cfg.persistent = persistent ? 1 : 0;
+    c->cfg.persistent = persistent < 0 ? -1 : persistent ? 1 : 0;
     drop_graphs(c);
     return COW_OK;
 }

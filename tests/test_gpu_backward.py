@@ -182,4 +182,4 @@ def test_backward_every_launch_configuration(torch_cuda):
             gg, gp, gm = gpu_grads(torch, r, [view], sets, params, mlp, out["aux"],
                                    torch.tensor(g_rgb, dtype=torch.float32, device="cuda"))
             compare(gg, gp, gm, grads, gm_ref)
-    r.set_config(8, 4, 0)
+    r.set_config(8, 4, -1)

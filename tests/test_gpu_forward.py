@@ -194,7 +194,7 @@ def test_launch_variants_bitwise(c2, torch_cuda):
     sets = [sel, sel[:7]]
     mlp = torch.tensor(sg.xavier_mlp(1), device="cuda")
     p = sg.cityb_params()
-    r.set_config(8, 4, 0)
+    r.set_config(8, 4, -1)
     base = r.render(views, sets, p, mlp, counts=True)
     torch.cuda.synchronize()
     variants = []
@@ -203,7 +203,7 @@ def test_launch_variants_bitwise(c2, torch_cuda):
     for tw, wv, ps in ((16, 2, 0), (4, 1, 1), (32, 4, 0), (64, 1, 0), (1, 2, 0)):
         r.set_config(tw, wv, ps)
         variants.append(((tw, wv, ps), r.render(views, sets, p, mlp, counts=True)))
-    r.set_config(8, 4, 0)
+    r.set_config(8, 4, -1)
     # replay the cached graph a second time
     variants.append(("graph-replay", r.render(views, sets, p, mlp, counts=True, flags=F_GRAPH)))
     torch.cuda.synchronize()

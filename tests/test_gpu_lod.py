@@ -128,13 +128,13 @@ def test_autotune_invariance(c3):
     sets = [r.select(v, thresholds=THR, cull=True) for v in views]
     mlp = torch.tensor(sg.xavier_mlp(3), device="cuda")
     p = sg.cityb_params()
-    r.set_config(8, 4, 0)
+    r.set_config(8, 4, -1)
     base = r.render(views, sets, p, mlp)
     cfg = r.autotune(views, sets, p, mlp)
     tuned = r.render(views, sets, p, mlp)
     torch.cuda.synchronize()
     assert torch.equal(base["rgb"], tuned["rgb"]) and torch.equal(base["aux"], tuned["aux"])
-    r.set_config(8, 4, 0)
+    r.set_config(8, 4, -1)
     print("autotuned config", cfg)
 
 
@@ -147,7 +147,7 @@ def test_every_launch_configuration_bitwise(c3):
     sets = [r.select(v, thresholds=THR, cull=True) for v in views]
     mlp = torch.tensor(sg.xavier_mlp(3), device="cuda")
     p = sg.cityb_params()
-    r.set_config(8, 4, 0)
+    r.set_config(8, 4, -1)
     base = r.render(views, sets, p, mlp, counts=True)
     torch.cuda.synchronize()
     for persistent in (0, 1):
@@ -158,4 +158,4 @@ def test_every_launch_configuration_bitwise(c3):
                 torch.cuda.synchronize()
                 for key in ("rgb", "trans", "aux", "counts"):
                     assert torch.equal(o[key], base[key]), (tw, wv, persistent, key)
-    r.set_config(8, 4, 0)
+    r.set_config(8, 4, -1)
