@@ -488,20 +488,21 @@ __device__ inline void raw_u8(const BlockU& b, const float q[3], int cell, float
 // fp32 block: a texel pair is 64 contiguous bytes (channels 0-3, 4-7 of each
 // texel).  All 40 loads are issued before any is consumed, so one sample's
 // memory latency is paid once; the four textures are then summed
-// ((G + XY) + XZ) + YZ.
+// ((G + XY) + XZ) + YZ.  SPLIT: the grid's 16 loads are summed before the
+// planes' 24 are issued (the same sums in the same order, 64 fewer registers
+// in flight, for kernels whose other state needs them).
+template <bool SPLIT = false>
 __device__ inline void raw_f32(const BlockU& b, const Taps& T, float raw[kNch]) {
     float4 lo[20], hi[20];
-#pragma unroll
-    for (int j = 0; j < 10; ++j) {
+    auto load = [&](int j) {
         const __amdgpu_buffer_rsrc_t r = b.tex[pair_tex(j)];
         const int off = 32 * T.pidx[j];
         lo[2 * j] = ld16(r, off);
         hi[2 * j] = ld16(r, off + 16);
         lo[2 * j + 1] = ld16(r, off + 32);
         hi[2 * j + 1] = ld16(r, off + 48);
-    }
-#pragma unroll
-    for (int tex = 0; tex < 4; ++tex) {
+    };
+    auto sum = [&](int tex) {
         const int k0 = tex == 0 ? 0 : 4 + 4 * tex, n = tex == 0 ? 8 : 4;
         float a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -518,6 +519,20 @@ __device__ inline void raw_f32(const BlockU& b, const Taps& T, float raw[kNch]) 
         }
 #pragma unroll
         for (int c = 0; c < 8; ++c) raw[c] = tex == 0 ? a[c] : raw[c] + a[c];
+    };
+    if (SPLIT) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) load(j);
+        sum(0);
+#pragma unroll
+        for (int j = 4; j < 10; ++j) load(j);
+#pragma unroll
+        for (int tex = 1; tex < 4; ++tex) sum(tex);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 10; ++j) load(j);
+#pragma unroll
+        for (int tex = 0; tex < 4; ++tex) sum(tex);
     }
 }
 

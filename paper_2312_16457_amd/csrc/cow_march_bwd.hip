@@ -83,23 +83,173 @@ __device__ inline void scatter_planes(ScatterLds& L, int lane, const Taps& T, co
     }
 }
 
-// Grid pairs (taps 0-3): consecutive samples of a ray often fall between the
-// same eight grid texels (a 128^3 grid cell spans about 2.7 steps of 1/512),
-// so a lane sums its grid gradient in registers while its cell stays the same
-// and scatters the sum when the cell changes or the block ends.  Only the
-// summation order differs from a per-sample scatter.
+// Grid pairs (taps 0-3): the samples of a wave's rays fall between far fewer
+// distinct grid texels than they visit.  Consecutive samples of a ray share
+// a 128^3 grid cell for about 2.7 steps of 1/512, so a lane sums its cell's
+// gradient in registers while the cell stays the same (GridAcc); and
+// neighbouring rays of a packet pass about half a cell apart, so when its
+// cell changes the lane adds the sum into a small direct-mapped cache of
+// texel pairs in LDS shared by the wave, and a pair goes to memory only when
+// another pair takes its slot or the block ends.  The slot of the pair at
+// grid texel (x, y, z) is (x + 5 y + 19 z) mod 128, so the four pairs of a
+// cell never share a slot.  Pairs leaving the cache wait in a queue of 64
+// rows and go out through the transposed scatter when it fills or the block
+// ends.  Only the summation order differs from a per-sample scatter.
+constexpr int kGridSlots = 128;
+struct GridLds {
+    int tag[kGridSlots];      // texel index of the pair a slot holds, -1: empty
+    float v[kGridSlots][17];  // its 16 values (row padded against bank conflicts)
+};
+struct OutQueue {
+    float v[64][17];  // 16 values of a pair leaving the cache
+    int p[64];        // its texel index
+};
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline void grid_cache_clear(GridLds& G, int lane) {
+    for (int s = lane; s < kGridSlots; s += 64) G.tag[s] = -1;
+    wave_sync();
+}
+
+__device__ inline int grid_slot(int pid, int lgx, int lgy) {
+    const int x = pid & ((1 << lgx) - 1), y = (pid >> lgx) & ((1 << lgy) - 1), z = pid >> (lgx + lgy);
+    return (x + 5 * y + 19 * z) & (kGridSlots - 1);
+}
+
+// Scatter the q queued pairs (q is wave-uniform): rows 4j..4j+3 per atomic
+// instruction, 16 lanes per row, as in scatter_pair.
+__device__ inline void queue_flush(OutQueue& Q, int lane, int& q, const __amdgpu_buffer_rsrc_t& gr,
+                                   const __amdgpu_buffer_rsrc_t& gs) {
+    wave_sync();
+    const int e = lane & 15, sub = lane >> 4;
+    for (int j = 0; 4 * j < q; ++j) {
+        const int src = 4 * j + sub;
+        if (src < q) {
+            const int p = Q.p[src];
+            const float val = Q.v[src][e];
+            const int o = 32 * (p + (p & 1)) + 4 * e;
+            if (p & 1)
+                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gs, o, 0, 0);
+            else
+                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gr, o, 0, 0);
+        }
+    }
+    wave_sync();
+    q = 0;
+}
+
+// Row of this lane's entry among the lanes with `out`, after flushing the
+// queue if they do not all fit.
+__device__ inline int queue_row(OutQueue& Q, int lane, int& q, bool out, const __amdgpu_buffer_rsrc_t& gr,
+                                const __amdgpu_buffer_rsrc_t& gs) {
+    const uint64_t m = __ballot(out);
+    const int n = __popcll(m);
+    if (q + n > 64) queue_flush(Q, lane, q, gr, gs);
+    const int row = q + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    q += n;
+    return row;
+}
+
+// Add one grid pair per lane (texel index pid, values val(c); want ==
+// false: none) into the wave's cache, in three ordered phases: a pair that
+// holds its slot adds to it; the others try to take the slot (the first in
+// lane order wins, queues the pair the slot held, if any, and writes its own
+// values); the rest add to the slot if the winner holds their pair too, else
+// queue their own values.
+template <class Val>
+__device__ inline void grid_cache_add(GridLds& G, OutQueue& Q, int lane, int& q, int pid, bool want, int lgx, int lgy,
+                                      const __amdgpu_buffer_rsrc_t& gr, const __amdgpu_buffer_rsrc_t& gs, Val val) {
+    const int slot = want ? grid_slot(pid, lgx, lgy) : 0;
+    const int t = want ? G.tag[slot] : -2;
+    const bool hit = want && t == pid;
+    if (hit) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            __hip_atomic_fetch_add(&G.v[slot][c], val(c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+    const bool miss = want && !hit;
+    if (!__any(miss)) return;
+    wave_sync();
+    bool won = false;
+    if (miss) {
+        int expected = t;
+        won = __hip_atomic_compare_exchange_strong(&G.tag[slot], &expected, pid, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+    const bool ev = won && t >= 0;
+    const int row = queue_row(Q, lane, q, ev, gr, gs);
+    if (ev) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) Q.v[row][c] = G.v[slot][c];
+        Q.p[row] = t;
+    }
+    if (won) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) G.v[slot][c] = val(c);
+    }
+    wave_sync();
+    bool fb = false;
+    if (miss && !won) {
+        if (G.tag[slot] == pid) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                __hip_atomic_fetch_add(&G.v[slot][c], val(c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        } else {
+            fb = true;
+        }
+    }
+    const int row2 = queue_row(Q, lane, q, fb, gr, gs);
+    if (fb) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) Q.v[row2][c] = val(c);
+        Q.p[row2] = pid;
+    }
+    wave_sync();
+}
+
+// a lane's pending grid cell: its four pairs' gradient summed over the
+// ray's consecutive samples in the cell
 struct GridAcc {
-    int cell;        // pair index of tap 0 of the pending cell, -1: none
+    int cell;        // texel index of pair 0 of the pending cell, -1: none
     float v[4][16];  // pending gradient of the cell's four pairs
 };
 
-__device__ inline void flush_grid(ScatterLds& L, int lane, GridAcc& g, bool flush, int lgx, int lgy,
-                                  const __amdgpu_buffer_rsrc_t& gr, const __amdgpu_buffer_rsrc_t& gs) {
+__device__ inline void grid_acc_push(GridLds& G, OutQueue& Q, int lane, int& q, GridAcc& g, bool push, int lgx,
+                                     int lgy, const __amdgpu_buffer_rsrc_t& gr, const __amdgpu_buffer_rsrc_t& gs) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int pidx = g.cell + ((((j >> 1) << lgy) + (j & 1)) << lgx);
-        scatter_pair(L, lane, g.v[j], flush ? pidx : -1, gr, gs);
+        const int pid = g.cell + ((((j >> 1) << lgy) + (j & 1)) << lgx);
+        grid_cache_add(G, Q, lane, q, pid, push, lgx, lgy, gr, gs, [&](int c) { return g.v[j][c]; });
     }
+    if (push) {
+        g.cell = -1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int c = 0; c < 16; ++c) g.v[j][c] = 0.0f;
+    }
+}
+
+// send every pair the cache and the queue hold and empty both (the block's end)
+__device__ inline void grid_cache_flush(GridLds& G, OutQueue& Q, int lane, int& q, const __amdgpu_buffer_rsrc_t& gr,
+                                        const __amdgpu_buffer_rsrc_t& gs) {
+    for (int s0 = 0; s0 < kGridSlots; s0 += 64) {
+        const int s = s0 + lane;
+        const int t = G.tag[s];
+        const int row = queue_row(Q, lane, q, t >= 0, gr, gs);
+        if (t >= 0) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) Q.v[row][c] = G.v[s][c];
+            Q.p[row] = t;
+        }
+    }
+    if (q > 0) queue_flush(Q, lane, q, gr, gs);
+    grid_cache_clear(G, lane);
 }
 
 // BMLP: per-block deferred MLPs before the merge.  Per block k with prefix
@@ -110,7 +260,8 @@ __device__ inline void flush_grid(ScatterLds& L, int lane, GridAcc& g, bool flus
 // single-chain one with these per-block u and transmittance term.
 template <int MODE, bool OPAC, bool BMLP>
 __device__ __attribute__((always_inline)) inline void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile,
-                                                                       int lane, ScatterLds& lds) {
+                                                                       int lane, ScatterLds& lds, GridLds& glds,
+                                                                       OutQueue& gq) {
     const MarchArgs& a = ba.m;
     ViewU v;
     load_view(V, v);
@@ -202,13 +353,15 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
         int cur_cell = -1;
         bool cur_occ = false;
         float Tk = 1.0f;  // block-local transmittance, for the same termination decision as the forward
+        const bool want_grid = gptr[0] != nullptr;
+        int nq = 0;  // pairs waiting in the wave's queue
         GridAcc gacc;
         gacc.cell = -1;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int c = 0; c < 16; ++c) gacc.v[j][c] = 0.0f;
-        const bool want_grid = gptr[0] != nullptr;
+        if (want_grid) grid_cache_clear(glds, lane);
         for (;;) {
             float q[3];
             int cell = 0;
@@ -220,7 +373,7 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
             if (have) {
                 sample_taps(b, q, T);
                 float raw[8];
-                raw_f32(b, T, raw);
+                raw_f32<true>(b, T, raw);
                 const float sigma = __expf(raw[0]);
                 const float alpha = alpha_of(sigma * sp.delta);
                 const float w = Tg * alpha;
@@ -243,20 +396,12 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
                 Tk *= 1.0f - alpha;
                 if (T_blk * Tk < a.t_min) kb = k;  // early ray termination, as in the forward
             }
-            // collective over the wave: lanes without a sample take part with nothing to add
+            // collectives over the wave: lanes without a sample take part with nothing to add
+            scatter_planes(lds, lane, T, draw, gptr, gr, gs, have);
             if (want_grid) {
                 const int cell_now = have ? T.pidx[0] : -1;
-                const bool flush = have && gacc.cell >= 0 && cell_now != gacc.cell;
-                if (__any(flush)) {
-                    flush_grid(lds, lane, gacc, flush, b.lgx, b.lgy, gr[0], gs[0]);
-                    if (flush) {
-                        gacc.cell = -1;
-#pragma unroll
-                        for (int j = 0; j < 4; ++j)
-#pragma unroll
-                            for (int c = 0; c < 16; ++c) gacc.v[j][c] = 0.0f;
-                    }
-                }
+                const bool push = have && gacc.cell >= 0 && cell_now != gacc.cell;
+                if (__any(push)) grid_acc_push(glds, gq, lane, nq, gacc, push, b.lgx, b.lgy, gr[0], gs[0]);
                 if (have) {
                     gacc.cell = cell_now;
 #pragma unroll
@@ -268,9 +413,12 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
                         }
                 }
             }
-            scatter_planes(lds, lane, T, draw, gptr, gr, gs, have);
         }
-        if (want_grid && __any(gacc.cell >= 0)) flush_grid(lds, lane, gacc, gacc.cell >= 0, b.lgx, b.lgy, gr[0], gs[0]);
+        if (want_grid) {
+            if (__any(gacc.cell >= 0))
+                grid_acc_push(glds, gq, lane, nq, gacc, gacc.cell >= 0, b.lgx, b.lgy, gr[0], gs[0]);
+            grid_cache_flush(glds, gq, lane, nq, gr[0], gs[0]);
+        }
         T_blk *= Tk;
     }
 }
@@ -281,6 +429,8 @@ template <int MODE, bool OPAC, bool BMLP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void march_bwd_kernel(BwdArgs ba) {
     const MarchArgs& a = ba.m;
     __shared__ ScatterLds lds[4];
+    __shared__ GridLds glds[4];
+    __shared__ OutQueue gq[4];
     const int lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
     const int wave = ufl(threadIdx.x >> 6);
@@ -294,7 +444,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
         }
         if (p >= a.total_tiles) return;
         const DevView* V = find_view_by_tile(a.views, a.n_views, p);
-        march_bwd_packet<MODE, OPAC, BMLP>(ba, V, p - ufl(V->tile_begin), lane, lds[wave]);
+        march_bwd_packet<MODE, OPAC, BMLP>(ba, V, p - ufl(V->tile_begin), lane, lds[wave], glds[wave], gq[wave]);
         if (!a.persistent) return;
     }
 }
