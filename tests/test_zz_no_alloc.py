@@ -40,6 +40,31 @@ def test_noalloc_matches_render_on_two_calls(have_gpu):
         assert int(ref["counts"][:, 0].sum()) > 0
 
 
+def test_noalloc_fp32_blocks_default_launch(have_gpu):
+    """fp32 blocks take persistent launches by default: their work counters
+    live in the scratch too (two calls, the second smaller)."""
+    import torch
+    from paper_2312_16457_amd import Renderer
+    scene = sg.make_scene(2, 2, ((16, 32, 4),), sg.F32, blobs_per_block=10, blob_z=(0.0, 0.4), seed=8, shift=2.0)
+    r = Renderer(0).load_blocks(scene.blocks)
+    assert r.get_config() == (8, 4, -1)
+    refs = [(b.block_id, b.lod) for b in scene.blocks]
+    mlp = torch.tensor(sg.xavier_mlp(3), device="cuda")
+    p = sg.cityb_params()
+    calls = (([_view(48, 40, (1.0, -1.1, 1.3), (1.0, 1.0, 0.1))], [refs]),
+             ([_view(16, 12, (2.6, 1.0, 1.0), (0.8, 1.1, 0.2))], [refs[:2]]))
+    for views, sets in calls:
+        ref = r.render(views, sets, p, mlp, counts=True)
+        out = {k: torch.full_like(ref[k], float("nan")) for k in ("rgb", "trans", "aux")}
+        out["counts"] = torch.full_like(ref["counts"], -1)
+        r.render_noalloc(views, sets, p, mlp, out)
+        torch.cuda.synchronize()
+        print("noalloc fp32 call:", ref["rgb"].shape[0], "pixels", flush=True)
+        for k in ("rgb", "trans", "aux", "counts"):
+            assert torch.equal(out[k], ref[k]), k
+        assert int(ref["counts"][:, 0].sum()) > 0
+
+
 def test_noalloc_limits_are_refused(have_gpu):
     import torch
     from paper_2312_16457_amd import F_GRAPH, CowError, Renderer
