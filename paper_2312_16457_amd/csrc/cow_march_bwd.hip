@@ -49,7 +49,12 @@ __device__ inline void scatter_pair(ScatterLds& L, int lane, const float vals[16
     const int e = lane & 15, sub = lane >> 4;
 #pragma unroll 4
     for (int j = 0; j < 16; ++j) {
-        const int src = 4 * j + sub;
+        // the four rows of one instruction come from lanes far apart in the
+        // 8 x 8 packet (pixel (x, y) of lane 8y + x: x shifted by 3 and y by 2
+        // per row), since neighbouring rays often share a pair and two rows
+        // of one instruction on the same segment cost the L2 five requests
+        // instead of two
+        const int src = (((j & 7) + 3 * sub) & 7) + 8 * ((j >> 3) + 2 * sub);
         const int o = __float_as_int(L.v[src][16 + (e >> 3)]);
         const float val = L.v[src][e];
         const bool odd = __float_as_int(L.v[src][18]) != 0;
