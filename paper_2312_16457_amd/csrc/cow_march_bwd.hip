@@ -27,47 +27,81 @@ namespace cow {
 // far fewer cache-line requests for the L2 atomic units, whose request rate
 // bounds the adjoint.
 struct ScatterLds {
-    float v[64][20];  // 16 values, byte offsets of the two texels (-1: none), target, pad
+    // 16 values; the pair's byte offset with its parity in bit 0 (-1: none);
+    // the lane whose values ride along in this row (-1: none)
+    float v[64][18];
+    // lanes of one step that scatter the same pair: (p << 6 | first lane) by
+    // a hash of p, -1 between steps
+    int merge[256];
 };
+
+__device__ inline void wave_fence() {
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline void scatter_lds_init(ScatterLds& L, int lane) {
+    for (int i = lane; i < 256; i += 64) L.merge[i] = -1;
+    wave_fence();
+}
 
 // Add vals[16] (texel p channels 0-7, texel p + 1 channels 0-7) for the pair
 // at texel index p (-1: nothing from this lane) of one gradient texture: an
 // even p into the gradient at byte 32 p, an odd p into its shadow at byte
-// 32 (p + 1), so every pair is one aligned 64-byte segment.
+// 32 (p + 1), so every pair is one aligned 64-byte segment.  Neighbouring
+// rays often scatter the same pair in the same step (a sixth of the plane
+// pairs on the differentiable workload), so a lane whose pair another lane
+// entered first in a small LDS table hands its row to that lane's row (one
+// such lane per row, taken by compare-and-swap): the scatter adds the two
+// rows' values and sends one request for them.  Other repeats keep their
+// rows.
 __device__ inline void scatter_pair(ScatterLds& L, int lane, const float vals[16], int p,
                                     const __amdgpu_buffer_rsrc_t& gr, const __amdgpu_buffer_rsrc_t& gs) {
     float* row = L.v[lane];
 #pragma unroll
     for (int c = 0; c < 16; ++c) row[c] = vals[c];
-    const int off = p < 0 ? -1 : 32 * (p + (p & 1));
-    row[16] = __int_as_float(off);
-    row[17] = __int_as_float(off < 0 ? -1 : off + 32);
-    row[18] = __int_as_float(p & 1);
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    row[16] = __int_as_float(p < 0 ? -1 : (32 * (p + (p & 1))) | (p & 1));
+    row[17] = __int_as_float(-1);
+    wave_fence();
+    const bool merge = p >= 0 && p < (1 << 25);  // the table packs p and a lane into 31 bits
+    int h = 0;
+    if (merge) {
+        h = (int)(((uint32_t)p * 2654435761u) >> 24);
+        int expected = -1;
+        if (!__hip_atomic_compare_exchange_strong(&L.merge[h], &expected, (p << 6) | lane, __ATOMIC_RELAXED,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) &&
+            (expected >> 6) == p) {
+            int none = -1;
+            int* slot = reinterpret_cast<int*>(&L.v[expected & 63][17]);
+            if (__hip_atomic_compare_exchange_strong(slot, &none, lane, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WAVEFRONT))
+                row[16] = __int_as_float(-1);  // sent with the first lane's row
+        }
+    }
+    wave_fence();
     const int e = lane & 15, sub = lane >> 4;
 #pragma unroll 4
     for (int j = 0; j < 16; ++j) {
         // the four rows of one instruction come from lanes far apart in the
         // 8 x 8 packet (pixel (x, y) of lane 8y + x: x shifted by 3 and y by 2
-        // per row), since neighbouring rays often share a pair and two rows
-        // of one instruction on the same segment cost the L2 five requests
-        // instead of two
+        // per row): two rows of one instruction on the same segment cost the
+        // L2 five requests instead of two
         const int src = (((j & 7) + 3 * sub) & 7) + 8 * ((j >> 3) + 2 * sub);
-        const int o = __float_as_int(L.v[src][16 + (e >> 3)]);
-        const float val = L.v[src][e];
-        const bool odd = __float_as_int(L.v[src][18]) != 0;
-        if (o >= 0) {
-            if (odd)
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gs, o + 4 * (e & 7), 0, 0);
+        const int ov = __float_as_int(L.v[src][16]);
+        const int f = __float_as_int(L.v[src][17]);
+        float val = L.v[src][e];
+        if (f >= 0) val += L.v[f][e];
+        if (ov >= 0) {
+            const int o = (ov & ~1) + 4 * e;
+            if (ov & 1)
+                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gs, o, 0, 0);
             else
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gr, o + 4 * (e & 7), 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gr, o, 0, 0);
         }
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_fence();
+    if (merge) L.merge[h] = -1;
 }
 
 // Plane pairs (taps 4-9) of one sample: scattered at once.
@@ -439,6 +473,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
     const int lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
     const int wave = ufl(threadIdx.x >> 6);
+    scatter_lds_init(lds[wave], lane);
     int p = a.persistent ? 0 : ufl(xcd_packet(waves, wave));  // one call site, as in the forward
     for (;;) {
         if (a.persistent) {
