@@ -343,8 +343,10 @@ COW_API cow_status cow_sparsity(cow_ctx* ctx, const cow_block_set* set, const fl
 
 /* Time the launch configurations (ray-packet shape, waves per workgroup,
  * persistent or not) on this workload and keep the fastest for later
- * renders; reads/writes a JSON cache at cache_path (nullable).  The choice
- * never changes results. */
+ * renders; the fastest of the short trials replaces the configuration in
+ * force only if longer interleaved runs of both show it at least 1% faster.
+ * Reads/writes a JSON cache at cache_path (nullable).  The choice never
+ * changes results. */
 COW_API cow_status cow_autotune(cow_ctx* ctx, const cow_view* views, int n_views, const cow_block_set* sets,
                         const cow_render_params* params, const float* mlp, void* ws,
                         size_t ws_bytes, const char* cache_path, hipStream_t stream);
