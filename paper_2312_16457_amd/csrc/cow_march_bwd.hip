@@ -35,6 +35,8 @@ struct ScatterLds {
     int merge[256];
 };
 
+// ordering point for one wave's LDS traffic: no memory operation moves across
+// it (a wave's LDS operations complete in order)
 __device__ inline void wave_fence() {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -144,15 +146,9 @@ struct OutQueue {
     int p[64];        // its texel index
 };
 
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __device__ inline void grid_cache_clear(GridLds& G, int lane) {
     for (int s = lane; s < kGridSlots; s += 64) G.tag[s] = -1;
-    wave_sync();
+    wave_fence();
 }
 
 __device__ inline int grid_slot(int pid, int lgx, int lgy) {
@@ -164,7 +160,7 @@ __device__ inline int grid_slot(int pid, int lgx, int lgy) {
 // instruction, 16 lanes per row, as in scatter_pair.
 __device__ inline void queue_flush(OutQueue& Q, int lane, int& q, const __amdgpu_buffer_rsrc_t& gr,
                                    const __amdgpu_buffer_rsrc_t& gs) {
-    wave_sync();
+    wave_fence();
     const int e = lane & 15, sub = lane >> 4;
     for (int j = 0; 4 * j < q; ++j) {
         const int src = 4 * j + sub;
@@ -178,7 +174,7 @@ __device__ inline void queue_flush(OutQueue& Q, int lane, int& q, const __amdgpu
                 __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gr, o, 0, 0);
         }
     }
-    wave_sync();
+    wave_fence();
     q = 0;
 }
 
@@ -213,7 +209,7 @@ __device__ inline void grid_cache_add(GridLds& G, OutQueue& Q, int lane, int& q,
     }
     const bool miss = want && !hit;
     if (!__any(miss)) return;
-    wave_sync();
+    wave_fence();
     bool won = false;
     if (miss) {
         int expected = t;
@@ -231,7 +227,7 @@ __device__ inline void grid_cache_add(GridLds& G, OutQueue& Q, int lane, int& q,
 #pragma unroll
         for (int c = 0; c < 16; ++c) G.v[slot][c] = val(c);
     }
-    wave_sync();
+    wave_fence();
     bool fb = false;
     if (miss && !won) {
         if (G.tag[slot] == pid) {
@@ -248,7 +244,7 @@ __device__ inline void grid_cache_add(GridLds& G, OutQueue& Q, int lane, int& q,
         for (int c = 0; c < 16; ++c) Q.v[row2][c] = val(c);
         Q.p[row2] = pid;
     }
-    wave_sync();
+    wave_fence();
 }
 
 // a lane's pending grid cell: its four pairs' gradient summed over the
