@@ -206,10 +206,11 @@ COW_API const char* cow_last_error(const cow_ctx* ctx);
 
 /* Workspace sizes in bytes for loading `blocks` and for render / backward
  * calls of up to max_views views and max_pixels pixels in total.  The
- * backward size includes a shadow of every float32 texture (its texel count
- * plus one, 32 bytes each): texel pairs that start at an odd texel are
- * accumulated there, one aligned 64-byte segment per pair, and folded into
- * the caller's gradients at the end of the call. */
+ * backward size includes a pair-slot buffer for every float32 texture (64
+ * bytes per texel): the adjoint adds the gradient of each pair of adjacent
+ * texels into the slot of its first texel, one aligned 64-byte segment per
+ * pair, and folds the slots into the caller's gradients at the end of the
+ * call. */
 COW_API cow_status cow_query_workspace(cow_ctx* ctx, const cow_block_desc* blocks, int n_blocks,
                                int max_views, int64_t max_pixels, size_t* load_bytes,
                                size_t* render_bytes, size_t* backward_bytes);

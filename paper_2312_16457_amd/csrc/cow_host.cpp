@@ -465,27 +465,28 @@ struct RenderWs {
     float* u;
     float* grad_mlp_scratch;
     cow::FoldJob* jobs;
-    unsigned char* shadow;
+    unsigned char* slots;
     size_t bytes;
 };
 
-// shadow texture of a gradient texture of n texels: n + 1 texels of 32 bytes
-size_t shadow_bytes(int64_t n_texels) { return align_up((size_t)(n_texels + 1) * 32); }
+// pair-slot buffer of a gradient texture of n texels: one 64-byte slot per
+// texel, the pair that starts there
+size_t slot_bytes(int64_t n_texels) { return align_up((size_t)n_texels * 64); }
 
-// shadows of every float32 entry: grid, then the three planes
-size_t shadow_total(const cow_block_desc* d, int64_t n) {
+// pair-slot buffers of every float32 entry: grid, then the three planes
+size_t slots_total(const cow_block_desc* d, int64_t n) {
     size_t t = 0;
     for (int64_t i = 0; i < n; ++i) {
         if (d[i].dtype != COW_F32) continue;
-        t += shadow_bytes((int64_t)grid_texels(d[i]));
-        for (int p = 0; p < 3; ++p) t += shadow_bytes((int64_t)plane_texels(d[i], p));
+        t += slot_bytes((int64_t)grid_texels(d[i]));
+        for (int p = 0; p < 3; ++p) t += slot_bytes((int64_t)plane_texels(d[i], p));
     }
     return t;
 }
 
-// render workspace: [views][refs][aux scratch][counter][grad pointers][u][mlp grad scratch][fold jobs][shadows]
+// render workspace: [views][refs][aux scratch][counter][grad pointers][u][mlp grad scratch][fold jobs][pair slots]
 size_t render_ws_layout(int64_t n_views, int64_t n_refs, int64_t n_pix, bool need_aux, bool backward,
-                        int64_t n_entries, size_t shadow, unsigned char* base, RenderWs* w) {
+                        int64_t n_entries, size_t slots, unsigned char* base, RenderWs* w) {
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -498,12 +499,12 @@ size_t render_ws_layout(int64_t n_views, int64_t n_refs, int64_t n_pix, bool nee
     r.aux = need_aux ? (float*)take(32 * (size_t)n_pix) : nullptr;
     r.counter = (int32_t*)take(64);
     if (backward) {
-        // gradient pointers (4 per entry), then shadow pointers (4 per entry)
+        // gradient pointers (4 per entry), then pair-slot pointers (4 per entry)
         r.grad_ptrs = (float**)take(sizeof(float*) * 8 * (size_t)std::max<int64_t>(n_entries, 1));
         r.u = (float*)take(32 * (size_t)n_pix);
         r.grad_mlp_scratch = (float*)take(4 * cow::kMlpParamsMax);
         r.jobs = (cow::FoldJob*)take(sizeof(cow::FoldJob) * 4 * (size_t)std::max<int64_t>(n_entries, 1));
-        r.shadow = (unsigned char*)take(shadow);
+        r.slots = (unsigned char*)take(slots);
     }
     r.bytes = off;
     if (w) *w = r;
@@ -888,7 +889,7 @@ cow_status cow_query_workspace(cow_ctx* c, const cow_block_desc* blocks, int n_b
     if (render_bytes) *render_bytes = render_ws_layout(max_views, refs, max_pixels, true, false, n_blocks, 0, nullptr, nullptr);
     if (backward_bytes)
         *backward_bytes = render_ws_layout(max_views, refs, max_pixels, true, true, n_blocks,
-                                           shadow_total(blocks, n_blocks), nullptr, nullptr);
+                                           slots_total(blocks, n_blocks), nullptr, nullptr);
     return COW_OK;
 }
 
@@ -1286,7 +1287,7 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     std::vector<cow_block_desc> descs;
     for (const Entry& en : c->entries) descs.push_back(en.desc);
     const size_t need = render_ws_layout(n_views, (int64_t)T.refs.size(), T.n_pix, false, true,
-                                         (int64_t)c->entries.size(), shadow_total(descs.data(), (int64_t)descs.size()),
+                                         (int64_t)c->entries.size(), slots_total(descs.data(), (int64_t)descs.size()),
                                          (unsigned char*)ws, &w);
     if (!ws || ws_bytes < need) return fail(c, COW_E_WORKSPACE, "backward workspace too small");
     const size_t ne = c->entries.size();
@@ -1298,14 +1299,14 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     }
     if (T.n_pix == 0) return COW_OK;
     HIP_TRY(c, hipSetDevice(c->device));
-    // views, refs, the per-entry gradient and shadow pointer tables and the
+    // views, refs, the per-entry gradient and pair-slot pointer tables and the
     // fold jobs (the textures of the entries this call renders) in one upload
     std::vector<float*> ptrs(8 * ne, nullptr);
     std::vector<char> used(ne, 0);
     for (int32_t e : T.refs) used[e] = 1;
     std::vector<cow::FoldJob> jobs;
     int64_t max_texels = 0;
-    size_t sh_off = 0;
+    size_t sl_off = 0;
     for (size_t e = 0; e < ne; ++e) {
         ptrs[e] = grad_grid[e];
         for (int k = 0; k < 3; ++k) ptrs[ne + 3 * e + k] = grad_plane[3 * e + k];
@@ -1313,11 +1314,11 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
         for (int t = 0; t < 4; ++t) {
             const int64_t n = (int64_t)(t == 0 ? grid_texels(descs[e]) : plane_texels(descs[e], t - 1));
             float* g = t == 0 ? grad_grid[e] : grad_plane[3 * e + t - 1];
-            float* sh = (float*)(w.shadow + sh_off);
-            sh_off += shadow_bytes(n);
+            float* sl = (float*)(w.slots + sl_off);
+            sl_off += slot_bytes(n);
             if (!g || !used[e]) continue;
-            ptrs[4 * ne + 4 * e + t] = sh;
-            jobs.push_back(cow::FoldJob{g, sh, n});
+            ptrs[4 * ne + 4 * e + t] = sl;
+            jobs.push_back(cow::FoldJob{g, sl, n});
             max_texels = std::max(max_texels, n);
         }
     }
@@ -1337,7 +1338,7 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     if (jb) HIP_TRY(c, hipMemcpyAsync(w.jobs, sl->buf + o_job, jb, hipMemcpyHostToDevice, s));
     st = release_staging(c, sl, s);
     if (st != COW_OK) return st;
-    HIP_TRY(c, cow::launch_shadow_zero(w.jobs, (int)jobs.size(), max_texels, s));
+    HIP_TRY(c, cow::launch_slots_zero(w.jobs, (int)jobs.size(), max_texels, s));
     cow::MlpBwdArgs mb{};
     mb.views = w.views;
     mb.n_views = n_views;
@@ -1360,13 +1361,13 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     ba.grad_block_mlp = p->grad_block_mlp;
     ba.grad_grid = w.grad_ptrs;
     ba.grad_plane = w.grad_ptrs + ne;
-    ba.shadow = w.grad_ptrs + 4 * ne;
+    ba.slots = w.grad_ptrs + 4 * ne;
     c->have_bwd = c->timing;
     if (ba.m.persistent) HIP_TRY(c, cow::launch_reset_counter(ba.m.work_counter, s));
     if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[2], s));
     HIP_TRY(c, cow::launch_march_bwd(ba, c->cfg.waves, s));
     if (c->timing) HIP_TRY(c, hipEventRecord(c->ev[3], s));
-    HIP_TRY(c, cow::launch_shadow_fold(w.jobs, (int)jobs.size(), max_texels, s));
+    HIP_TRY(c, cow::launch_slots_fold(w.jobs, (int)jobs.size(), max_texels, s));
     return COW_OK;
 } catch (...) {
     return fail(c, COW_E_INTERNAL, "internal error");

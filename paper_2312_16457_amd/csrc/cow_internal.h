@@ -125,19 +125,20 @@ struct BwdArgs {
     float* grad_block_mlp;     // [entries][mlp_params(pe)], accumulated, or null
     float* const* grad_grid;   // device array of per-entry pointers
     float* const* grad_plane;  // device array, 3 per entry
-    // Odd-pair gradients: a texel pair (p, p + 1) with p odd straddles two
-    // 64-byte segments of the gradient, so it is added to a shadow texture
-    // shifted by one texel instead (texel x at position x + 1), where it is
-    // one aligned segment; the shadow is folded into the gradient after the
-    // march.  Device array, 4 per entry (grid, xy, xz, yz; null: none).
-    float* const* shadow;
+    // Pair-slot buffers: the march adds the gradient of texel pair (p, p + 1)
+    // into slot p of its texture's buffer (16 floats, at byte 64 p), one
+    // aligned 64-byte segment per pair whatever the parity of p (in the
+    // gradient itself an odd pair would straddle two); the slots are folded
+    // into the gradient after the march.  Device array, 4 per entry (grid,
+    // xy, xz, yz; null: none).
+    float* const* slots;
 };
 
-// zero the shadows, then (after the march) add shadow texel x + 1 into
-// gradient texel x
+// zero the pair slots, then (after the march) add slot x's first texel and
+// slot x - 1's second texel into gradient texel x
 struct FoldJob {
     float* grad;      // [n_texels][8]
-    float* shadow;    // [n_texels + 1][8]
+    float* slots;     // [n_texels][2][8]
     int64_t n_texels;
 };
 
@@ -166,8 +167,8 @@ hipError_t launch_clear_aux(float* aux, int64_t n_pix, hipStream_t s);
 hipError_t launch_mlp(const MlpArgs& a, hipStream_t s);
 hipError_t launch_mlp_bwd(const MlpBwdArgs& a, hipStream_t s);
 hipError_t launch_march_bwd(const BwdArgs& a, int waves_per_group, hipStream_t s);
-hipError_t launch_shadow_zero(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s);
-hipError_t launch_shadow_fold(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s);
+hipError_t launch_slots_zero(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s);
+hipError_t launch_slots_fold(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s);
 hipError_t launch_sparsity(const SparsityArgs& a, hipStream_t s);
 hipError_t launch_pack_bricks(const DevBlock* blocks, int entry, int n_cells, int s_cells,
                               const int32_t* slot_host_unused, hipStream_t st);

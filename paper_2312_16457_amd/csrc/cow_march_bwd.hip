@@ -27,8 +27,8 @@ namespace cow {
 // far fewer cache-line requests for the L2 atomic units, whose request rate
 // bounds the adjoint.
 struct ScatterLds {
-    // 16 values; the pair's byte offset with its parity in bit 0 (-1: none);
-    // the lane whose values ride along in this row (-1: none)
+    // 16 values; the pair's byte offset in its pair-slot buffer, 64 p (-1:
+    // none); the lane whose values ride along in this row (-1: none)
     float v[64][18];
     // lanes of one step that scatter the same pair: (p << 6 | first lane) by
     // a hash of p, -1 between steps
@@ -49,9 +49,12 @@ __device__ inline void scatter_lds_init(ScatterLds& L, int lane) {
 }
 
 // Add vals[16] (texel p channels 0-7, texel p + 1 channels 0-7) for the pair
-// at texel index p (-1: nothing from this lane) of one gradient texture: an
-// even p into the gradient at byte 32 p, an odd p into its shadow at byte
-// 32 (p + 1), so every pair is one aligned 64-byte segment.  Neighbouring
+// at texel index p (-1: nothing from this lane) of one gradient texture into
+// slot p of its pair-slot buffer (64 bytes per texel, at byte 64 p): every
+// pair is one aligned 64-byte segment whatever its parity, and one buffer
+// resource serves every row of an atomic instruction.  The fold after the
+// march adds slot p's first texel and slot p - 1's second texel into
+// gradient texel p.  Neighbouring
 // rays often scatter the same pair in the same step (a sixth of the plane
 // pairs on the differentiable workload), so a lane whose pair another lane
 // entered first in a small LDS table hands its row to that lane's row (one
@@ -59,11 +62,12 @@ __device__ inline void scatter_lds_init(ScatterLds& L, int lane) {
 // rows' values and sends one request for them.  Other repeats keep their
 // rows.
 __device__ inline void scatter_pair(ScatterLds& L, int lane, const float vals[16], int p,
-                                    const __amdgpu_buffer_rsrc_t& gr, const __amdgpu_buffer_rsrc_t& gs) {
+                                    const __amdgpu_buffer_rsrc_t& ga) {
     float* row = L.v[lane];
 #pragma unroll
     for (int c = 0; c < 16; ++c) row[c] = vals[c];
-    row[16] = __int_as_float(p < 0 ? -1 : (32 * (p + (p & 1))) | (p & 1));
+    // a multiple of 64 below 2^32 (fewer than 2^26 texels), so never -1
+    row[16] = __int_as_float(p < 0 ? -1 : (int)((uint32_t)p << 6));
     row[17] = __int_as_float(-1);
     wave_fence();
     const bool merge = p >= 0 && p < (1 << 25);  // the table packs p and a lane into 31 bits
@@ -94,13 +98,7 @@ __device__ inline void scatter_pair(ScatterLds& L, int lane, const float vals[16
         const int f = __float_as_int(L.v[src][17]);
         float val = L.v[src][e];
         if (f >= 0) val += L.v[f][e];
-        if (ov >= 0) {
-            const int o = (ov & ~1) + 4 * e;
-            if (ov & 1)
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gs, o, 0, 0);
-            else
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gr, o, 0, 0);
-        }
+        if (ov != -1) __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, ga, (int)((uint32_t)ov + 4u * e), 0, 0);
     }
     wave_fence();
     if (merge) L.merge[h] = -1;
@@ -108,8 +106,7 @@ __device__ inline void scatter_pair(ScatterLds& L, int lane, const float vals[16
 
 // Plane pairs (taps 4-9) of one sample: scattered at once.
 __device__ inline void scatter_planes(ScatterLds& L, int lane, const Taps& T, const float draw[8],
-                                      float* const gptr[4], const __amdgpu_buffer_rsrc_t gr[4],
-                                      const __amdgpu_buffer_rsrc_t gs[4], bool have) {
+                                      float* const gptr[4], const __amdgpu_buffer_rsrc_t ga[4], bool have) {
 #pragma unroll
     for (int pr = 4; pr < 10; ++pr) {
         const int tex = pair_tex(pr);
@@ -120,7 +117,7 @@ __device__ inline void scatter_planes(ScatterLds& L, int lane, const Taps& T, co
             vals[c] = T.w[2 * pr] * draw[c];
             vals[8 + c] = T.w[2 * pr + 1] * draw[c];
         }
-        scatter_pair(L, lane, vals, have ? T.pidx[pr] : -1, gr[tex], gs[tex]);
+        scatter_pair(L, lane, vals, have ? T.pidx[pr] : -1, ga[tex]);
     }
 }
 
@@ -158,20 +155,15 @@ __device__ inline int grid_slot(int pid, int lgx, int lgy) {
 
 // Scatter the q queued pairs (q is wave-uniform): rows 4j..4j+3 per atomic
 // instruction, 16 lanes per row, as in scatter_pair.
-__device__ inline void queue_flush(OutQueue& Q, int lane, int& q, const __amdgpu_buffer_rsrc_t& gr,
-                                   const __amdgpu_buffer_rsrc_t& gs) {
+__device__ inline void queue_flush(OutQueue& Q, int lane, int& q, const __amdgpu_buffer_rsrc_t& ga) {
     wave_fence();
     const int e = lane & 15, sub = lane >> 4;
     for (int j = 0; 4 * j < q; ++j) {
         const int src = 4 * j + sub;
         if (src < q) {
-            const int p = Q.p[src];
+            const uint32_t p = (uint32_t)Q.p[src];
             const float val = Q.v[src][e];
-            const int o = 32 * (p + (p & 1)) + 4 * e;
-            if (p & 1)
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gs, o, 0, 0);
-            else
-                __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, gr, o, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, ga, (int)((p << 6) + 4u * e), 0, 0);
         }
     }
     wave_fence();
@@ -180,11 +172,10 @@ __device__ inline void queue_flush(OutQueue& Q, int lane, int& q, const __amdgpu
 
 // Row of this lane's entry among the lanes with `out`, after flushing the
 // queue if they do not all fit.
-__device__ inline int queue_row(OutQueue& Q, int lane, int& q, bool out, const __amdgpu_buffer_rsrc_t& gr,
-                                const __amdgpu_buffer_rsrc_t& gs) {
+__device__ inline int queue_row(OutQueue& Q, int lane, int& q, bool out, const __amdgpu_buffer_rsrc_t& ga) {
     const uint64_t m = __ballot(out);
     const int n = __popcll(m);
-    if (q + n > 64) queue_flush(Q, lane, q, gr, gs);
+    if (q + n > 64) queue_flush(Q, lane, q, ga);
     const int row = q + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
     q += n;
     return row;
@@ -198,7 +189,7 @@ __device__ inline int queue_row(OutQueue& Q, int lane, int& q, bool out, const _
 // queue their own values.
 template <class Val>
 __device__ inline void grid_cache_add(GridLds& G, OutQueue& Q, int lane, int& q, int pid, bool want, int lgx, int lgy,
-                                      const __amdgpu_buffer_rsrc_t& gr, const __amdgpu_buffer_rsrc_t& gs, Val val) {
+                                      const __amdgpu_buffer_rsrc_t& ga, Val val) {
     const int slot = want ? grid_slot(pid, lgx, lgy) : 0;
     const int t = want ? G.tag[slot] : -2;
     const bool hit = want && t == pid;
@@ -217,7 +208,7 @@ __device__ inline void grid_cache_add(GridLds& G, OutQueue& Q, int lane, int& q,
                                                    __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
     const bool ev = won && t >= 0;
-    const int row = queue_row(Q, lane, q, ev, gr, gs);
+    const int row = queue_row(Q, lane, q, ev, ga);
     if (ev) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) Q.v[row][c] = G.v[slot][c];
@@ -238,7 +229,7 @@ __device__ inline void grid_cache_add(GridLds& G, OutQueue& Q, int lane, int& q,
             fb = true;
         }
     }
-    const int row2 = queue_row(Q, lane, q, fb, gr, gs);
+    const int row2 = queue_row(Q, lane, q, fb, ga);
     if (fb) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) Q.v[row2][c] = val(c);
@@ -255,11 +246,11 @@ struct GridAcc {
 };
 
 __device__ inline void grid_acc_push(GridLds& G, OutQueue& Q, int lane, int& q, GridAcc& g, bool push, int lgx,
-                                     int lgy, const __amdgpu_buffer_rsrc_t& gr, const __amdgpu_buffer_rsrc_t& gs) {
+                                     int lgy, const __amdgpu_buffer_rsrc_t& ga) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int pid = g.cell + ((((j >> 1) << lgy) + (j & 1)) << lgx);
-        grid_cache_add(G, Q, lane, q, pid, push, lgx, lgy, gr, gs, [&](int c) { return g.v[j][c]; });
+        grid_cache_add(G, Q, lane, q, pid, push, lgx, lgy, ga, [&](int c) { return g.v[j][c]; });
     }
     if (push) {
         g.cell = -1;
@@ -271,19 +262,18 @@ __device__ inline void grid_acc_push(GridLds& G, OutQueue& Q, int lane, int& q, 
 }
 
 // send every pair the cache and the queue hold and empty both (the block's end)
-__device__ inline void grid_cache_flush(GridLds& G, OutQueue& Q, int lane, int& q, const __amdgpu_buffer_rsrc_t& gr,
-                                        const __amdgpu_buffer_rsrc_t& gs) {
+__device__ inline void grid_cache_flush(GridLds& G, OutQueue& Q, int lane, int& q, const __amdgpu_buffer_rsrc_t& ga) {
     for (int s0 = 0; s0 < kGridSlots; s0 += 64) {
         const int s = s0 + lane;
         const int t = G.tag[s];
-        const int row = queue_row(Q, lane, q, t >= 0, gr, gs);
+        const int row = queue_row(Q, lane, q, t >= 0, ga);
         if (t >= 0) {
 #pragma unroll
             for (int c = 0; c < 16; ++c) Q.v[row][c] = G.v[s][c];
             Q.p[row] = t;
         }
     }
-    if (q > 0) queue_flush(Q, lane, q, gr, gs);
+    if (q > 0) queue_flush(Q, lane, q, ga);
     grid_cache_clear(G, lane);
 }
 
@@ -339,15 +329,14 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
         const int e = ufl(a.refs[v.set_begin + j]);
         BlockU b;
         load_block<1>(a.blocks + e, b);
-        // gradient tensors as buffer resources: base in scalar registers,
+        // the textures whose gradient the caller wants (null: none), and their
+        // pair-slot buffers as buffer resources: base in scalar registers,
         // no-return buffer_atomic_add_f32 with a 32-bit offset per lane
         float* gptr[4] = {ufp(ba.grad_grid[e]), ufp(ba.grad_plane[3 * e + 0]), ufp(ba.grad_plane[3 * e + 1]),
                           ufp(ba.grad_plane[3 * e + 2])};
-        __amdgpu_buffer_rsrc_t gr[4], gs[4];
-        gr[0] = tex_rsrc(gptr[0], grid_texels(b) * 32u);
-        for (int t = 1; t < 4; ++t) gr[t] = tex_rsrc(gptr[t], plane_texels(b, t - 1) * 32u);
-        gs[0] = tex_rsrc(ufp(ba.shadow[4 * e]), (grid_texels(b) + 1u) * 32u);
-        for (int t = 1; t < 4; ++t) gs[t] = tex_rsrc(ufp(ba.shadow[4 * e + t]), (plane_texels(b, t - 1) + 1u) * 32u);
+        __amdgpu_buffer_rsrc_t ga[4];
+        ga[0] = tex_rsrc(ufp(ba.slots[4 * e]), grid_texels(b) * 64u);
+        for (int t = 1; t < 4; ++t) ga[t] = tex_rsrc(ufp(ba.slots[4 * e + t]), plane_texels(b, t - 1) * 64u);
         const bool alive = hit && !(T_blk < a.t_min);
         const Span sp = block_span<MODE>(a, b, r, alive, w0, w1);
         if (!__any(sp.ka < sp.kb)) continue;
@@ -432,11 +421,11 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
                 if (T_blk * Tk < a.t_min) kb = k;  // early ray termination, as in the forward
             }
             // collectives over the wave: lanes without a sample take part with nothing to add
-            scatter_planes(lds, lane, T, draw, gptr, gr, gs, have);
+            scatter_planes(lds, lane, T, draw, gptr, ga, have);
             if (want_grid) {
                 const int cell_now = have ? T.pidx[0] : -1;
                 const bool push = have && gacc.cell >= 0 && cell_now != gacc.cell;
-                if (__any(push)) grid_acc_push(glds, gq, lane, nq, gacc, push, b.lgx, b.lgy, gr[0], gs[0]);
+                if (__any(push)) grid_acc_push(glds, gq, lane, nq, gacc, push, b.lgx, b.lgy, ga[0]);
                 if (have) {
                     gacc.cell = cell_now;
 #pragma unroll
@@ -451,8 +440,8 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
         }
         if (want_grid) {
             if (__any(gacc.cell >= 0))
-                grid_acc_push(glds, gq, lane, nq, gacc, gacc.cell >= 0, b.lgx, b.lgy, gr[0], gs[0]);
-            grid_cache_flush(glds, gq, lane, nq, gr[0], gs[0]);
+                grid_acc_push(glds, gq, lane, nq, gacc, gacc.cell >= 0, b.lgx, b.lgy, ga[0]);
+            grid_cache_flush(glds, gq, lane, nq, ga[0]);
         }
         T_blk *= Tk;
     }
@@ -485,40 +474,44 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
     }
 }
 
-// blockIdx.y: job; grid-stride over the job's floats
-__global__ __launch_bounds__(256) void shadow_zero_kernel(const FoldJob* jobs) {
+// blockIdx.y: job; grid-stride over the job's slots (four float4 each)
+__global__ __launch_bounds__(256) void slots_zero_kernel(const FoldJob* jobs) {
     const FoldJob j = jobs[blockIdx.y];
-    float4* sh = reinterpret_cast<float4*>(j.shadow);
-    const int64_t n = 2 * (j.n_texels + 1);
+    float4* sl = reinterpret_cast<float4*>(j.slots);
+    const int64_t n = 4 * j.n_texels;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        sh[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        sl[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-__global__ __launch_bounds__(256) void shadow_fold_kernel(const FoldJob* jobs) {
+// gradient texel x += first texel of slot x + second texel of slot x - 1;
+// grid-stride over the gradient's float4 (two per texel)
+__global__ __launch_bounds__(256) void slots_fold_kernel(const FoldJob* jobs) {
     const FoldJob j = jobs[blockIdx.y];
     float4* g = reinterpret_cast<float4*>(j.grad);
-    const float4* sh = reinterpret_cast<const float4*>(j.shadow) + 2;  // texel x + 1
+    const float4* sl = reinterpret_cast<const float4*>(j.slots);
     const int64_t n = 2 * j.n_texels;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float4 a = g[i], b = sh[i];
-        g[i] = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+        const int64_t x = i >> 1, h = i & 1;
+        const float4 a = g[i], b = sl[4 * x + h];
+        const float4 c = x > 0 ? sl[4 * (x - 1) + 2 + h] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        g[i] = make_float4(a.x + (b.x + c.x), a.y + (b.y + c.y), a.z + (b.z + c.z), a.w + (b.w + c.w));
     }
 }
 
 static dim3 fold_grid(int n_jobs, int64_t max_texels) {
-    const int64_t blocks = (2 * (max_texels + 1) + 255) / 256;
+    const int64_t blocks = (4 * max_texels + 255) / 256;
     return dim3((unsigned)(blocks < 2048 ? blocks : 2048), (unsigned)n_jobs);
 }
 
-hipError_t launch_shadow_zero(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s) {
+hipError_t launch_slots_zero(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s) {
     if (n_jobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(shadow_zero_kernel, fold_grid(n_jobs, max_texels), dim3(256), 0, s, jobs);
+    hipLaunchKernelGGL(slots_zero_kernel, fold_grid(n_jobs, max_texels), dim3(256), 0, s, jobs);
     return hipGetLastError();
 }
 
-hipError_t launch_shadow_fold(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s) {
+hipError_t launch_slots_fold(const FoldJob* jobs, int n_jobs, int64_t max_texels, hipStream_t s) {
     if (n_jobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(shadow_fold_kernel, fold_grid(n_jobs, max_texels), dim3(256), 0, s, jobs);
+    hipLaunchKernelGGL(slots_fold_kernel, fold_grid(n_jobs, max_texels), dim3(256), 0, s, jobs);
     return hipGetLastError();
 }
 
