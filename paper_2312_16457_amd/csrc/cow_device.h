@@ -644,12 +644,16 @@ __device__ inline float wave_sum(float v) {
 // (with P folded in; the direction inputs are constants).  With want_gw, the
 // gradient of the weights is summed over the wave and added once to gw
 // (wave-collective: every lane calls it, an inactive lane with zero weight).
+// wp and gwp are wave-uniform; the function is not inlined, so its arguments
+// arrive in vector registers and are made scalar again here (one buffer
+// resource for the weight-gradient atomics, no per-lane waterfall).
 template <int L>
-__device__ __attribute__((noinline)) void block_shade_adjoint(const float* w, const float A[7], const float d[3],
+__device__ __attribute__((noinline)) void block_shade_adjoint(const float* wp, const float A[7], const float d[3],
                                                               float P, const float g[3], bool active, float C[3],
-                                                              float u[7], bool want_gw, __amdgpu_buffer_rsrc_t gw,
-                                                              int lane) {
+                                                              float u[7], float* gwp, int lane) {
     using S = MlpShape<L>;
+    const float* w = ufp(wp);
+    const bool want_gw = ufl(gwp != nullptr);
     float x[S::NI], h1[16], h2[16], s[3];
     mlp_input<L>(A, d, x);
 #pragma unroll
@@ -730,6 +734,7 @@ __device__ __attribute__((noinline)) void block_shade_adjoint(const float* w, co
         COW_RED(S::B3 + o, dz[o]);
     }
 #undef COW_RED
+    const __amdgpu_buffer_rsrc_t gw = tex_rsrc(ufp(gwp), 4u * (uint32_t)S::N);
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
         if (q * 64 + lane < S::N) __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(acc[q], gw, 4 * (q * 64 + lane), 0, 0);

@@ -349,15 +349,11 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
             march_block<1, MODE, false, false>(a, b, r, sp, T_blk, Af, Tkf, ne, nm);
             float Ck[3];
             const int np = mlp_params(a.pe);  // weights per block: 499, or 883 with four PE frequencies
-            __amdgpu_buffer_rsrc_t gw = tex_rsrc(ba.grad_block_mlp ? ufp(ba.grad_block_mlp) + (size_t)e * np
-                                                                   : nullptr,
-                                                 4u * (uint32_t)np);
+            float* gwp = ba.grad_block_mlp ? ufp(ba.grad_block_mlp) + (size_t)e * np : nullptr;
             if (a.pe == 4)
-                block_shade_adjoint<4>(ufp(a.block_mlp) + (size_t)e * np, Af, r.d, T_blk, g, nm > 0, Ck, u,
-                                       ba.grad_block_mlp != nullptr, gw, lane);
+                block_shade_adjoint<4>(ufp(a.block_mlp) + (size_t)e * np, Af, r.d, T_blk, g, nm > 0, Ck, u, gwp, lane);
             else
-                block_shade_adjoint<0>(ufp(a.block_mlp) + (size_t)e * np, Af, r.d, T_blk, g, nm > 0, Ck, u,
-                                       ba.grad_block_mlp != nullptr, gw, lane);
+                block_shade_adjoint<0>(ufp(a.block_mlp) + (size_t)e * np, Af, r.d, T_blk, g, nm > 0, Ck, u, gwp, lane);
             float R = gT * TN;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
