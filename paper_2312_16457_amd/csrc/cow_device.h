@@ -320,7 +320,12 @@ struct Lin {
 // [0, D - 1] first gives both edge cases directly: p = 0 with f = 0 below,
 // p = D - 2 with f = 1 above; inside, f = u - floor(u).
 __device__ inline Lin lin_pair(float q, int R, int D) {
-    const float u = fmaf(q, (float)R, -0.5f);  // q R is exact (R a power of two): one rounding
+    // u = q R - 1/2 in one rounding (q R is exact, R a power of two), as
+    // v_fmaak_f32 (a two-operand encoding with the constant as a literal):
+    // the compiler's choice, v_fma_f32 with an inline constant, is a
+    // three-operand instruction that issues at about 4.3 cycles against 2.7
+    float u;
+    asm("v_fmaak_f32 %0, %1, %2, 0xbf000000" : "=v"(u) : "v"(q), "v"((float)R));
     const float uc = __builtin_amdgcn_fmed3f(u, 0.0f, (float)(D - 1));
     const int a = (int)uc;
     Lin t;
@@ -418,8 +423,9 @@ __device__ inline void fold_texel(uint32_t x, uint32_t y, float w, float s[kNch]
 
 typedef const __attribute__((address_space(4))) float cfloat;
 
-// raw[c] += scale[c] * (sum over N pairs of w q[c]) for one texture
-template <int N>
+// raw[c] += scale[c] * (sum over N pairs of w q[c]) for one texture (FIRST:
+// raw[c] = the product, a two-operand multiply)
+template <int N, bool FIRST = false>
 __device__ inline void fold_u8(const uint4 (&t)[N], const float* w, const cfloat* sc, float raw[kNch]) {
     float s[kNch] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -428,7 +434,7 @@ __device__ inline void fold_u8(const uint4 (&t)[N], const float* w, const cfloat
         fold_texel(t[k].z, t[k].w, w[2 * k + 1], s);
     }
 #pragma unroll
-    for (int c = 0; c < kNch; ++c) raw[c] = fmaf(s[c], sc[c], raw[c]);
+    for (int c = 0; c < kNch; ++c) raw[c] = FIRST ? s[c] * sc[c] : fmaf(s[c], sc[c], raw[c]);
 }
 
 // Pre-activation features of a uint8 block at local coordinate q, in the
@@ -455,34 +461,49 @@ __device__ inline void raw_u8(const BlockU& b, const float q[3], int cell, float
         for (int j = 0; j < 4; ++j)
             g[j] = ld16u(b.brick, 8 * (base + ((zs + (j >> 1)) * s2 + ys + (j & 1)) * s2 + xs));
     } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) g[j] = ld16g(b.tp[0], 8u * (uint32_t)T.pidx[j]);
+        // the other three grid rows lie one row (8 B x gd[0]), one slice
+        // (8 B x gd[0] gd[1]) and both further than row 0: wave-uniform
+        // strides added to one offset (two-operand adds)
+        const uint32_t g0 = 8u * (uint32_t)T.pidx[0], gr = 8u << b.lgx, gs = 8u << (b.lgx + b.lgy);
+        g[0] = ld16g(b.tp[0], g0);
+        g[1] = ld16g(b.tp[0], g0 + gr);
+        g[2] = ld16g(b.tp[0], g0 + gs);
+        g[3] = ld16g(b.tp[0], g0 + (gs + gr));
     }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        p0[j] = ld16g(b.tp[1], 8u * (uint32_t)T.pidx[4 + j]);
-        p1[j] = ld16g(b.tp[2], 8u * (uint32_t)T.pidx[6 + j]);
-        p2[j] = ld16g(b.tp[3], 8u * (uint32_t)T.pidx[8 + j]);
-    }
+    // the second row of each plane footprint is one row (8 B x its u extent) further
+    const uint32_t rx = 8u << b.lpx, ry = 8u << b.lpy;
+    const uint32_t o0 = 8u * (uint32_t)T.pidx[4], o1 = 8u * (uint32_t)T.pidx[6], o2 = 8u * (uint32_t)T.pidx[8];
+    p0[0] = ld16g(b.tp[1], o0);
+    p0[1] = ld16g(b.tp[1], o0 + rx);
+    p1[0] = ld16g(b.tp[2], o1);
+    p1[1] = ld16g(b.tp[2], o1 + rx);
+    p2[0] = ld16g(b.tp[3], o2);
+    p2[1] = ld16g(b.tp[3], o2 + ry);
+    // every load of the sample is issued before the first is consumed, so
+    // the sample pays one memory latency
+    __builtin_amdgcn_sched_barrier(0);
     // The decode constants are read sample by sample with scalar loads (the
     // block table is constant during a launch), eight at a time beside the
     // texture that uses them: each group's pointer is an opaque copy that
     // depends on the previous group's result, so the loads can neither leave
     // the march loop (the 40 wave-uniform values would then hold 40 vector
-    // registers) nor gather at its top (40 scalar registers at once).
+    // registers) nor gather at its top (40 scalar registers at once).  The
+    // offsets come last: (((G + XY) + XZ) + YZ) + offsets, every step a
+    // two-operand multiply or add with a scalar operand except the three
+    // multiply-adds.
     const float* dg = b.dec;
     asm volatile("" : "+s"(dg));
-    const cfloat* off = (const cfloat*)dg + 4 * kNch;
-#pragma unroll
-    for (int c = 0; c < kNch; ++c) raw[c] = off[c];
-    asm volatile("" : "+s"(dg) : "v"(raw[0]));
-    fold_u8<4>(g, T.w, (const cfloat*)dg, raw);
+    fold_u8<4, true>(g, T.w, (const cfloat*)dg, raw);
     asm volatile("" : "+s"(dg) : "v"(raw[0]));
     fold_u8<2>(p0, T.w + 8, (const cfloat*)dg + kNch, raw);
     asm volatile("" : "+s"(dg) : "v"(raw[0]));
     fold_u8<2>(p1, T.w + 12, (const cfloat*)dg + 2 * kNch, raw);
     asm volatile("" : "+s"(dg) : "v"(raw[0]));
     fold_u8<2>(p2, T.w + 16, (const cfloat*)dg + 3 * kNch, raw);
+    asm volatile("" : "+s"(dg) : "v"(raw[0]));
+    const cfloat* off = (const cfloat*)dg + 4 * kNch;
+#pragma unroll
+    for (int c = 0; c < kNch; ++c) raw[c] += off[c];
 }
 
 // fp32 block: a texel pair is 64 contiguous bytes (channels 0-3, 4-7 of each
