@@ -183,3 +183,45 @@ def test_backward_every_launch_configuration(torch_cuda):
                                    torch.tensor(g_rgb, dtype=torch.float32, device="cuda"))
             compare(gg, gp, gm, grads, gm_ref)
     r.set_config(8, 4, -1)
+
+
+def test_backward_texture_row_ends(torch_cuda):
+    """Texels at both ends of a texture row: the first texel's gradient comes
+    from the pair that starts at it alone, the last texel's from the pair that
+    ends at it alone.  Rays along +y just inside x = 0 and x = 1 put large
+    gradients on the first and last x columns of the grid and of the xy and
+    xz planes, and cross every column of the yz plane; those columns are
+    compared texel by texel against the fp64 adjoint."""
+    torch = torch_cuda
+    from paper_2312_16457_amd import Renderer
+    scene = sg.make_scene(1, 1, ((16, 32, 4),), sg.F32, blobs_per_block=12, seed=21, shift=2.0)
+    views = [sg.pinhole(24, 16, (x, -0.6, 0.5), sg.look_rotation((0.0, 1.0, 0.0)), vfov_deg=20.0)
+             for x in (0.012, 0.988)]
+    params = sg.cityb_params()
+    w = sg.random_mlp(5, 0.6)
+    r = Renderer(0).load_blocks(scene.blocks)
+    sets = [[(b.block_id, b.lod) for b in scene.blocks]] * 2
+    mlp = torch.tensor(w, device="cuda")
+    out = r.render(views, sets, params, mlp)
+    rng = np.random.default_rng(4)
+    g_rgb = [rng.uniform(-1, 1, (v.n_pixels, 3)) for v in views]
+    gg, gp, gm = gpu_grads(torch, r, views, sets, params, mlp, out["aux"],
+                           torch.tensor(np.concatenate(g_rgb), dtype=torch.float32, device="cuda"))
+    ob = O.OracleScene(scene.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    ref_g, ref_p, gm_ref = None, None, 0.0
+    for v, g in zip(views, g_rgb):
+        grads, gmv = O.adjoint(ob, occs, v, [0], params, w, O.pixels_of(v), g)
+        ref_g = grads[0][0] if ref_g is None else ref_g + grads[0][0]
+        ref_p = list(grads[0][1]) if ref_p is None else [a + b for a, b in zip(ref_p, grads[0][1])]
+        gm_ref = gm_ref + gmv
+    compare(gg, gp, gm, {0: (ref_g, ref_p)}, gm_ref)
+    # the x axis is axis 2 of the grid [z][y][x][c] and axis 1 of a plane [v][u][c]
+    for a, b, ax in [(gg[0], ref_g, 2)] + [(gp[0][i], ref_p[i], 1) for i in range(3)]:
+        a = a.cpu().numpy()
+        big = 1e-2 * np.abs(b).max()
+        for end in (0, -1):
+            ga, gb = np.take(a, end, axis=ax), np.take(b, end, axis=ax)
+            m = np.abs(gb) >= big
+            assert m.sum() > 0, "no large gradient at this row end"
+            assert np.all(np.abs(ga[m] - gb[m]) <= 1e-3 * np.abs(gb[m])), (ax, end)
