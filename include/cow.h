@@ -313,8 +313,10 @@ COW_API cow_status cow_render_noalloc(cow_ctx* ctx, const cow_view* views, int n
  * ACCUMULATED into grad_grid[e] / grad_plane[3e + k] for loaded entry e (in
  * load order; NULL entries skipped) and into grad_mlp[499]; fp32 atomics, so
  * summation order varies run to run.  Per-ray samples are recomputed.
- * Gradient buffers must be 16-byte aligned (COW_E_INVALID otherwise); at
- * 64-byte alignment every texel pair is one 64-byte atomic segment.
+ * Gradient buffers and ws must be 16-byte aligned (COW_E_INVALID otherwise).
+ * The atomics go to the pair-slot buffers in ws (see cow_query_workspace),
+ * which are added into the gradients at the end of the call; with ws 64-byte
+ * aligned every texel pair is one 64-byte atomic segment.
  * With params->block_mlp the weights' gradient goes to
  * params->grad_block_mlp instead (grad_mlp and mlp unused, may be NULL): each
  * lane re-composites a block, runs that block's MLP adjoint, and the wave's

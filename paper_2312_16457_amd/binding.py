@@ -359,14 +359,17 @@ class Renderer:
 
     def render_backward(self, views, sets, params, mlp, aux, grad_rgb, grad_trans=None, grad_grid=None,
                         grad_plane=None, grad_mlp=None, opacity_weight=None, block_mlp=None, grad_block_mlp=None,
-                        flags=0):
+                        flags=0, ws=None):
         """grad_grid[e] / grad_plane[e][k]: torch fp32 tensors (or None) per
         loaded entry e, accumulated in place; grad_mlp likewise.
-        opacity_weight: per-pixel dL/d(opacity regulariser) or None."""
+        opacity_weight: per-pixel dL/d(opacity regulariser) or None.
+        ws: a caller's uint8 device workspace (cow_query_workspace's backward
+        size), or None for one the renderer keeps."""
         vs = (View * len(views))(*[make_view(v) for v in views])
         cs, keep = self._sets(sets)
         n_pix = sum(int(v.crop[2]) * int(v.crop[3]) for v in views)
-        ws = self._ws("bwd_ws", len(views), n_pix, backward=True)
+        if ws is None:
+            ws = self._ws("bwd_ws", len(views), n_pix, backward=True)
         gg, gp = self._grad_tables(grad_grid, grad_plane)
         ow = None if opacity_weight is None else opacity_weight.contiguous()
         pe = int(getattr(params, "pe_freqs", 0))

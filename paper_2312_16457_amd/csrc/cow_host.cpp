@@ -1290,6 +1290,7 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
                                          (int64_t)c->entries.size(), slots_total(descs.data(), (int64_t)descs.size()),
                                          (unsigned char*)ws, &w);
     if (!ws || ws_bytes < need) return fail(c, COW_E_WORKSPACE, "backward workspace too small");
+    if ((uintptr_t)ws % 16) return fail(c, COW_E_INVALID, "the backward workspace must be 16-byte aligned");
     const size_t ne = c->entries.size();
     for (size_t e = 0; e < ne; ++e) {
         if ((uintptr_t)grad_grid[e] % 16) return fail(c, COW_E_INVALID, "gradient buffers must be 16-byte aligned");

@@ -225,3 +225,33 @@ def test_backward_texture_row_ends(torch_cuda):
             m = np.abs(gb) >= big
             assert m.sum() > 0, "no large gradient at this row end"
             assert np.all(np.abs(ga[m] - gb[m]) <= 1e-3 * np.abs(gb[m])), (ax, end)
+
+
+def test_backward_workspace_alignment(torch_cuda):
+    """A workspace off 16-byte alignment is refused before any launch; the
+    same workspace aligned gives the gradients of the renderer's own."""
+    torch = torch_cuda
+    from paper_2312_16457_amd import Renderer
+    scene = sg.make_scene(1, 1, ((16, 32, 4),), sg.F32, blobs_per_block=6, seed=5, shift=2.0)
+    view = sg.pinhole(16, 12, (0.5, -0.8, 0.6), sg.look_rotation((0.0, 1.0, -0.1)))
+    params = sg.cityb_params()
+    r = Renderer(0).load_blocks(scene.blocks)
+    sets = [[(b.block_id, b.lod) for b in scene.blocks]]
+    mlp = torch.tensor(sg.random_mlp(3, 0.6), device="cuda")
+    out = r.render([view], sets, params, mlp)
+    g_rgb = torch.ones((view.n_pixels, 3), device="cuda")
+    gg0, gp0, gm0 = gpu_grads(torch, r, [view], sets, params, mlp, out["aux"], g_rgb)
+    need = r.bwd_ws.numel()
+    raw = torch.empty(need + 64, dtype=torch.uint8, device="cuda")
+    base = (-raw.data_ptr()) % 64
+    gg = [torch.zeros_like(t[0]) for t in r.textures]
+    gp = [[torch.zeros_like(p) for p in t[1]] for t in r.textures]
+    gm = torch.zeros(499, device="cuda")
+    with pytest.raises(RuntimeError, match="16-byte aligned"):
+        r.render_backward([view], sets, params, mlp, out["aux"], g_rgb, None, gg, gp, gm, ws=raw[base + 4:])
+    torch.cuda.synchronize()
+    assert gm.abs().max().item() == 0 and gg[0].abs().max().item() == 0
+    r.render_backward([view], sets, params, mlp, out["aux"], g_rgb, None, gg, gp, gm, ws=raw[base:base + need])
+    torch.cuda.synchronize()
+    for a, b in [(gg[0], gg0[0])] + [(gp[0][i], gp0[0][i]) for i in range(3)] + [(gm, gm0)]:
+        assert (a - b).abs().max().item() <= 1e-6 * max(b.abs().max().item(), 1e-30)
