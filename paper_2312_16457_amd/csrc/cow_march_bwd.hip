@@ -54,13 +54,12 @@ __device__ inline void scatter_lds_init(ScatterLds& L, int lane) {
 // pair is one aligned 64-byte segment whatever its parity, and one buffer
 // resource serves every row of an atomic instruction.  The fold after the
 // march adds slot p's first texel and slot p - 1's second texel into
-// gradient texel p.  Neighbouring
-// rays often scatter the same pair in the same step (a sixth of the plane
-// pairs on the differentiable workload), so a lane whose pair another lane
-// entered first in a small LDS table hands its row to that lane's row (one
-// such lane per row, taken by compare-and-swap): the scatter adds the two
-// rows' values and sends one request for them.  Other repeats keep their
-// rows.
+// gradient texel p.  Neighbouring rays often scatter the same pair in the
+// same step (a sixth of the plane pairs on the differentiable workload), so
+// a lane whose pair another lane entered first in a small LDS table hands
+// its row to that lane's row (one such lane per row, taken by
+// compare-and-swap): the scatter adds the two rows' values and sends one
+// request for them.  Other repeats keep their rows.
 __device__ inline void scatter_pair(ScatterLds& L, int lane, const float vals[16], int p,
                                     const __amdgpu_buffer_rsrc_t& ga) {
     float* row = L.v[lane];
