@@ -322,3 +322,36 @@ def test_early_termination_parity(torch_cuda, mode):
     assert stopped.mean() > 0.2  # the opaque scene does terminate rays early
     gap = (out["aux"][:, :7] - full["aux"][:, :7]).abs().max(dim=1).values.cpu().numpy()
     assert (gap <= out["trans"].cpu().numpy() + 1e-6).all()
+
+
+def test_mixed_dtype_scene(torch_cuda):
+    """A loaded scene may hold uint8 and fp32 entries side by side; each
+    call's sets must use one dtype.  A set of either dtype renders bit for bit
+    as in a scene of that block alone, and a call mixing the two is refused
+    (COW_E_UNSUPPORTED) with its outputs untouched."""
+    torch = torch_cuda
+    from paper_2312_16457_amd import CowError, Renderer
+    from paper_2312_16457_amd.binding import COW_E_UNSUPPORTED
+    u8 = sg.make_scene(2, 1, ((16, 32, 4),), sg.U8, blobs_per_block=8, seed=31, shift=2.0).blocks
+    f32 = sg.make_scene(2, 1, ((16, 32, 4),), sg.F32, blobs_per_block=8, seed=32, shift=2.0).blocks
+    both = [u8[0], f32[1]]
+    v = sg.pinhole(40, 24, (1.0, -1.2, 0.8), sg.look_rotation(np.array([1.0, 0.5, 0.3]) - [1.0, -1.2, 0.8]))
+    params = sg.cityb_params()
+    mlp = torch.tensor(sg.random_mlp(2, 0.5), device="cuda")
+    r = Renderer(0).load_blocks(both)
+    for blk in both:
+        alone = Renderer(0).load_blocks([blk])
+        ref = alone.render([v], [[(blk.block_id, 0)]], params, mlp, counts=True)
+        got = r.render([v], [[(blk.block_id, 0)]], params, mlp, counts=True)
+        torch.cuda.synchronize()
+        assert ref["counts"][:, 0].sum().item() > 0
+        for k in ("rgb", "trans", "aux", "counts"):
+            assert torch.equal(got[k], ref[k]), (blk.dtype, k)
+    out = {k: t.clone().fill_(7.0) for k, t in r.render([v], [[(0, 0)]], params, mlp).items() if t is not None}
+    before = {k: t.clone() for k, t in out.items()}
+    with pytest.raises(CowError) as ei:
+        r.render([v], [[(0, 0), (1, 0)]], params, mlp, out=out)
+    assert ei.value.status == COW_E_UNSUPPORTED
+    torch.cuda.synchronize()
+    for k in out:
+        assert torch.equal(out[k], before[k]), k
