@@ -195,6 +195,21 @@ typedef struct cow_render_params {
      * cow_sparsity reject contracted blocks with COW_E_UNSUPPORTED. */
     float ext_delta;
     int32_t ext_max_steps;
+    /* Per-block composites handed from the forward to the backward.  Device
+     * [P][block_aux_n][8] float, 16-byte aligned, or NULL.  cow_render and
+     * cow_render_noalloc write, for each pixel and the j-th block of its
+     * view's set in the order the call composites the set, (A^k, T^k): the
+     * block's own composite of (C_d, F) (Eq. "volume rendering inside
+     * blocks") and its transmittance prod(1 - alpha_i), with T^k = -1 for a
+     * block in which the ray marches no sample.  cow_render_backward, given
+     * the buffer its forward wrote for the same views and sets, takes A^k and
+     * T^k from it instead of marching each block a second time for them (the
+     * per-block MLPs' adjoint, the opacity gradient); the gradients are the
+     * same.  block_aux_n: slots per pixel, at least the largest set size of
+     * the call's views (COW_E_INVALID otherwise).  COW_F32 blocks only, like
+     * the backward (COW_E_UNSUPPORTED for a call over uint8 blocks). */
+    float* block_aux;
+    int32_t block_aux_n;
 } cow_render_params;
 
 /* Create a context bound to HIP device `device` (host state only). */

@@ -60,7 +60,8 @@ class Params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_steps", C.c_int32), ("delta", C.c_float), ("max_steps", C.c_int32),
                 ("t_min", C.c_float), ("flags", C.c_int32), ("counts", C.c_void_p), ("opacity", C.c_void_p),
                 ("opacity_weight", C.c_void_p), ("block_mlp", C.c_void_p), ("grad_block_mlp", C.c_void_p),
-                ("pe_freqs", C.c_int32), ("ext_delta", C.c_float), ("ext_max_steps", C.c_int32)]
+                ("pe_freqs", C.c_int32), ("ext_delta", C.c_float), ("ext_max_steps", C.c_int32),
+                ("block_aux", C.c_void_p), ("block_aux_n", C.c_int32)]
 
 
 _lib = None
@@ -116,7 +117,8 @@ def make_view(v):
     return s
 
 
-def make_params(p, flags=0, counts=None, opacity=None, opacity_weight=None, block_mlp=None, grad_block_mlp=None):
+def make_params(p, flags=0, counts=None, opacity=None, opacity_weight=None, block_mlp=None, grad_block_mlp=None,
+                block_aux=None):
     s = Params()
     s.mode, s.n_steps, s.delta, s.max_steps = int(p.mode), int(p.n_steps), float(p.delta), int(p.max_steps)
     s.t_min = float(getattr(p, "t_min", 0.0))
@@ -129,6 +131,9 @@ def make_params(p, flags=0, counts=None, opacity=None, opacity_weight=None, bloc
     s.pe_freqs = int(getattr(p, "pe_freqs", 0))
     s.ext_delta = float(getattr(p, "ext_delta", 0.0))
     s.ext_max_steps = int(getattr(p, "ext_max_steps", 0))
+    if block_aux is not None:
+        s.block_aux = block_aux.data_ptr()
+        s.block_aux_n = int(block_aux.shape[1])
     return s
 
 
@@ -303,12 +308,23 @@ class Renderer:
             raise ValueError(f"block_mlp must be [loaded entries][{n}] float32 on the device")
         return block_mlp.contiguous()
 
+    def _check_block_aux(self, block_aux, n_pix):
+        torch = self.torch
+        if block_aux is None:
+            return None
+        if (block_aux.dtype != torch.float32 or block_aux.device != self.device or block_aux.dim() != 3
+                or block_aux.shape[0] != n_pix or block_aux.shape[2] != 8 or not block_aux.is_contiguous()):
+            raise ValueError("block_aux must be a contiguous float32 device tensor [pixels][slots][8]")
+        return block_aux
+
     def render(self, views, sets, params, mlp, want_aux=True, counts=False, flags=0, out=None, opacity=False,
-               block_mlp=None):
+               block_mlp=None, block_aux=None):
         """block_mlp: [loaded entries][P] per-block deferred MLPs (shading
         before the merge); mlp is then unused and may be None.  P =
         mlp_params(params.pe_freqs): 499, or 883 with four encoding
-        frequencies of the direction."""
+        frequencies of the direction.  block_aux: [pixels][slots][8] float32,
+        filled with each block's composite (A^k, T^k) for render_backward
+        (slots: at least the largest set size), or None."""
         torch = self.torch
         vs = (View * len(views))(*[make_view(v) for v in views])
         cs, keep = self._sets(sets)
@@ -322,7 +338,8 @@ class Renderer:
         ws = self._ws("render_ws", len(views), n_pix)
         pe = int(getattr(params, "pe_freqs", 0))
         bm = self._check_block_mlp(block_mlp, pe)
-        p = make_params(params, flags, out.get("counts"), out.get("opacity"), block_mlp=bm)
+        p = make_params(params, flags, out.get("counts"), out.get("opacity"), block_mlp=bm,
+                        block_aux=self._check_block_aux(block_aux, n_pix))
         if bm is None and (mlp is None or mlp.dtype != torch.float32 or mlp.device != self.device
                            or mlp.numel() != mlp_params(pe)):
             raise ValueError(f"mlp must be {mlp_params(pe)} float32 values on the device")
@@ -332,12 +349,14 @@ class Renderer:
                                       None if aux is None else aux.data_ptr(), ws.data_ptr(), ws.numel(), _stream()))
         return out
 
-    def render_noalloc(self, views, sets, params, mlp, out, flags=0):
+    def render_noalloc(self, views, sets, params, mlp, out, flags=0, block_aux=None):
         """cow_render_noalloc into caller-given outputs `out` (rgb, trans, aux
         and optionally counts, as returned by render): no workspace."""
         vs = (View * len(views))(*[make_view(v) for v in views])
         cs, keep = self._sets(sets)
-        p = make_params(params, flags, out.get("counts"), out.get("opacity"))
+        n_pix = sum(int(v.crop[2]) * int(v.crop[3]) for v in views)
+        p = make_params(params, flags, out.get("counts"), out.get("opacity"),
+                        block_aux=self._check_block_aux(block_aux, n_pix))
         aux = out.get("aux")
         self._check(self.L.cow_render_noalloc(self.h, vs, len(views), cs, C.byref(p), mlp.data_ptr(),
                                               out["rgb"].data_ptr(), out["trans"].data_ptr(),
@@ -359,12 +378,14 @@ class Renderer:
 
     def render_backward(self, views, sets, params, mlp, aux, grad_rgb, grad_trans=None, grad_grid=None,
                         grad_plane=None, grad_mlp=None, opacity_weight=None, block_mlp=None, grad_block_mlp=None,
-                        flags=0, ws=None):
+                        flags=0, ws=None, block_aux=None):
         """grad_grid[e] / grad_plane[e][k]: torch fp32 tensors (or None) per
         loaded entry e, accumulated in place; grad_mlp likewise.
         opacity_weight: per-pixel dL/d(opacity regulariser) or None.
         ws: a caller's uint8 device workspace (cow_query_workspace's backward
-        size), or None for one the renderer keeps."""
+        size), or None for one the renderer keeps.  block_aux: the buffer the
+        forward filled for the same views and sets, or None (the adjoint then
+        re-composites each block where it needs A^k or T^k)."""
         vs = (View * len(views))(*[make_view(v) for v in views])
         cs, keep = self._sets(sets)
         n_pix = sum(int(v.crop[2]) * int(v.crop[3]) for v in views)
@@ -381,7 +402,8 @@ class Renderer:
             raise ValueError(f"mlp must hold {n} weights")
         if grad_mlp is not None and grad_mlp.numel() != n:
             raise ValueError(f"grad_mlp must hold {n} values")
-        p = make_params(params, flags=flags, opacity_weight=ow, block_mlp=bm, grad_block_mlp=grad_block_mlp)
+        p = make_params(params, flags=flags, opacity_weight=ow, block_mlp=bm, grad_block_mlp=grad_block_mlp,
+                        block_aux=self._check_block_aux(block_aux, n_pix))
         self._check(self.L.cow_render_backward(
             self.h, vs, len(views), cs, C.byref(p), None if mlp is None else mlp.data_ptr(), aux.data_ptr(),
             grad_rgb.contiguous().data_ptr(),

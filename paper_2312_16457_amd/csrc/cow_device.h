@@ -904,6 +904,25 @@ struct Span {
     float tn, dr, delta;
 };
 
+// Per-block composites handed from the forward to the backward: slot j of
+// pixel pix holds (A^k[0..6], T^k) of the j-th block of the view's set, T^k =
+// -1 for a block the ray marches no sample in.
+__device__ inline void put_block_aux(const MarchArgs& a, int64_t pix, int j, const float A[7], float T) {
+    float4* p = reinterpret_cast<float4*>(a.block_aux + ((size_t)pix * a.block_aux_n + j) * 8);
+    p[0] = make_float4(A[0], A[1], A[2], A[3]);
+    p[1] = make_float4(A[4], A[5], A[6], T);
+}
+
+// Returns whether the ray marched a sample in the block; A and T are then its
+// composite, else zero and 1.
+__device__ inline bool get_block_aux(const MarchArgs& a, int64_t pix, int j, float A[7], float& T) {
+    const float4* p = reinterpret_cast<const float4*>(a.block_aux + ((size_t)pix * a.block_aux_n + j) * 8);
+    const float4 lo = p[0], hi = p[1];
+    A[0] = lo.x, A[1] = lo.y, A[2] = lo.z, A[3] = lo.w, A[4] = hi.x, A[5] = hi.y, A[6] = hi.z;
+    T = hi.w < 0.0f ? 1.0f : hi.w;
+    return hi.w >= 0.0f;
+}
+
 template <int MODE>
 __device__ inline Span block_span(const MarchArgs& a, const BlockU& b, const Ray& r, bool hit, int w0, int w1) {
     Span s{0, 0, 0.0f, 0.0f, a.delta};

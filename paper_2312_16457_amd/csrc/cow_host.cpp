@@ -538,6 +538,15 @@ bool any_contracted(const cow_ctx* c, const std::vector<int32_t>& refs) {
     return false;
 }
 
+// the per-block composites buffer holds a slot for every set position of every view
+cow_status check_block_aux(cow_ctx* c, const CallTables& T, const cow_render_params* p) {
+    if (!p->block_aux) return COW_OK;
+    if ((uintptr_t)p->block_aux % 16) return fail(c, COW_E_INVALID, "block_aux must be 16-byte aligned");
+    for (const DevView& v : T.views)
+        if (v.set_n > p->block_aux_n) return fail(c, COW_E_INVALID, "block_aux_n is below a view's set size");
+    return COW_OK;
+}
+
 cow_status check_dtypes(cow_ctx* c, const CallTables& T, int* dtype) {
     int dt = -1;
     for (int32_t e : T.refs) {
@@ -594,6 +603,8 @@ cow::MarchArgs march_args(cow_ctx* c, const CallTables& T, const RenderWs& w,
     a.contract = any_contracted(c, T.refs) ? 1 : 0;
     a.ext_delta = a.contract && p->ext_max_steps > 0 ? p->ext_delta : 0.0f;
     a.ext_max_steps = a.ext_delta > 0.0f ? p->ext_max_steps : 0;
+    a.block_aux = p->block_aux;
+    a.block_aux_n = p->block_aux_n;
     return a;
 }
 
@@ -1210,9 +1221,13 @@ static cow_status render_impl(cow_ctx* c, const cow_view* views, int n_views, co
     CallTables T;
     st = build_tables(c, views, n_views, sets, c->cfg.tile_w, &T);
     if (st != COW_OK) return st;
+    st = check_block_aux(c, T, p);
+    if (st != COW_OK) return st;
     int dtype;
     st = check_dtypes(c, T, &dtype);
     if (st != COW_OK) return st;
+    if (p->block_aux && dtype != COW_F32)
+        return fail(c, COW_E_UNSUPPORTED, "block_aux is the backward's input: float32 blocks only");
     if ((p->flags & COW_F_SPARSE) && dtype != COW_U8) return fail(c, COW_E_UNSUPPORTED, "sparse bricks hold uint8 grids only");
     if (any_contracted(c, T.refs) && (p->mode != COW_MODE_GRID || p->block_mlp || p->opacity || (p->flags & COW_F_PER_BLOCK)))
         return fail(c, COW_E_UNSUPPORTED, "contracted blocks render in grid mode with one MLP after the merge, "
@@ -1278,6 +1293,8 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
         return fail(c, COW_E_INVALID, "null mlp, aux, grad_rgb or gradient table");
     CallTables T;
     st = build_tables(c, views, n_views, sets, c->cfg.tile_w, &T);
+    if (st != COW_OK) return st;
+    st = check_block_aux(c, T, p);
     if (st != COW_OK) return st;
     for (int32_t e : T.refs)
         if (c->entries[e].desc.dtype != COW_F32)

@@ -91,6 +91,9 @@ struct MarchArgs {
     float ext_delta;
     int32_t ext_max_steps;
     int32_t contract;          // some block of the call is contracted: the contraction kernel
+    // per-block composites (A^k, T^k) per pixel and set position, [P][block_aux_n][8], or null
+    float* block_aux;
+    int32_t block_aux_n;
 };
 
 struct MlpArgs {

@@ -197,10 +197,16 @@ __device__ __attribute__((always_inline)) inline void march_packet(const MarchAr
         load_block<DT>(a.blocks + e, b);
         const bool alive = hit && !(T < a.t_min);  // a terminated ray takes no more samples
         const Span sp = block_span<MODE>(a, b, r, alive, w0, w1);
-        if (!__any(sp.ka < sp.kb)) continue;
         float Ak[7] = {0, 0, 0, 0, 0, 0, 0}, Tk = 1.0f;
+        // per-block composites for the backward (float32 blocks only, the
+        // adjoint's input; the uint8 kernels carry none of this code)
+        if (!__any(sp.ka < sp.kb)) {
+            if (DT == 1 && a.block_aux && r.active) put_block_aux(a, r.pix, j, Ak, -1.0f);
+            continue;
+        }
         const int64_t marched_before = n_march;
         march_block<DT, MODE, SPARSE, true, CT>(a, b, r, sp, T, Ak, Tk, n_eval, n_march);
+        if (DT == 1 && a.block_aux && r.active) put_block_aux(a, r.pix, j, Ak, n_march > marched_before ? Tk : -1.0f);
         // opacity regulariser: entropy of the block's opacity 1 - Tk, for
         // every block the ray marches (Eq. "opacity loss")
         if (a.opacity && n_march > marched_before) H += opacity_entropy(Tk);

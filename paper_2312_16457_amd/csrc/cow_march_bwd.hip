@@ -345,7 +345,11 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
             int64_t ne = 0, nm = 0;
 #pragma unroll
             for (int c = 0; c < 7; ++c) Af[c] = 0.0f;
-            march_block<1, MODE, false, false>(a, b, r, sp, T_blk, Af, Tkf, ne, nm);
+            if (a.block_aux) {  // the block's composite as the forward formed it
+                if (r.active) nm = get_block_aux(a, r.pix, j, Af, Tkf) ? 1 : 0;
+            } else {
+                march_block<1, MODE, false, false>(a, b, r, sp, T_blk, Af, Tkf, ne, nm);
+            }
             float Ck[3];
             const int np = mlp_params(a.pe);  // weights per block: 499, or 883 with four PE frequencies
             float* gwp = ba.grad_block_mlp ? ufp(ba.grad_block_mlp) + (size_t)e * np : nullptr;
@@ -365,7 +369,13 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
             for (int c = 0; c < 7; ++c) Ap[c] = 0.0f;
             Tg = 1.0f;
         } else if (OPAC && __any(w_op != 0.0f)) {
-            const float Tkf = block_trans_f32<MODE>(b, r, sp, T_blk, a.t_min, true, w_op != 0.0f);
+            float Tkf = 1.0f;
+            if (a.block_aux) {
+                float Ab[7];
+                if (r.active) (void)get_block_aux(a, r.pix, j, Ab, Tkf);
+            } else {
+                Tkf = block_trans_f32<MODE>(b, r, sp, T_blk, a.t_min, true, w_op != 0.0f);
+            }
             g_op = w_op * opacity_dentropy(Tkf) * Tkf;
         }
         int k = sp.ka, kb = sp.kb;
