@@ -562,13 +562,24 @@ def leg_backward(torch, sg, Renderer, reps=2):
     ms = _timed(torch, lambda: r.render_backward(views, sets, p, mlp, out["aux"], g, None, gg, gp, gm,
                                                  opacity_weight=w_op), 1)
     res["with_opacity_entropy_ms"] = round(ms, 3)
+    # the same two options with the forward's per-block composites handed over
+    # (block_aux): the adjoint then marches each block once
+    ba = torch.empty((out["rgb"].shape[0], max(len(s) for s in sets), 8), dtype=torch.float32, device="cuda")
+    r.render(views, sets, p, mlp, out=out, block_aux=ba)
+    ms = _timed(torch, lambda: r.render_backward(views, sets, p, mlp, out["aux"], g, None, gg, gp, gm,
+                                                 opacity_weight=w_op, block_aux=ba), 1)
+    res["with_opacity_entropy_block_aux_ms"] = round(ms, 3)
     bm = torch.tensor(np.stack([sg.xavier_mlp(200 + k) for k in range(len(r.blocks))]), device="cuda")
     gbm = torch.zeros_like(bm)
     out_b = r.render(views, sets, p, None, block_mlp=bm)
     ms = _timed(torch, lambda: r.render_backward(views, sets, p, None, out_b["aux"], g, None, gg, gp, None,
                                                  block_mlp=bm, grad_block_mlp=gbm), 1)
     res["per_block_mlps_ms"] = round(ms, 3)
-    del out_b
+    r.render(views, sets, p, None, block_mlp=bm, out=out_b, block_aux=ba)
+    ms = _timed(torch, lambda: r.render_backward(views, sets, p, None, out_b["aux"], g, None, gg, gp, None,
+                                                 block_mlp=bm, grad_block_mlp=gbm, block_aux=ba), 1)
+    res["per_block_mlps_block_aux_ms"] = round(ms, 3)
+    del out_b, ba
     pts = torch.rand((1 << 14, 3), device="cuda") * torch.tensor([4.0, 4.0, 1.0], device="cuda")
     refs = [(b.block_id, 0) for b in learn.blocks]
     ms = _timed(torch, lambda: r.sparsity(refs, pts, 1.0 / 512, 1e-3, grad_grid=gg, grad_plane=gp), 5)

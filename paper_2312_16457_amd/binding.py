@@ -485,17 +485,27 @@ def make_render_fn(with_opacity=False, per_block_mlp=False):
     loaded blocks (grid, xy, xz, yz per entry, in load order).  Outputs rgb
     and trans, plus the per-ray opacity regulariser with with_opacity.  With
     per_block_mlp the MLP input is [loaded entries][P], one deferred MLP
-    per block applied before the merge (P = mlp_params(params.pe_freqs))."""
+    per block applied before the merge (P = mlp_params(params.pe_freqs)).
+    With either option the forward keeps each block's composite (32 bytes
+    per pixel and set entry) for the backward, which then does not march
+    the blocks a second time."""
     import torch
 
     class RenderFn(torch.autograd.Function):
         @staticmethod
         def forward(ctx, renderer, views, sets, params, mlp, *textures):
+            ba = None
+            if with_opacity or per_block_mlp:
+                n_pix = sum(int(v.crop[2]) * int(v.crop[3]) for v in views)
+                ba = torch.empty((n_pix, max(1, max(len(x) for x in sets)), 8), dtype=torch.float32,
+                                 device=renderer.device)
             if per_block_mlp:
-                out = renderer.render(views, sets, params, None, want_aux=True, opacity=with_opacity, block_mlp=mlp)
+                out = renderer.render(views, sets, params, None, want_aux=True, opacity=with_opacity, block_mlp=mlp,
+                                      block_aux=ba)
             else:
-                out = renderer.render(views, sets, params, mlp, want_aux=True, opacity=with_opacity)
+                out = renderer.render(views, sets, params, mlp, want_aux=True, opacity=with_opacity, block_aux=ba)
             ctx.renderer, ctx.views, ctx.sets, ctx.params = renderer, views, sets, params
+            ctx.block_aux = ba
             ctx.save_for_backward(mlp, out["aux"])
             ctx.n_tex = len(textures)
             if with_opacity:
@@ -511,10 +521,10 @@ def make_render_fn(with_opacity=False, per_block_mlp=False):
             g_rgb = g_rgb if g_rgb is not None else torch.zeros((aux.shape[0], 3), device=aux.device)
             if per_block_mlp:
                 r.render_backward(ctx.views, ctx.sets, ctx.params, None, aux, g_rgb, g_trans, gg, gp, None,
-                                  opacity_weight=g_opacity, block_mlp=mlp, grad_block_mlp=gm)
+                                  opacity_weight=g_opacity, block_mlp=mlp, grad_block_mlp=gm, block_aux=ctx.block_aux)
             else:
                 r.render_backward(ctx.views, ctx.sets, ctx.params, mlp, aux, g_rgb, g_trans, gg, gp, gm,
-                                  opacity_weight=g_opacity)
+                                  opacity_weight=g_opacity, block_aux=ctx.block_aux)
             return (None, None, None, None, gm) + _tex_grads(gg, gp, ctx.n_tex)
 
     return RenderFn
