@@ -145,3 +145,29 @@ def test_block_aux_refused(torch_cuda):
     with pytest.raises(CowError) as ei:
         ru.render([v], [s], sg.cityb_params(), mlp, block_aux=torch.zeros((v.n_pixels, 4, 8), device="cuda"))
     assert ei.value.status == COW_E_UNSUPPORTED
+
+
+def test_block_aux_every_launch_form(torch_cuda):
+    """Fused, graph-replayed, persistent, one launch per view per block, and
+    the entry point that allocates nothing write the same per-block
+    composites, bit for bit."""
+    torch = torch_cuda
+    from paper_2312_16457_amd import F_GRAPH, F_PER_BLOCK, F_PERSISTENT, Renderer
+    scene = small_scene(sg.F32, 4)
+    r = Renderer(0).load_blocks(scene.blocks)
+    vs = views()
+    sets = [[(b.block_id, 0) for b in scene.blocks], [(scene.blocks[1].block_id, 0), (scene.blocks[3].block_id, 0)]]
+    mlp = torch.tensor(sg.random_mlp(2, 0.5), device="cuda")
+    n_pix = sum(v.n_pixels for v in vs)
+    got = []
+    for flags in (0, F_GRAPH, F_PERSISTENT, F_PER_BLOCK):
+        ba = torch.full((n_pix, 4, 8), 7.0, device="cuda")
+        r.render(vs, sets, sg.cityb_params(), mlp, flags=flags, block_aux=ba)
+        got.append(ba)
+    out = r.render(vs, sets, sg.cityb_params(), mlp)
+    ba = torch.full((n_pix, 4, 8), 7.0, device="cuda")
+    r.render_noalloc(vs, sets, sg.cityb_params(), mlp, out, block_aux=ba)
+    got.append(ba)
+    torch.cuda.synchronize()
+    for b in got[1:]:
+        assert torch.equal(b, got[0])
