@@ -60,7 +60,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the render path shards by view or by block with no "
-              "inter-GPU exchange in the forward pass, and this build runs on a single MI355X.", file=sys.stderr)
+              "inter-GPU exchange in the forward pass, and the benchmark runs on a single MI355X.", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.calib_copy:
