@@ -28,8 +28,10 @@ namespace cow {
 // bounds the adjoint.
 struct ScatterLds {
     // 16 values; the pair's byte offset in its pair-slot buffer, 64 p (-1:
-    // none); the lane whose values ride along in this row (-1: none)
-    float v[64][18];
+    // none); the lanes whose values ride along in this row (two slots, -1:
+    // none).  Rows of 19 floats leave the LDS room for two workgroups of four
+    // waves per CU; a third follower slot (rows of 20) leaves room for one.
+    float v[64][19];
     // lanes of one step that scatter the same pair: (p << 6 | first lane) by
     // a hash of p, -1 between steps
     int merge[256];
@@ -57,9 +59,9 @@ __device__ inline void scatter_lds_init(ScatterLds& L, int lane) {
 // gradient texel p.  Neighbouring rays often scatter the same pair in the
 // same step (a sixth of the plane pairs on the differentiable workload), so
 // a lane whose pair another lane entered first in a small LDS table hands
-// its row to that lane's row (one such lane per row, taken by
-// compare-and-swap): the scatter adds the two rows' values and sends one
-// request for them.  Other repeats keep their rows.
+// its row to that lane's row (up to two such lanes per row, each taking a
+// follower slot by compare-and-swap): the scatter adds the rows' values and
+// sends one request for them.  Further repeats keep their rows.
 __device__ inline void scatter_pair(ScatterLds& L, int lane, const float vals[16], int p,
                                     const __amdgpu_buffer_rsrc_t& ga) {
     float* row = L.v[lane];
@@ -68,6 +70,7 @@ __device__ inline void scatter_pair(ScatterLds& L, int lane, const float vals[16
     // a multiple of 64 below 2^32 (fewer than 2^26 texels), so never -1
     row[16] = __int_as_float(p < 0 ? -1 : (int)((uint32_t)p << 6));
     row[17] = __int_as_float(-1);
+    row[18] = __int_as_float(-1);
     wave_fence();
     const bool merge = p >= 0 && p < (1 << 25);  // the table packs p and a lane into 31 bits
     int h = 0;
@@ -77,11 +80,15 @@ __device__ inline void scatter_pair(ScatterLds& L, int lane, const float vals[16
         if (!__hip_atomic_compare_exchange_strong(&L.merge[h], &expected, (p << 6) | lane, __ATOMIC_RELAXED,
                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) &&
             (expected >> 6) == p) {
-            int none = -1;
-            int* slot = reinterpret_cast<int*>(&L.v[expected & 63][17]);
-            if (__hip_atomic_compare_exchange_strong(slot, &none, lane, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_WAVEFRONT))
-                row[16] = __int_as_float(-1);  // sent with the first lane's row
+            for (int f = 17; f <= 18; ++f) {
+                int none = -1;
+                int* slot = reinterpret_cast<int*>(&L.v[expected & 63][f]);
+                if (__hip_atomic_compare_exchange_strong(slot, &none, lane, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WAVEFRONT)) {
+                    row[16] = __int_as_float(-1);  // sent with the first lane's row
+                    break;
+                }
+            }
         }
     }
     wave_fence();
@@ -94,9 +101,10 @@ __device__ inline void scatter_pair(ScatterLds& L, int lane, const float vals[16
         // L2 five requests instead of two
         const int src = (((j & 7) + 3 * sub) & 7) + 8 * ((j >> 3) + 2 * sub);
         const int ov = __float_as_int(L.v[src][16]);
-        const int f = __float_as_int(L.v[src][17]);
+        const int f1 = __float_as_int(L.v[src][17]), f2 = __float_as_int(L.v[src][18]);
         float val = L.v[src][e];
-        if (f >= 0) val += L.v[f][e];
+        if (f1 >= 0) val += L.v[f1][e];
+        if (f2 >= 0) val += L.v[f2][e];
         if (ov != -1) __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(val, ga, (int)((uint32_t)ov + 4u * e), 0, 0);
     }
     wave_fence();
