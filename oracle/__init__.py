@@ -415,7 +415,7 @@ def adjoint(ob, occs, view, set_idx, params, mlp, pix, grad_rgb, grad_trans=None
                       C.byref(ps_), _ptr(np.ascontiguousarray(mlp, np.float64)), _ptr(pix), pix.shape[0],
                       _ptr(gr), _ptr(gt), _ptr(wo), gg, gp, _ptr(gm))
     if r != 0:
-        raise ValueError("adjoint needs float blocks")
+        raise ValueError("adjoint needs float blocks (contracted ones: valid extents, no opacity term)")
     return grads, gm
 
 
@@ -440,7 +440,7 @@ def adjoint_block_mlp(ob, occs, view, set_idx, params, mlps, pix, grad_rgb, grad
                                 C.byref(ps_), _ptr(w), _ptr(pix), pix.shape[0], _ptr(gr), _ptr(gt), _ptr(wo),
                                 gg, gp, _ptr(gm))
     if r != 0:
-        raise ValueError("adjoint needs float blocks")
+        raise ValueError("adjoint needs float blocks, none of them contracted")
     return grads, gm.reshape(ob.n, npar)
 
 

@@ -1033,9 +1033,19 @@ int orc_adjoint(const orc_block* blocks, int nblocks, const unsigned char* const
                 const double* mlp, const int* pix, int npix, const double* grad_rgb,
                 const double* grad_trans, const double* w_opacity, double* const* grad_grid,
                 double* const* grad_plane, double* grad_mlp) {
-    for (int s = 0; s < nset; ++s)
+    int any_ct = 0;
+    for (int s = 0; s < nset; ++s) {
         if (blocks[set[s]].dtype != ORC_F64) return -1;
+        any_ct |= blocks[set[s]].contracted;
+    }
     if (p->pe < 0 || p->pe > 4) return -1;
+    /* contracted blocks: the samples are those of the forward (the exterior
+     * segments in ray order around the blocks, each with its own step), so
+     * the single-chain adjoint below applies unchanged; the opacity term is
+     * defined per block run and an exterior segment splits a block's run,
+     * so it is not taken with them */
+    if (!contracted_ok(blocks, nblocks, p)) return -1;
+    if (any_ct && w_opacity) return -1;
     long cap = sample_cap(p, nset);
     sample* buf = (sample*)malloc(sizeof(sample) * cap);
     pt_val* pv = (pt_val*)malloc(sizeof(pt_val) * cap);
@@ -1180,7 +1190,7 @@ int orc_adjoint_block_mlp(const orc_block* blocks, int nblocks, const unsigned c
                           const double* grad_trans, const double* w_opacity, double* const* grad_grid,
                           double* const* grad_plane, double* grad_mlp) {
     for (int s = 0; s < nset; ++s)
-        if (blocks[set[s]].dtype != ORC_F64) return -1;
+        if (blocks[set[s]].dtype != ORC_F64 || blocks[set[s]].contracted) return -1;
     if (p->pe < 0 || p->pe > 4) return -1;
     const mlp_shape sh = mlp_shape_of(p->pe);
     long cap = sample_cap(p, nset);

@@ -687,6 +687,81 @@ def test_adjoint_matches_finite_differences():
     assert abs(g[idx] - fd) <= 1e-4 * abs(fd) + 1e-9
 
 
+def test_contracted_adjoint_matches_finite_differences():
+    """P13 over contracted boundary blocks (implementation details, the
+    contraction equation): the exterior samples, each with its own step and
+    read through the contraction, join the single-chain adjoint in ray order.
+    Central differences of the loss agree with the fp64 adjoint on texels
+    that only the exterior's samples reach and on texels of the blocks' own
+    samples, with dL/dT included."""
+    scene = tiny_city(nb=2, lods=((8, 16, 4),), shift=1.5, blobs=8, seed=13)
+    blocks = sg.contract_boundary(scene.blocks)
+    assert all(b.contracted for b in blocks)
+    ob = O.OracleScene(blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    v = tiny_view(12, 10, eye=(1.0, -1.5, 1.0), target=(1.0, 1.0, 0.15))
+    p = sg.RenderParams(mode=1, delta=1.0 / 128, max_steps=4096, ext_delta=1.0 / 32, ext_max_steps=128)
+    p0 = sg.RenderParams(mode=1, delta=1.0 / 128, max_steps=4096)
+    w = kink_free_mlp(3)
+    setv = list(range(ob.n))
+    pix = O.pixels_of(v)
+    target = np.random.default_rng(4).uniform(0, 1, (len(pix), 3))
+    g_tr = np.random.default_rng(5).uniform(-0.1, 0.1, len(pix))
+
+    def loss():
+        r = O.render(ob, occs, v, setv, p, w, pix=pix)
+        return np.mean((r["rgb"] - target) ** 2) + np.sum(g_tr * r["trans"]), r
+
+    L0, r0 = loss()
+    g_rgb = 2 * (r0["rgb"] - target) / target.size
+    grads, gm = O.adjoint(ob, occs, v, setv, p, w, pix, g_rgb, g_tr)
+    grads0, _ = O.adjoint(ob, occs, v, setv, p0, w, pix, g_rgb, g_tr)
+    gmax = max(max(np.abs(g).max(), max(np.abs(q).max() for q in ps)) for g, ps in grads.values())
+    assert gmax > 0
+    rng = np.random.default_rng(6)
+    h = 1e-3
+    picks = []
+    n_ext = 0
+    for k, (g, ps) in grads.items():
+        for arr_i, arr in enumerate([g] + ps):
+            arr0 = grads0[k][0] if arr_i == 0 else grads0[k][1][arr_i - 1]
+            big = np.abs(arr) > 1e-3 * gmax
+            ext_only = np.argwhere(big & (arr0 == 0))  # reached by exterior samples alone
+            own = np.argwhere(big & (arr0 != 0))
+            if len(ext_only):
+                picks.append((k, arr_i, tuple(ext_only[rng.integers(len(ext_only))])))
+                n_ext += 1
+            if len(own):
+                picks.append((k, arr_i, tuple(own[rng.integers(len(own))])))
+    assert n_ext >= 8, n_ext
+    for k, arr_i, idx in picks:
+        fg, fps = ob.f64[k]
+        arr = fg if arr_i == 0 else fps[arr_i - 1]
+        ga = (grads[k][0] if arr_i == 0 else grads[k][1][arr_i - 1])[idx]
+        old = arr[idx]
+        arr[idx] = old + h
+        Lp, _ = loss()
+        arr[idx] = old - h
+        Lm, _ = loss()
+        arr[idx] = old
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(ga - fd) <= 1e-4 * abs(fd) + 1e-6 * gmax, (k, arr_i, idx, ga, fd)
+    for i in rng.choice(499, 8, replace=False):
+        old = w[i]
+        w[i] = old + h
+        Lp, _ = loss()
+        w[i] = old - h
+        Lm, _ = loss()
+        w[i] = old
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(gm[i] - fd) <= 1e-4 * abs(fd) + 1e-8, (i, gm[i], fd)
+    # the opacity term and per-block MLPs are not defined over contracted blocks
+    with pytest.raises(ValueError):
+        O.adjoint(ob, occs, v, setv, p, w, pix, g_rgb, g_tr, w_opacity=np.ones(len(pix)))
+    with pytest.raises(ValueError):
+        O.adjoint_block_mlp(ob, occs, v, setv, p, [w] * ob.n, pix, g_rgb)
+
+
 # ---------------------------------------------------------------------------
 # Early ray termination: the ray stops after the first evaluated sample whose
 # transmittance is below t_min; what it skips is bounded by that transmittance
