@@ -191,8 +191,11 @@ typedef struct cow_render_params {
      * counts like any sample.  ext_delta = 0 (or ext_max_steps = 0): no
      * exterior sampling.  A call whose sets hold a contracted block must use
      * grid mode, one MLP after the merge, no opacity output and no per-block
-     * launches (else COW_E_UNSUPPORTED); cow_render_backward and
-     * cow_sparsity reject contracted blocks with COW_E_UNSUPPORTED. */
+     * launches (else COW_E_UNSUPPORTED).  cow_render_backward takes
+     * contracted blocks under the same rule and without the opacity term
+     * (the exterior's samples, each with its own step, join the chain in ray
+     * order and scatter into their owner's textures); cow_sparsity rejects
+     * them.  Both with COW_E_UNSUPPORTED. */
     float ext_delta;
     int32_t ext_max_steps;
     /* Per-block composites handed from the forward to the backward.  Device
@@ -335,7 +338,10 @@ COW_API cow_status cow_render_noalloc(cow_ctx* ctx, const cow_view* views, int n
  * With params->block_mlp the weights' gradient goes to
  * params->grad_block_mlp instead (grad_mlp and mlp unused, may be NULL): each
  * lane re-composites a block, runs that block's MLP adjoint, and the wave's
- * sum of the 499 weight gradients is added once per block and wave. */
+ * sum of the 499 weight gradients is added once per block and wave.
+ * Contracted boundary blocks: grid mode, one MLP after the merge, no
+ * opacity_weight (COW_E_UNSUPPORTED otherwise); their exterior samples are
+ * those of the forward with the same ext_delta and ext_max_steps. */
 COW_API cow_status cow_render_backward(cow_ctx* ctx, const cow_view* views, int n_views,
                                const cow_block_set* sets, const cow_render_params* params,
                                const float* mlp, const float* aux, const float* grad_rgb,

@@ -1123,4 +1123,110 @@ __device__ inline float block_trans_f32(const BlockU& b, const Ray& r, const Spa
     return Tk;
 }
 
+// The ray's interval inside the footprint's column: the exact slab test on
+// x and y only, t clamped at 0.
+__device__ inline bool slab_xy(const float o[3], const float d[3], const float lo[3], const float hi[3], float* tn,
+                               float* tf) {
+    float t0 = 0.0f, t1 = INFINITY;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        if (d[c] == 0.0f) {
+            if (o[c] < lo[c] || o[c] > hi[c]) return false;
+            continue;
+        }
+        const float inv = 1.0f / d[c];
+        const float a = (lo[c] - o[c]) * inv;
+        const float b = (hi[c] - o[c]) * inv;
+        const float mn = a < b ? a : b, mx = a < b ? b : a;
+        if (mn > t0) t0 = mn;
+        if (mx < t1) t1 = mx;
+    }
+    *tn = t0;
+    *tf = t1;
+    return t0 < t1;
+}
+
+// Walk of one exterior segment [t_start, t_end) of a lane's ray outside the
+// scene's footprint, sampled in the contracted representation of the
+// boundary block that owns each point (implementation details; Eq. "blocks"
+// in the max norm, ties to the clamped unit cell).  From t the next point
+// lies ext_delta m^2 further, m = max(1, |x|_inf) in the owner cell's
+// normalised coordinate: about uniform steps in contracted space.  A point is
+// sampled when it lies outside the footprint, within the far limit
+// m <= 1/ext_delta, and its owner is a contracted block of the view's set;
+// the segment after the column (post) ends at the far limit.  The forward
+// and the adjoint take the same walk, so they see the same samples.
+struct ExtWalk {
+    float t, t_end, m_prev, cur_fx, cur_fy;
+    int st;     // steps taken
+    int owner;  // entry of the owner of the current cell, -1: none
+    bool live, post;
+};
+
+__device__ inline void ext_begin(const MarchArgs& a, float t_start, float t_end, bool post, bool want, ExtWalk& W) {
+    W.t = t_start + 0.5f * a.ext_delta;
+    W.t_end = t_end;
+    W.m_prev = INFINITY;
+    W.cur_fx = W.cur_fy = -1.0f;
+    W.st = 0;
+    W.owner = -1;
+    W.live = want;
+    W.post = post;
+}
+
+// Advance to the segment's next sample: its texture coordinate q in the
+// owner's textures (owner in W.owner) and its step w.  False once the lane's
+// segment has ended (W.live is cleared by the caller on early termination).
+__device__ inline bool ext_next(const MarchArgs& a, const ViewU& v, const Ray& r, ExtWalk& W, float q[3], float& w,
+                                int64_t& n_march) {
+    const float slo[3] = {a.scene_lo[0], a.scene_lo[1], a.scene_lo[2]};
+    const float shi[3] = {a.scene_hi[0], a.scene_hi[1], a.scene_hi[2]};
+    const float nxm = (shi[0] - slo[0]) - 1.0f, nym = (shi[1] - slo[1]) - 1.0f;
+    const float far = 1.0f / a.ext_delta;
+    while (W.live && W.st < a.ext_max_steps) {
+        if (!W.post && !(W.t < W.t_end)) {
+            W.live = false;
+            break;
+        }
+        float p[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p[c] = coord(r.o[c], W.t, r.d[c]);
+        float fx = floorf(p[0] - slo[0]), fy = floorf(p[1] - slo[1]);
+        fx = fx < 0.0f ? 0.0f : (fx > nxm ? nxm : fx);
+        fy = fy < 0.0f ? 0.0f : (fy > nym ? nym : fy);
+        const float clo[3] = {slo[0] + fx, slo[1] + fy, slo[2]};
+        const float chi[3] = {clo[0] + 1.0f, clo[1] + 1.0f, shi[2]};
+        float m = contract_q(clo, chi, p, q);
+        if (m < 1.0f) m = 1.0f;
+        w = (a.ext_delta * m) * m;
+        ++W.st;
+        W.t = W.t + w;
+        // beyond the far limit: the segment after the column ends there,
+        // the one before it once m grows past it (m is convex along a ray
+        // outside the column: it never comes back)
+        const bool rising = m > W.m_prev;
+        W.m_prev = m;
+        if (m > far) {
+            if (W.post || rising) W.live = false;
+            continue;
+        }
+        if (slo[0] <= p[0] && p[0] < shi[0] && slo[1] <= p[1] && p[1] < shi[1]) continue;
+        if (fx != W.cur_fx || fy != W.cur_fy) {  // owner of the cell: a contracted block of the set
+            W.cur_fx = fx, W.cur_fy = fy, W.owner = -1;
+            for (int j = 0; j < v.set_n; ++j) {
+                const int e = ufl(a.refs[v.set_begin + j]);
+                const DevBlock* B = a.blocks + e;
+                if (ufl(B->contracted) && uff(B->lo[0]) == clo[0] && uff(B->lo[1]) == clo[1]) {
+                    W.owner = e;
+                    break;
+                }
+            }
+        }
+        if (W.owner < 0) continue;
+        ++n_march;
+        return true;
+    }
+    return false;
+}
+
 }  // namespace cow

@@ -1299,7 +1299,9 @@ cow_status cow_render_backward(cow_ctx* c, const cow_view* views, int n_views, c
     for (int32_t e : T.refs)
         if (c->entries[e].desc.dtype != COW_F32)
             return fail(c, COW_E_UNSUPPORTED, "backward needs float32 textures");
-    if (any_contracted(c, T.refs)) return fail(c, COW_E_UNSUPPORTED, "the adjoint does not march contracted blocks");
+    if (any_contracted(c, T.refs) && (p->mode != COW_MODE_GRID || p->block_mlp || p->opacity_weight))
+        return fail(c, COW_E_UNSUPPORTED, "the adjoint of contracted blocks runs in grid mode with one MLP after "
+                                          "the merge and no opacity term");
     RenderWs w;
     std::vector<cow_block_desc> descs;
     for (const Entry& en : c->entries) descs.push_back(en.desc);

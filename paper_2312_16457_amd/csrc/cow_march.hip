@@ -8,102 +8,20 @@
 
 namespace cow {
 
-// The ray's interval inside the footprint's column: the exact slab test on
-// x and y only, t clamped at 0.
-__device__ inline bool slab_xy(const float o[3], const float d[3], const float lo[3], const float hi[3], float* tn,
-                               float* tf) {
-    float t0 = 0.0f, t1 = INFINITY;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        if (d[c] == 0.0f) {
-            if (o[c] < lo[c] || o[c] > hi[c]) return false;
-            continue;
-        }
-        const float inv = 1.0f / d[c];
-        const float a = (lo[c] - o[c]) * inv;
-        const float b = (hi[c] - o[c]) * inv;
-        const float mn = a < b ? a : b, mx = a < b ? b : a;
-        if (mn > t0) t0 = mn;
-        if (mx < t1) t1 = mx;
-    }
-    *tn = t0;
-    *tf = t1;
-    return t0 < t1;
-}
-
-// One exterior segment [t_start, t_end) of a lane's ray outside the scene's
-// footprint, sampled in the contracted representation of the boundary block
-// that owns each point (implementation details; Eq. "blocks" in the max
-// norm, ties to the clamped unit cell).  From t the next point lies
-// ext_delta m^2 further, m = max(1, |x|_inf) in the owner cell's normalised
-// coordinate: about uniform steps in contracted space.  A point is sampled
-// when it lies outside the footprint, within the far limit m <= 1/ext_delta,
-// and its owner is a contracted block of the view's set; the segment after
-// the column (post) ends at the far limit.  The segment's samples composite
-// into (Ae, Te), merged into (A, T) at the end (Eq. "volume rendering across
+// One exterior segment of a lane's ray (see ExtWalk), composited into
+// (Ae, Te) and merged into (A, T) at the end (Eq. "volume rendering across
 // blocks").  Lanes of a wave may sample different owners: each round
 // evaluates one owner for all lanes that need it, the textures addressed
 // through that block's wave-uniform descriptors.
 template <int DT, bool SPARSE>
 __device__ inline void march_exterior(const MarchArgs& a, const ViewU& v, const Ray& r, float t_start, float t_end,
                                       bool post, bool want, float A[7], float& T, int64_t& n_eval, int64_t& n_march) {
-    const float slo[3] = {a.scene_lo[0], a.scene_lo[1], a.scene_lo[2]};
-    const float shi[3] = {a.scene_hi[0], a.scene_hi[1], a.scene_hi[2]};
-    const float nxm = (shi[0] - slo[0]) - 1.0f, nym = (shi[1] - slo[1]) - 1.0f;
-    const float far = 1.0f / a.ext_delta;
-    float t = t_start + 0.5f * a.ext_delta;
-    int st = 0;
-    bool live = want;
-    float cur_fx = -1.0f, cur_fy = -1.0f, m_prev = INFINITY;
-    int cur_e = -1;
+    ExtWalk W;
+    ext_begin(a, t_start, t_end, post, want, W);
     float Ae[7] = {0, 0, 0, 0, 0, 0, 0}, Te = 1.0f;
     for (;;) {
-        bool have = false;
         float q[3] = {0.0f, 0.0f, 0.0f}, w = 0.0f;
-        while (live && st < a.ext_max_steps) {
-            if (!post && !(t < t_end)) {
-                live = false;
-                break;
-            }
-            float p[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) p[c] = coord(r.o[c], t, r.d[c]);
-            float fx = floorf(p[0] - slo[0]), fy = floorf(p[1] - slo[1]);
-            fx = fx < 0.0f ? 0.0f : (fx > nxm ? nxm : fx);
-            fy = fy < 0.0f ? 0.0f : (fy > nym ? nym : fy);
-            const float clo[3] = {slo[0] + fx, slo[1] + fy, slo[2]};
-            const float chi[3] = {clo[0] + 1.0f, clo[1] + 1.0f, shi[2]};
-            float m = contract_q(clo, chi, p, q);
-            if (m < 1.0f) m = 1.0f;
-            w = (a.ext_delta * m) * m;
-            ++st;
-            t = t + w;
-            // beyond the far limit: the segment after the column ends there,
-            // the one before it once m grows past it (m is convex along a ray
-            // outside the column: it never comes back)
-            const bool rising = m > m_prev;
-            m_prev = m;
-            if (m > far) {
-                if (post || rising) live = false;
-                continue;
-            }
-            if (slo[0] <= p[0] && p[0] < shi[0] && slo[1] <= p[1] && p[1] < shi[1]) continue;
-            if (fx != cur_fx || fy != cur_fy) {  // owner of the cell: a contracted block of the set
-                cur_fx = fx, cur_fy = fy, cur_e = -1;
-                for (int j = 0; j < v.set_n; ++j) {
-                    const int e = ufl(a.refs[v.set_begin + j]);
-                    const DevBlock* B = a.blocks + e;
-                    if (ufl(B->contracted) && uff(B->lo[0]) == clo[0] && uff(B->lo[1]) == clo[1]) {
-                        cur_e = e;
-                        break;
-                    }
-                }
-            }
-            if (cur_e < 0) continue;
-            ++n_march;
-            have = true;
-            break;
-        }
+        const bool have = ext_next(a, v, r, W, q, w, n_march);
         if (!__any(have)) break;
         bool pending = have;
         bool occupied = false;
@@ -111,10 +29,10 @@ __device__ inline void march_exterior(const MarchArgs& a, const ViewU& v, const 
         while (__any(pending)) {
             const uint64_t mask = __ballot(pending);
             const int first = __ffsll((unsigned long long)mask) - 1;
-            const int eu = ufl(__shfl(cur_e, first));
+            const int eu = ufl(__shfl(W.owner, first));
             BlockU b;
             load_block<DT>(a.blocks + eu, b);
-            if (pending && cur_e == eu) {
+            if (pending && W.owner == eu) {
                 pending = false;
                 const int cell = occ_cell(b, q);
                 occupied = ld1g(b.skip, (uint32_t)cell) == 0;
@@ -143,7 +61,7 @@ __device__ inline void march_exterior(const MarchArgs& a, const ViewU& v, const 
             for (int c = 0; c < 7; ++c) Ae[c] = fmaf(wt, val[c], Ae[c]);
             Te *= 1.0f - alpha;
             ++n_eval;
-            if (T * Te < a.t_min) live = false;  // early ray termination
+            if (T * Te < a.t_min) W.live = false;  // early ray termination
         }
     }
 #pragma unroll

@@ -284,13 +284,97 @@ __device__ inline void grid_cache_flush(GridLds& G, OutQueue& Q, int lane, int& 
     grid_cache_clear(G, lane);
 }
 
+// Adjoint of one exterior segment of a lane's ray (contracted boundary
+// blocks): the samples of the forward's walk, in its order, each with its
+// own step w as its delta, join the running prefix (Ap, Tg) of the single
+// chain; dL/draw of a sample is scattered into the pair slots of the block
+// that owns it.  Lanes may have different owners: each round serves one
+// owner, whose wave-uniform descriptors address its textures.  Tm is the
+// merged transmittance before the segment as the forward forms it (its
+// early-termination decision uses Tm Te), multiplied by the segment's Te at
+// the end.
+__device__ inline void bwd_exterior(const BwdArgs& ba, const ViewU& v, const Ray& r, float t_start, float t_end,
+                                    bool post, bool want, const float u[7], const float Af[7], float tn_term,
+                                    float Ap[7], float& Tg, float& Tm, ScatterLds& lds, int lane) {
+    const MarchArgs& a = ba.m;
+    ExtWalk W;
+    ext_begin(a, t_start, t_end, post, want, W);
+    float Te = 1.0f;
+    int64_t unused = 0;
+    for (;;) {
+        float q[3] = {0.0f, 0.0f, 0.0f}, w = 0.0f;
+        const bool have = ext_next(a, v, r, W, q, w, unused);
+        if (!__any(have)) break;
+        bool pending = have;
+        while (__any(pending)) {
+            const uint64_t mask = __ballot(pending);
+            const int first = __ffsll((unsigned long long)mask) - 1;
+            const int eu = ufl(__shfl(W.owner, first));
+            BlockU b;
+            load_block<1>(a.blocks + eu, b);
+            Taps T;
+            float draw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            bool sampled = false;
+            if (pending && W.owner == eu) {
+                pending = false;
+                const int cell = occ_cell(b, q);
+                if (ld1g(b.skip, (uint32_t)cell) == 0) {
+                    sampled = true;
+                    sample_taps(b, q, T);
+                    float raw[8];
+                    raw_f32<true>(b, T, raw);
+                    const float sigma = __expf(raw[0]);
+                    const float alpha = alpha_of(sigma * w);
+                    const float wt = Tg * alpha;
+                    float vv[7];
+                    float uv = 0.0f, us = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < 7; ++c) {
+                        vv[c] = sigmoidf_(raw[1 + c]);
+                        Ap[c] = fmaf(wt, vv[c], Ap[c]);
+                        uv = fmaf(u[c], vv[c], uv);
+                        us = fmaf(u[c], Af[c] - Ap[c], us);
+                    }
+                    const float Tn = Tg * (1.0f - alpha);
+                    const float dsig = w * (Tn * uv - us) - w * tn_term;
+                    draw[0] = sigma * dsig;
+#pragma unroll
+                    for (int c = 0; c < 7; ++c) draw[1 + c] = wt * u[c] * vv[c] * (1.0f - vv[c]);
+                    Tg = Tn;
+                    Te *= 1.0f - alpha;
+                    if (Tm * Te < a.t_min) W.live = false;  // early ray termination, as in the forward
+                }
+            }
+            // the owner's ten pairs, from the lanes it serves this round
+            float* gptr[4] = {ufp(ba.grad_grid[eu]), ufp(ba.grad_plane[3 * eu + 0]), ufp(ba.grad_plane[3 * eu + 1]),
+                              ufp(ba.grad_plane[3 * eu + 2])};
+            __amdgpu_buffer_rsrc_t ga[4];
+            ga[0] = tex_rsrc(ufp(ba.slots[4 * eu]), grid_texels(b) * 64u);
+            for (int t = 1; t < 4; ++t) ga[t] = tex_rsrc(ufp(ba.slots[4 * eu + t]), plane_texels(b, t - 1) * 64u);
+#pragma unroll
+            for (int pr = 0; pr < 10; ++pr) {
+                const int tex = pair_tex(pr);
+                if (!gptr[tex]) continue;
+                float vals[16];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    vals[c] = T.w[2 * pr] * draw[c];
+                    vals[8 + c] = T.w[2 * pr + 1] * draw[c];
+                }
+                scatter_pair(lds, lane, vals, sampled ? T.pidx[pr] : -1, ga[tex]);
+            }
+        }
+    }
+    Tm *= Te;
+}
+
 // BMLP: per-block deferred MLPs before the merge.  Per block k with prefix
 // transmittance P, a first pass composites the block (A^k, T^k); the lane
 // then runs the block's MLP adjoint for u = dL/dA^k and takes
 // T^k dL/dT^k = g . R_k + gT T, with R_k = C - (colour merged up to block k)
 // the light of the later blocks; the sample adjoint inside the block is the
 // single-chain one with these per-block u and transmittance term.
-template <int MODE, bool OPAC, bool BMLP>
+template <int MODE, bool OPAC, bool BMLP, bool CT>
 __device__ __attribute__((always_inline)) inline void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile,
                                                                        int lane, ScatterLds& lds, GridLds& glds,
                                                                        OutQueue& gq) {
@@ -332,6 +416,13 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
     float T_blk = 1.0f;  // merged transmittance before the block, as the forward forms it
     float tn_term = TN * gT;
     int64_t unused = 0;
+    float fin = INFINITY, fout = INFINITY;  // the ray's interval in the footprint's column
+    if (CT && a.ext_delta > 0.0f) {
+        const float slo[3] = {a.scene_lo[0], a.scene_lo[1], a.scene_lo[2]};
+        const float shi[3] = {a.scene_hi[0], a.scene_hi[1], a.scene_hi[2]};
+        if (!slab_xy(r.o, r.d, slo, shi, &fin, &fout)) fin = fout = INFINITY;
+        bwd_exterior(ba, v, r, 0.0f, fin, false, r.active, u, Af, tn_term, Ap, Tg, T_blk, lds, lane);
+    }
     for (int j = 0; j < v.set_n; ++j) {
         const int e = ufl(a.refs[v.set_begin + j]);
         BlockU b;
@@ -403,7 +494,8 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
             float q[3];
             int cell = 0;
             // one step at a time (see march_block): the same samples as the forward's jumps
-            const bool have = next_occupied<MODE>(b, r, sp, kb, sp.delta, true, k, q, cell, cur_cell, cur_occ, unused);
+            const bool have =
+                next_occupied<MODE, CT>(b, r, sp, kb, sp.delta, true, k, q, cell, cur_cell, cur_occ, unused);
             if (!__any(have)) break;
             Taps T;
             float draw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -458,6 +550,12 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
         }
         T_blk *= Tk;
     }
+    if (CT && a.ext_delta > 0.0f) {
+        // the cap truncates the ray, as in the forward
+        const bool capped = MODE == 1 && hit && step_t(w1, a.delta) < fout;
+        bwd_exterior(ba, v, r, fout, INFINITY, true, r.active && fout < INFINITY && !capped && !(T_blk < a.t_min), u,
+                     Af, tn_term, Ap, Tg, T_blk, lds, lane);
+    }
 }
 
 // OPAC: with the opacity regulariser's pre-march (a separate instance keeps
@@ -482,7 +580,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void m
         }
         if (p >= a.total_tiles) return;
         const DevView* V = find_view_by_tile(a.views, a.n_views, p);
-        march_bwd_packet<MODE, OPAC, BMLP>(ba, V, p - ufl(V->tile_begin), lane, lds[wave], glds[wave], gq[wave]);
+        march_bwd_packet<MODE, OPAC, BMLP, false>(ba, V, p - ufl(V->tile_begin), lane, lds[wave], glds[wave], gq[wave]);
+        if (!a.persistent) return;
+    }
+}
+
+// Contracted boundary blocks (their samples read through the contraction,
+// the exterior segments around the blocks): grid mode, one MLP after the
+// merge, no opacity term.  A kernel of its own, the same packet walk, so the
+// plain adjoint carries none of its code.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void march_bwd_ct_kernel(BwdArgs ba) {
+    const MarchArgs& a = ba.m;
+    __shared__ ScatterLds lds[4];
+    __shared__ GridLds glds[4];
+    __shared__ OutQueue gq[4];
+    const int lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    const int wave = ufl(threadIdx.x >> 6);
+    scatter_lds_init(lds[wave], lane);
+    int p = a.persistent ? 0 : ufl(xcd_packet(waves, wave));  // one call site, as in the forward
+    for (;;) {
+        if (a.persistent) {
+            int q = -1;
+            if (lane == 0) q = take_packet(a.work_counter, a.total_tiles);
+            p = ufl(__shfl(q, 0));
+            if (p < 0) return;
+        }
+        if (p >= a.total_tiles) return;
+        const DevView* V = find_view_by_tile(a.views, a.n_views, p);
+        march_bwd_packet<1, false, false, true>(ba, V, p - ufl(V->tile_begin), lane, lds[wave], glds[wave], gq[wave]);
         if (!a.persistent) return;
     }
 }
@@ -540,7 +666,9 @@ hipError_t launch_march_bwd(const BwdArgs& a, int waves, hipStream_t s) {
     const bool op = a.w_opacity != nullptr, bm = a.m.block_mlp != nullptr;
     const size_t shm = 0;
 #define COW_LAUNCH(M, O, B) hipLaunchKernelGGL((march_bwd_kernel<M, O, B>), grid, block, shm, s, a)
-    if (a.m.mode == 1) {
+    if (a.m.contract) {  // grid mode, one MLP after the merge, no opacity term (checked on the host)
+        hipLaunchKernelGGL(march_bwd_ct_kernel, grid, block, shm, s, a);
+    } else if (a.m.mode == 1) {
         if (bm)
             COW_LAUNCH(1, false, true);
         else if (op)

@@ -1,7 +1,9 @@
 """Contracted boundary blocks and the exterior they own (implementation
 details, the contraction equation; Eq. "blocks" for ownership): the HIP
 march against the oracle, element by element, with the sample counts
-bit-exact (every decision on both sides is the same fp32 sequence)."""
+bit-exact (every decision on both sides is the same fp32 sequence); the
+adjoint against the fp64 oracle adjoint (pinned to central differences),
+each gradient tensor within 1e-3 of its largest value."""
 import types
 
 import numpy as np
@@ -227,3 +229,124 @@ def test_selection_with_contracted_blocks(torch_cuda, quadtree):
         print(name, "quadtree" if quadtree else "per-block", len(sel), "entries,",
               int(ref["n_march"].sum()), "samples", flush=True)
         check(a, ref)
+
+
+REL = 1e-3
+
+
+def backward_both(torch, sc, views, p, w, g_rgb, g_tr):
+    """GPU backward (one call over all views) and the oracle's per view."""
+    from paper_2312_16457_amd import Renderer
+    r = Renderer(0).load_blocks(sc.blocks)
+    refs = [(b.block_id, b.lod) for b in sc.blocks]
+    mlp = torch.tensor(w, device="cuda")
+    out = r.render(views, [refs] * len(views), p, mlp)
+    gg = [torch.zeros_like(t[0]) for t in r.textures]
+    gp = [[torch.zeros_like(q) for q in t[1]] for t in r.textures]
+    gm = torch.zeros(499, device="cuda")
+    r.render_backward(views, [refs] * len(views), p, mlp, out["aux"],
+                      torch.tensor(g_rgb, dtype=torch.float32, device="cuda"),
+                      torch.tensor(g_tr, dtype=torch.float32, device="cuda"), gg, gp, gm)
+    torch.cuda.synchronize()
+    ob = O.OracleScene(sc.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    ref, gm_ref, off = None, 0.0, 0
+    for v in views:
+        n = v.n_pixels
+        gr, gmr = O.adjoint(ob, occs, v, list(range(ob.n)), p, w, O.pixels_of(v), g_rgb[off:off + n],
+                            g_tr[off:off + n])
+        if ref is None:
+            ref = gr
+        else:
+            for k in gr:
+                ref[k][0][...] += gr[k][0]
+                for i in range(3):
+                    ref[k][1][i][...] += gr[k][1][i]
+        gm_ref = gm_ref + gmr
+        off += n
+    return (gg, gp, gm), (ref, gm_ref), r, out
+
+
+def compare_grads(got, want, rel=REL):
+    gg, gp, gm = got
+    ref, gm_ref = want
+    for k, (g, ps) in ref.items():
+        for a, b in [(gg[k], g)] + [(gp[k][i], ps[i]) for i in range(3)]:
+            den = np.abs(b).max()
+            a = a.cpu().numpy()
+            if den == 0:
+                assert np.abs(a).max() == 0, k
+                continue
+            e = np.abs(a - b).max() / den
+            assert e <= rel, (k, e)
+    e = np.abs(gm.cpu().numpy() - gm_ref).max() / np.abs(gm_ref).max()
+    assert e <= rel, ("mlp", e)
+
+
+@pytest.mark.parametrize("name", sorted(VIEWS))
+def test_contracted_adjoint_matches_oracle(torch_cuda, name):
+    eye, fwd = VIEWS[name]
+    view = sg.pinhole(29, 23, eye, sg.look_rotation(np.asarray(fwd)))
+    p = sg.RenderParams(mode=1, ext_delta=1.0 / 64, ext_max_steps=512)
+    sc = city(sg.F32)
+    w = sg.random_mlp(2, 0.7)
+    rng = np.random.default_rng(3)
+    g_rgb = rng.uniform(-1, 1, (view.n_pixels, 3))
+    g_tr = rng.uniform(-1, 1, view.n_pixels)
+    print(name, "contracted adjoint", flush=True)
+    got, want, _, _ = backward_both(torch_cuda, sc, [view], p, w, g_rgb, g_tr)
+    compare_grads(got, want)
+    # the exterior's samples carry part of the gradient
+    ob = O.OracleScene(sc.blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    g0, _ = O.adjoint(ob, occs, view, list(range(ob.n)), sg.RenderParams(mode=1), w, O.pixels_of(view), g_rgb, g_tr)
+    moved = max(np.abs(want[0][k][1][i] - g0[k][1][i]).max() / max(np.abs(want[0][k][1][i]).max(), 1e-30)
+                for k in g0 for i in range(3))
+    assert moved > 1e-2
+
+
+def test_contracted_adjoint_two_views_termination_and_rules(torch_cuda):
+    """Two views in one call on the opaque variant with early termination
+    (t_min = 1e-3, decided in the exterior as in the forward); two calls
+    agree to atomics' reordering; the opacity term, per-block MLPs and chord
+    mode are refused over contracted blocks."""
+    from paper_2312_16457_amd import CowError
+    torch = torch_cuda
+    scene = sg.make_scene(3, 3, ((16, 64, 8),), sg.F32, blobs_per_block=10, blob_z=(0, 0.3), seed=5, shift=0.0)
+    sc = types.SimpleNamespace(blocks=sg.contract_boundary(scene.blocks))
+    views = [sg.pinhole(27, 19, e, sg.look_rotation(np.asarray(f))) for e, f in
+             (VIEWS["outside_looking_in"], VIEWS["above_looking_out"])]
+    p = sg.RenderParams(mode=1, t_min=1e-3, ext_delta=1.0 / 64, ext_max_steps=512)
+    w = sg.random_mlp(6, 0.7)
+    n = sum(v.n_pixels for v in views)
+    rng = np.random.default_rng(8)
+    g_rgb = rng.uniform(-1, 1, (n, 3))
+    g_tr = rng.uniform(-1, 1, n)
+    print("contracted adjoint, two views, t_min", flush=True)
+    got, want, r, out = backward_both(torch, sc, views, p, w, g_rgb, g_tr)
+    compare_grads(got, want)
+    refs = [(b.block_id, b.lod) for b in sc.blocks]
+    mlp = torch.tensor(w, device="cuda")
+    gg = [torch.zeros_like(t[0]) for t in r.textures]
+    gp = [[torch.zeros_like(q) for q in t[1]] for t in r.textures]
+    gm = torch.zeros(499, device="cuda")
+    tg = torch.tensor(g_rgb, dtype=torch.float32, device="cuda")
+    tt = torch.tensor(g_tr, dtype=torch.float32, device="cuda")
+    r.render_backward(views, [refs, refs], p, mlp, out["aux"], tg, tt, gg, gp, gm)
+    torch.cuda.synchronize()
+    for a, b in zip(gg + [x for ps in gp for x in ps] + [gm], got[0] + [x for ps in got[1] for x in ps] + [got[2]]):
+        den = b.abs().max().item()
+        assert (a - b).abs().max().item() <= 1e-6 * max(den, 1e-30)
+    with pytest.raises(CowError) as ei:
+        r.render_backward(views, [refs, refs], p, mlp, out["aux"], tg, tt, gg, gp, gm,
+                          opacity_weight=torch.ones_like(out["trans"]))
+    assert ei.value.status == 4
+    bm = torch.tensor(np.stack([w] * len(sc.blocks)), dtype=torch.float32, device="cuda")
+    with pytest.raises(CowError) as ei:
+        r.render_backward(views, [refs, refs], p, None, out["aux"], tg, tt, gg, gp, None, block_mlp=bm,
+                          grad_block_mlp=torch.zeros_like(bm).reshape(-1))
+    assert ei.value.status == 4
+    with pytest.raises(CowError) as ei:
+        r.render_backward(views, [refs, refs], sg.RenderParams(mode=0, n_steps=32), mlp, out["aux"], tg, tt, gg, gp,
+                          gm)
+    assert ei.value.status == 4
