@@ -585,7 +585,27 @@ def leg_backward(torch, sg, Renderer, reps=2):
     ms = _timed(torch, lambda: r.sparsity(refs, pts, 1.0 / 512, 1e-3, grad_grid=gg, grad_plane=gp), 5)
     res["sparsity_2e14_points_ms"] = round(ms, 4)
     log("backward variants done")
-    del r, gg, gp, out, g
+    del r, gg, gp, out
+    torch.cuda.empty_cache()
+    # the same scene with its 12 edge blocks contracted and the exterior
+    # sampled (ext_delta 1/64, at most 512 steps per segment): forward and
+    # backward of the contraction kernels
+    from dataclasses import replace
+    rc = Renderer(0)
+    rc.load_blocks(sg.contract_boundary(learn.blocks))
+    pc = replace(p, ext_delta=1.0 / 64, ext_max_steps=512)
+    oc = rc.render(views, sets, pc, mlp, counts=True)
+    n_ct = int(oc["counts"][:, 0].sum().item())
+    ct_fwd = _timed(torch, lambda: rc.render(views, sets, pc, mlp, out=oc), reps)
+    gg = [torch.zeros_like(t[0]) for t in rc.textures]
+    gp = [[torch.zeros_like(x) for x in t[1]] for t in rc.textures]
+    ct_bwd = _timed(torch, lambda: rc.render_backward(views, sets, pc, mlp, oc["aux"], g, None, gg, gp, gm), reps)
+    res["contracted"] = {"workload": "the same 4x4 fp32 scene, 12 edge blocks contracted, exterior ext_delta 1/64, "
+                                     "<= 512 steps per segment", "evaluated_samples": n_ct,
+                         "fwd_ms": round(ct_fwd, 3), "bwd_ms": round(ct_bwd, 3),
+                         "bwd_Msamples_per_s": round(n_ct / (ct_bwd * 1e-3) / 1e6, 2)}
+    log(f"backward, contracted: {ct_bwd:.1f} ms")
+    del rc, gg, gp, oc, g
     torch.cuda.empty_cache()
     # the fp32 forward's gather rate against the probe at the same footprint
     from paper_2312_16457_amd import COW_F32
