@@ -357,9 +357,9 @@ __device__ inline void bwd_exterior(const BwdArgs& ba, const ViewU& v, const Ray
                 if (!gptr[tex]) continue;
                 float vals[16];
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    vals[c] = T.w[2 * pr] * draw[c];
-                    vals[8 + c] = T.w[2 * pr + 1] * draw[c];
+                for (int c = 0; c < 8; ++c) {  // a lane without a sample this round sends nothing
+                    vals[c] = sampled ? T.w[2 * pr] * draw[c] : 0.0f;
+                    vals[8 + c] = sampled ? T.w[2 * pr + 1] * draw[c] : 0.0f;
                 }
                 scatter_pair(lds, lane, vals, sampled ? T.pidx[pr] : -1, ga[tex]);
             }
