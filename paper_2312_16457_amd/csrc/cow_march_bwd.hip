@@ -284,6 +284,49 @@ __device__ inline void grid_cache_flush(GridLds& G, OutQueue& Q, int lane, int& 
     grid_cache_clear(G, lane);
 }
 
+// Local composite (Ae, Te) of one exterior segment, as the forward forms it
+// (the same walk, samples and early-termination rule; Tm the merged
+// transmittance before the segment).
+__device__ inline void bwd_exterior_total(const BwdArgs& ba, const ViewU& v, const Ray& r, float t_start,
+                                          float t_end, bool post, bool want, float Tm, float Ae[7], float& Te) {
+    const MarchArgs& a = ba.m;
+    ExtWalk W;
+    ext_begin(a, t_start, t_end, post, want, W);
+#pragma unroll
+    for (int c = 0; c < 7; ++c) Ae[c] = 0.0f;
+    Te = 1.0f;
+    int64_t unused = 0;
+    for (;;) {
+        float q[3] = {0.0f, 0.0f, 0.0f}, w = 0.0f;
+        const bool have = ext_next(a, v, r, W, q, w, unused);
+        if (!__any(have)) break;
+        bool pending = have;
+        while (__any(pending)) {
+            const uint64_t mask = __ballot(pending);
+            const int first = __ffsll((unsigned long long)mask) - 1;
+            const int eu = ufl(__shfl(W.owner, first));
+            BlockU b;
+            load_block<1>(a.blocks + eu, b);
+            if (pending && W.owner == eu) {
+                pending = false;
+                const int cell = occ_cell(b, q);
+                if (ld1g(b.skip, (uint32_t)cell) == 0) {
+                    Taps T;
+                    sample_taps(b, q, T);
+                    float raw[8];
+                    raw_f32<true>(b, T, raw);
+                    const float alpha = alpha_of(__expf(raw[0]) * w);
+                    const float wt = Te * alpha;
+#pragma unroll
+                    for (int c = 0; c < 7; ++c) Ae[c] = fmaf(wt, sigmoidf_(raw[1 + c]), Ae[c]);
+                    Te *= 1.0f - alpha;
+                    if (Tm * Te < a.t_min) W.live = false;
+                }
+            }
+        }
+    }
+}
+
 // Adjoint of one exterior segment of a lane's ray (contracted boundary
 // blocks): the samples of the forward's walk, in its order, each with its
 // own step w as its delta, join the running prefix (Ap, Tg) of the single
@@ -292,14 +335,22 @@ __device__ inline void grid_cache_flush(GridLds& G, OutQueue& Q, int lane, int& 
 // owner, whose wave-uniform descriptors address its textures.  Tm is the
 // merged transmittance before the segment as the forward forms it (its
 // early-termination decision uses Tm Te), multiplied by the segment's Te at
-// the end.
+// the end.  The light after sample i, A - A_{<=i}, is formed locally as
+// Tm (Ae - Ae_{<=i}) + rest, from the segment's own composite Ae and the
+// light after the segment (rest), not as the ray's A minus the running
+// prefix: that difference carries fp32 rounding of the whole ray's light,
+// which the exterior's long steps (delta up to ext_delta m^2) would multiply
+// into the gradient of samples behind opaque content.  Each part is clamped
+// to where it lies exactly: features are in (0, 1), so the light after a
+// sample is at most the transmittance after it.
 __device__ inline void bwd_exterior(const BwdArgs& ba, const ViewU& v, const Ray& r, float t_start, float t_end,
-                                    bool post, bool want, const float u[7], const float Af[7], float tn_term,
-                                    float Ap[7], float& Tg, float& Tm, ScatterLds& lds, int lane) {
+                                    bool post, bool want, const float u[7], const float Ae_tot[7],
+                                    const float rest[7], float tn_term, float Ap[7], float& Tg, float& Tm,
+                                    ScatterLds& lds, int lane) {
     const MarchArgs& a = ba.m;
     ExtWalk W;
     ext_begin(a, t_start, t_end, post, want, W);
-    float Te = 1.0f;
+    float Te = 1.0f, Ael[7] = {0, 0, 0, 0, 0, 0, 0};
     int64_t unused = 0;
     for (;;) {
         float q[3] = {0.0f, 0.0f, 0.0f}, w = 0.0f;
@@ -325,15 +376,18 @@ __device__ inline void bwd_exterior(const BwdArgs& ba, const ViewU& v, const Ray
                     raw_f32<true>(b, T, raw);
                     const float sigma = __expf(raw[0]);
                     const float alpha = alpha_of(sigma * w);
-                    const float wt = Tg * alpha;
+                    const float wt = Tg * alpha, wl = Te * alpha;
+                    const float Tel = Te * (1.0f - alpha);  // the segment's transmittance after the sample
                     float vv[7];
                     float uv = 0.0f, us = 0.0f;
 #pragma unroll
                     for (int c = 0; c < 7; ++c) {
                         vv[c] = sigmoidf_(raw[1 + c]);
-                        Ap[c] = fmaf(wt, vv[c], Ap[c]);
+                        Ap[c] = fmaf(wt, vv[c], Ap[c]);  // the ray's prefix, for the blocks after the segment
+                        Ael[c] = fmaf(wl, vv[c], Ael[c]);
+                        const float after = fmaf(Tm, fminf(fmaxf(Ae_tot[c] - Ael[c], 0.0f), Tel), rest[c]);
                         uv = fmaf(u[c], vv[c], uv);
-                        us = fmaf(u[c], Af[c] - Ap[c], us);
+                        us = fmaf(u[c], after, us);
                     }
                     const float Tn = Tg * (1.0f - alpha);
                     const float dsig = w * (Tn * uv - us) - w * tn_term;
@@ -341,7 +395,7 @@ __device__ inline void bwd_exterior(const BwdArgs& ba, const ViewU& v, const Ray
 #pragma unroll
                     for (int c = 0; c < 7; ++c) draw[1 + c] = wt * u[c] * vv[c] * (1.0f - vv[c]);
                     Tg = Tn;
-                    Te *= 1.0f - alpha;
+                    Te = Tel;
                     if (Tm * Te < a.t_min) W.live = false;  // early ray termination, as in the forward
                 }
             }
@@ -421,7 +475,11 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
         const float slo[3] = {a.scene_lo[0], a.scene_lo[1], a.scene_lo[2]};
         const float shi[3] = {a.scene_hi[0], a.scene_hi[1], a.scene_hi[2]};
         if (!slab_xy(r.o, r.d, slo, shi, &fin, &fout)) fin = fout = INFINITY;
-        bwd_exterior(ba, v, r, 0.0f, fin, false, r.active, u, Af, tn_term, Ap, Tg, T_blk, lds, lane);
+        float Ae[7], Te, rest[7];
+        bwd_exterior_total(ba, v, r, 0.0f, fin, false, r.active, T_blk, Ae, Te);
+#pragma unroll
+        for (int c = 0; c < 7; ++c) rest[c] = fminf(fmaxf(Af[c] - Ae[c], 0.0f), Te);  // light after the segment
+        bwd_exterior(ba, v, r, 0.0f, fin, false, r.active, u, Ae, rest, tn_term, Ap, Tg, T_blk, lds, lane);
     }
     for (int j = 0; j < v.set_n; ++j) {
         const int e = ufl(a.refs[v.set_begin + j]);
@@ -553,8 +611,11 @@ __device__ __attribute__((always_inline)) inline void march_bwd_packet(const Bwd
     if (CT && a.ext_delta > 0.0f) {
         // the cap truncates the ray, as in the forward
         const bool capped = MODE == 1 && hit && step_t(w1, a.delta) < fout;
-        bwd_exterior(ba, v, r, fout, INFINITY, true, r.active && fout < INFINITY && !capped && !(T_blk < a.t_min), u,
-                     Af, tn_term, Ap, Tg, T_blk, lds, lane);
+        const bool want = r.active && fout < INFINITY && !capped && !(T_blk < a.t_min);
+        float Ae[7], Te;
+        const float rest[7] = {0, 0, 0, 0, 0, 0, 0};  // nothing after the last segment
+        bwd_exterior_total(ba, v, r, fout, INFINITY, true, want, T_blk, Ae, Te);
+        bwd_exterior(ba, v, r, fout, INFINITY, true, want, u, Ae, rest, tn_term, Ap, Tg, T_blk, lds, lane);
     }
 }
 

@@ -6,7 +6,8 @@ sampled rows of every view for the forward (rgb and T <= 1e-4, evaluated
 and marched sample counts exact), and for the adjoint an upstream gradient
 that is zero except on 48 seeded pixels spread over the views (every other
 ray scatters zeros), against the fp64 adjoint of those pixels (<= 1e-3
-normwise per tensor)."""
+normwise per tensor).  The same with the edge blocks contracted and the
+exterior sampled."""
 import numpy as np
 import pytest
 
@@ -92,6 +93,66 @@ def test_c5_full_size_adjoint_sparse_upstream(c5):
     gp = [[torch.zeros_like(x) for x in t[1]] for t in r.textures]
     gm = torch.zeros(499, device="cuda")
     r.render_backward(views, sets, params, mlp, out["aux"], torch.tensor(g_rgb, dtype=torch.float32, device="cuda"),
+                      None, gg, gp, gm)
+    torch.cuda.synchronize()
+    touched = [k for k, (g, ps) in grads.items() if np.abs(g).max() > 0]
+    assert len(touched) >= 4
+    compare(gg, gp, gm, {k: grads[k] for k in touched}, gm_ref)
+    for k in set(range(len(learn.blocks))) - set(touched):
+        assert gg[k].abs().max().item() == 0
+
+
+def test_c5_contracted_full_size_forward_rows_and_adjoint(c5):
+    """The same workload with its 12 edge blocks contracted and the exterior
+    sampled (ext_delta 1/64, at most 512 steps per segment), as the benchmark
+    times it: two sampled rows of every view (rgb and T <= 1e-4, sample
+    counts exact), and the adjoint of an upstream gradient on 48 seeded
+    pixels against the fp64 adjoint of those pixels."""
+    from dataclasses import replace
+
+    from paper_2312_16457_amd import Renderer
+    torch, learn, views, params, w, _, sets, mlp, _, _, _ = c5
+    blocks = sg.contract_boundary(learn.blocks)
+    assert sum(b.contracted for b in blocks) == 12
+    p = replace(params, ext_delta=1.0 / 64, ext_max_steps=512)
+    r = Renderer(0).load_blocks(blocks)
+    out = r.render(views, sets, p, mlp, counts=True)
+    torch.cuda.synchronize()
+    ob = O.OracleScene(blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    rgb, trans, counts = out["rgb"].cpu().numpy(), out["trans"].cpu().numpy(), out["counts"].cpu().numpy()
+    rows = np.array([3, 611])
+    base = 0
+    for v in views:
+        pix = O.pixels_of(v, rows=rows)
+        ref = O.render(ob, occs, v, list(range(ob.n)), p, w, pix=pix)
+        idx = base + pix[:, 1].astype(np.int64) * v.W + pix[:, 0]
+        assert np.abs(rgb[idx] - ref["rgb"]).max() <= 1e-4
+        assert np.abs(trans[idx] - ref["trans"]).max() <= 1e-4
+        assert np.array_equal(counts[idx, 0], ref["n_eval"])
+        assert np.array_equal(counts[idx, 1], ref["n_march"])
+        base += v.n_pixels
+    rng = np.random.default_rng(12)
+    g_rgb = np.zeros((out["rgb"].shape[0], 3))
+    grads, gm_ref, base = None, None, 0
+    for v in views:
+        pix = np.stack([rng.integers(0, v.W, 6), rng.integers(0, v.H, 6)], axis=1).astype(np.int32)
+        g = rng.uniform(-1, 1, (6, 3))
+        g_rgb[base + pix[:, 1].astype(np.int64) * v.W + pix[:, 0]] = g
+        gr, gmr = O.adjoint(ob, occs, v, list(range(ob.n)), p, w, pix, g)
+        if grads is None:
+            grads, gm_ref = gr, gmr
+        else:
+            for k, (gg_k, gp_k) in gr.items():
+                grads[k][0][...] += gg_k
+                for i in range(3):
+                    grads[k][1][i][...] += gp_k[i]
+            gm_ref = gm_ref + gmr
+        base += v.n_pixels
+    gg = [torch.zeros_like(t[0]) for t in r.textures]
+    gp = [[torch.zeros_like(x) for x in t[1]] for t in r.textures]
+    gm = torch.zeros(499, device="cuda")
+    r.render_backward(views, sets, p, mlp, out["aux"], torch.tensor(g_rgb, dtype=torch.float32, device="cuda"),
                       None, gg, gp, gm)
     torch.cuda.synchronize()
     touched = [k for k, (g, ps) in grads.items() if np.abs(g).max() > 0]
