@@ -194,8 +194,9 @@ typedef struct cow_render_params {
      * launches (else COW_E_UNSUPPORTED).  cow_render_backward takes
      * contracted blocks under the same rule and without the opacity term
      * (the exterior's samples, each with its own step, join the chain in ray
-     * order and scatter into their owner's textures); cow_sparsity rejects
-     * them.  Both with COW_E_UNSUPPORTED. */
+     * order and scatter into their owner's textures), COW_E_UNSUPPORTED
+     * otherwise.  cow_sparsity reads a point in a contracted block's box
+     * through the contraction; it samples no exterior. */
     float ext_delta;
     int32_t ext_max_steps;
     /* Per-block composites handed from the forward to the backward.  Device
@@ -352,7 +353,8 @@ COW_API cow_status cow_render_backward(cow_ctx* ctx, const cow_view* views, int 
 /* Sparsity regulariser (Sec. 4.3, Eq. "sparse loss"): the mean opacity
  * alpha_i = 1 - exp(-sigma(p_i) delta) at n points, times weight.  sigma is
  * the render's density: the point takes the first entry of `set` whose
- * half-open box holds it, and is zero in an unoccupied cell or outside every
+ * half-open box holds it (read through the contraction in a contracted
+ * boundary block), and is zero in an unoccupied cell or outside every
  * entry.  pts: device float [n][3] (world).  alpha: device float [n] or NULL.
  * loss: device float [1]; weight / n * sum alpha_i is ADDED to it (fp32
  * atomics, order unspecified).  grad_grid / grad_plane: host tables of device

@@ -1411,8 +1411,6 @@ cow_status cow_sparsity(cow_ctx* c, const cow_block_set* set, const float* pts, 
         const int e = find_entry(c, set->refs[r].block_id, set->refs[r].lod);
         if (e < 0) return fail(c, COW_E_INVALID, "set names a (block, lod) that is not loaded");
         idx[r] = e;
-        if (c->entries[e].desc.flags & COW_BLOCK_CONTRACTED)
-            return fail(c, COW_E_UNSUPPORTED, "sparsity points are not mapped through the contraction");
         const int d = c->entries[e].desc.dtype;
         if (dtype >= 0 && d != dtype) return fail(c, COW_E_UNSUPPORTED, "one call must use blocks of a single dtype");
         dtype = d;

@@ -32,8 +32,14 @@ __global__ __launch_bounds__(256) void sparsity_kernel(SparsityArgs s) {
         BlockU b;
         load_block<DT>(s.blocks + e, b);
         if (first != j) continue;
+        // texture coordinate: p - lo, or the contracted coordinate of a
+        // contracted boundary block (its box fills the middle half of its
+        // textures), as the march reads it
         float q[3];
-        for (int c = 0; c < 3; ++c) q[c] = p[c] - b.lo[c];
+        if (b.contracted)
+            contract_q(b.lo, b.hi, p, q);
+        else
+            for (int c = 0; c < 3; ++c) q[c] = p[c] - b.lo[c];
         const int cell = occ_cell(b, q);
         if (b.occ[cell] == 0) continue;  // the render's density is zero here
         Taps T;

@@ -762,6 +762,45 @@ def test_contracted_adjoint_matches_finite_differences():
         O.adjoint_block_mlp(ob, occs, v, setv, p, [w] * ob.n, pix, g_rgb)
 
 
+def test_sparsity_over_contracted_blocks():
+    """The sparsity term over contracted blocks (Sec. 4.3 sparsity loss; the
+    contraction equation): a point in a contracted block's box reads the
+    block's textures at the contracted coordinate.  Independently: q from the
+    fp64 contraction (pinned by P22), the field by numpy interpolation at q,
+    alpha = 1 - exp(-exp(raw_0) delta) in occupied cells; points outside every
+    box take zero."""
+    scene = tiny_city(nb=2, lods=((8, 16, 4),), shift=1.0, blobs=8, seed=29)
+    blocks = sg.contract_boundary(scene.blocks)
+    assert all(b.contracted for b in blocks)
+    ob = O.OracleScene(blocks)
+    occs = [O.occupancy(ob, k) for k in range(ob.n)]
+    rng = np.random.default_rng(31)
+    pts = np.concatenate([rng.uniform(0, 2, (3000, 2)), rng.uniform(0, 1, (3000, 1))], 1).astype(np.float32)
+    pts = np.concatenate([pts, np.array([[2.5, 0.5, 0.5], [0.5, -0.1, 0.5], [0.5, 0.5, 1.2]], np.float32)])
+    delta = 1.0 / 64
+    _, _, a = O.sparsity(ob, occs, list(range(ob.n)), pts, delta, 1.0, want_alpha=True, want_grad=False)
+    assert (a[-3:] == 0).all()
+    want = np.zeros(len(pts) - 3)
+    occupied = np.zeros(len(pts) - 3, bool)
+    for k, b in enumerate(blocks):
+        lo, hi = np.asarray(b.aabb_min, np.float64), np.asarray(b.aabb_max, np.float64)
+        p64 = pts[:-3].astype(np.float64)
+        sel = np.all((p64 >= lo) & (p64 < hi), axis=1)
+        x = (p64[sel] - (lo + hi) / 2) * 2 / (hi - lo)
+        q = (np.array([O.contract(xi) for xi in x]) + 2) * (hi - lo) / 4
+        raw = np_field(b, lo + q)
+        O_ = b.occ_res
+        cell = np.clip(np.floor(q * O_).astype(np.int64), 0, O_ - 1)
+        occ = occs[k].reshape(O_, O_, O_)[cell[:, 2], cell[:, 1], cell[:, 0]] != 0
+        want[sel] = np.where(occ, -np.expm1(-np.exp(raw[:, 0]) * delta), 0.0)
+        occupied[sel] = occ
+    got = a[:-3]
+    same = (got != 0) == occupied
+    assert same.mean() > 0.995, same.mean()  # cell decisions: fp32 here, fp64 in the check
+    assert occupied.sum() > 1000
+    assert np.abs(got - want)[same].max() <= 1e-5
+
+
 # ---------------------------------------------------------------------------
 # Early ray termination: the ray stops after the first evaluated sample whose
 # transmittance is below t_min; what it skips is bounded by that transmittance
