@@ -390,3 +390,42 @@ def test_contracted_sparsity_matches_oracle(torch_cuda, dtype):
                     assert x.abs().max().item() == 0
                     continue
                 assert np.abs(x.cpu().numpy() - y).max() <= 1e-3 * den, k
+
+
+def test_contracted_autograd_matches_direct_call(torch_cuda):
+    """make_render_fn over the contracted city: torch autograd of a loss on
+    rgb and T gives the gradients of a direct cow_render_backward call with
+    the same upstream gradients (to atomics' reordering)."""
+    torch = torch_cuda
+    from paper_2312_16457_amd import Renderer, make_render_fn
+    sc = city(sg.F32, seed=11)
+    r = Renderer(0).load_blocks(sc.blocks)
+    refs = [(b.block_id, b.lod) for b in sc.blocks]
+    eye, fwd = VIEWS["outside_looking_in"]
+    view = sg.pinhole(31, 23, eye, sg.look_rotation(np.asarray(fwd)))
+    p = sg.RenderParams(mode=1, ext_delta=1.0 / 64, ext_max_steps=512)
+    mlp = torch.tensor(sg.random_mlp(4, 0.6), device="cuda", requires_grad=True)
+    tex = []
+    for g, ps in r.textures:
+        g.requires_grad_(True)
+        for q in ps:
+            q.requires_grad_(True)
+        tex += [g] + ps
+    target = torch.rand((view.n_pixels, 3), device="cuda")
+    rgb, trans = make_render_fn().apply(r, [view], [refs], p, mlp, *tex)
+    loss = ((rgb - target) ** 2).mean() + 0.1 * trans.mean()
+    grads = torch.autograd.grad(loss, [mlp] + tex)
+    with torch.no_grad():
+        out = r.render([view], [refs], p, mlp.detach())
+        g_rgb = 2 * (out["rgb"] - target) / target.numel()
+        g_tr = torch.full_like(out["trans"], 0.1 / view.n_pixels)
+    gg = [torch.zeros_like(t[0]) for t in r.textures]
+    gp = [[torch.zeros_like(q) for q in t[1]] for t in r.textures]
+    gm = torch.zeros(499, device="cuda")
+    r.render_backward([view], [refs], p, mlp.detach(), out["aux"], g_rgb, g_tr, gg, gp, gm)
+    torch.cuda.synchronize()
+    direct = [gm] + [x for g, ps in zip(gg, gp) for x in [g] + ps]
+    assert sum(int(a.abs().max().item() > 0) for a in direct) > 8
+    for a, b in zip(grads, direct):
+        den = b.abs().max().item()
+        assert (a - b).abs().max().item() <= 1e-6 * max(den, 1e-30)
