@@ -42,8 +42,8 @@ BYTES_PER_SAMPLE_U8 = 160  # 20 texels x 8 uint8 channels gathered per evaluated
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; 3 with --profile)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 5; 1 with --profile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the backward and batched measurements")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no CPU leg, no extras)")
@@ -98,7 +98,8 @@ def main():
     n_eval = int(out["counts"][:, 0].sum().item())
     n_march = int(out["counts"][:, 1].sum().item())
     out = r.render([view], [sel], params, mlp, want_aux=False)
-    steps, warm = (3, 1) if args.profile else (args.steps, args.warmup)
+    steps = args.steps if args.steps is not None else (3 if args.profile else 20)
+    warm = args.warmup if args.warmup is not None else (1 if args.profile else 5)
     for _ in range(warm):
         r.render([view], [sel], params, mlp, out=out)
     torch.cuda.synchronize()
