@@ -432,6 +432,8 @@ template <int MODE, bool OPAC, bool BMLP, bool CT>
 __device__ __attribute__((always_inline)) inline void march_bwd_packet(const BwdArgs& ba, const DevView* V, int tile,
                                                                        int lane, ScatterLds& lds, GridLds& glds,
                                                                        OutQueue& gq) {
+    // the exterior's adjoint reads the ray's A from aux: one MLP after the merge
+    static_assert(!(CT && (OPAC || BMLP || MODE != 1)), "contracted blocks: grid mode, one MLP, no opacity term");
     const MarchArgs& a = ba.m;
     ViewU v;
     load_view(V, v);
